@@ -1,0 +1,212 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: dense
+matrix exponentials of the Hamiltonians, closed forms, Eq. (8), counting
+arguments, and the invariants of a Gram matrix of unit vectors.
+"""
+import numpy as np
+import pytest
+from scipy.linalg import expm
+
+from oracle import circuit, gates, gram, mps
+from oracle import statevector as sv
+import synthdata as sd
+
+
+# ---------------------------------------------------------------- gates
+def test_gate_matrices_match_exponentials():
+    for th in (0.0, 0.3, -1.7, 2.9):
+        assert np.allclose(gates.rz(th), expm(-0.5j * th * gates.Z), atol=1e-14)
+        assert np.allclose(gates.rxx(th), expm(-0.5j * th * np.kron(gates.X, gates.X)), atol=1e-14)
+        for u in (gates.rz(th), gates.rxx(th), gates.SWAP, gates.H):
+            assert np.allclose(u.conj().T @ u, np.eye(u.shape[0]), atol=1e-14)
+    # SWAP exchanges the two tensor factors: SWAP (a (x) b) = b (x) a
+    rng = np.random.default_rng(3)
+    a, b = rng.standard_normal(2) + 1j * rng.standard_normal(2), rng.standard_normal(2) + 0j
+    assert np.allclose(gates.SWAP @ np.kron(a, b), np.kron(b, a))
+    # H|0> = |+>
+    assert np.allclose(gates.H @ np.array([1, 0]), np.full(2, 2 ** -0.5))
+
+
+# ---------------------------------------------------------------- gate list
+@pytest.mark.parametrize("m,d,reps", [(8, 1, 1), (8, 3, 2), (50, 2, 2), (100, 4, 2), (165, 8, 2), (5, 9, 1), (1, 2, 1)])
+@pytest.mark.parametrize("routing", [0, 1])
+def test_gate_counts_closed_form(m, d, reps, routing):
+    g = circuit.build_gate_list(m, d, reps, routing)
+    counts = tuple(int((g[:, 0] == op).sum()) if len(g) else 0 for op in (0, 1, 2))
+    assert counts == circuit.gate_counts_closed_form(m, d, reps, routing)
+    if len(g):
+        assert g[:, 1].min() >= 0
+        two = g[g[:, 0] != 0]
+        if len(two):
+            assert two[:, 1].max() <= m - 2
+
+
+def test_full_scale_gate_count():
+    # 165 qubits, d = 8, 2 repetitions: 20,376 two-qubit gates with routing 0
+    g = circuit.build_gate_list(165, 8, 2, 0)
+    assert int((g[:, 0] != 0).sum()) == 20376
+    g1 = circuit.build_gate_list(165, 8, 2, 1)
+    assert int((g1[:, 0] != 0).sum()) == 7048
+
+
+def test_routing_moves_the_right_qubits():
+    """Track qubit positions through the SWAPs: every Rxx meets its two features."""
+    for routing in (0, 1):
+        m, d = 9, 4
+        g = circuit.build_gate_list(m, d, 1, routing)
+        pos = list(range(m))          # pos[site] = qubit
+        seen = set()
+        for op, p, fi, fj in g:
+            if op == 2:
+                pos[p], pos[p + 1] = pos[p + 1], pos[p]
+            elif op == 1:
+                assert {pos[p], pos[p + 1]} == {fi, fj}
+                seen.add((min(fi, fj), max(fi, fj)))
+            elif op == 0:
+                assert pos[p] == fi
+        assert pos == list(range(m))
+        assert seen == {(i, j) for i in range(m) for j in range(i + 1, min(m, i + d + 1))}
+
+
+# ---------------------------------------------------------------- statevector vs Hamiltonians
+@pytest.mark.parametrize("m,d,reps", [(3, 1, 1), (4, 2, 2), (5, 3, 1), (6, 2, 2)])
+def test_statevector_matches_hamiltonian_exponentials(m, d, reps):
+    """Eq. (3)-(5): U(x)|+> from expm of dense H_Z, H_XX equals the gate circuit.
+
+    gamma_z = coef_z / 2 and gamma_xx = coef_xx / 2 under Rz(t)=exp(-itZ/2),
+    Rxx(t)=exp(-itXX/2); coef_z = 2 gamma, coef_xx = gamma^2 pi is the paper.
+    """
+    rng = np.random.default_rng(m * 10 + d)
+    x = rng.random(m)
+    for gamma in (1.0, 0.37):
+        cz, cxx = 2 * gamma, gamma ** 2 * np.pi
+        U = sv.unitary_from_hamiltonians(x, d, reps, gamma, gamma ** 2 * np.pi / 2)
+        ref = U @ sv.plus_state(m)
+        psi = sv.state_logical(x, d, reps, cz, cxx)
+        assert np.allclose(psi, ref, atol=1e-12)
+        for routing in (0, 1):
+            g = circuit.build_gate_list(m, d, reps, routing)
+            psi2 = sv.state_from_gate_list(x, g, cz, cxx)
+            assert np.allclose(psi2, ref, atol=1e-12)
+
+
+# ---------------------------------------------------------------- MPS vs statevector
+@pytest.mark.parametrize("m,d,reps", [(8, 1, 1), (8, 3, 2), (10, 5, 2), (7, 6, 1), (11, 2, 2)])
+@pytest.mark.parametrize("routing", [0, 1])
+def test_untruncated_mps_equals_statevector(m, d, reps, routing):
+    rng = np.random.default_rng(100 + m + d)
+    X = rng.random((3, m))
+    states, mps_states = [], []
+    for x in X:
+        r = mps.simulate(x, d, reps, chi=2 ** (m // 2), cutoff=0.0, routing=routing)
+        assert r.discarded < 1e-24
+        psi = mps.to_statevector(r.tensors)
+        ref = sv.state_logical(x, d, reps, 2.0, 2.0)
+        assert abs(abs(np.vdot(psi, ref)) ** 2 - 1.0) < 1e-12
+        assert abs(np.linalg.norm(psi) - 1) < 1e-13
+        states.append(ref)
+        mps_states.append(r.tensors)
+        # bond dims never exceed the exact Schmidt-rank bound
+        for l, D in enumerate(r.bond_dims):
+            assert D <= 2 ** min(l, m - l)
+        # left-canonical: every site but the last is a left isometry
+        for t in r.tensors[:-1]:
+            M = t.reshape(-1, t.shape[2])
+            assert np.allclose(M.conj().T @ M, np.eye(M.shape[1]), atol=1e-13)
+    K_sv = sv.gram_from_states(np.array(states))
+    K_mps = gram.gram(mps_states)
+    assert np.allclose(K_mps, K_sv, atol=1e-12)
+
+
+def test_overlap_against_statevector_inner_product():
+    """Fig. 2 contraction == <a|b> of the contracted vectors (catches a missing conj)."""
+    rng = np.random.default_rng(5)
+    for _ in range(4):
+        xa, xb = rng.random(7), rng.random(7)
+        ra = mps.simulate(xa, 2, 2, 64, 0.0)
+        rb = mps.simulate(xb, 2, 2, 64, 0.0)
+        ov = gram.overlap(ra.tensors, rb.tensors)
+        ref = np.vdot(mps.to_statevector(ra.tensors), mps.to_statevector(rb.tensors))
+        assert abs(ov - ref) < 1e-13
+        assert abs(gram.overlap(rb.tensors, ra.tensors) - np.conj(ov)) < 1e-13
+
+
+# ---------------------------------------------------------------- closed forms
+def test_product_state_closed_form_full_scale():
+    """coef_xx = 0: K = prod_i cos^2(reps coef_z (x_i - x'_i) / 2), any m, through all SWAPs."""
+    X = sd.workload_features(sd.WORKLOADS["full"], 3)
+    X = 0.5 + 0.02 * (X - 0.5)      # keep K well above underflow
+    reps, cz = 2, 2.0
+    res = [mps.simulate(x, 8, reps, 64, 1e-12, coef_z=cz, coef_xx=0.0) for x in X]
+    for r in res:
+        assert max(r.bond_dims) == 1
+    K = gram.gram([r.tensors for r in res])
+    for i in range(3):
+        for j in range(3):
+            ref = np.prod(np.cos(reps * cz * (X[i] - X[j]) / 2) ** 2)
+            assert abs(K[i, j] - ref) < 1e-12
+
+
+def test_rxx_only_gives_all_ones():
+    """coef_z = 0: |+>^m is an eigenvector of every X_i X_j, so K == 1."""
+    X = sd.make_uniform(3, 30, seed=4)
+    res = [mps.simulate(x, 4, 2, 64, 1e-12, coef_z=0.0, coef_xx=2.0) for x in X]
+    K = gram.gram([r.tensors for r in res])
+    assert np.allclose(K, 1.0, atol=1e-12)
+
+
+# ---------------------------------------------------------------- Eq. (8)
+def test_single_truncation_fidelity_eq8():
+    """Truncating one bond of a normalised canonical state: |<psi|psi_tr>|^2 = 1 - eps."""
+    rng = np.random.default_rng(11)
+    m = 10
+    x = rng.random(m)
+    r = mps.simulate(x, 4, 2, 64, 0.0)
+    A_full = [t.copy() for t in r.tensors]
+    psi = mps.to_statevector(A_full)
+    # centre currently at m-1; move it to p and apply an identity gate with a cap
+    for p in (3, 4, 5):
+        A = [t.copy() for t in A_full]
+        c = mps.move_center(A, m - 1, p + 1)
+        res = mps.MPSResult(tensors=A)
+        theta = np.tensordot(A[p], A[p + 1], axes=(2, 0)).reshape(A[p].shape[0] * 2, -1)
+        s = np.linalg.svd(theta, compute_uv=False)
+        k = 5
+        eps = float(np.sum(s[k:] ** 2) / np.sum(s ** 2))
+        assert eps > 1e-6
+        mps.apply_two_qubit(A, p, np.eye(4, dtype=complex), k, 0.0, True, res)
+        psi_tr = mps.to_statevector(A)
+        assert abs(np.linalg.norm(psi_tr) - 1) < 1e-12
+        assert abs(abs(np.vdot(psi, psi_tr)) ** 2 - (1 - eps)) < 1e-12
+        assert abs(res.discarded - eps) < 1e-14
+
+
+def test_truncation_rank_rule():
+    s = np.sqrt(np.array([0.5, 0.3, 0.15, 0.04, 0.009, 0.001]))
+    assert mps.truncation_rank(s, 64, 0.0) == 6
+    assert mps.truncation_rank(s, 3, 0.0) == 3
+    assert mps.truncation_rank(s, 64, 0.001) == 5          # tail 0.001 <= 0.001
+    assert mps.truncation_rank(s, 64, 0.0009) == 6
+    assert mps.truncation_rank(s, 64, 0.0101) == 4          # 0.009 + 0.001 = 0.010
+    assert mps.truncation_rank(s, 64, 0.99) == 1            # never below one
+    assert mps.truncation_rank(s, 2, 0.0101) == 2
+
+
+# ---------------------------------------------------------------- invariants under truncation
+def test_truncated_gram_invariants():
+    w = sd.WORKLOADS["fp32"]
+    X = sd.workload_features(w, 12)
+    X = np.vstack([X, sd.perturb_near_duplicates(X[:4])])
+    res = [mps.simulate(x, w.distance, w.reps, 8, w.cutoff) for x in X]
+    for r in res:
+        assert max(r.bond_dims) <= 8
+        assert r.max_discarded > 0
+    K = gram.gram([r.tensors for r in res])
+    assert np.allclose(np.diag(K), 1.0, atol=1e-12)
+    assert np.allclose(K, K.T, atol=0)
+    assert K.min() >= 0 and K.max() <= 1 + 1e-12
+    # |G|^2 of unit vectors is PSD (Schur product of a PSD Gram with its conjugate)
+    assert np.linalg.eigvalsh(K).min() > -1e-12
+    # the near-duplicates give mid-range kernel values
+    assert K[np.arange(4), 12 + np.arange(4)].min() > 0.05
