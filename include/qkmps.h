@@ -1,0 +1,222 @@
+/*
+ * qkmps.h -- C ABI of the MI355X (gfx950) quantum-kernel MPS library.
+ *
+ * The library computes the quantum-kernel Gram matrix
+ *     K[i][j] = |<psi(x_i) | psi(x_j)>|^2                      (Eq. (1))
+ * where |psi(x)> = U(x)|+>^m is the paper's feature-map state (Eqs. (2)-(5)),
+ * represented as a matrix product state (MPS, Sec. II-B) produced by truncated
+ * MPS simulation of the circuit of Sec. II-C, and each overlap is contracted
+ * site by site as in Fig. 2.
+ *
+ * Conventions shared by every entry point
+ *   - Plain C types only; no C++ types or exceptions cross this boundary.
+ *   - Every call returns a qk_status.  On failure a thread-local message is
+ *     available from qk_last_error().  All argument checks happen before any
+ *     device work is enqueued; a failed check enqueues nothing.
+ *   - "dev" pointers are device (HBM) pointers owned by the caller.  "host"
+ *     pointers are ordinary host memory owned by the caller.
+ *   - Device work is asynchronous on the given HIP stream (a hipStream_t
+ *     passed as void*; NULL = the default stream).  Host-returning calls
+ *     (info, export, save) synchronise that stream first.
+ *   - Batches (qk_mps_batch) are opaque and owned by the library; free them
+ *     with mps_batch_free().  A batch lives on the device that was current
+ *     when it was created.
+ *   - Device faults surface as QK_EDEVICE at the next synchronising call.
+ *
+ * MPS storage (one batch = n MPS with the same qubit count m)
+ *   Site l of MPS i is a complex tensor A[s][a][b], s in {0,1} the physical
+ *   index, a < D_l and b < D_{l+1} the bond indices (D_0 = D_m = 1).  The
+ *   batch stores every site with a padded shape [2][P_l][P_{l+1}], where the
+ *   pad profile P_l is a multiple of 32 shared by the whole batch, and all
+ *   padding is zero.  Exported MPS are left-canonical and normalised.
+ */
+#ifndef QKMPS_H
+#define QKMPS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  QK_OK = 0,
+  QK_EINVAL = -1,     /* invalid argument (NULL, size, NaN feature, mismatch) */
+  QK_ENOMEM = -2,     /* device or host allocation failed                     */
+  QK_EDEVICE = -3,    /* HIP runtime error or device fault                    */
+  QK_ENOTSUP = -4,    /* valid but unsupported combination (e.g. chi > 64 in  */
+                      /* simulation, precision not packed)                     */
+  QK_ENUMERIC = -5,   /* an SVD did not converge within its sweep limit       */
+  QK_EABORTED = -6
+} qk_status;
+
+/* Arithmetic of the overlap contractions in mps_gram.  In every form the
+ * final |overlap|^2 is formed in FP64. */
+typedef enum {
+  QK_FP64 = 0,        /* complex128 operands, FP64 MFMA                        */
+  QK_FP32 = 1,        /* complex64 operands, FP32 MFMA, per-site 2^e rescale   */
+  QK_SPLIT_BF16 = 2   /* each real operand split into three bf16 pieces        */
+                      /* (hi + mid + lo); the six products of order >= 2^-16   */
+                      /* go into one FP32 MFMA accumulator; 2^e rescale        */
+} qk_precision;
+
+/* Circuit of Sec. II-C.  Rotation angles: Rz on qubit i uses coef_z * x_i;
+ * Rxx on qubits (i, j) uses coef_xx * (1 - x_i) * (1 - x_j), with
+ * Rz(t) = exp(-i t Z / 2) and Rxx(t) = exp(-i t XX / 2).  The paper's
+ * bandwidth gamma corresponds to coef_z = 2 gamma, coef_xx = gamma^2 pi.  */
+typedef struct {
+  int32_t n_qubits;              /* m = features per point, >= 1             */
+  int32_t interaction_distance;  /* d: edges (i, j) with 1 <= j - i <= d     */
+  int32_t repetitions;           /* r of Eq. (3): Z layer then XX layer       */
+  int32_t routing;               /* 0: 2(k-1) SWAPs around every Rxx at       */
+                                 /*    distance k (Sec. II-C);                */
+                                 /* 1: back-to-back inverse SWAPs of one      */
+                                 /*    E_i block cancelled                    */
+  double coef_z;
+  double coef_xx;
+  int32_t reserved[4];           /* must be zero                              */
+} qk_circuit_spec;
+
+/* Gate-list record: op 0 = RZ (site, feature), 1 = RXX (left site, feature i,
+ * feature j), 2 = SWAP (left site).  Unused fields are -1. */
+typedef struct {
+  int32_t op, site, feat_i, feat_j;
+} qk_gate;
+
+typedef struct qk_mps_batch qk_mps_batch;
+
+/* Per-batch simulation statistics. */
+typedef struct {
+  int64_t n;                 /* number of MPS                                  */
+  int32_t m;                 /* sites                                          */
+  int32_t max_bond;          /* largest bond dimension in the batch            */
+  int32_t pad_max;           /* largest pad P_l                                */
+  int32_t n_two_qubit_gates; /* per circuit (0 for imported batches)           */
+  double max_discarded;      /* largest single-truncation discarded weight     */
+  double mean_total_discarded; /* mean over MPS of the summed discarded weight */
+  int64_t degenerate_cuts;   /* truncations whose kept/discarded gap < 1e-10   */
+  int64_t unconverged_svds;  /* SVDs that hit the sweep limit                  */
+  int64_t bytes_f64, bytes_f32, bytes_split_bf16; /* device bytes per form     */
+} qk_batch_info;
+
+/* ---------------------------------------------------------------- setup */
+
+/* Select the HIP device for subsequent calls on this thread. */
+qk_status qk_init(int device);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *qk_last_error(void);
+
+/* Library version string. */
+const char *qk_version(void);
+
+/* Gate list of a circuit spec (Sec. II-C; Eq. (3)).  Writes up to `cap`
+ * records to `out_host` (may be NULL with cap 0) and the total count to
+ * *n_gates.  QK_EINVAL if cap is too small (count still written). */
+qk_status qk_circuit_compile(const qk_circuit_spec *spec, qk_gate *out_host,
+                             int64_t cap, int64_t *n_gates);
+
+/* ---------------------------------------------------------------- simulation */
+
+/* Simulate |psi(x_i)> for every row of `features_dev` (n_points x n_qubits,
+ * row-major FP64, any finite reals) with truncated MPS simulation
+ * (Sec. II-B, Fig. 1): two-qubit gates are applied by contracting the gate
+ * into the two site tensors, taking an FP64 SVD (batched one-sided Jacobi),
+ * keeping k = max(1, min(chi_max, k_cut)) singular values, where k_cut is the
+ * smallest count whose discarded weight sum_{i>=k} s_i^2 is at most
+ * cutoff * sum_i s_i^2 (Eq. (8)); cutoff <= 0 disables weight truncation.
+ * Kept values are renormalised to unit norm.  The orthogonality centre is
+ * moved next to each gate before its SVD, and singular values are absorbed
+ * toward the next two-qubit gate.  The result is left-canonical with the last
+ * site normalised, stored in FP64; other precisions are packed on demand.
+ * chi_max must be in [1, 64].  On success *out receives a new batch. */
+qk_status mps_simulate(const double *features_dev, int64_t n_points,
+                       const qk_circuit_spec *spec, int32_t chi_max,
+                       double cutoff, void *hip_stream, qk_mps_batch **out);
+
+/* ---------------------------------------------------------------- Gram */
+
+/* K[i][j] = |<a_i | b_j>|^2 for i < na, j < nb, written to K_dev (row-major,
+ * leading dimension ldk >= nb, FP64) following Fig. 2: for every site l,
+ * E <- sum_s A_a[l][s]^H E A_b[l][s], starting from E = 1.
+ * If b == NULL or b == a the matrix is symmetric: only i <= j is contracted
+ * and mirrored (the diagonal is computed, not assumed).
+ * `a` and `b` must have the same m.  The precision's packed form is built
+ * (and kept) on first use. */
+qk_status mps_gram(const qk_mps_batch *a, const qk_mps_batch *b,
+                   qk_precision prec, double *K_dev, int64_t ldk,
+                   void *hip_stream);
+
+/* Block form for slabs and tile rows: rows a[a0 .. a0+na), columns
+ * b[b0 .. b0+nb), written to K_dev[(i - a0) * ldk + (j - b0)].  With
+ * upper_only != 0 (requires a == b) only entries with global j >= i are
+ * contracted; each is also written to the transposed position (j, i) when
+ * that position lies inside the block.  Other entries are left untouched. */
+qk_status mps_gram_block(const qk_mps_batch *a, int64_t a0, int64_t na,
+                         const qk_mps_batch *b, int64_t b0, int64_t nb,
+                         int32_t upper_only, qk_precision prec,
+                         double *K_dev, int64_t ldk, void *hip_stream);
+
+/* Several Gram jobs (different batches, qubit counts and pads) in ONE
+ * persistent launch: workgroups pop tiles from a device work queue across
+ * all jobs.  Each job is as in mps_gram_block with `upper_only` meaning
+ * symmetric. */
+typedef struct {
+  const qk_mps_batch *a;
+  const qk_mps_batch *b;   /* == a with upper_only != 0 for symmetric jobs */
+  int64_t a0, na, b0, nb;
+  int32_t upper_only;
+  int32_t reserved;
+  double *K_dev;
+  int64_t ldk;
+} qk_gram_job;
+
+qk_status mps_gram_multi(const qk_gram_job *jobs, int32_t n_jobs,
+                         qk_precision prec, void *hip_stream);
+
+/* ---------------------------------------------------------------- batches */
+
+/* Build an MPS batch from host FP64 tensors.  `dims_host` holds n x (m+1)
+ * bond dimensions (first and last 1).  `tensors_host` holds, for MPS 0..n-1
+ * and site 0..m-1 in order, the complex tensor A[s][a][b] with s in {0,1},
+ * a < D_l, b < D_{l+1}, as interleaved (re, im) doubles, densely packed.
+ * Bond dimensions must be in [1, 128]. */
+qk_status mps_batch_import(const double *tensors_host, const int32_t *dims_host,
+                           int64_t n, int32_t m, void *hip_stream,
+                           qk_mps_batch **out);
+
+qk_status mps_batch_info(const qk_mps_batch *b, qk_batch_info *info);
+
+/* n x (m+1) bond dimensions into host memory. */
+qk_status mps_batch_bond_dims(const qk_mps_batch *b, int32_t *dims_host);
+
+/* Per-MPS statistics into host arrays of length n (any may be NULL):
+ * summed discarded weight, number of near-degenerate cuts. */
+qk_status mps_batch_trunc_stats(const qk_mps_batch *b, double *discarded_host,
+                                int32_t *degenerate_host);
+
+/* FP64 tensors of MPS `idx` in the densely packed import layout.  `cap` is
+ * the capacity in doubles; QK_EINVAL if too small.  *written = doubles used. */
+qk_status mps_batch_export(const qk_mps_batch *b, int64_t idx, double *host_buf,
+                           int64_t cap, int64_t *written);
+
+/* Build the packed operand planes of `prec` now (otherwise built by the first
+ * mps_gram with that precision).  QK_FP64 is always present. */
+qk_status mps_batch_pack(qk_mps_batch *b, qk_precision prec, void *hip_stream);
+
+/* Release the packed planes of `prec` (not QK_FP64). */
+qk_status mps_batch_drop(qk_mps_batch *b, qk_precision prec);
+
+/* New batch holding copies of MPS idx[0..count) of `src` (indices may
+ * repeat).  Used to assemble workloads and test subsets. */
+qk_status mps_batch_gather(const qk_mps_batch *src, const int64_t *idx_host,
+                           int64_t count, void *hip_stream, qk_mps_batch **out);
+
+void mps_batch_free(qk_mps_batch *b);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QKMPS_H */

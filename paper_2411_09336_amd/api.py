@@ -1,0 +1,303 @@
+"""ctypes binding of the C ABI in ``include/qkmps.h`` (argument marshalling only).
+
+Every computation happens in the HIP library; these wrappers convert Python
+and torch arguments into plain pointers, sizes and stream handles.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libqkmps.so")
+_lib = None
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+class QKError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"qkmps status {status}: {msg}")
+        self.status = status
+
+
+class Precision:
+    FP64 = 0
+    FP32 = 1
+    SPLIT_BF16 = 2
+    _names = {"fp64": 0, "fp32": 1, "split_bf16": 2, "sbf16": 2, "bf16x6": 2}
+
+    @classmethod
+    def of(cls, p) -> int:
+        if isinstance(p, str):
+            return cls._names[p.lower()]
+        if int(p) not in (0, 1, 2):
+            raise ValueError("precision must be fp64, fp32 or split_bf16")
+        return int(p)
+
+
+class _Spec(C.Structure):
+    _fields_ = [("n_qubits", C.c_int32), ("interaction_distance", C.c_int32),
+                ("repetitions", C.c_int32), ("routing", C.c_int32),
+                ("coef_z", C.c_double), ("coef_xx", C.c_double),
+                ("reserved", C.c_int32 * 4)]
+
+
+class _Gate(C.Structure):
+    _fields_ = [("op", C.c_int32), ("site", C.c_int32), ("feat_i", C.c_int32), ("feat_j", C.c_int32)]
+
+
+class _Info(C.Structure):
+    _fields_ = [("n", C.c_int64), ("m", C.c_int32), ("max_bond", C.c_int32), ("pad_max", C.c_int32),
+                ("n_two_qubit_gates", C.c_int32), ("max_discarded", C.c_double),
+                ("mean_total_discarded", C.c_double), ("degenerate_cuts", C.c_int64),
+                ("unconverged_svds", C.c_int64), ("bytes_f64", C.c_int64), ("bytes_f32", C.c_int64),
+                ("bytes_split_bf16", C.c_int64)]
+
+
+class _Job(C.Structure):
+    _fields_ = [("a", C.c_void_p), ("b", C.c_void_p), ("a0", C.c_int64), ("na", C.c_int64),
+                ("b0", C.c_int64), ("nb", C.c_int64), ("upper_only", C.c_int32), ("reserved", C.c_int32),
+                ("K_dev", C.c_void_p), ("ldk", C.c_int64)]
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise RuntimeError(f"{_LIB_PATH} is not built; run `python -m paper_2411_09336_amd.build`")
+    L = C.CDLL(_LIB_PATH)
+    P, I32, I64, D, S = C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_int
+    sig = {
+        "qk_init": (S, [C.c_int]),
+        "qk_last_error": (C.c_char_p, []),
+        "qk_version": (C.c_char_p, []),
+        "qk_circuit_compile": (S, [C.POINTER(_Spec), P, I64, C.POINTER(I64)]),
+        "mps_simulate": (S, [P, I64, C.POINTER(_Spec), I32, D, P, C.POINTER(P)]),
+        "mps_gram": (S, [P, P, C.c_int, P, I64, P]),
+        "mps_gram_block": (S, [P, I64, I64, P, I64, I64, I32, C.c_int, P, I64, P]),
+        "mps_gram_multi": (S, [C.POINTER(_Job), I32, C.c_int, P]),
+        "mps_batch_import": (S, [P, P, I64, I32, P, C.POINTER(P)]),
+        "mps_batch_info": (S, [P, C.POINTER(_Info)]),
+        "mps_batch_bond_dims": (S, [P, P]),
+        "mps_batch_trunc_stats": (S, [P, P, P]),
+        "mps_batch_export": (S, [P, I64, P, I64, C.POINTER(I64)]),
+        "mps_batch_pack": (S, [P, C.c_int, P]),
+        "mps_batch_drop": (S, [P, C.c_int]),
+        "mps_batch_gather": (S, [P, P, I64, P, C.POINTER(P)]),
+        "mps_batch_free": (None, [P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(st: int):
+    if st != 0:
+        raise QKError(st, _load().qk_last_error().decode())
+
+
+def version() -> str:
+    return _load().qk_version().decode()
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+@dataclass(frozen=True)
+class CircuitSpec:
+    """Circuit of Sec. II-C: Rz(coef_z x_i), Rxx(coef_xx (1-x_i)(1-x_j)) at distance <= d."""
+    n_qubits: int
+    distance: int
+    reps: int
+    coef_z: float = 2.0
+    coef_xx: float = 2.0
+    routing: int = 0
+
+    def _c(self) -> _Spec:
+        s = _Spec()
+        s.n_qubits, s.interaction_distance, s.repetitions, s.routing = (
+            self.n_qubits, self.distance, self.reps, self.routing)
+        s.coef_z, s.coef_xx = float(self.coef_z), float(self.coef_xx)
+        return s
+
+
+def circuit_compile(spec: CircuitSpec) -> np.ndarray:
+    """Gate list (n_gates x 4 int32: op, site, feat_i, feat_j) built by the library."""
+    L = _load()
+    cs = spec._c()
+    n = C.c_int64(0)
+    _check(L.qk_circuit_compile(C.byref(cs), None, 0, C.byref(n)))
+    out = np.zeros((n.value, 4), dtype=np.int32)
+    if n.value:
+        _check(L.qk_circuit_compile(C.byref(cs), out.ctypes.data, n.value, C.byref(n)))
+    return out
+
+
+class MPSBatch:
+    """Owning handle of a device-resident MPS batch."""
+
+    def __init__(self, handle: int):
+        self._h = C.c_void_p(handle)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def free(self):
+        if self._h and self._h.value:
+            _load().mps_batch_free(self._h)
+            self._h = C.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        inf = _Info()
+        _check(_load().mps_batch_info(self._h, C.byref(inf)))
+        return {f: getattr(inf, f) for f, _ in _Info._fields_}
+
+    @property
+    def n(self) -> int:
+        return self.info()["n"]
+
+    @property
+    def m(self) -> int:
+        return self.info()["m"]
+
+    def bond_dims(self) -> np.ndarray:
+        inf = self.info()
+        out = np.zeros((inf["n"], inf["m"] + 1), dtype=np.int32)
+        _check(_load().mps_batch_bond_dims(self._h, out.ctypes.data))
+        return out
+
+    def trunc_stats(self):
+        n = self.info()["n"]
+        disc = np.zeros(n)
+        deg = np.zeros(n, dtype=np.int32)
+        _check(_load().mps_batch_trunc_stats(self._h, disc.ctypes.data, deg.ctypes.data))
+        return disc, deg
+
+    def export(self, idx: int) -> List[np.ndarray]:
+        """FP64 tensors of MPS ``idx`` as a list of (D_l, 2, D_{l+1}) complex arrays."""
+        dims = self.bond_dims()[idx]
+        m = len(dims) - 1
+        need = int(sum(4 * dims[l] * dims[l + 1] for l in range(m)))
+        buf = np.zeros(need)
+        wr = C.c_int64(0)
+        _check(_load().mps_batch_export(self._h, idx, buf.ctypes.data, need, C.byref(wr)))
+        out, off = [], 0
+        for l in range(m):
+            dl, dr = int(dims[l]), int(dims[l + 1])
+            cnt = 2 * dl * dr
+            z = buf[2 * off: 2 * (off + cnt)].view(np.complex128).reshape(2, dl, dr)
+            out.append(np.ascontiguousarray(z.transpose(1, 0, 2)))
+            off += cnt
+        return out
+
+    def pack(self, precision, stream=None):
+        _check(_load().mps_batch_pack(self._h, Precision.of(precision), _stream_ptr(stream)))
+
+    def drop(self, precision):
+        _check(_load().mps_batch_drop(self._h, Precision.of(precision)))
+
+    def gather(self, indices: Sequence[int], stream=None) -> "MPSBatch":
+        idx = np.ascontiguousarray(np.asarray(indices, dtype=np.int64))
+        h = C.c_void_p(0)
+        _check(_load().mps_batch_gather(self._h, idx.ctypes.data, len(idx), _stream_ptr(stream), C.byref(h)))
+        return MPSBatch(h.value)
+
+
+def import_batch(mps_list: Sequence[Sequence[np.ndarray]], stream=None) -> MPSBatch:
+    """Upload MPS given as lists of (D_l, 2, D_{l+1}) complex arrays."""
+    n = len(mps_list)
+    if n == 0:
+        raise ValueError("empty MPS list")
+    m = len(mps_list[0])
+    dims = np.zeros((n, m + 1), dtype=np.int32)
+    parts = []
+    for i, mps in enumerate(mps_list):
+        if len(mps) != m:
+            raise ValueError("MPS of different lengths")
+        dims[i, 0] = mps[0].shape[0]
+        for l, t in enumerate(mps):
+            dims[i, l + 1] = t.shape[2]
+            parts.append(np.ascontiguousarray(np.asarray(t, dtype=np.complex128).transpose(1, 0, 2)).reshape(-1))
+    flat = np.ascontiguousarray(np.concatenate(parts)).view(np.float64)
+    h = C.c_void_p(0)
+    _check(_load().mps_batch_import(flat.ctypes.data, dims.ctypes.data, n, m, _stream_ptr(stream), C.byref(h)))
+    return MPSBatch(h.value)
+
+
+def simulate(features, spec: CircuitSpec, chi: int, cutoff: float, stream=None) -> MPSBatch:
+    """Truncated MPS simulation of every row of ``features`` (a CUDA float64 tensor, n x m)."""
+    import torch
+    if not isinstance(features, torch.Tensor) or features.device.type != "cuda":
+        raise TypeError("features must be a CUDA tensor")
+    x = features.to(torch.float64).contiguous()
+    if x.dim() != 2 or x.shape[1] != spec.n_qubits:
+        raise ValueError("features must be n x n_qubits")
+    cs = spec._c()
+    h = C.c_void_p(0)
+    _check(_load().mps_simulate(C.c_void_p(x.data_ptr()), x.shape[0], C.byref(cs), int(chi), float(cutoff),
+                                _stream_ptr(stream), C.byref(h)))
+    return MPSBatch(h.value)
+
+
+def gram(a: MPSBatch, b: Optional[MPSBatch] = None, precision="fp64", out=None, stream=None):
+    """K[i, j] = |<a_i|b_j>|^2 as a CUDA float64 tensor (symmetric when b is None)."""
+    import torch
+    na = a.n
+    nb = na if b is None else b.n
+    if out is None:
+        out = torch.empty((na, nb), dtype=torch.float64, device="cuda")
+    if out.dtype != torch.float64 or not out.is_cuda or out.stride(1) != 1:
+        raise ValueError("out must be a CUDA float64 tensor with unit column stride")
+    _check(_load().mps_gram(a.handle, None if b is None else b.handle, Precision.of(precision),
+                            C.c_void_p(out.data_ptr()), out.stride(0), _stream_ptr(stream)))
+    return out
+
+
+def gram_block(a: MPSBatch, a0: int, na: int, b: MPSBatch, b0: int, nb: int, precision="fp64",
+               upper_only: bool = False, out=None, stream=None):
+    import torch
+    if out is None:
+        out = torch.zeros((na, nb), dtype=torch.float64, device="cuda")
+    _check(_load().mps_gram_block(a.handle, a0, na, b.handle, b0, nb, int(bool(upper_only)),
+                                  Precision.of(precision), C.c_void_p(out.data_ptr()), out.stride(0),
+                                  _stream_ptr(stream)))
+    return out
+
+
+def gram_multi(jobs, precision="fp64", stream=None):
+    """jobs: list of dicts {a, b, a0, na, b0, nb, upper_only, out} -> one persistent launch."""
+    arr = (_Job * len(jobs))()
+    for k, j in enumerate(jobs):
+        arr[k].a = j["a"].handle.value
+        arr[k].b = j["b"].handle.value
+        arr[k].a0, arr[k].na = j.get("a0", 0), j["na"]
+        arr[k].b0, arr[k].nb = j.get("b0", 0), j["nb"]
+        arr[k].upper_only = int(bool(j.get("upper_only", False)))
+        arr[k].reserved = 0
+        arr[k].K_dev = j["out"].data_ptr()
+        arr[k].ldk = j["out"].stride(0)
+    _check(_load().mps_gram_multi(arr, len(jobs), Precision.of(precision), _stream_ptr(stream)))

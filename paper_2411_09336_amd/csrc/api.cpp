@@ -1,0 +1,524 @@
+// C-ABI entry points of libqkmps: argument checking, batch management and
+// dispatch to the HIP launchers.  No device arithmetic lives here.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <string>
+#include <vector>
+
+#include "qk_internal.h"
+
+namespace qk {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+qk_status fail(qk_status st, const std::string &msg) {
+  g_last_error = msg;
+  return st;
+}
+
+static qk_status ok() {
+  g_last_error.clear();
+  return QK_OK;
+}
+
+qk_status validate_spec(const qk_circuit_spec *spec) {
+  if (!spec) return fail(QK_EINVAL, "circuit spec is NULL");
+  if (spec->n_qubits < 1 || spec->n_qubits > 100000)
+    return fail(QK_EINVAL, "n_qubits must be in [1, 100000]");
+  if (spec->interaction_distance < 0) return fail(QK_EINVAL, "interaction_distance < 0");
+  if (spec->repetitions < 0) return fail(QK_EINVAL, "repetitions < 0");
+  if (spec->routing != 0 && spec->routing != 1) return fail(QK_EINVAL, "routing must be 0 or 1");
+  if (!std::isfinite(spec->coef_z) || !std::isfinite(spec->coef_xx))
+    return fail(QK_EINVAL, "angle coefficients must be finite");
+  for (int k = 0; k < 4; ++k)
+    if (spec->reserved[k] != 0) return fail(QK_EINVAL, "reserved fields must be zero");
+  return QK_OK;
+}
+
+// Gate list: per repetition the Z layer (one Rz per qubit), then the XX
+// layer in E_i-block order; an Rxx between qubits i and i+k is applied on
+// sites (i+k-1, i+k) after SWAPs carry qubit i up to site i+k-1.
+std::vector<qk_gate> compile_circuit(const qk_circuit_spec &spec) {
+  const int m = spec.n_qubits, d = spec.interaction_distance;
+  std::vector<qk_gate> g;
+  auto push = [&](int op, int site, int fi, int fj) { g.push_back(qk_gate{op, site, fi, fj}); };
+  for (int r = 0; r < spec.repetitions; ++r) {
+    for (int q = 0; q < m; ++q) push(0, q, q, -1);
+    for (int i = 0; i + 1 < m; ++i) {
+      const int kmax = std::min(d, m - 1 - i);
+      if (spec.routing == 0) {
+        for (int k = 1; k <= kmax; ++k) {
+          for (int p = i; p <= i + k - 2; ++p) push(2, p, -1, -1);
+          push(1, i + k - 1, i, i + k);
+          for (int p = i + k - 2; p >= i; --p) push(2, p, -1, -1);
+        }
+      } else {
+        for (int k = 1; k <= kmax; ++k) {
+          if (k > 1) push(2, i + k - 2, -1, -1);
+          push(1, i + k - 1, i, i + k);
+        }
+        for (int p = i + kmax - 2; p >= i; --p) push(2, p, -1, -1);
+      }
+    }
+  }
+  return g;
+}
+
+static void compute_layout(qk_mps_batch *b) {
+  const int m = b->m;
+  b->site_off.assign(m + 1, 0);
+  b->split_off.assign(m + 1, 0);
+  for (int l = 0; l < m; ++l) {
+    b->site_off[l + 1] = b->site_off[l] + int64_t(2) * b->pad[l] * b->pad[l + 1];
+    b->split_off[l + 1] = b->split_off[l] + split_site_bytes(b->pad[l], b->pad[l + 1]);
+  }
+  b->mps_stride = b->site_off[m];
+  b->split_stride = b->split_off[m];
+}
+
+static void batch_release(qk_mps_batch *b) {
+  if (!b) return;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(b->device);
+  void *ptrs[] = {b->f64, b->f32, b->sbf16, b->dims_dev, b->pad_dev, b->site_off_dev,
+                  b->split_off_dev, b->disc_dev, b->maxdisc_dev, b->degen_dev, b->unconv_dev};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  (void)hipSetDevice(cur);
+  delete b;
+}
+
+qk_status batch_create(int64_t n, int32_t m, const std::vector<int32_t> &pad,
+                       hipStream_t stream, qk_mps_batch **out) {
+  auto *b = new qk_mps_batch();
+  QK_HIP_CHECK(hipGetDevice(&b->device));
+  b->n = n;
+  b->m = m;
+  b->pad = pad;
+  compute_layout(b);
+  auto alloc = [&](void **p, size_t bytes) -> bool {
+    if (bytes == 0) bytes = 16;
+    if (hipMalloc(p, bytes) != hipSuccess) return false;
+    return hipMemsetAsync(*p, 0, bytes, stream) == hipSuccess;
+  };
+  const size_t nn = size_t(std::max<int64_t>(n, 1));
+  bool good = alloc((void **)&b->f64, sizeof(double2) * nn * size_t(b->mps_stride)) &&
+              alloc((void **)&b->dims_dev, sizeof(int32_t) * nn * size_t(m + 1)) &&
+              alloc((void **)&b->pad_dev, sizeof(int32_t) * size_t(m + 1)) &&
+              alloc((void **)&b->site_off_dev, sizeof(int64_t) * size_t(m + 1)) &&
+              alloc((void **)&b->split_off_dev, sizeof(int64_t) * size_t(m + 1)) &&
+              alloc((void **)&b->disc_dev, sizeof(double) * nn) &&
+              alloc((void **)&b->maxdisc_dev, sizeof(double) * nn) &&
+              alloc((void **)&b->degen_dev, sizeof(int32_t) * nn) &&
+              alloc((void **)&b->unconv_dev, sizeof(int32_t) * nn);
+  if (!good) {
+    (void)hipGetLastError();
+    batch_release(b);
+    return fail(QK_ENOMEM, "device allocation failed for an MPS batch of " + std::to_string(n) +
+                               " x " + std::to_string(m) + " sites");
+  }
+  if (hipMemcpyAsync(b->pad_dev, pad.data(), sizeof(int32_t) * (m + 1), hipMemcpyHostToDevice, stream) != hipSuccess ||
+      hipMemcpyAsync(b->site_off_dev, b->site_off.data(), sizeof(int64_t) * (m + 1), hipMemcpyHostToDevice, stream) != hipSuccess ||
+      hipMemcpyAsync(b->split_off_dev, b->split_off.data(), sizeof(int64_t) * (m + 1), hipMemcpyHostToDevice, stream) != hipSuccess ||
+      hipStreamSynchronize(stream) != hipSuccess) {
+    batch_release(b);
+    return fail(QK_EDEVICE, "copy of batch layout failed");
+  }
+  *out = b;
+  return QK_OK;
+}
+
+qk_status batch_ensure_packed(qk_mps_batch *b, qk_precision prec, hipStream_t stream) {
+  if (prec == QK_FP64) return QK_OK;
+  if (prec == QK_FP32) {
+    if (b->f32) return QK_OK;
+    size_t bytes = sizeof(float2) * size_t(std::max<int64_t>(b->n, 1)) * size_t(b->mps_stride);
+    if (hipMalloc((void **)&b->f32, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      b->f32 = nullptr;
+      return fail(QK_ENOMEM, "device allocation of FP32 planes failed");
+    }
+    return launch_pack_f32(b, stream);
+  }
+  if (prec == QK_SPLIT_BF16) {
+    if (b->sbf16) return QK_OK;
+    size_t bytes = size_t(std::max<int64_t>(b->n, 1)) * size_t(b->split_stride);
+    if (hipMalloc((void **)&b->sbf16, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      b->sbf16 = nullptr;
+      return fail(QK_ENOMEM, "device allocation of split-BF16 planes failed");
+    }
+    return launch_pack_split(b, stream);
+  }
+  return fail(QK_EINVAL, "unknown precision");
+}
+
+}  // namespace qk
+
+using namespace qk;
+
+extern "C" {
+
+qk_status qk_init(int device) {
+  int count = 0;
+  QK_HIP_CHECK(hipGetDeviceCount(&count));
+  if (device < 0 || device >= count) return fail(QK_EINVAL, "device index out of range");
+  QK_HIP_CHECK(hipSetDevice(device));
+  return ok();
+}
+
+const char *qk_last_error(void) { return g_last_error.c_str(); }
+
+const char *qk_version(void) { return "qkmps 0.1 (gfx950)"; }
+
+qk_status qk_circuit_compile(const qk_circuit_spec *spec, qk_gate *out_host, int64_t cap,
+                             int64_t *n_gates) {
+  qk_status st = validate_spec(spec);
+  if (st != QK_OK) return st;
+  if (!n_gates) return fail(QK_EINVAL, "n_gates is NULL");
+  auto g = compile_circuit(*spec);
+  *n_gates = int64_t(g.size());
+  if (cap < int64_t(g.size())) {
+    if (cap == 0 && out_host == nullptr) return ok();
+    return fail(QK_EINVAL, "gate buffer too small");
+  }
+  if (!out_host && !g.empty()) return fail(QK_EINVAL, "out_host is NULL");
+  if (!g.empty()) std::memcpy(out_host, g.data(), g.size() * sizeof(qk_gate));
+  return ok();
+}
+
+qk_status mps_simulate(const double *features_dev, int64_t n_points, const qk_circuit_spec *spec,
+                       int32_t chi_max, double cutoff, void *hip_stream, qk_mps_batch **out) {
+  if (!out) return fail(QK_EINVAL, "out is NULL");
+  *out = nullptr;
+  qk_status st = validate_spec(spec);
+  if (st != QK_OK) return st;
+  if (n_points < 0) return fail(QK_EINVAL, "n_points < 0");
+  if (n_points > 0 && !features_dev) return fail(QK_EINVAL, "features_dev is NULL");
+  if (chi_max < 1) return fail(QK_EINVAL, "chi_max must be >= 1");
+  if (chi_max > kMaxSimChi) return fail(QK_ENOTSUP, "chi_max above 64 is not supported in simulation");
+  if (!std::isfinite(cutoff)) return fail(QK_EINVAL, "cutoff must be finite");
+  hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+  const int m = spec->n_qubits;
+  // Worst-case bond profile: D_l <= min(chi, 2^min(l, m-l)).
+  std::vector<int32_t> pad(m + 1);
+  for (int l = 0; l <= m; ++l) {
+    int e = std::min(l, m - l);
+    int64_t cap = e >= 30 ? (int64_t(1) << 30) : (int64_t(1) << e);
+    pad[l] = pad_of(int(std::min<int64_t>(chi_max, cap)));
+  }
+  qk_mps_batch *b = nullptr;
+  st = batch_create(n_points, m, pad, stream, &b);
+  if (st != QK_OK) return st;
+  auto gates = compile_circuit(*spec);
+  st = run_simulation(b, features_dev, gates, *spec, chi_max, cutoff, stream);
+  if (st != QK_OK) {
+    batch_release(b);
+    return st;
+  }
+  *out = b;
+  return ok();
+}
+
+static qk_status check_pair_batches(const qk_mps_batch *a, const qk_mps_batch *b) {
+  if (!a || !b) return fail(QK_EINVAL, "batch is NULL");
+  if (a->m != b->m) return fail(QK_EINVAL, "batches have different qubit counts");
+  int dev = 0;
+  QK_HIP_CHECK(hipGetDevice(&dev));
+  if (a->device != dev || b->device != dev)
+    return fail(QK_EINVAL, "batch lives on another device than the current one");
+  return QK_OK;
+}
+
+static int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+static qk_status make_job(const qk_mps_batch *a, int64_t a0, int64_t na, const qk_mps_batch *b,
+                          int64_t b0, int64_t nb, int32_t upper, double *K, int64_t ldk,
+                          qk_precision prec, hipStream_t stream, GramJobDev *job) {
+  qk_status st = check_pair_batches(a, b);
+  if (st != QK_OK) return st;
+  if (na < 0 || nb < 0 || a0 < 0 || b0 < 0 || a0 + na > a->n || b0 + nb > b->n)
+    return fail(QK_EINVAL, "row/column range outside the batch");
+  if (na > 0 && nb > 0 && !K) return fail(QK_EINVAL, "K_dev is NULL");
+  if (ldk < nb) return fail(QK_EINVAL, "ldk < number of columns");
+  if (upper && a != b) return fail(QK_EINVAL, "upper_only requires a == b");
+  if (prec != QK_FP64 && prec != QK_FP32 && prec != QK_SPLIT_BF16)
+    return fail(QK_EINVAL, "unknown precision");
+  auto *am = const_cast<qk_mps_batch *>(a);
+  auto *bm = const_cast<qk_mps_batch *>(b);
+  st = batch_ensure_packed(am, prec, stream);
+  if (st != QK_OK) return st;
+  st = batch_ensure_packed(bm, prec, stream);
+  if (st != QK_OK) return st;
+  auto base = [&](qk_mps_batch *x) -> const void * {
+    return prec == QK_FP64 ? (const void *)x->f64
+                           : prec == QK_FP32 ? (const void *)x->f32 : (const void *)x->sbf16;
+  };
+  const bool split = prec == QK_SPLIT_BF16;
+  job->a_base = base(am);
+  job->b_base = base(bm);
+  job->a_off = split ? am->split_off_dev : am->site_off_dev;
+  job->b_off = split ? bm->split_off_dev : bm->site_off_dev;
+  job->a_pad = am->pad_dev;
+  job->b_pad = bm->pad_dev;
+  job->a_stride = split ? am->split_stride : am->mps_stride;
+  job->b_stride = split ? bm->split_stride : bm->mps_stride;
+  job->a0 = a0;
+  job->na = na;
+  job->b0 = b0;
+  job->nb = nb;
+  job->K = K;
+  job->ldk = ldk;
+  job->m = a->m;
+  job->upper = upper ? 1 : 0;
+  job->tiles_i = 0;
+  job->tiles_j = 0;
+  job->pair_begin = 0;
+  return QK_OK;
+}
+
+static int max_pad_of(const qk_mps_batch *x) {
+  return *std::max_element(x->pad.begin(), x->pad.end());
+}
+
+qk_status mps_gram_block(const qk_mps_batch *a, int64_t a0, int64_t na, const qk_mps_batch *b,
+                         int64_t b0, int64_t nb, int32_t upper_only, qk_precision prec,
+                         double *K_dev, int64_t ldk, void *hip_stream) {
+  hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+  GramJobDev job;
+  qk_status st = make_job(a, a0, na, b, b0, nb, upper_only, K_dev, ldk, prec, stream, &job);
+  if (st != QK_OK) return st;
+  if (na == 0 || nb == 0) return ok();
+  std::vector<GramJobDev> jobs{job};
+  st = launch_gram(jobs, std::max(max_pad_of(a), max_pad_of(b)), prec, stream);
+  if (st != QK_OK) return st;
+  return ok();
+}
+
+qk_status mps_gram(const qk_mps_batch *a, const qk_mps_batch *b, qk_precision prec, double *K_dev,
+                   int64_t ldk, void *hip_stream) {
+  if (!a) return fail(QK_EINVAL, "batch a is NULL");
+  if (b == nullptr || b == a) return mps_gram_block(a, 0, a->n, a, 0, a->n, 1, prec, K_dev, ldk, hip_stream);
+  return mps_gram_block(a, 0, a->n, b, 0, b->n, 0, prec, K_dev, ldk, hip_stream);
+}
+
+qk_status mps_gram_multi(const qk_gram_job *jobs, int32_t n_jobs, qk_precision prec, void *hip_stream) {
+  if (n_jobs < 0 || (n_jobs > 0 && !jobs)) return fail(QK_EINVAL, "invalid job list");
+  hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+  std::vector<GramJobDev> dj;
+  int max_pad = 32;
+  for (int k = 0; k < n_jobs; ++k) {
+    const qk_gram_job &j = jobs[k];
+    if (j.reserved != 0) return fail(QK_EINVAL, "reserved job field must be zero");
+    GramJobDev job;
+    qk_status st = make_job(j.a, j.a0, j.na, j.b, j.b0, j.nb, j.upper_only, j.K_dev, j.ldk, prec,
+                            stream, &job);
+    if (st != QK_OK) return st;
+    if (j.na == 0 || j.nb == 0) continue;
+    max_pad = std::max({max_pad, max_pad_of(j.a), max_pad_of(j.b)});
+    dj.push_back(job);
+  }
+  if (dj.empty()) return ok();
+  qk_status st = launch_gram(dj, max_pad, prec, stream);
+  if (st != QK_OK) return st;
+  return ok();
+}
+
+qk_status mps_batch_import(const double *tensors_host, const int32_t *dims_host, int64_t n, int32_t m,
+                           void *hip_stream, qk_mps_batch **out) {
+  if (!out) return fail(QK_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (n < 0 || m < 1) return fail(QK_EINVAL, "need n >= 0 and m >= 1");
+  if (n > 0 && (!tensors_host || !dims_host)) return fail(QK_EINVAL, "NULL host buffer");
+  hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+  std::vector<int32_t> maxd(m + 1, 1);
+  int64_t total = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    const int32_t *d = dims_host + i * (m + 1);
+    if (d[0] != 1 || d[m] != 1) return fail(QK_EINVAL, "first and last bond dimensions must be 1");
+    for (int l = 0; l <= m; ++l) {
+      if (d[l] < 1 || d[l] > kMaxBond) return fail(QK_EINVAL, "bond dimension outside [1, 128]");
+      maxd[l] = std::max(maxd[l], d[l]);
+    }
+    for (int l = 0; l < m; ++l) total += int64_t(2) * d[l] * d[l + 1];
+  }
+  for (int64_t k = 0; k < 2 * total; ++k)
+    if (!std::isfinite(tensors_host[k])) return fail(QK_EINVAL, "non-finite tensor entry");
+  std::vector<int32_t> pad(m + 1);
+  for (int l = 0; l <= m; ++l) pad[l] = pad_of(maxd[l]);
+  qk_mps_batch *b = nullptr;
+  qk_status st = batch_create(n, m, pad, stream, &b);
+  if (st != QK_OK) return st;
+  std::vector<double2> host(size_t(std::max<int64_t>(n, 1)) * size_t(b->mps_stride), double2{0.0, 0.0});
+  const double *src = tensors_host;
+  for (int64_t i = 0; i < n; ++i) {
+    const int32_t *d = dims_host + i * (m + 1);
+    for (int l = 0; l < m; ++l) {
+      double2 *dst = host.data() + i * b->mps_stride + b->site_off[l];
+      for (int s = 0; s < 2; ++s)
+        for (int a = 0; a < d[l]; ++a)
+          for (int c = 0; c < d[l + 1]; ++c) {
+            dst[(size_t(s) * pad[l] + a) * pad[l + 1] + c] = double2{src[0], src[1]};
+            src += 2;
+          }
+    }
+  }
+  if (n > 0) {
+    if (hipMemcpyAsync(b->f64, host.data(), sizeof(double2) * host.size(), hipMemcpyHostToDevice, stream) != hipSuccess ||
+        hipMemcpyAsync(b->dims_dev, dims_host, sizeof(int32_t) * n * (m + 1), hipMemcpyHostToDevice, stream) != hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess) {
+      batch_release(b);
+      return fail(QK_EDEVICE, "copy of imported tensors failed");
+    }
+  }
+  *out = b;
+  return ok();
+}
+
+qk_status mps_batch_info(const qk_mps_batch *b, qk_batch_info *info) {
+  if (!b || !info) return fail(QK_EINVAL, "NULL argument");
+  std::memset(info, 0, sizeof(*info));
+  info->n = b->n;
+  info->m = b->m;
+  info->pad_max = max_pad_of(b);
+  info->n_two_qubit_gates = b->n_two_qubit_gates;
+  const size_t n = size_t(b->n);
+  if (n > 0) {
+    std::vector<int32_t> dims(n * (b->m + 1));
+    std::vector<double> disc(n), maxd(n);
+    std::vector<int32_t> deg(n), unc(n);
+    QK_HIP_CHECK(hipDeviceSynchronize());
+    QK_HIP_CHECK(hipMemcpy(dims.data(), b->dims_dev, sizeof(int32_t) * dims.size(), hipMemcpyDeviceToHost));
+    QK_HIP_CHECK(hipMemcpy(disc.data(), b->disc_dev, sizeof(double) * n, hipMemcpyDeviceToHost));
+    QK_HIP_CHECK(hipMemcpy(maxd.data(), b->maxdisc_dev, sizeof(double) * n, hipMemcpyDeviceToHost));
+    QK_HIP_CHECK(hipMemcpy(deg.data(), b->degen_dev, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+    QK_HIP_CHECK(hipMemcpy(unc.data(), b->unconv_dev, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+    info->max_bond = *std::max_element(dims.begin(), dims.end());
+    double sum = 0.0;
+    for (size_t i = 0; i < n; ++i) {
+      sum += disc[i];
+      info->max_discarded = std::max(info->max_discarded, maxd[i]);
+      info->degenerate_cuts += deg[i];
+      info->unconverged_svds += unc[i];
+    }
+    info->mean_total_discarded = sum / double(n);
+  }
+  info->bytes_f64 = int64_t(sizeof(double2)) * b->n * b->mps_stride;
+  info->bytes_f32 = b->f32 ? int64_t(sizeof(float2)) * b->n * b->mps_stride : 0;
+  info->bytes_split_bf16 = b->sbf16 ? b->n * b->split_stride : 0;
+  return ok();
+}
+
+qk_status mps_batch_bond_dims(const qk_mps_batch *b, int32_t *dims_host) {
+  if (!b || !dims_host) return fail(QK_EINVAL, "NULL argument");
+  if (b->n == 0) return ok();
+  QK_HIP_CHECK(hipDeviceSynchronize());
+  QK_HIP_CHECK(hipMemcpy(dims_host, b->dims_dev, sizeof(int32_t) * b->n * (b->m + 1), hipMemcpyDeviceToHost));
+  return ok();
+}
+
+qk_status mps_batch_trunc_stats(const qk_mps_batch *b, double *discarded_host, int32_t *degenerate_host) {
+  if (!b) return fail(QK_EINVAL, "NULL batch");
+  if (b->n == 0) return ok();
+  QK_HIP_CHECK(hipDeviceSynchronize());
+  if (discarded_host)
+    QK_HIP_CHECK(hipMemcpy(discarded_host, b->disc_dev, sizeof(double) * b->n, hipMemcpyDeviceToHost));
+  if (degenerate_host)
+    QK_HIP_CHECK(hipMemcpy(degenerate_host, b->degen_dev, sizeof(int32_t) * b->n, hipMemcpyDeviceToHost));
+  return ok();
+}
+
+qk_status mps_batch_export(const qk_mps_batch *b, int64_t idx, double *host_buf, int64_t cap,
+                           int64_t *written) {
+  if (!b || !written) return fail(QK_EINVAL, "NULL argument");
+  if (idx < 0 || idx >= b->n) return fail(QK_EINVAL, "index out of range");
+  const int m = b->m;
+  std::vector<int32_t> d(m + 1);
+  QK_HIP_CHECK(hipDeviceSynchronize());
+  QK_HIP_CHECK(hipMemcpy(d.data(), b->dims_dev + idx * (m + 1), sizeof(int32_t) * (m + 1), hipMemcpyDeviceToHost));
+  int64_t need = 0;
+  for (int l = 0; l < m; ++l) need += int64_t(4) * d[l] * d[l + 1];
+  *written = need;
+  if (cap < need || !host_buf) return fail(QK_EINVAL, "export buffer too small");
+  std::vector<double2> mps(size_t(b->mps_stride));
+  QK_HIP_CHECK(hipMemcpy(mps.data(), b->f64 + idx * b->mps_stride, sizeof(double2) * mps.size(), hipMemcpyDeviceToHost));
+  double *dst = host_buf;
+  for (int l = 0; l < m; ++l) {
+    const double2 *src = mps.data() + b->site_off[l];
+    for (int s = 0; s < 2; ++s)
+      for (int a = 0; a < d[l]; ++a)
+        for (int c = 0; c < d[l + 1]; ++c) {
+          double2 v = src[(size_t(s) * b->pad[l] + a) * b->pad[l + 1] + c];
+          *dst++ = v.x;
+          *dst++ = v.y;
+        }
+  }
+  return ok();
+}
+
+qk_status mps_batch_pack(qk_mps_batch *b, qk_precision prec, void *hip_stream) {
+  if (!b) return fail(QK_EINVAL, "NULL batch");
+  qk_status st = batch_ensure_packed(b, prec, reinterpret_cast<hipStream_t>(hip_stream));
+  if (st != QK_OK) return st;
+  return ok();
+}
+
+qk_status mps_batch_drop(qk_mps_batch *b, qk_precision prec) {
+  if (!b) return fail(QK_EINVAL, "NULL batch");
+  QK_HIP_CHECK(hipDeviceSynchronize());
+  if (prec == QK_FP32 && b->f32) {
+    QK_HIP_CHECK(hipFree(b->f32));
+    b->f32 = nullptr;
+  } else if (prec == QK_SPLIT_BF16 && b->sbf16) {
+    QK_HIP_CHECK(hipFree(b->sbf16));
+    b->sbf16 = nullptr;
+  } else if (prec == QK_FP64) {
+    return fail(QK_EINVAL, "the FP64 form cannot be dropped");
+  }
+  return ok();
+}
+
+qk_status mps_batch_gather(const qk_mps_batch *src, const int64_t *idx_host, int64_t count,
+                           void *hip_stream, qk_mps_batch **out) {
+  if (!src || !out) return fail(QK_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (count < 0 || (count > 0 && !idx_host)) return fail(QK_EINVAL, "invalid index list");
+  for (int64_t k = 0; k < count; ++k)
+    if (idx_host[k] < 0 || idx_host[k] >= src->n) return fail(QK_EINVAL, "gather index out of range");
+  hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+  qk_mps_batch *b = nullptr;
+  qk_status st = batch_create(count, src->m, src->pad, stream, &b);
+  if (st != QK_OK) return st;
+  b->n_two_qubit_gates = src->n_two_qubit_gates;
+  const int m1 = src->m + 1;
+  for (int64_t k = 0; k < count; ++k) {
+    const int64_t i = idx_host[k];
+    bool good =
+        hipMemcpyAsync(b->f64 + k * b->mps_stride, src->f64 + i * src->mps_stride,
+                       sizeof(double2) * src->mps_stride, hipMemcpyDeviceToDevice, stream) == hipSuccess &&
+        hipMemcpyAsync(b->dims_dev + k * m1, src->dims_dev + i * m1, sizeof(int32_t) * m1,
+                       hipMemcpyDeviceToDevice, stream) == hipSuccess &&
+        hipMemcpyAsync(b->disc_dev + k, src->disc_dev + i, sizeof(double), hipMemcpyDeviceToDevice, stream) == hipSuccess &&
+        hipMemcpyAsync(b->maxdisc_dev + k, src->maxdisc_dev + i, sizeof(double), hipMemcpyDeviceToDevice, stream) == hipSuccess &&
+        hipMemcpyAsync(b->degen_dev + k, src->degen_dev + i, sizeof(int32_t), hipMemcpyDeviceToDevice, stream) == hipSuccess &&
+        hipMemcpyAsync(b->unconv_dev + k, src->unconv_dev + i, sizeof(int32_t), hipMemcpyDeviceToDevice, stream) == hipSuccess;
+    if (!good) {
+      batch_release(b);
+      return fail(QK_EDEVICE, "device copy failed in gather");
+    }
+  }
+  *out = b;
+  return ok();
+}
+
+void mps_batch_free(qk_mps_batch *b) { batch_release(b); }
+
+}  // extern "C"

@@ -1,0 +1,766 @@
+// Gram matrix of MPS overlaps on MI355X (gfx950).
+//
+// For every pair (bra a_i, ket b_j) the overlap <a_i|b_j> is contracted site
+// by site as in Fig. 2 of the paper:
+//     E_0 = [[1]],   E_{l+1} = sum_s A_a[l][s]^H E_l A_b[l][s],
+// and K[i][j] = |E_m|^2 (Eq. (1)).  Each site update is two complex GEMMs:
+//     GEMM1  T_s  = E A_b[s]              (contract the ket's left bond)
+//     GEMM2  E'^T = sum_s T_s^T conj(A_a[s])   (contract the bra's left bond)
+// One workgroup of four waves owns a pair at a time; E lives in LDS and wave
+// w computes E' for the 16-column block w of the ket's right bond.  Site
+// tensors stream from HBM (re-used across concurrently running pairs through
+// L2); the T accumulators of GEMM1 feed GEMM2 directly as MFMA A-operands:
+// the accumulator rows become the contraction index, and the bra operand is
+// laid out with the matching row order.
+//
+// After every site E' is rescaled by a power of two (exact) so that FP32 and
+// BF16 operands never underflow; the exponents are summed in an integer and
+// K = |E_m|^2 * 2^(2 * sum e) is formed in FP64.
+//
+// Pairs are taken from a device work queue (one atomic per pair) over a list
+// of 16 x 16 pair tiles that may span several jobs (batches with different
+// qubit counts and pads).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "qk_internal.h"
+
+namespace qk {
+
+namespace {
+
+constexpr int kTileSide = 16;
+constexpr int kTilePairs = kTileSide * kTileSide;
+constexpr int kThreads = 256;
+
+struct GramTile {
+  int32_t job;
+  int32_t ti;
+  int32_t tj;
+  int32_t unused;
+};
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x8 __attribute__((__vector_size__(8 * sizeof(__bf16))));
+
+__device__ inline f32x4 mma(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ inline f64x4 mma(double a, double b, f64x4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ inline f32x4 mma16(uint4 a, uint4 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                 __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+}
+
+__device__ inline uint4 neg_bf16(uint4 v) {
+  return make_uint4(v.x ^ 0x80008000u, v.y ^ 0x80008000u, v.z ^ 0x80008000u, v.w ^ 0x80008000u);
+}
+
+__device__ inline float wave_max(float v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ inline double wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Decode the next pair of the queue.  Returns false when the queue is empty;
+// *valid is false for pairs outside the job's range or below the diagonal.
+__device__ inline bool next_pair(const GramJobDev *jobs, const GramTile *tiles, int64_t total,
+                                 unsigned long long *counter, int64_t *s_slot, int *job, int64_t *i,
+                                 int64_t *j, bool *valid) {
+  if (threadIdx.x == 0) *s_slot = int64_t(atomicAdd(counter, 1ull));
+  __syncthreads();
+  const int64_t p = *s_slot;
+  __syncthreads();
+  if (p >= total) return false;
+  const GramTile t = tiles[p / kTilePairs];
+  const int q = int(p % kTilePairs);
+  const GramJobDev &J = jobs[t.job];
+  const int64_t li = int64_t(t.ti) * kTileSide + q / kTileSide;
+  const int64_t lj = int64_t(t.tj) * kTileSide + q % kTileSide;
+  *job = t.job;
+  *i = li;
+  *j = lj;
+  bool ok = li < J.na && lj < J.nb;
+  if (ok && J.upper) ok = (J.b0 + lj) >= (J.a0 + li);
+  *valid = ok;
+  return true;
+}
+
+__device__ inline void write_k(const GramJobDev &J, int64_t li, int64_t lj, double k) {
+  J.K[li * J.ldk + lj] = k;
+  if (J.upper) {
+    // mirror inside the written block when the transposed entry is in range
+    const int64_t gi = J.a0 + li, gj = J.b0 + lj;
+    const int64_t mi = gj - J.a0, mj = gi - J.b0;
+    if (gi != gj && mi >= 0 && mi < J.na && mj >= 0 && mj < J.nb) J.K[mi * J.ldk + mj] = k;
+  }
+}
+
+// Row held by element e of lane j + 16 g in a 16 x 16 MFMA accumulator: the
+// FP32 and BF16 instructions hold rows 4 g + e, the FP64 instruction holds
+// rows 4 e + g (both verified on gfx950).
+template <typename T>
+__device__ constexpr int acc_row(int g, int e) {
+  return sizeof(T) == 8 ? 4 * e + g : 4 * g + e;
+}
+
+// ------------------------------------------------------------------------
+// FP64 / FP32 forms.  E in LDS in MFMA A-operand fragment order:
+// fragment (rt, kq) holds E[16 rt + i][4 kq + g] at lane i + 16 g, as an
+// interleaved complex value.
+template <typename T, typename V4, typename T2, int MAXP>
+__device__ void overlap_plain(const GramJobDev &J, int64_t ia, int64_t ib, T2 *E, T *s_red,
+                              T &ov_re, T &ov_im, int &ov_exp) {
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int j = lane & 15, g = lane >> 4;
+  const T2 *abase = reinterpret_cast<const T2 *>(J.a_base) + ia * J.a_stride;
+  const T2 *bbase = reinterpret_cast<const T2 *>(J.b_base) + ib * J.b_stride;
+  {
+    const int n0 = J.a_pad[0] * J.b_pad[0];
+    for (int x = tid; x < n0; x += kThreads) {
+      T2 z;
+      z.x = T(0);
+      z.y = T(0);
+      E[x] = z;
+    }
+    __syncthreads();
+    if (tid == 0) E[0].x = T(1);
+    __syncthreads();
+  }
+  int expacc = 0;
+  constexpr int NT = MAXP / 16;
+  constexpr int CT_PER_WAVE = (NT + 3) / 4;
+  for (int l = 0; l < J.m; ++l) {
+    const int Da = J.a_pad[l], Dan = J.a_pad[l + 1], Db = J.b_pad[l], Dbn = J.b_pad[l + 1];
+    const T2 *A = abase + J.a_off[l];
+    const T2 *B = bbase + J.b_off[l];
+    const int nrt = Da / 16, nkq = Db / 4, nat = Dan / 16, nct = Dbn / 16, nkqn = Dbn / 4;
+    V4 Ep[CT_PER_WAVE][NT][2];
+    T lmax = T(0);
+#pragma unroll
+    for (int c = 0; c < CT_PER_WAVE; ++c) {
+      const int ct = wave + 4 * c;
+#pragma unroll
+      for (int at = 0; at < NT; ++at) {
+        Ep[c][at][0] = V4{0, 0, 0, 0};
+        Ep[c][at][1] = V4{0, 0, 0, 0};
+      }
+      if (ct >= nct) continue;
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        V4 Tt[NT][2];
+#pragma unroll
+        for (int rt = 0; rt < NT; ++rt) {
+          Tt[rt][0] = V4{0, 0, 0, 0};
+          Tt[rt][1] = V4{0, 0, 0, 0};
+        }
+        // GEMM1: T_s[a][b'] = sum_b E[a][b] B_s[b][b'],  b' in block ct
+        for (int kq = 0; kq < nkq; ++kq) {
+          const T2 bv = B[(size_t(s) * Db + 4 * kq + g) * Dbn + 16 * ct + j];
+          const T bneg = -bv.y;
+#pragma unroll
+          for (int rt = 0; rt < NT; ++rt) {
+            if (rt < nrt) {
+              const T2 ev = E[(rt * nkq + kq) * 64 + lane];
+              Tt[rt][0] = mma(ev.x, bv.x, Tt[rt][0]);
+              Tt[rt][0] = mma(ev.y, bneg, Tt[rt][0]);
+              Tt[rt][1] = mma(ev.x, bv.y, Tt[rt][1]);
+              Tt[rt][1] = mma(ev.y, bv.x, Tt[rt][1]);
+            }
+          }
+        }
+        // GEMM2: E'^T[b'][a'] += sum_a T_s[a][b'] conj(A_s[a][a'])
+#pragma unroll
+        for (int rt = 0; rt < NT; ++rt) {
+          if (rt < nrt) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const T tr = Tt[rt][0][e], ti = Tt[rt][1][e];
+              const int a = 16 * rt + acc_row<T>(g, e);
+              const T2 *arow = A + (size_t(s) * Da + a) * Dan + j;
+#pragma unroll
+              for (int at = 0; at < NT; ++at) {
+                if (at < nat) {
+                  const T2 av = arow[16 * at];
+                  Ep[c][at][0] = mma(tr, av.x, Ep[c][at][0]);
+                  Ep[c][at][0] = mma(ti, av.y, Ep[c][at][0]);
+                  Ep[c][at][1] = mma(ti, av.x, Ep[c][at][1]);
+                  Ep[c][at][1] = mma(-tr, av.y, Ep[c][at][1]);
+                }
+              }
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int at = 0; at < NT; ++at)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          lmax = fmax(lmax, fmax(fabs(Ep[c][at][0][e]), fabs(Ep[c][at][1][e])));
+    }
+    lmax = wave_max(lmax);
+    if (lane == 0) s_red[wave] = lmax;
+    __syncthreads();  // every wave is done reading E
+    const T gmax = fmax(fmax(s_red[0], s_red[1]), fmax(s_red[2], s_red[3]));
+    const int e2 = gmax > T(0) ? ilogb(gmax) : 0;
+    const T scale = ldexp(T(1), -e2);
+    expacc += e2;
+#pragma unroll
+    for (int c = 0; c < CT_PER_WAVE; ++c) {
+      const int ct = wave + 4 * c;
+      if (ct >= nct) continue;
+#pragma unroll
+      for (int at = 0; at < NT; ++at) {
+        if (at < nat) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            T2 v;
+            v.x = Ep[c][at][0][e] * scale;
+            v.y = Ep[c][at][1][e] * scale;
+            // E'[16 at + j][bp] -> fragment (at, bp / 4), lane j + 16 (bp % 4)
+            const int bp = 16 * ct + acc_row<T>(g, e);
+            E[(at * nkqn + (bp >> 2)) * 64 + j + 16 * (bp & 3)] = v;
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  ov_re = E[0].x;
+  ov_im = E[0].y;
+  ov_exp = expacc;
+  __syncthreads();
+}
+
+// ------------------------------------------------------------------------
+// Split-BF16 form with fixed-point slices (layout in qk_internal.h).
+//
+// Every GEMM operand is cut into four bf16 slices that share one exponent per
+// row (A-operand) or column (B-operand), so each slice is an integer
+// |n| <= 128 times a power of two.  A real product X Y is then
+//     2^(eX + eY - 14) * ( X0.Y0  +  sum of ten smaller slice products )
+// where X0.Y0 accumulates EXACTLY in one FP32 MFMA accumulator (integers below
+// 2^22) and the other ten slice pairs (weights 2^-8 .. 2^-32, smallest first)
+// share a second FP32 accumulator, whose rounding is then ~2^-32 of the result.
+// The two accumulators are combined in FP64.  This removes the FP32
+// accumulation error that otherwise grows along the chain (about 2e-6 at 50
+// sites and 2e-5 at 100 sites for K = 1 with plain FP32 operands).
+//
+// E lives in LDS as slices plus one exponent per row; T and E' are formed in
+// FP64 registers and re-sliced for the next GEMM.
+__device__ inline int exp_above(double mx) {
+  // smallest e with mx < 2^e (0 for mx == 0)
+  return mx > 0.0 ? ilogb(mx) + 1 : 0;
+}
+
+__device__ inline uint32_t bf16_bits_exact(float v) { return __float_as_uint(v) >> 16; }
+
+// Four pre-scaled slices n_k 2^-8k (k = 0..3) of xh in (-1, 1), bf16 bits.
+__device__ inline void slice4(double xh, uint32_t (&o)[4]) {
+  double r = xh * 128.0;
+  const float kp[4] = {1.0f, 0x1p-8f, 0x1p-16f, 0x1p-24f};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const double nk = rint(r);
+    o[k] = bf16_bits_exact(float(nk) * kp[k]);
+    r = (r - nk) * 256.0;
+  }
+}
+
+struct Sl4 {
+  uint4 v[4];
+};
+
+__device__ inline Sl4 neg4(const Sl4 &x) {
+  Sl4 y;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) y.v[k] = neg_bf16(x.v[k]);
+  return y;
+}
+
+// hi += X0 Y0 (exact); lo += the ten smaller slice products, smallest first.
+__device__ inline void slice_mac(const Sl4 &X, const Sl4 &Y, f32x4 &hi, f32x4 &lo) {
+  hi = mma16(X.v[0], Y.v[0], hi);
+  lo = mma16(X.v[3], Y.v[0], lo);
+  lo = mma16(X.v[0], Y.v[3], lo);
+  lo = mma16(X.v[2], Y.v[1], lo);
+  lo = mma16(X.v[1], Y.v[2], lo);
+  lo = mma16(X.v[2], Y.v[2], lo);
+  lo = mma16(X.v[2], Y.v[0], lo);
+  lo = mma16(X.v[1], Y.v[1], lo);
+  lo = mma16(X.v[0], Y.v[2], lo);
+  lo = mma16(X.v[1], Y.v[0], lo);
+  lo = mma16(X.v[0], Y.v[1], lo);
+}
+
+// Pack the 8 values of one A-operand chunk into four slice registers.
+__device__ inline Sl4 make_slices(const double (&xh)[8]) {
+  Sl4 r;
+  uint32_t sl[8][4];
+#pragma unroll
+  for (int v = 0; v < 8; ++v) slice4(xh[v], sl[v]);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    r.v[k].x = sl[0][k] | (sl[1][k] << 16);
+    r.v[k].y = sl[2][k] | (sl[3][k] << 16);
+    r.v[k].z = sl[4][k] | (sl[5][k] << 16);
+    r.v[k].w = sl[6][k] | (sl[7][k] << 16);
+  }
+  return r;
+}
+
+template <int MAXP>
+__device__ void overlap_split(const GramJobDev &J, int64_t ia, int64_t ib, uint8_t *E, int *s_ea,
+                              double *s_rmax, double *s_wmax, double *s_ov, double &ov_re, double &ov_im,
+                              int &ov_exp) {
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int j = lane & 15, g = lane >> 4;
+  const uint8_t *abase = reinterpret_cast<const uint8_t *>(J.a_base) + ia * J.a_stride;
+  const uint8_t *bbase = reinterpret_cast<const uint8_t *>(J.b_base) + ib * J.b_stride;
+  // LDS E: fragment group (rt, kc) = [slice 4][plane 2][lane 64][16 B] = 8 KiB
+  auto egroup = [&](int rt, int kc, int nkc) -> uint8_t * { return E + size_t(rt * nkc + kc) * 8192; };
+  {
+    const int nbytes = J.a_pad[0] * J.b_pad[0] * 16;
+    uint32_t *E32 = reinterpret_cast<uint32_t *>(E);
+    for (int x = tid; x < nbytes / 4; x += kThreads) E32[x] = 0u;
+    for (int x = tid; x < MAXP; x += kThreads) s_ea[x] = 0;
+    __syncthreads();
+    // E_0 = [[1]]: row exponent 1, leading slice 64 (= 0.5 * 128)
+    if (tid == 0) {
+      reinterpret_cast<uint16_t *>(E)[0] = uint16_t(bf16_bits_exact(64.0f));
+      s_ea[0] = 1;
+    }
+    __syncthreads();
+  }
+  int expacc = 0;
+  constexpr int NT = MAXP / 16;
+  constexpr int NK = MAXP / 32;
+  constexpr int CT_PER_WAVE = (NT + 3) / 4;
+  for (int l = 0; l < J.m; ++l) {
+    const int Da = J.a_pad[l], Dan = J.a_pad[l + 1], Db = J.b_pad[l], Dbn = J.b_pad[l + 1];
+    const uint8_t *A = abase + J.a_off[l];
+    const uint8_t *B = bbase + J.b_off[l];
+    const int8_t *eA = reinterpret_cast<const int8_t *>(A);
+    const int8_t *eB = reinterpret_cast<const int8_t *>(B);
+    const int nrt = Da / 16, nkcb = Db / 32, nkca = Da / 32, nat = Dan / 16, nct = Dbn / 16;
+    const int nkcn = Dbn / 32;
+    const bool last = (l + 1 == J.m);
+    auto frag = [&](const uint8_t *site, int s, int k, int q, int kc, int ct, int nkc, int ncol) {
+      return *reinterpret_cast<const uint4 *>(
+          site + kSplitExpBytes +
+          ((size_t((((s * 4 + k) * 2 + q) * nkc + kc)) * ncol + ct) * 1024 + lane * 16));
+    };
+    double Epd[CT_PER_WAVE][NT][2][4];
+    double wmax = 0.0;
+#pragma unroll
+    for (int c = 0; c < CT_PER_WAVE; ++c) {
+      const int ct = wave + 4 * c;
+#pragma unroll
+      for (int at = 0; at < NT; ++at)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) Epd[c][at][q][e] = 0.0;
+      if (ct >= nct) continue;
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        // ---- GEMM1: T_s[a][b'] = sum_b E[a][b] B_s[b][b'], b' in block ct
+        f32x4 h1[NT][2], l1[NT][2];
+#pragma unroll
+        for (int rt = 0; rt < NT; ++rt)
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            h1[rt][q] = f32x4{0, 0, 0, 0};
+            l1[rt][q] = f32x4{0, 0, 0, 0};
+          }
+        for (int kc = 0; kc < nkcb; ++kc) {
+          Sl4 Br, Bi;
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            Br.v[k] = frag(B, s, k, 0, kc, ct, nkcb, nct);
+            Bi.v[k] = frag(B, s, k, 1, kc, ct, nkcb, nct);
+          }
+          const Sl4 Bin = neg4(Bi);
+#pragma unroll
+          for (int rt = 0; rt < NT; ++rt) {
+            if (rt < nrt) {
+              const uint8_t *eg = egroup(rt, kc, nkcb) + lane * 16;
+              Sl4 Er, Ei;
+#pragma unroll
+              for (int k = 0; k < 4; ++k) {
+                Er.v[k] = *reinterpret_cast<const uint4 *>(eg + (k * 2 + 0) * 1024);
+                Ei.v[k] = *reinterpret_cast<const uint4 *>(eg + (k * 2 + 1) * 1024);
+              }
+              // re += Er Br - Ei Bi ; im += Er Bi + Ei Br
+              slice_mac(Er, Br, h1[rt][0], l1[rt][0]);
+              slice_mac(Ei, Bin, h1[rt][0], l1[rt][0]);
+              slice_mac(Er, Bi, h1[rt][1], l1[rt][1]);
+              slice_mac(Ei, Br, h1[rt][1], l1[rt][1]);
+            }
+          }
+        }
+        // T in FP64; the row max of T^T (column b' = 16 ct + j) over a
+        double Td[NT][2][4];
+        double tmax = 0.0;
+        const int ebc = int(eB[s * 128 + 16 * ct + j]);
+#pragma unroll
+        for (int rt = 0; rt < NT; ++rt)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int ex = (rt < nrt ? s_ea[16 * rt + 4 * g + e] : 0) + ebc - 14;
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+              const double v = rt < nrt ? ldexp(double(h1[rt][q][e]) + double(l1[rt][q][e]), ex) : 0.0;
+              Td[rt][q][e] = v;
+              tmax = fmax(tmax, fabs(v));
+            }
+          }
+        tmax = fmax(tmax, __shfl_xor(tmax, 16, 64));
+        tmax = fmax(tmax, __shfl_xor(tmax, 32, 64));
+        const int eT = exp_above(tmax);       // exponent of row b' = 16 ct + j
+        // ---- GEMM2: E'^T[b'][a'] += sum_a T_s[a][b'] conj(A_s[a][a'])
+        f32x4 h2[NT][2], l2[NT][2];
+#pragma unroll
+        for (int at = 0; at < NT; ++at)
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            h2[at][q] = f32x4{0, 0, 0, 0};
+            l2[at][q] = f32x4{0, 0, 0, 0};
+          }
+#pragma unroll
+        for (int kc = 0; kc < NK; ++kc) {
+          if (kc < nkca) {
+            double xr[8], xi[8];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              xr[v] = ldexp(Td[2 * kc][0][v], -eT);
+              xi[v] = ldexp(Td[2 * kc][1][v], -eT);
+              xr[4 + v] = ldexp(Td[2 * kc + 1][0][v], -eT);
+              xi[4 + v] = ldexp(Td[2 * kc + 1][1][v], -eT);
+            }
+            const Sl4 Tr = make_slices(xr), Ti = make_slices(xi);
+            const Sl4 Trn = neg4(Tr);
+#pragma unroll
+            for (int at = 0; at < NT; ++at) {
+              if (at < nat) {
+                Sl4 Ar, Ai;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                  Ar.v[k] = frag(A, s, k, 0, kc, at, nkca, nat);
+                  Ai.v[k] = frag(A, s, k, 1, kc, at, nkca, nat);
+                }
+                // re += Tr Ar + Ti Ai ; im += Ti Ar - Tr Ai
+                slice_mac(Tr, Ar, h2[at][0], l2[at][0]);
+                slice_mac(Ti, Ai, h2[at][0], l2[at][0]);
+                slice_mac(Ti, Ar, h2[at][1], l2[at][1]);
+                slice_mac(Trn, Ai, h2[at][1], l2[at][1]);
+              }
+            }
+          }
+        }
+        // output row b' = 16 ct + 4 g + e takes the exponent of lane 4 g + e
+        int eTr[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) eTr[e] = __shfl(eT, 4 * g + e, 64);
+#pragma unroll
+        for (int at = 0; at < NT; ++at) {
+          if (at < nat) {
+            const int eac = int(eA[s * 128 + 16 * at + j]);
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+#pragma unroll
+              for (int q = 0; q < 2; ++q)
+                Epd[c][at][q][e] += ldexp(double(h2[at][q][e]) + double(l2[at][q][e]), eTr[e] + eac - 14);
+          }
+        }
+      }
+      // row maxima of E' rows a' = 16 at + j over this wave's columns
+#pragma unroll
+      for (int at = 0; at < NT; ++at) {
+        double rm = 0.0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) rm = fmax(rm, fmax(fabs(Epd[c][at][0][e]), fabs(Epd[c][at][1][e])));
+        rm = fmax(rm, __shfl_xor(rm, 16, 64));
+        rm = fmax(rm, __shfl_xor(rm, 32, 64));
+        if (at < nat && g == 0) s_rmax[(wave + 4 * c) * MAXP + 16 * at + j] = rm;
+        wmax = fmax(wmax, rm);
+      }
+    }
+    // waves without a column block report zero rows
+    for (int c = 0; c < CT_PER_WAVE; ++c) {
+      const int ct = wave + 4 * c;
+      if (ct >= nct)
+        for (int x = lane; x < Dan; x += 64) s_rmax[(wave + 4 * c) * MAXP + x] = 0.0;
+    }
+    if (lane == 0) s_wmax[wave] = wmax;
+    if (last && wave == 0 && lane == 0) {
+      s_ov[0] = Epd[0][0][0][0];
+      s_ov[1] = Epd[0][0][1][0];
+    }
+    __syncthreads();  // every wave is done reading E and s_ea
+    if (!last) {
+      double gm = 0.0;
+      for (int w = 0; w < kThreads / 64; ++w) gm = fmax(gm, s_wmax[w]);
+      const int e2 = exp_above(gm);
+      expacc += e2;
+      const int nblk = (nct + 3) / 4 * 4;  // column blocks reported in s_rmax
+#pragma unroll
+      for (int c = 0; c < CT_PER_WAVE; ++c) {
+        const int ct = wave + 4 * c;
+        if (ct >= nct) continue;
+#pragma unroll
+        for (int at = 0; at < NT; ++at) {
+          if (at < nat) {
+            const int a_row = 16 * at + j;
+            double rm = 0.0;
+            for (int w = 0; w < nblk; ++w) rm = fmax(rm, s_rmax[w * MAXP + a_row]);
+            const int er = exp_above(rm);
+            uint8_t *eg = egroup(at, ct >> 1, nkcn) + lane * 16 + (ct & 1) * 8;
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+              uint32_t sl[4][4];
+#pragma unroll
+              for (int e = 0; e < 4; ++e) slice4(ldexp(Epd[c][at][q][e], -er), sl[e]);
+#pragma unroll
+              for (int k = 0; k < 4; ++k)
+                *reinterpret_cast<uint2 *>(eg + (k * 2 + q) * 1024) =
+                    make_uint2(sl[0][k] | (sl[1][k] << 16), sl[2][k] | (sl[3][k] << 16));
+            }
+            if (ct == 0 && g == 0) s_ea[a_row] = er - e2;
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  ov_re = s_ov[0];
+  ov_im = s_ov[1];
+  ov_exp = expacc;
+  __syncthreads();
+}
+
+template <int PREC, int MAXP>
+__global__ __launch_bounds__(kThreads) void gram_kernel(const GramJobDev *__restrict__ jobs,
+                                                        const GramTile *__restrict__ tiles,
+                                                        int64_t total, unsigned long long *counter) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  __shared__ int64_t s_slot;
+  __shared__ double s_red[4];
+  __shared__ double s_ov[2];
+  __shared__ int s_ea[MAXP];
+  __shared__ double s_rmax[((MAXP / 16 + 3) / 4) * 4 * MAXP];
+  int job;
+  int64_t i, j;
+  bool valid;
+  while (next_pair(jobs, tiles, total, counter, &s_slot, &job, &i, &j, &valid)) {
+    if (!valid) continue;
+    const GramJobDev &J = jobs[job];
+    double k;
+    if constexpr (PREC == QK_FP64) {
+      double re, im;
+      int ex;
+      overlap_plain<double, f64x4, double2, MAXP>(J, J.a0 + i, J.b0 + j,
+                                                  reinterpret_cast<double2 *>(smem), s_red, re, im, ex);
+      k = ldexp(re * re + im * im, 2 * ex);
+    } else if constexpr (PREC == QK_FP32) {
+      float re, im;
+      int ex;
+      overlap_plain<float, f32x4, float2, MAXP>(J, J.a0 + i, J.b0 + j, reinterpret_cast<float2 *>(smem),
+                                                reinterpret_cast<float *>(s_red), re, im, ex);
+      k = ldexp(double(re) * re + double(im) * im, 2 * ex);
+    } else {
+      double re, im;
+      int ex;
+      overlap_split<MAXP>(J, J.a0 + i, J.b0 + j, smem, s_ea, s_rmax, s_red, s_ov, re, im, ex);
+      k = ldexp(re * re + im * im, 2 * ex);
+    }
+    if (threadIdx.x == 0) write_k(J, i, j, k);
+  }
+}
+
+template <int PREC, int MAXP>
+size_t lds_bytes() {
+  if (PREC == QK_FP64) return size_t(MAXP) * MAXP * 16;
+  if (PREC == QK_FP32) return size_t(MAXP) * MAXP * 8;
+  return size_t(MAXP) * MAXP * 16;
+}
+
+template <int PREC, int MAXP>
+qk_status launch_one(const GramJobDev *jobs_dev, const GramTile *tiles_dev, int64_t total,
+                     unsigned long long *counter, hipStream_t stream) {
+  int dev = 0, cus = 256;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  const size_t lds = lds_bytes<PREC, MAXP>();
+  auto kern = gram_kernel<PREC, MAXP>;
+  QK_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+  int per_cu = 0;
+  QK_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kThreads, lds));
+  per_cu = std::max(per_cu, 1);
+  int64_t grid = int64_t(cus) * per_cu;
+  grid = std::min<int64_t>(grid, std::max<int64_t>(total, 1));
+  hipLaunchKernelGGL(kern, dim3(unsigned(grid)), dim3(kThreads), lds, stream, jobs_dev, tiles_dev, total,
+                     counter);
+  QK_HIP_CHECK(hipGetLastError());
+  return QK_OK;
+}
+
+}  // namespace
+
+qk_status launch_gram(const std::vector<GramJobDev> &jobs_in, int max_pad, qk_precision prec,
+                      hipStream_t stream) {
+  if (max_pad > 64) return fail(QK_ENOTSUP, "Gram kernels support bond pads up to 64");
+  std::vector<GramJobDev> jobs = jobs_in;
+  std::vector<GramTile> tiles;
+  for (size_t k = 0; k < jobs.size(); ++k) {
+    GramJobDev &J = jobs[k];
+    J.tiles_i = (J.na + kTileSide - 1) / kTileSide;
+    J.tiles_j = (J.nb + kTileSide - 1) / kTileSide;
+    J.pair_begin = int64_t(tiles.size()) * kTilePairs;
+    for (int64_t ti = 0; ti < J.tiles_i; ++ti)
+      for (int64_t tj = 0; tj < J.tiles_j; ++tj) {
+        if (J.upper) {
+          // skip tiles entirely below the global diagonal
+          const int64_t max_col = J.b0 + std::min(J.nb, (tj + 1) * kTileSide) - 1;
+          const int64_t min_row = J.a0 + ti * kTileSide;
+          if (max_col < min_row) continue;
+        }
+        tiles.push_back(GramTile{int32_t(k), int32_t(ti), int32_t(tj), 0});
+      }
+  }
+  if (tiles.empty()) return QK_OK;
+  const int64_t total = int64_t(tiles.size()) * kTilePairs;
+  const size_t jbytes = sizeof(GramJobDev) * jobs.size();
+  const size_t tbytes = sizeof(GramTile) * tiles.size();
+  uint8_t *ws = nullptr;
+  const size_t ws_bytes = 256 + jbytes + tbytes;
+  QK_HIP_CHECK(hipMallocAsync(reinterpret_cast<void **>(&ws), ws_bytes, stream));
+  auto *counter = reinterpret_cast<unsigned long long *>(ws);
+  auto *jobs_dev = reinterpret_cast<GramJobDev *>(ws + 256);
+  auto *tiles_dev = reinterpret_cast<GramTile *>(ws + 256 + jbytes);
+  QK_HIP_CHECK(hipMemsetAsync(counter, 0, sizeof(unsigned long long), stream));
+  QK_HIP_CHECK(hipMemcpyAsync(jobs_dev, jobs.data(), jbytes, hipMemcpyHostToDevice, stream));
+  QK_HIP_CHECK(hipMemcpyAsync(tiles_dev, tiles.data(), tbytes, hipMemcpyHostToDevice, stream));
+  // the host tile list must stay alive until the copies have run
+  QK_HIP_CHECK(hipStreamSynchronize(stream));
+  qk_status st;
+  if (prec == QK_FP64)
+    st = launch_one<QK_FP64, 64>(jobs_dev, tiles_dev, total, counter, stream);
+  else if (prec == QK_FP32)
+    st = launch_one<QK_FP32, 64>(jobs_dev, tiles_dev, total, counter, stream);
+  else
+    st = launch_one<QK_SPLIT_BF16, 64>(jobs_dev, tiles_dev, total, counter, stream);
+  (void)hipFreeAsync(ws, stream);
+  return st;
+}
+
+// ------------------------------------------------------------------------
+// Packing of the FP64 master into the FP32 and split-BF16 operand forms.
+
+__global__ void pack_f32_kernel(const double2 *__restrict__ src, float2 *__restrict__ dst, int64_t count) {
+  for (int64_t x = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; x < count;
+       x += int64_t(gridDim.x) * blockDim.x) {
+    const double2 v = src[x];
+    dst[x] = make_float2(float(v.x), float(v.y));
+  }
+}
+
+// One block per (site, mps): column exponents e[s][c] (max |x| < 2^e over the
+// column's rows and both planes), then the four fixed-point slices of every
+// value, in B-operand fragment order.
+__global__ __launch_bounds__(256) void pack_split_kernel(const double2 *__restrict__ src, uint8_t *__restrict__ dst,
+                                                         const int32_t *__restrict__ pad,
+                                                         const int64_t *__restrict__ site_off,
+                                                         const int64_t *__restrict__ split_off, int64_t mps_stride,
+                                                         int64_t split_stride, int32_t m, int64_t n) {
+  const int l = blockIdx.x;
+  const int64_t i = blockIdx.y;
+  if (i >= n || l >= m) return;
+  __shared__ int s_e[2 * 128];
+  const int pl = pad[l], pr = pad[l + 1];
+  const int nkc = pl / 32, nct = pr / 16;
+  const double2 *site = src + i * mps_stride + site_off[l];
+  uint8_t *out = dst + i * split_stride + split_off[l];
+  for (int t = threadIdx.x; t < 2 * 128; t += blockDim.x) {
+    const int s = t / 128, c = t % 128;
+    int e = 0;
+    if (c < pr) {
+      double mx = 0.0;
+      for (int r = 0; r < pl; ++r) {
+        const double2 x = site[(size_t(s) * pl + r) * pr + c];
+        mx = fmax(mx, fmax(fabs(x.x), fabs(x.y)));
+      }
+      e = exp_above(mx);
+    }
+    s_e[t] = e;
+    out[t] = uint8_t(int8_t(e));
+  }
+  __syncthreads();
+  const int work = 2 * nkc * nct * 64;
+  for (int w = threadIdx.x; w < work; w += blockDim.x) {
+    const int lane = w % 64;
+    const int ct = (w / 64) % nct;
+    const int kc = (w / (64 * nct)) % nkc;
+    const int s = w / (64 * nct * nkc);
+    const int jj = lane & 15, gg = lane >> 4;
+    const int col = 16 * ct + jj;
+    const int e = s_e[s * 128 + col];
+    uint32_t sl[2][8][4];
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+      const int row = 32 * kc + (v < 4 ? 4 * gg + v : 16 + 4 * gg + (v - 4));
+      const double2 x = site[(size_t(s) * pl + row) * pr + col];
+      slice4(ldexp(x.x, -e), sl[0][v]);
+      slice4(ldexp(x.y, -e), sl[1][v]);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        uint4 o;
+        o.x = sl[q][0][k] | (sl[q][1][k] << 16);
+        o.y = sl[q][2][k] | (sl[q][3][k] << 16);
+        o.z = sl[q][4][k] | (sl[q][5][k] << 16);
+        o.w = sl[q][6][k] | (sl[q][7][k] << 16);
+        *reinterpret_cast<uint4 *>(out + kSplitExpBytes +
+                                   ((size_t(((s * 4 + k) * 2 + q) * nkc + kc) * nct + ct) * 1024 + lane * 16)) = o;
+      }
+  }
+}
+
+qk_status launch_pack_f32(const qk_mps_batch *b, hipStream_t stream) {
+  const int64_t count = b->n * b->mps_stride;
+  if (count == 0) return QK_OK;
+  const int64_t blocks = std::min<int64_t>((count + 255) / 256, 65536);
+  hipLaunchKernelGGL(pack_f32_kernel, dim3(unsigned(blocks)), dim3(256), 0, stream, b->f64, b->f32, count);
+  QK_HIP_CHECK(hipGetLastError());
+  return QK_OK;
+}
+
+qk_status launch_pack_split(const qk_mps_batch *b, hipStream_t stream) {
+  if (b->n == 0) return QK_OK;
+  if (b->n > 65535 * 16) return fail(QK_ENOTSUP, "batch too large for the packing grid");
+  // grid.y = MPS (chunked), grid.z = site
+  const int64_t chunk = 65535;
+  for (int64_t i0 = 0; i0 < b->n; i0 += chunk) {
+    const int64_t cnt = std::min(chunk, b->n - i0);
+    hipLaunchKernelGGL(pack_split_kernel, dim3(unsigned(b->m), unsigned(cnt)), dim3(256), 0, stream,
+                       b->f64 + i0 * b->mps_stride, b->sbf16 + i0 * b->split_stride, b->pad_dev,
+                       b->site_off_dev, b->split_off_dev, b->mps_stride, b->split_stride, b->m, cnt);
+    QK_HIP_CHECK(hipGetLastError());
+  }
+  return QK_OK;
+}
+
+}  // namespace qk

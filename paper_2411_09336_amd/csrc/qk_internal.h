@@ -1,0 +1,128 @@
+// Internal declarations shared by the host library and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/qkmps.h"
+
+namespace qk {
+
+// Thread-local error reporting used by every C-ABI entry point.
+void set_error(const std::string &msg);
+qk_status fail(qk_status st, const std::string &msg);
+
+#define QK_HIP_CHECK(expr)                                                     \
+  do {                                                                         \
+    hipError_t _e = (expr);                                                    \
+    if (_e != hipSuccess)                                                      \
+      return ::qk::fail(QK_EDEVICE, std::string(#expr " -> ") +               \
+                                        hipGetErrorString(_e));                \
+  } while (0)
+
+constexpr int kPadQuantum = 32;      // bond pads are multiples of 32
+constexpr int kMaxBond = 128;        // largest supported pad in a batch
+constexpr int kMaxSimChi = 64;       // largest bond cap in simulation
+
+inline int pad_of(int d) { return ((d + kPadQuantum - 1) / kPadQuantum) * kPadQuantum; }
+
+// Split-BF16 operand form (fixed-point slices).  Every real value x of a
+// site tensor column c (per physical index s) is written as
+//   x = 2^(e[s][c] - 7) * (n0 + n1 2^-8 + n2 2^-16 + n3 2^-24) + O(2^(e-32))
+// with a shared column exponent e[s][c] (max |x| of the column < 2^e) and
+// integers |n_k| <= 128; slice k is stored as the bf16 value n_k 2^(-8k),
+// which is exact.  Products of leading slices are integers below 2^14, so
+// the (0,0) slice product accumulates exactly in an FP32 MFMA accumulator.
+// A site block is:
+//   [int8 exponents e[s][c], s in {0,1}, c < 128 : 256 bytes]
+//   [fragments: [s][slice 0..3][plane 0..1 = re, im][kc][ct][lane][8 bf16]]
+// where fragment (kc, ct) is the MFMA B-operand of K = 32 rows by 16
+// columns: lane l = j + 16 g, slot v holds row perm(kc, g, v), column
+// 16 ct + j, with
+//   perm(kc, g, v) = 32 kc + 4 g + v          for v < 4
+//                  = 32 kc + 16 + 4 g + v - 4 for v >= 4.
+constexpr int kFragBytes = 64 * 8 * 2;   // 1 KiB
+constexpr int kSlices = 4;
+constexpr int kSplitExpBytes = 256;
+
+inline int64_t split_site_bytes(int pl, int pr) {
+  return kSplitExpBytes + int64_t(2) * kSlices * 2 * (pl / 32) * (pr / 16) * kFragBytes;
+}
+
+}  // namespace qk
+
+// Opaque batch.  Every MPS of a batch has m sites with the pad profile
+// pad[0..m]; site l of MPS i starts at complex offset
+//   i * mps_stride + site_off[l]
+// in the FP64 (complex128) and FP32 (complex64) forms, and at byte offset
+//   i * split_stride + split_off[l]
+// in the split-BF16 form.
+struct qk_mps_batch {
+  int device = 0;
+  int64_t n = 0;
+  int32_t m = 0;
+  std::vector<int32_t> pad;        // m + 1 entries
+  std::vector<int64_t> site_off;   // m + 1 entries (last = mps_stride)
+  int64_t mps_stride = 0;          // complex elements per MPS
+  std::vector<int64_t> split_off;  // m + 1 entries, bytes
+  int64_t split_stride = 0;        // bytes per MPS
+
+  double2 *f64 = nullptr;          // n * mps_stride
+  float2 *f32 = nullptr;           // packed on demand
+  uint8_t *sbf16 = nullptr;        // packed on demand
+
+  int32_t *dims_dev = nullptr;     // n * (m + 1)
+  int32_t *pad_dev = nullptr;      // m + 1
+  int64_t *site_off_dev = nullptr; // m + 1
+  int64_t *split_off_dev = nullptr;// m + 1
+  double *disc_dev = nullptr;      // n: summed discarded weight
+  double *maxdisc_dev = nullptr;   // n: largest single discarded weight
+  int32_t *degen_dev = nullptr;    // n: near-degenerate cuts
+  int32_t *unconv_dev = nullptr;   // n: SVDs at the sweep limit
+
+  int32_t n_two_qubit_gates = 0;
+};
+
+namespace qk {
+
+// Allocate a batch with the given pad profile (device memory zeroed).
+qk_status batch_create(int64_t n, int32_t m, const std::vector<int32_t> &pad,
+                       hipStream_t stream, qk_mps_batch **out);
+qk_status batch_ensure_packed(qk_mps_batch *b, qk_precision prec, hipStream_t stream);
+
+// Launchers implemented in the .hip files.
+qk_status launch_pack_f32(const qk_mps_batch *b, hipStream_t stream);
+qk_status launch_pack_split(const qk_mps_batch *b, hipStream_t stream);
+
+struct GramJobDev {
+  const void *a_base;              // form-specific base pointer of batch a
+  const void *b_base;
+  const int64_t *a_off;            // per-site offsets (complex elems or bytes)
+  const int64_t *b_off;
+  const int32_t *a_pad;            // m + 1
+  const int32_t *b_pad;
+  int64_t a_stride, b_stride;      // per-MPS stride (complex elems or bytes)
+  int64_t a0, na, b0, nb;
+  double *K;
+  int64_t ldk;
+  int32_t m;
+  int32_t upper;                   // symmetric: only global j >= i
+  int64_t tiles_i, tiles_j;        // tile grid of this job
+  int64_t pair_begin;              // first flat pair index of this job
+};
+
+qk_status launch_gram(const std::vector<GramJobDev> &jobs, int max_pad,
+                      qk_precision prec, hipStream_t stream);
+
+// Simulation launchers.
+qk_status run_simulation(qk_mps_batch *b, const double *features_dev,
+                         const std::vector<qk_gate> &gates,
+                         const qk_circuit_spec &spec, int chi, double cutoff,
+                         hipStream_t stream);
+
+std::vector<qk_gate> compile_circuit(const qk_circuit_spec &spec);
+qk_status validate_spec(const qk_circuit_spec *spec);
+
+}  // namespace qk

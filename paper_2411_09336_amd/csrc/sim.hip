@@ -1,0 +1,632 @@
+// Batched truncated MPS simulation of the feature-map circuit (Sec. II-B,
+// Fig. 1; circuit of Sec. II-C).
+//
+// Every circuit of a batch shares one gate list, so each gate is one launch
+// over all circuits (one workgroup per circuit).  Rz layers are diagonal and
+// applied in place (Fig. 1a).  A two-qubit gate on sites (p, p+1) (Fig. 1b):
+//   * theta[(s,a),(t,b)] = sum_{s',t'} G[st,s't'] sum_c A_p[s'][a][c] A_{p+1}[t'][c][b]
+//     is built directly in registers;
+//   * its SVD is taken by one-sided (Hestenes) Jacobi in FP64: pairs of
+//     columns are rotated until every pair is orthogonal to relative
+//     tolerance 1e-15; the columns then are U S.  To absorb S to the right
+//     the columns of theta are orthogonalised (U = W / |W|, the new right
+//     tensor is U^H theta); to absorb it to the left the columns of theta^H
+//     are (giving V, the new left tensor is theta V).  The isometric factor
+//     is therefore always a set of normalised Jacobi columns and the other
+//     factor an exact projection, so no V matrix is accumulated;
+//   * truncation keeps k = max(1, min(chi, k_cut)) columns by decreasing norm
+//     (Eq. (8): k_cut is the smallest count whose discarded weight is at most
+//     cutoff times the total; cutoff <= 0 keeps all non-zero columns) and the
+//     kept weight is renormalised to one.
+// Orthogonality-centre moves (canonicalisation before each truncation) use
+// the same machinery without truncation: the site matrix is orthogonalised
+// and the remainder is pushed into the neighbour via the identity two-site
+// theta.
+//
+// Register layout of the Jacobi matrix M (<= 128 x 128 complex): wave w of
+// 16 owns rows 8w .. 8w+7; lane l owns column positions 2l and 2l+1 (slots A
+// and B), so every rotation pair is local to a lane.  Each round the partial
+// inner products of the 16 waves are reduced through LDS, rotations are
+// applied, and the columns move one step along the round-robin (circle)
+// ordering, so n-1 rounds visit every pair once per sweep.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "qk_internal.h"
+
+namespace qk {
+
+namespace {
+
+constexpr int kSvWaves = 16;
+constexpr int kSvRows = 8;                // rows per wave
+constexpr int kSvThreads = kSvWaves * 64; // 1024
+constexpr int kSvMaxN = 128;
+constexpr int kMaxSweeps = 30;
+constexpr double kJacobiTol = 1e-14;
+// columns whose weight is below this fraction of ||M||_F^2 are numerical zeros
+constexpr double kZeroWeight = 1e-28;
+constexpr double kDegenerateGap = 1e-10;
+
+enum SvMode { GATE_RIGHT = 0, GATE_LEFT = 1, MOVE_RIGHT = 2, MOVE_LEFT = 3 };
+enum GateOp { OP_RZ = 0, OP_RXX = 1, OP_SWAP = 2, OP_ID = 3 };
+
+struct SvParams {
+  double2 *f64;
+  int64_t mps_stride;
+  const int64_t *site_off;
+  const int32_t *pad;
+  int32_t *dims;
+  int32_t m;
+  int32_t p;
+  int32_t mode;
+  int32_t op;
+  int32_t fi, fj;
+  int32_t chi;
+  int32_t pad_unused;
+  double coef_xx;
+  double cutoff;
+  const double *X;
+  int64_t ldx;
+  double2 *scratch;  // per circuit 2 * kSvMaxN * kSvMaxN
+  double *disc;
+  double *maxdisc;
+  int32_t *degen;
+  int32_t *unconv;
+  int64_t n;
+};
+
+__device__ inline double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ inline double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+
+// P(s', t')[a][b] = sum_c A_p[s'][a][c] A_{p+1}[t'][c][b]
+__device__ inline double2 pair_prod(const double2 *Ap, const double2 *Aq, int Pp, int Pm, int Pn, int Dm,
+                                    int s1, int a, int t1, int b) {
+  double re = 0.0, im = 0.0;
+  const double2 *x = Ap + (size_t(s1) * Pp + a) * Pm;
+  const double2 *y = Aq + size_t(t1) * Pm * Pn + b;
+  for (int c = 0; c < Dm; ++c) {
+    const double2 u = x[c], v = y[size_t(c) * Pn];
+    re = fma(u.x, v.x, fma(-u.y, v.y, re));
+    im = fma(u.x, v.y, fma(u.y, v.x, im));
+  }
+  return make_double2(re, im);
+}
+
+// Two-site theta element for the gate of this step (identity for moves).
+__device__ inline double2 theta_elem(const SvParams &P, const double2 *Ap, const double2 *Aq, int Pp, int Pm,
+                                     int Pn, int Dm, double cg, double sg, int s, int a, int t, int b) {
+  if (P.op == OP_SWAP) return pair_prod(Ap, Aq, Pp, Pm, Pn, Dm, t, a, s, b);
+  if (P.op == OP_RXX) {
+    // Rxx = cos(phi/2) I - i sin(phi/2) X(x)X
+    const double2 d = pair_prod(Ap, Aq, Pp, Pm, Pn, Dm, s, a, t, b);
+    const double2 x = pair_prod(Ap, Aq, Pp, Pm, Pn, Dm, 1 - s, a, 1 - t, b);
+    return make_double2(cg * d.x + sg * x.y, cg * d.y - sg * x.x);
+  }
+  return pair_prod(Ap, Aq, Pp, Pm, Pn, Dm, s, a, t, b);
+}
+
+__global__ __launch_bounds__(kSvThreads) void svd_step_kernel(SvParams P) {
+  const int64_t ci = blockIdx.x;
+  if (ci >= P.n) return;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+
+  __shared__ double s_part[64][17][4];
+  __shared__ double s_par[64][4];
+  __shared__ double s_norm[kSvMaxN];
+  __shared__ double s_sorted[kSvMaxN];
+  __shared__ int s_rank[kSvMaxN];
+  __shared__ int s_flag[2];
+  __shared__ int s_k;
+  __shared__ double s_nrm;
+
+  int32_t *dims = P.dims + ci * (P.m + 1);
+  const int p = P.p;
+  const int Dp = dims[p], Dm = dims[p + 1], Dn = dims[p + 2];
+  const int Pp = P.pad[p], Pm = P.pad[p + 1], Pn = P.pad[p + 2];
+  double2 *Ap = P.f64 + ci * P.mps_stride + P.site_off[p];
+  double2 *Aq = P.f64 + ci * P.mps_stride + P.site_off[p + 1];
+  double2 *S = P.scratch + ci * (2 * kSvMaxN * kSvMaxN);
+
+  double cg = 1.0, sg = 0.0;
+  if (P.op == OP_RXX) {
+    const double xi = P.X[ci * P.ldx + P.fi], xj = P.X[ci * P.ldx + P.fj];
+    const double phi = P.coef_xx * (1.0 - xi) * (1.0 - xj);
+    sincos(0.5 * phi, &sg, &cg);
+  }
+
+  const bool right = (P.mode == GATE_RIGHT || P.mode == MOVE_RIGHT);
+  const bool gate = (P.mode == GATE_RIGHT || P.mode == GATE_LEFT);
+  // Jacobi matrix shape and projection-source width
+  int nr, nc, ncs;
+  if (P.mode == GATE_RIGHT) { nr = 2 * Dp; nc = 2 * Dn; ncs = nc; }
+  else if (P.mode == GATE_LEFT) { nr = 2 * Dn; nc = 2 * Dp; ncs = nc; }
+  else if (P.mode == MOVE_RIGHT) { nr = 2 * Dp; nc = Dm; ncs = 2 * Dn; }
+  else { nr = 2 * Dn; nc = Dm; ncs = 2 * Dp; }
+
+  // ---------------------------------------------------------- build M
+  // M (Jacobi matrix) goes to scratch region SM, the projection source to S;
+  // for gates they coincide.
+  double2 *SM = gate ? S : S + kSvMaxN * kSvMaxN;
+  for (int e = tid; e < nr * nc; e += kSvThreads) {
+    const int r = e / nc, c = e % nc;
+    double2 v;
+    if (P.mode == GATE_RIGHT)
+      v = theta_elem(P, Ap, Aq, Pp, Pm, Pn, Dm, cg, sg, r / Dp, r % Dp, c / Dn, c % Dn);
+    else if (P.mode == GATE_LEFT)
+      v = cconj(theta_elem(P, Ap, Aq, Pp, Pm, Pn, Dm, cg, sg, c / Dp, c % Dp, r / Dn, r % Dn));
+    else if (P.mode == MOVE_RIGHT)
+      v = Ap[(size_t(r / Dp) * Pp + r % Dp) * Pm + c];
+    else
+      v = cconj(Aq[(size_t(r / Dn) * Pm + c) * Pn + r % Dn]);
+    SM[r * kSvMaxN + c] = v;
+  }
+  if (!gate) {
+    // identity two-site theta (or its adjoint) as the projection source
+    for (int e = tid; e < nr * ncs; e += kSvThreads) {
+      const int y = e / ncs, x = e % ncs;
+      double2 v;
+      if (P.mode == MOVE_RIGHT)
+        v = pair_prod(Ap, Aq, Pp, Pm, Pn, Dm, y / Dp, y % Dp, x / Dn, x % Dn);
+      else
+        v = cconj(pair_prod(Ap, Aq, Pp, Pm, Pn, Dm, x / Dp, x % Dp, y / Dn, y % Dn));
+      S[y * kSvMaxN + x] = v;
+    }
+  }
+  __syncthreads();
+  double Ar[kSvRows], Ai[kSvRows], Br[kSvRows], Bi[kSvRows];
+#pragma unroll
+  for (int rr = 0; rr < kSvRows; ++rr) {
+    const int r = wave * kSvRows + rr;
+    const int c0 = 2 * lane, c1 = 2 * lane + 1;
+    const double2 va = (r < nr && c0 < nc) ? SM[r * kSvMaxN + c0] : make_double2(0.0, 0.0);
+    const double2 vb = (r < nr && c1 < nc) ? SM[r * kSvMaxN + c1] : make_double2(0.0, 0.0);
+    Ar[rr] = va.x;
+    Ai[rr] = va.y;
+    Br[rr] = vb.x;
+    Bi[rr] = vb.y;
+  }
+  if (tid == 0) {
+    s_flag[0] = 0;
+    s_flag[1] = 0;
+  }
+  // ||M||_F^2 (invariant under the rotations)
+  {
+    double w = 0.0;
+#pragma unroll
+    for (int rr = 0; rr < kSvRows; ++rr)
+      w = fma(Ar[rr], Ar[rr], fma(Ai[rr], Ai[rr], fma(Br[rr], Br[rr], fma(Bi[rr], Bi[rr], w))));
+    s_part[lane][wave][0] = w;
+    __syncthreads();
+    if (tid < 64) {
+      double t = 0.0;
+      for (int u = 0; u < kSvWaves; ++u) t += s_part[tid][u][0];
+      for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+      if (tid == 0) s_nrm = t;
+    }
+    __syncthreads();
+  }
+  const double zero_w = kZeroWeight * s_nrm;
+  __syncthreads();
+
+  // ---------------------------------------------------------- Jacobi sweeps
+  const int NP = (nc + (nc & 1)) < 2 ? 2 : (nc + (nc & 1));
+  const int H = NP / 2;
+  bool converged = false;
+  int sweep = 0;
+  for (; sweep < kMaxSweeps && !converged; ++sweep) {
+    for (int round = 0; round < NP - 1; ++round) {
+      double al = 0.0, be = 0.0, gr = 0.0, gi = 0.0;
+#pragma unroll
+      for (int rr = 0; rr < kSvRows; ++rr) {
+        al = fma(Ar[rr], Ar[rr], fma(Ai[rr], Ai[rr], al));
+        be = fma(Br[rr], Br[rr], fma(Bi[rr], Bi[rr], be));
+        gr = fma(Ar[rr], Br[rr], fma(Ai[rr], Bi[rr], gr));
+        gi = fma(Ar[rr], Bi[rr], fma(-Ai[rr], Br[rr], gi));
+      }
+      s_part[lane][wave][0] = al;
+      s_part[lane][wave][1] = be;
+      s_part[lane][wave][2] = gr;
+      s_part[lane][wave][3] = gi;
+      __syncthreads();
+      {
+        const int pr = tid >> 4, w = tid & 15;
+        double a = s_part[pr][w][0], b = s_part[pr][w][1], x = s_part[pr][w][2], y = s_part[pr][w][3];
+#pragma unroll
+        for (int o = 8; o > 0; o >>= 1) {
+          a += __shfl_xor(a, o, 16);
+          b += __shfl_xor(b, o, 16);
+          x += __shfl_xor(x, o, 16);
+          y += __shfl_xor(y, o, 16);
+        }
+        if (w == 0 && pr < H) {
+          double c = 1.0, s = 0.0, ur = 1.0, ui = 0.0;
+          const double gabs = sqrt(x * x + y * y);
+          if (a > zero_w && b > zero_w && gabs > kJacobiTol * sqrt(a) * sqrt(b)) {
+            const double zeta = (b - a) / (2.0 * gabs);
+            const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+            c = 1.0 / sqrt(1.0 + t * t);
+            s = c * t;
+            ur = x / gabs;   // u = conj(gamma) / |gamma|
+            ui = -y / gabs;
+            s_flag[sweep & 1] = 1;
+          }
+          s_par[pr][0] = c;
+          s_par[pr][1] = s;
+          s_par[pr][2] = ur;
+          s_par[pr][3] = ui;
+        }
+        if (round == 0 && tid == 0) s_flag[(sweep + 1) & 1] = 0;
+      }
+      __syncthreads();
+      if (round == NP - 2) converged = (s_flag[sweep & 1] == 0);
+      if (lane < H) {
+        const double c = s_par[lane][0], s = s_par[lane][1], ur = s_par[lane][2], ui = s_par[lane][3];
+#pragma unroll
+        for (int rr = 0; rr < kSvRows; ++rr) {
+          // uB = u * B ; A' = c A - s uB ; B' = s A + c uB
+          const double ubr = ur * Br[rr] - ui * Bi[rr];
+          const double ubi = ur * Bi[rr] + ui * Br[rr];
+          const double nar = c * Ar[rr] - s * ubr, nai = c * Ai[rr] - s * ubi;
+          const double nbr = s * Ar[rr] + c * ubr, nbi = s * Ai[rr] + c * ubi;
+          Ar[rr] = nar;
+          Ai[rr] = nai;
+          Br[rr] = nbr;
+          Bi[rr] = nbi;
+        }
+      }
+      // circle ordering: A_1 -> A_2 -> ... -> A_{H-1} -> B_{H-1} -> ... -> B_0 -> A_1
+      if (H > 1) {
+        const int srcA = lane > 0 ? lane - 1 : 0;
+        const int srcB = lane < 63 ? lane + 1 : 63;
+#pragma unroll
+        for (int rr = 0; rr < kSvRows; ++rr) {
+          const double pa_r = __shfl(Ar[rr], srcA), pa_i = __shfl(Ai[rr], srcA);
+          const double nb_r = __shfl(Br[rr], srcB), nb_i = __shfl(Bi[rr], srcB);
+          const double b0_r = __shfl(Br[rr], 0), b0_i = __shfl(Bi[rr], 0);
+          if (lane < H) {
+            const double oar = Ar[rr], oai = Ai[rr];
+            if (lane == 1) { Ar[rr] = b0_r; Ai[rr] = b0_i; }
+            else if (lane > 1) { Ar[rr] = pa_r; Ai[rr] = pa_i; }
+            if (lane == H - 1) { Br[rr] = oar; Bi[rr] = oai; }
+            else { Br[rr] = nb_r; Bi[rr] = nb_i; }
+          }
+        }
+      }
+    }
+  }
+
+  // ---------------------------------------------------------- norms, order, k
+  {
+    double na = 0.0, nb = 0.0;
+#pragma unroll
+    for (int rr = 0; rr < kSvRows; ++rr) {
+      na = fma(Ar[rr], Ar[rr], fma(Ai[rr], Ai[rr], na));
+      nb = fma(Br[rr], Br[rr], fma(Bi[rr], Bi[rr], nb));
+    }
+    s_part[lane][wave][0] = na;
+    s_part[lane][wave][1] = nb;
+    __syncthreads();
+    const int pr = tid >> 4, w = tid & 15;
+    double a = s_part[pr][w][0], b = s_part[pr][w][1];
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) {
+      a += __shfl_xor(a, o, 16);
+      b += __shfl_xor(b, o, 16);
+    }
+    if (w == 0) {
+      s_norm[2 * pr] = (2 * pr < NP) ? a : 0.0;
+      s_norm[2 * pr + 1] = (2 * pr + 1 < NP) ? b : 0.0;
+    }
+    __syncthreads();
+    if (tid < kSvMaxN) {
+      const double v = s_norm[tid];
+      int rank = 0;
+#pragma unroll 1
+      for (int u = 0; u < kSvMaxN; ++u) {
+        const double o = s_norm[u];
+        rank += (o > v || (o == v && u < tid)) ? 1 : 0;
+      }
+      s_rank[tid] = rank;
+      s_sorted[rank] = v;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      const int nsv = min(nr, nc);
+      int nnz = 0;
+#pragma unroll 1
+      for (int u = 0; u < kSvMaxN; ++u) nnz += s_sorted[u] > zero_w ? 1 : 0;
+      double total = 0.0;
+#pragma unroll 1
+      for (int u = kSvMaxN - 1; u >= 0; --u) total += s_sorted[u];
+      int k;
+      double disc = 0.0;
+      if (gate) {
+        int kcut = nsv;
+        if (P.cutoff > 0.0) {
+          // smallest k with sum_{r >= k} w_r <= cutoff * total
+          double tail = 0.0;
+          kcut = nsv;
+    #pragma unroll 1
+      for (int kk = nsv; kk >= 0; --kk) {
+            if (kk < nsv) tail += s_sorted[kk];
+            if (tail <= P.cutoff * total) kcut = kk;
+            else break;
+          }
+        }
+        k = max(1, min(min(P.chi, kcut), max(nnz, 1)));
+        double kept = 0.0;
+  #pragma unroll 1
+      for (int u = k - 1; u >= 0; --u) kept += s_sorted[u];
+        double tail = 0.0;
+  #pragma unroll 1
+      for (int u = kSvMaxN - 1; u >= k; --u) tail += s_sorted[u];
+        disc = total > 0.0 ? tail / total : 0.0;
+        s_nrm = kept > 0.0 ? 1.0 / sqrt(kept) : 1.0;
+        P.disc[ci] += disc;
+        P.maxdisc[ci] = fmax(P.maxdisc[ci], disc);
+        if (k < nsv && s_sorted[0] > 0.0 &&
+            (sqrt(s_sorted[k - 1]) - sqrt(s_sorted[k])) / sqrt(s_sorted[0]) < kDegenerateGap)
+          P.degen[ci] += 1;
+      } else {
+        k = max(1, min(nsv, max(nnz, 1)));
+        s_nrm = 1.0;
+      }
+      if (!converged) P.unconv[ci] += 1;
+      s_k = k;
+    }
+    __syncthreads();
+  }
+  const int k = s_k;
+  const double nrm = s_nrm;
+
+  // ---------------------------------------------------------- write factors
+  // zero both site tensors (padded blocks), then the isometric factor
+  for (int e = tid; e < 2 * Pp * Pm; e += kSvThreads) Ap[e] = make_double2(0.0, 0.0);
+  for (int e = tid; e < 2 * Pm * Pn; e += kSvThreads) Aq[e] = make_double2(0.0, 0.0);
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int pos = 2 * lane + q;
+    const int j = s_rank[pos];
+    if (pos < NP && j < k) {
+      const double inv = 1.0 / sqrt(s_norm[pos]);
+#pragma unroll
+      for (int rr = 0; rr < kSvRows; ++rr) {
+        const int r = wave * kSvRows + rr;
+        if (r < nr) {
+          const double vr = (q == 0 ? Ar[rr] : Br[rr]) * inv;
+          const double vi = (q == 0 ? Ai[rr] : Bi[rr]) * inv;
+          if (right) Ap[(size_t(r / Dp) * Pp + r % Dp) * Pm + j] = make_double2(vr, vi);
+          else Aq[(size_t(r / Dn) * Pm + j) * Pn + r % Dn] = make_double2(vr, -vi);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // projection: out[j][x] = sum_y conj(U[y][j]) S[y][x]
+  {
+    const int x = tid & 127, jg = tid >> 7;
+    if (x < ncs) {
+      double2 acc[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc[u] = make_double2(0.0, 0.0);
+      for (int y = 0; y < nr; ++y) {
+        const double2 sv = S[y * kSvMaxN + x];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int j = jg + 8 * u;
+          if (j < k) {
+            double2 uv;
+            if (right) uv = Ap[(size_t(y / Dp) * Pp + y % Dp) * Pm + j];
+            else uv = cconj(Aq[(size_t(y / Dn) * Pm + j) * Pn + y % Dn]);
+            // conj(uv) * sv
+            acc[u].x = fma(uv.x, sv.x, fma(uv.y, sv.y, acc[u].x));
+            acc[u].y = fma(uv.x, sv.y, fma(-uv.y, sv.x, acc[u].y));
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int j = jg + 8 * u;
+        if (j < k) {
+          if (right) {
+            Aq[(size_t(x / Dn) * Pm + j) * Pn + x % Dn] = make_double2(nrm * acc[u].x, nrm * acc[u].y);
+          } else {
+            Ap[(size_t(x / Dp) * Pp + x % Dp) * Pm + j] = make_double2(nrm * acc[u].x, -nrm * acc[u].y);
+          }
+        }
+      }
+    }
+  }
+  if (tid == 0) dims[p + 1] = k;
+}
+
+// Rz on a run of gate records (Fig. 1a): A[site][s] *= exp(-/+ i theta / 2).
+__global__ void rz_kernel(double2 *f64, int64_t mps_stride, const int64_t *site_off, const int32_t *pad,
+                          const qk_gate *recs, int n_recs, const double *X, int64_t ldx, double coef_z,
+                          int64_t n) {
+  const int64_t ci = blockIdx.x;
+  const int r = blockIdx.y;
+  if (ci >= n || r >= n_recs) return;
+  const qk_gate g = recs[r];
+  const double th = coef_z * X[ci * ldx + g.feat_i];
+  double sn, cs;
+  sincos(0.5 * th, &sn, &cs);
+  const int pl = pad[g.site], pr = pad[g.site + 1];
+  double2 *A = f64 + ci * mps_stride + site_off[g.site];
+  const int half = pl * pr;
+  for (int e = threadIdx.x; e < 2 * half; e += blockDim.x) {
+    const double2 v = A[e];
+    const double ph = e < half ? -sn : sn;  // s = 0: exp(-i th/2), s = 1: exp(+i th/2)
+    A[e] = make_double2(cs * v.x - ph * v.y, cs * v.y + ph * v.x);
+  }
+}
+
+__global__ void init_plus_kernel(double2 *f64, int64_t mps_stride, const int64_t *site_off, const int32_t *pad,
+                                 int32_t *dims, int32_t m, int64_t n) {
+  const int64_t ci = blockIdx.x;
+  if (ci >= n) return;
+  const double h = 0.70710678118654752440;
+  for (int l = threadIdx.x; l <= m; l += blockDim.x) {
+    dims[ci * (m + 1) + l] = 1;
+    if (l < m) {
+      double2 *A = f64 + ci * mps_stride + site_off[l];
+      A[0] = make_double2(h, 0.0);                                  // s = 0, a = 0, b = 0
+      A[size_t(pad[l]) * pad[l + 1]] = make_double2(h, 0.0);        // s = 1
+    }
+  }
+}
+
+__global__ void normalize_last_kernel(double2 *f64, int64_t mps_stride, const int64_t *site_off,
+                                      const int32_t *pad, int32_t m, int64_t n) {
+  const int64_t ci = blockIdx.x;
+  if (ci >= n) return;
+  __shared__ double s_red[256];
+  double2 *A = f64 + ci * mps_stride + site_off[m - 1];
+  const int cnt = 2 * pad[m - 1] * pad[m];
+  double acc = 0.0;
+  for (int e = threadIdx.x; e < cnt; e += blockDim.x) acc = fma(A[e].x, A[e].x, fma(A[e].y, A[e].y, acc));
+  s_red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (int(threadIdx.x) < o) s_red[threadIdx.x] += s_red[threadIdx.x + o];
+    __syncthreads();
+  }
+  const double nrm = s_red[0];
+  if (nrm <= 0.0) return;
+  const double inv = 1.0 / sqrt(nrm);
+  for (int e = threadIdx.x; e < cnt; e += blockDim.x) A[e] = make_double2(A[e].x * inv, A[e].y * inv);
+}
+
+}  // namespace
+
+qk_status run_simulation(qk_mps_batch *b, const double *features_dev, const std::vector<qk_gate> &gates,
+                         const qk_circuit_spec &spec, int chi, double cutoff, hipStream_t stream) {
+  const int64_t n = b->n;
+  const int m = b->m;
+  int n2q = 0;
+  for (const auto &g : gates) n2q += g.op != OP_RZ ? 1 : 0;
+  b->n_two_qubit_gates = n2q;
+  if (n == 0) return QK_OK;
+  if (n > 0x7fffffff) return fail(QK_EINVAL, "too many points for one launch");
+
+  // reject non-finite features before any launch
+  {
+    std::vector<double> xh(size_t(n) * m);
+    QK_HIP_CHECK(hipMemcpyAsync(xh.data(), features_dev, sizeof(double) * xh.size(), hipMemcpyDeviceToHost, stream));
+    QK_HIP_CHECK(hipStreamSynchronize(stream));
+    for (double v : xh)
+      if (!std::isfinite(v)) return fail(QK_EINVAL, "non-finite feature value");
+  }
+
+  qk_gate *recs_dev = nullptr;
+  double2 *scratch = nullptr;
+  const size_t rec_bytes = sizeof(qk_gate) * std::max<size_t>(gates.size(), 1);
+  QK_HIP_CHECK(hipMallocAsync(reinterpret_cast<void **>(&recs_dev), rec_bytes, stream));
+  if (hipMallocAsync(reinterpret_cast<void **>(&scratch), sizeof(double2) * 2 * kSvMaxN * kSvMaxN * size_t(n), stream) !=
+      hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipFreeAsync(recs_dev, stream);
+    return fail(QK_ENOMEM, "device allocation of SVD scratch failed");
+  }
+  if (!gates.empty())
+    QK_HIP_CHECK(hipMemcpyAsync(recs_dev, gates.data(), sizeof(qk_gate) * gates.size(), hipMemcpyHostToDevice, stream));
+
+  hipLaunchKernelGGL(init_plus_kernel, dim3(unsigned(n)), dim3(64), 0, stream, b->f64, b->mps_stride, b->site_off_dev,
+                     b->pad_dev, b->dims_dev, m, n);
+  QK_HIP_CHECK(hipGetLastError());
+
+  SvParams P{};
+  P.f64 = b->f64;
+  P.mps_stride = b->mps_stride;
+  P.site_off = b->site_off_dev;
+  P.pad = b->pad_dev;
+  P.dims = b->dims_dev;
+  P.m = m;
+  P.chi = chi;
+  P.coef_xx = spec.coef_xx;
+  P.cutoff = cutoff;
+  P.X = features_dev;
+  P.ldx = m;
+  P.scratch = scratch;
+  P.disc = b->disc_dev;
+  P.maxdisc = b->maxdisc_dev;
+  P.degen = b->degen_dev;
+  P.unconv = b->unconv_dev;
+  P.n = n;
+
+  auto launch_step = [&](int p, int mode, int op, int fi, int fj) -> qk_status {
+    SvParams q = P;
+    q.p = p;
+    q.mode = mode;
+    q.op = op;
+    q.fi = fi;
+    q.fj = fj;
+    hipLaunchKernelGGL(svd_step_kernel, dim3(unsigned(n)), dim3(kSvThreads), 0, stream, q);
+    QK_HIP_CHECK(hipGetLastError());
+    return QK_OK;
+  };
+
+  // next two-qubit gate position after each gate
+  std::vector<int> next2q(gates.size(), -1);
+  {
+    int nxt = -1;
+    for (int gi = int(gates.size()) - 1; gi >= 0; --gi) {
+      next2q[gi] = nxt;
+      if (gates[gi].op != OP_RZ) nxt = gates[gi].site;
+    }
+  }
+  int center = 0;
+  qk_status st = QK_OK;
+  size_t gi = 0;
+  while (gi < gates.size() && st == QK_OK) {
+    const qk_gate &g = gates[gi];
+    if (g.op == OP_RZ) {
+      size_t ge = gi;
+      while (ge < gates.size() && gates[ge].op == OP_RZ) ++ge;
+      hipLaunchKernelGGL(rz_kernel, dim3(unsigned(n), unsigned(ge - gi)), dim3(256), 0, stream, b->f64, b->mps_stride,
+                         b->site_off_dev, b->pad_dev, recs_dev + gi, int(ge - gi), features_dev, int64_t(m),
+                         spec.coef_z, n);
+      if (hipGetLastError() != hipSuccess) st = fail(QK_EDEVICE, "Rz launch failed");
+      gi = ge;
+      continue;
+    }
+    const int p = g.site;
+    while (st == QK_OK && center < p) {
+      st = launch_step(center, MOVE_RIGHT, OP_ID, -1, -1);
+      ++center;
+    }
+    while (st == QK_OK && center > p + 1) {
+      st = launch_step(center - 1, MOVE_LEFT, OP_ID, -1, -1);
+      --center;
+    }
+    if (st != QK_OK) break;
+    const int nx = next2q[gi];
+    const bool absorb_right = nx < 0 || nx > p;
+    st = launch_step(p, absorb_right ? GATE_RIGHT : GATE_LEFT, g.op == 1 ? OP_RXX : OP_SWAP, g.feat_i, g.feat_j);
+    center = absorb_right ? p + 1 : p;
+    ++gi;
+  }
+  while (st == QK_OK && center < m - 1) {
+    st = launch_step(center, MOVE_RIGHT, OP_ID, -1, -1);
+    ++center;
+  }
+  if (st == QK_OK) {
+    hipLaunchKernelGGL(normalize_last_kernel, dim3(unsigned(n)), dim3(256), 0, stream, b->f64, b->mps_stride,
+                       b->site_off_dev, b->pad_dev, m, n);
+    if (hipGetLastError() != hipSuccess) st = fail(QK_EDEVICE, "normalisation launch failed");
+  }
+  (void)hipFreeAsync(scratch, stream);
+  (void)hipFreeAsync(recs_dev, stream);
+  if (st != QK_OK) return st;
+  QK_HIP_CHECK(hipStreamSynchronize(stream));
+  return QK_OK;
+}
+
+}  // namespace qk

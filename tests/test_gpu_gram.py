@@ -1,0 +1,117 @@
+"""GPU Gram kernels vs the CPU FP64 oracle, on oracle-simulated MPS.
+
+The MPS are produced by the oracle, uploaded through mps_batch_import, and
+K is computed on the GPU in FP64, FP32 and split-BF16; the oracle computes
+K from the same tensors.  Tolerances: FP64 1e-12 (rounding of ~m * chi^3
+operations in FP64); FP32 1e-5 and split-BF16 1e-5 here (the full-scale
+target for split-BF16 is |dK| <= 1e-6 against FP64, checked in the bench).
+"""
+import numpy as np
+import pytest
+
+import synthdata as sd
+from oracle import gram as ogram
+from oracle import mps as omps
+from tests.gpu_util import require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _oracle_batch(w, n, chi=None, extra_dup=0):
+    X = sd.workload_features(w, n)
+    if extra_dup:
+        X = np.vstack([X, sd.perturb_near_duplicates(X[:extra_dup])])
+    return [omps.simulate(x, w.distance, w.reps, chi or w.chi, w.cutoff, w.coef_z, w.coef_xx).tensors for x in X]
+
+
+@pytest.fixture(scope="module")
+def small_sets():
+    torch = require_gpu()
+    tiny = _oracle_batch(sd.WORKLOADS["tiny"], 20)
+    mid = _oracle_batch(sd.WORKLOADS["fp32"], 10, chi=32, extra_dup=4)
+    return tiny, mid
+
+
+@pytest.mark.parametrize("which", [0, 1])
+def test_gram_fp64_matches_oracle(small_sets, which):
+    import paper_2411_09336_amd as q
+    mpss = small_sets[which]
+    K_ref = ogram.gram(mpss)
+    b = q.import_batch(mpss)
+    K = q.gram(b, precision="fp64").cpu().numpy()
+    print("fp64 max|dK|", np.abs(K - K_ref).max())
+    assert np.abs(K - K_ref).max() < 1e-12
+    assert np.allclose(np.diag(K), 1.0, atol=1e-12)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 2e-5), ("split_bf16", 1e-7)])
+def test_gram_reduced_precision(small_sets, prec, tol):
+    """FP32: plain complex64 operands and FP32 accumulation (error grows with
+    chain length; 2e-5 bounds 50 sites).  Split-BF16: fixed-point slices with
+    an exact leading-slice accumulator, ~1e-8 at 100 sites."""
+    import paper_2411_09336_amd as q
+    for mpss in small_sets:
+        K_ref = ogram.gram(mpss)
+        b = q.import_batch(mpss)
+        K = q.gram(b, precision=prec).cpu().numpy()
+        d = np.abs(K - K_ref)
+        print(prec, "max|dK|", d.max(), "mean", d.mean())
+        assert d.max() < tol
+
+
+def test_gram_rectangular_and_blocks(small_sets):
+    import paper_2411_09336_amd as q
+    import torch
+    mpss = small_sets[1]
+    a = q.import_batch(mpss[:5])
+    b = q.import_batch(mpss[5:])
+    K_ref = ogram.gram(mpss[:5], mpss[5:])
+    K = q.gram(a, b, precision="fp64").cpu().numpy()
+    assert np.abs(K - K_ref).max() < 1e-12
+    full = q.import_batch(mpss)
+    n = len(mpss)
+    Kf = ogram.gram(mpss)
+    # a slab of rows with the upper-triangle filter
+    out = torch.full((4, n), -1.0, dtype=torch.float64, device="cuda")
+    q.gram_block(full, 3, 4, full, 0, n, precision="fp64", upper_only=True, out=out)
+    o = out.cpu().numpy()
+    for r in range(4):
+        for c in range(n):
+            gi = 3 + r
+            if c >= gi or 3 <= c < 3 + 4:
+                # contracted (j >= i) or mirrored from inside the block
+                assert abs(o[r, c] - Kf[gi, c]) < 1e-12
+            else:
+                assert o[r, c] == -1.0
+
+
+def test_gauge_invariance_fp64():
+    """Inserting U U^H on every bond of the ket leaves <a|b> unchanged."""
+    import paper_2411_09336_amd as q
+    require_gpu()
+    rng = np.random.default_rng(3)
+    mpss = _oracle_batch(sd.WORKLOADS["fp32"], 3, chi=32)
+    b = mpss[1]
+    g = []
+    Us = [np.eye(1)]
+    for l in range(len(b) - 1):
+        D = b[l].shape[2]
+        z = rng.standard_normal((D, D)) + 1j * rng.standard_normal((D, D))
+        u, _ = np.linalg.qr(z)
+        Us.append(u)
+    Us.append(np.eye(1))
+    for l, t in enumerate(b):
+        g.append(np.einsum("ab,bsc,cd->asd", Us[l].conj().T, t, Us[l + 1]))
+    batch = q.import_batch([mpss[0], b, g])
+    K = q.gram(batch, precision="fp64").cpu().numpy()
+    assert abs(K[0, 1] - K[0, 2]) < 1e-12
+    assert abs(K[1, 2] - 1.0) < 1e-12
+
+
+def test_gram_deterministic(small_sets):
+    import paper_2411_09336_amd as q
+    b = q.import_batch(small_sets[1])
+    for prec in ("fp64", "split_bf16"):
+        k1 = q.gram(b, precision=prec).cpu().numpy()
+        k2 = q.gram(b, precision=prec).cpu().numpy()
+        assert (k1 == k2).all()

@@ -1,0 +1,87 @@
+"""GPU MPS simulation vs the oracle.
+
+Untruncated (tiny workload): the GPU states must equal the statevector of
+the circuit (fidelity 1 - 1e-12) and K must match to 1e-12.
+Truncated: per-circuit fidelity between the GPU MPS and the oracle MPS must
+be >= 1 - 1e-10 for circuits with no near-degenerate cut, bond dimensions
+must agree, and the discarded weights must agree to 1e-9 relative.
+"""
+import numpy as np
+import pytest
+
+import synthdata as sd
+from oracle import gram as ogram
+from oracle import mps as omps
+from oracle import statevector as sv
+from tests.gpu_util import fidelity, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _sim(X, w, chi=None, routing=0):
+    import paper_2411_09336_amd as q
+    torch = require_gpu()
+    xt = torch.tensor(X, dtype=torch.float64, device="cuda")
+    spec = q.CircuitSpec(X.shape[1], w.distance, w.reps, w.coef_z, w.coef_xx, routing)
+    return q.simulate(xt, spec, chi or w.chi, w.cutoff)
+
+
+def test_tiny_untruncated_vs_statevector():
+    import paper_2411_09336_amd as q
+    w = sd.WORKLOADS["tiny"]
+    X = sd.workload_features(w)
+    b = _sim(X, w)
+    inf = b.info()
+    assert inf["unconverged_svds"] == 0
+    for i in range(0, 64, 7):
+        psi = omps.to_statevector(b.export(i))
+        ref = sv.state_logical(X[i], w.distance, w.reps, w.coef_z, w.coef_xx)
+        assert abs(abs(np.vdot(psi, ref)) ** 2 - 1) < 1e-12
+    K = q.gram(b, precision="fp64").cpu().numpy()
+    states = np.array([sv.state_logical(x, w.distance, w.reps, w.coef_z, w.coef_xx) for x in X])
+    K_sv = sv.gram_from_states(states)
+    print("max|dK| vs statevector", np.abs(K - K_sv).max())
+    assert np.abs(K - K_sv).max() < 1e-12
+
+
+@pytest.mark.parametrize("m,d,reps", [(10, 3, 2), (9, 5, 1)])
+def test_small_circuits_vs_statevector(m, d, reps):
+    w = sd.Workload("t", 6, m, d, reps, 64, 0.0)
+    X = sd.make_uniform(6, m, seed=m + d)
+    for routing in (0, 1):
+        b = _sim(X, w, routing=routing)
+        for i in range(len(X)):
+            psi = omps.to_statevector(b.export(i))
+            ref = sv.state_logical(X[i], d, reps, 2.0, 2.0)
+            assert abs(abs(np.vdot(psi, ref)) ** 2 - 1) < 1e-12
+
+
+@pytest.mark.parametrize("name,n,chi", [("fp32", 6, 32), ("precision", 3, 16)])
+def test_truncated_vs_oracle(name, n, chi):
+    w = sd.WORKLOADS[name]
+    X = sd.workload_features(w, n)
+    b = _sim(X, w, chi=chi)
+    dims = b.bond_dims()
+    disc, deg = b.trunc_stats()
+    for i in range(n):
+        r = omps.simulate(X[i], w.distance, w.reps, chi, w.cutoff, w.coef_z, w.coef_xx)
+        g = b.export(i)
+        f = fidelity(g, r.tensors)
+        print(name, i, "fidelity", f, "bonds equal", list(dims[i]) == r.bond_dims, "disc", disc[i], r.discarded)
+        if r.degenerate_cuts == 0 and deg[i] == 0:
+            assert f > 1 - 1e-10
+            assert list(dims[i]) == r.bond_dims
+            assert abs(disc[i] - r.discarded) <= 1e-9 * max(1.0, r.discarded)
+
+
+def test_simulated_gram_invariants():
+    import paper_2411_09336_amd as q
+    w = sd.WORKLOADS["fp32"]
+    X = sd.workload_features(w, 24)
+    X = np.vstack([X, sd.perturb_near_duplicates(X[:8])])
+    b = _sim(X, w)
+    K = q.gram(b, precision="fp64").cpu().numpy()
+    assert np.allclose(np.diag(K), 1.0, atol=1e-12)
+    assert np.array_equal(K, K.T)
+    assert K.min() >= 0 and K.max() <= 1 + 1e-12
+    assert np.linalg.eigvalsh(K).min() > -1e-10
