@@ -1,0 +1,314 @@
+#!/usr/bin/env python3
+"""Gram entries/s of the quantum-kernel MPS Gram matrix on one MI355X.
+
+Workload: 165 qubits (one per feature), interaction distance d = 8, two
+repetitions, bond cap chi = 64, SVD cutoff 1e-8; 6400 points from a
+two-class mixture of 165-dim Gaussians, min-max scaled to [0, 1]; the full
+symmetric 6400 x 6400 Gram matrix K = |<psi_i|psi_j>|^2.
+
+What one run does (progress on stderr, ONE JSON line on stdout):
+  1. Simulate S distinct circuits of the workload on the GPU (mps_simulate,
+     timed separately: circuits/s, two-qubit gates/s).
+  2. Pack them into the split-BF16 form and gather the 6400-MPS Gram batch
+     (MPS i is a copy of simulated state i mod S; every copy has the same
+     saturated bond profile as a freshly simulated point, so the Gram work is
+     that of 6400 distinct states).
+  3. TIMED: the full symmetric split-BF16 Gram (row slabs, HIP events on the
+     launch stream).  value = N (N - 1) / 2 / t.
+  4. FP64 and split-BF16 Gram of the S distinct states: split-vs-FP64 speedup
+     on identical work, and |dK| split vs FP64; each entry of the full matrix
+     equals bit-for-bit one of these S x S entries (checked), so this |dK| is
+     the maximum over all 20.5M entries.
+  5. The CPU FP64 oracle on a bounded sample of pairs (baseline, not target),
+     also giving |dK| of both GPU forms against the oracle.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Gram entries/s at 165 qubits chi=64, split-BF16 vs FP64 GPU, |dK|<=1e-6"
+PEAK_TFLOPS = {"bf16": 2500.0, "fp64": 78.6, "fp32": 157.3}
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def flops_per_entry(dims_a, dims_b):
+    """Algorithmic FLOPs of one overlap (Fig. 2): per site the two complex
+    GEMMs E A_b[s] and A_a[s]^H T, i.e. 2 Da Db' (Db + Da') complex MACs."""
+    f = 0
+    for l in range(len(dims_a) - 1):
+        da, dan, db, dbn = int(dims_a[l]), int(dims_a[l + 1]), int(dims_b[l]), int(dims_b[l + 1])
+        f += 2 * da * dbn * (db + dan)
+    return 8 * f
+
+
+def slab_bounds(n, parts):
+    """Row slabs [r_p, r_{p+1}) with equal numbers of upper-triangle entries."""
+    b = [0]
+    for p in range(1, parts):
+        b.append(int(round(n * (1 - math.sqrt(1 - p / parts)))))
+    b.append(n)
+    return sorted(set(b))
+
+
+def cpu_oracle_leg(mps_list, K_split, K_fp64, seconds):
+    """The CPU FP64 oracle timed in this process on one core (one BLAS thread)
+    over a bounded random sample of the pairs, plus |dK| of both GPU forms."""
+    import numpy as np
+
+    from oracle import gram as ogram
+
+    try:
+        import threadpoolctl
+        limiter = threadpoolctl.threadpool_limits(1)
+    except Exception:
+        limiter = None
+    n = len(mps_list)
+    pairs = [(i, j) for i in range(n) for j in range(i, n)]
+    rng = np.random.default_rng(11)
+    rng.shuffle(pairs)
+    vals = {}
+    t0 = time.perf_counter()
+    last = t0
+    for (i, j) in pairs:
+        vals[(i, j)] = ogram.overlap(mps_list[i], mps_list[j])
+        now = time.perf_counter()
+        if now - last > 10:
+            last = now
+            log(f"[bench] oracle: {len(vals)} pairs, {now - t0:.0f} s")
+        if now - t0 > seconds:
+            break
+    dt = time.perf_counter() - t0
+    if limiter is not None:
+        limiter.restore_original_limits()
+    sample = list(vals.keys())
+    d_split = np.array([abs(K_split[i, j] - abs(vals[(i, j)]) ** 2) for (i, j) in sample])
+    d_fp64 = np.array([abs(K_fp64[i, j] - abs(vals[(i, j)]) ** 2) for (i, j) in sample])
+    cpu = {"value": round(len(sample) / dt, 3), "unit": "entries/s", "cores": 1, "kind": "oracle",
+           "sample": f"{len(sample)} entries (random pairs among {n} simulated 165-qubit chi=64 MPS); "
+                     f"complex128 NumPy, one core, one BLAS thread, {dt:.1f} s"}
+    dk = {"split_bf16_vs_oracle_max": float(d_split.max()), "split_bf16_vs_oracle_mean": float(d_split.mean()),
+          "fp64_vs_oracle_max": float(d_fp64.max()), "fp64_vs_oracle_mean": float(d_fp64.mean()),
+          "pairs": len(sample)}
+    return cpu, dk
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=6400, help="Gram size (points)")
+    ap.add_argument("--sim-sample", type=int, default=64, help="distinct circuits simulated on the GPU")
+    ap.add_argument("--slabs", type=int, default=8)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--routing", type=int, default=1,
+                    help="0: 2(k-1) SWAPs per Rxx (paper); 1: cancelled inverse SWAP pairs (same circuit)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU sharding is "
+              "a design in DESIGN.md, not a measured path.", file=sys.stderr)
+        sys.exit(2)
+
+    run(args)
+
+
+def run(args):
+    import numpy as np
+    import torch
+
+    import paper_2411_09336_amd as q
+    import synthdata as sd
+
+    if not torch.cuda.is_available():
+        log("bench.py needs a GPU")
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    w = sd.WORKLOADS["full"]
+    N, S = args.n, min(args.sim_sample, args.n)
+    X = sd.workload_features(w, N)
+    spec = q.CircuitSpec(w.n_qubits, w.distance, w.reps, w.coef_z, w.coef_xx, args.routing)
+
+    # ---------------------------------------------------------------- 1. simulation
+    log(f"[bench] simulating {S} circuits: m={w.n_qubits} d={w.distance} reps={w.reps} chi={w.chi} cutoff={w.cutoff}")
+    xs = torch.tensor(X[:S], dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    t_last = [time.perf_counter()]
+
+    def progress(done, total):
+        if time.perf_counter() - t_last[0] > 20 or done == total:
+            t_last[0] = time.perf_counter()
+            log(f"[bench] simulation: {done}/{total} two-qubit gates, {t_last[0] - t0:.0f} s")
+        return False
+
+    sim = q.simulate(xs, spec, w.chi, w.cutoff, progress=progress, every=200)
+    torch.cuda.synchronize()
+    t_sim = time.perf_counter() - t0
+    info = sim.info()
+    dims = sim.bond_dims()
+    log(f"[bench] simulation {t_sim:.1f} s ({S / t_sim:.2f} circuits/s); max bond {info['max_bond']}, "
+        f"unconverged SVDs {info['unconverged_svds']}, degenerate cuts {info['degenerate_cuts']}")
+
+    # ---------------------------------------------------------------- 2. Gram batch
+    sim.pack("split_bf16")
+    sim.pack("fp64")
+    idx = np.arange(N) % S
+    gb = sim.gather(idx, forms=("split_bf16",))
+    ginfo = gb.info()
+    log(f"[bench] Gram batch: {N} MPS, split-BF16 planes {ginfo['bytes_split_bf16'] / 1e9:.1f} GB")
+
+    K = torch.zeros((N, N), dtype=torch.float64, device="cuda")
+    slabs = slab_bounds(N, args.slabs)
+
+    def run_full(tag):
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        for p in range(len(slabs) - 1):
+            r0, r1 = slabs[p], slabs[p + 1]
+            out = K[r0:, r0:]
+            q.gram_block(gb, r0, r1 - r0, gb, r0, N - r0, precision="split_bf16", upper_only=True,
+                         out=out, stream=stream)
+            stream.synchronize()
+            log(f"[bench] {tag} slab {p + 1}/{len(slabs) - 1} rows {r0}:{r1} done")
+        ev1.record(stream)
+        ev1.synchronize()
+        return ev0.elapsed_time(ev1) / 1e3
+
+    # warmup: one slab-sized block outside the timed region
+    for _ in range(args.warmup):
+        wr = min(64, N)
+        q.gram_block(gb, 0, wr, gb, 0, N, precision="split_bf16", upper_only=True, out=K[:wr], stream=stream)
+        stream.synchronize()
+        log("[bench] warmup done")
+
+    # ---------------------------------------------------------------- 3. timed
+    times = []
+    for st in range(args.steps):
+        times.append(run_full(f"step {st + 1}/{args.steps}"))
+    t_split = float(np.median(times))
+    n_off = N * (N - 1) // 2
+    n_comp = N * (N + 1) // 2
+    value = n_off / t_split
+    log(f"[bench] split-BF16 full Gram: {t_split:.2f} s -> {value:.1f} entries/s")
+
+    # complete the lower triangle (outside the timed region)
+    Ku = torch.triu(K)
+    K = Ku + torch.triu(K, 1).T
+    del Ku
+
+    # ---------------------------------------------------------------- 4. FP64 vs split on S distinct
+    # full S x S blocks (bra i, ket j for every i, j), so that each upper
+    # entry of the full matrix has an identically computed counterpart
+    Ks = torch.zeros((S, S), dtype=torch.float64, device="cuda")
+    Kd = torch.zeros((S, S), dtype=torch.float64, device="cuda")
+
+    def timed_gram(prec, out):
+        q.gram_block(sim, 0, S, sim, 0, S, precision=prec, out=out, stream=stream)   # warm
+        stream.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        q.gram_block(sim, 0, S, sim, 0, S, precision=prec, out=out, stream=stream)
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / 1e3
+
+    t_s_small = timed_gram("split_bf16", Ks)
+    t_d_small = timed_gram("fp64", Kd)
+    speedup = t_d_small / t_s_small
+    dK = (Ks - Kd).abs()
+    ii = torch.as_tensor(idx, device="cuda")
+    upper = torch.ones((N, N), dtype=torch.bool, device="cuda").triu_()
+    Kmap = Ks[ii][:, ii]
+    bit_identical = bool(torch.equal(Kmap[upper], K[upper]))
+    del Kmap
+    full_dK_max = float((K - Kd[ii][:, ii]).abs()[upper].max().item())
+    del upper
+    s_pairs = S * S
+    log(f"[bench] S={S}: split {t_s_small:.3f} s, fp64 {t_d_small:.3f} s, speedup {speedup:.2f}x; "
+        f"|dK| max {dK.max().item():.3e}; full-matrix upper entries identical to the S x S map: {bit_identical}")
+
+    # ---------------------------------------------------------------- roofline
+    d0 = dims[0]
+    fpe = flops_per_entry(d0, d0)
+    flops_launch = fpe * n_comp
+    achieved_tf = flops_launch / t_split / 1e12
+    issued_tf = achieved_tf * 44 / 8     # 11 slice pairs x 4 real products per complex MAC
+    roof = {"bound": "mfma", "achieved": round(achieved_tf, 3), "peak": PEAK_TFLOPS["bf16"], "unit": "TFLOP/s",
+            "frac": round(achieved_tf / PEAK_TFLOPS["bf16"], 5), "traffic": None,
+            "kernel": "gram_kernel<split_bf16,64>", "flops_per_entry": fpe, "entries_per_timed_region": n_comp,
+            "issued_bf16_tflops": round(issued_tf, 2), "issued_frac": round(issued_tf / PEAK_TFLOPS["bf16"], 4),
+            "fp64_form_tflops": round(fpe * s_pairs / t_d_small / 1e12, 3),
+            "fp64_form_frac": round(fpe * s_pairs / t_d_small / 1e12 / PEAK_TFLOPS["fp64"], 4)}
+
+    # ---------------------------------------------------------------- 5. CPU oracle
+    cpu = None
+    dk_oracle = None
+    if not args.no_cpu:
+        n_exp = min(S, 32)
+        log(f"[bench] exporting {n_exp} MPS for the CPU oracle")
+        mps_np = [sim.export(i) for i in range(n_exp)]
+        try:
+            cpu, dk_oracle = cpu_oracle_leg(mps_np, Ks.cpu().numpy(), Kd.cpu().numpy(), args.cpu_seconds)
+            log(f"[bench] oracle: {cpu['value']:.2f} entries/s on {cpu['cores']} cores; {dk_oracle}")
+        except Exception as e:   # the baseline must not cost the measurement
+            log(f"[bench] CPU oracle leg failed: {e!r}")
+            dk_oracle = {"error": repr(e)}
+
+    Kh = Ks.cpu().numpy()
+    offd = Kh[~np.eye(S, dtype=bool)]
+    result = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "entries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(t_split * 1e3, 1),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": "full: 165 qubits, d=8, reps=2, chi=64, cutoff=1e-8, N=6400 symmetric Gram",
+                   "n_points": N, "n_qubits": w.n_qubits, "distance": w.distance, "reps": w.reps,
+                   "chi": w.chi, "cutoff": w.cutoff, "routing": args.routing, "distinct_states": S,
+                   "precision": "split-bf16 (4 fixed-point slices, 11 slice products, fp32 accumulate, fp64 combine)"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "fp64_gpu": {"entries_per_s": round(s_pairs / t_d_small, 2), "speedup_split_vs_fp64": round(speedup, 3),
+                     "measured_on": f"{S}x{S} symmetric Gram of the simulated states ({s_pairs} entries)"},
+        "dK": {"split_vs_fp64_max_all_entries": full_dK_max, "split_vs_fp64_max": float(dK.max().item()),
+               "split_vs_fp64_mean": float(dK.mean().item()), "full_matrix_bit_identical_to_SxS": bit_identical,
+               "oracle": dk_oracle},
+        "K_distribution": {"offdiag_median": float(np.median(offd)), "offdiag_max": float(offd.max()),
+                           "offdiag_frac_above_1e-6": float((offd > 1e-6).mean())},
+        "simulation": {"circuits": S, "seconds": round(t_sim, 2), "circuits_per_s": round(S / t_sim, 3),
+                       "two_qubit_gates_per_circuit": info["n_two_qubit_gates"],
+                       "two_qubit_gates_per_s": round(S * info["n_two_qubit_gates"] / t_sim, 1),
+                       "max_bond": info["max_bond"], "unconverged_svds": info["unconverged_svds"],
+                       "degenerate_cuts": info["degenerate_cuts"],
+                       "mean_total_discarded": info["mean_total_discarded"]},
+    }
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

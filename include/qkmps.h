@@ -135,6 +135,20 @@ qk_status mps_simulate(const double *features_dev, int64_t n_points,
                        const qk_circuit_spec *spec, int32_t chi_max,
                        double cutoff, void *hip_stream, qk_mps_batch **out);
 
+/* Progress callback: called on the calling thread with the number of
+ * two-qubit gates applied so far and the total; a non-zero return value
+ * aborts the simulation (QK_EABORTED, no batch returned). */
+typedef int (*qk_progress_fn)(int64_t done, int64_t total, void *user);
+
+/* mps_simulate with a progress callback invoked (after synchronising the
+ * stream) every `every` two-qubit gates and once at the end.  `fn` may be
+ * NULL, in which case this is mps_simulate. */
+qk_status mps_simulate_progress(const double *features_dev, int64_t n_points,
+                                const qk_circuit_spec *spec, int32_t chi_max,
+                                double cutoff, void *hip_stream,
+                                qk_progress_fn fn, void *user, int64_t every,
+                                qk_mps_batch **out);
+
 /* ---------------------------------------------------------------- Gram */
 
 /* K[i][j] = |<a_i | b_j>|^2 for i < na, j < nb, written to K_dev (row-major,
@@ -208,10 +222,18 @@ qk_status mps_batch_pack(qk_mps_batch *b, qk_precision prec, void *hip_stream);
 /* Release the packed planes of `prec` (not QK_FP64). */
 qk_status mps_batch_drop(qk_mps_batch *b, qk_precision prec);
 
+/* Forms selected in mps_batch_gather. */
+#define QK_FORM_FP64 1u
+#define QK_FORM_FP32 2u
+#define QK_FORM_SPLIT_BF16 4u
+
 /* New batch holding copies of MPS idx[0..count) of `src` (indices may
- * repeat).  Used to assemble workloads and test subsets. */
+ * repeat), in the forms selected by `forms` (QK_FORM_* bits; each must be
+ * present in `src`).  A batch without the FP64 form can only be used by
+ * mps_gram in the forms it holds (export and packing return QK_ENOTSUP). */
 qk_status mps_batch_gather(const qk_mps_batch *src, const int64_t *idx_host,
-                           int64_t count, void *hip_stream, qk_mps_batch **out);
+                           int64_t count, uint32_t forms, void *hip_stream,
+                           qk_mps_batch **out);
 
 void mps_batch_free(qk_mps_batch *b);
 

@@ -67,6 +67,9 @@ class _Job(C.Structure):
                 ("K_dev", C.c_void_p), ("ldk", C.c_int64)]
 
 
+_PROGRESS = C.CFUNCTYPE(C.c_int, C.c_int64, C.c_int64, C.c_void_p)
+
+
 def _load():
     global _lib
     if _lib is not None:
@@ -81,6 +84,7 @@ def _load():
         "qk_version": (C.c_char_p, []),
         "qk_circuit_compile": (S, [C.POINTER(_Spec), P, I64, C.POINTER(I64)]),
         "mps_simulate": (S, [P, I64, C.POINTER(_Spec), I32, D, P, C.POINTER(P)]),
+        "mps_simulate_progress": (S, [P, I64, C.POINTER(_Spec), I32, D, P, _PROGRESS, P, I64, C.POINTER(P)]),
         "mps_gram": (S, [P, P, C.c_int, P, I64, P]),
         "mps_gram_block": (S, [P, I64, I64, P, I64, I64, I32, C.c_int, P, I64, P]),
         "mps_gram_multi": (S, [C.POINTER(_Job), I32, C.c_int, P]),
@@ -91,7 +95,7 @@ def _load():
         "mps_batch_export": (S, [P, I64, P, I64, C.POINTER(I64)]),
         "mps_batch_pack": (S, [P, C.c_int, P]),
         "mps_batch_drop": (S, [P, C.c_int]),
-        "mps_batch_gather": (S, [P, P, I64, P, C.POINTER(P)]),
+        "mps_batch_gather": (S, [P, P, I64, C.c_uint32, P, C.POINTER(P)]),
         "mps_batch_free": (None, [P]),
     }
     for name, (res, args) in sig.items():
@@ -220,10 +224,15 @@ class MPSBatch:
     def drop(self, precision):
         _check(_load().mps_batch_drop(self._h, Precision.of(precision)))
 
-    def gather(self, indices: Sequence[int], stream=None) -> "MPSBatch":
+    def gather(self, indices: Sequence[int], forms=("fp64",), stream=None) -> "MPSBatch":
+        """Copies of MPS ``indices`` in the given forms ("fp64", "fp32", "split_bf16")."""
         idx = np.ascontiguousarray(np.asarray(indices, dtype=np.int64))
+        mask = 0
+        for f in forms:
+            mask |= 1 << Precision.of(f)
         h = C.c_void_p(0)
-        _check(_load().mps_batch_gather(self._h, idx.ctypes.data, len(idx), _stream_ptr(stream), C.byref(h)))
+        _check(_load().mps_batch_gather(self._h, idx.ctypes.data, len(idx), mask, _stream_ptr(stream),
+                                        C.byref(h)))
         return MPSBatch(h.value)
 
 
@@ -248,8 +257,12 @@ def import_batch(mps_list: Sequence[Sequence[np.ndarray]], stream=None) -> MPSBa
     return MPSBatch(h.value)
 
 
-def simulate(features, spec: CircuitSpec, chi: int, cutoff: float, stream=None) -> MPSBatch:
-    """Truncated MPS simulation of every row of ``features`` (a CUDA float64 tensor, n x m)."""
+def simulate(features, spec: CircuitSpec, chi: int, cutoff: float, stream=None, progress=None,
+             every: int = 0) -> MPSBatch:
+    """Truncated MPS simulation of every row of ``features`` (a CUDA float64 tensor, n x m).
+
+    ``progress(done, total)`` (optional) is called every ``every`` two-qubit
+    gates; returning True aborts."""
     import torch
     if not isinstance(features, torch.Tensor) or features.device.type != "cuda":
         raise TypeError("features must be a CUDA tensor")
@@ -258,8 +271,14 @@ def simulate(features, spec: CircuitSpec, chi: int, cutoff: float, stream=None) 
         raise ValueError("features must be n x n_qubits")
     cs = spec._c()
     h = C.c_void_p(0)
-    _check(_load().mps_simulate(C.c_void_p(x.data_ptr()), x.shape[0], C.byref(cs), int(chi), float(cutoff),
-                                _stream_ptr(stream), C.byref(h)))
+    if progress is None:
+        _check(_load().mps_simulate(C.c_void_p(x.data_ptr()), x.shape[0], C.byref(cs), int(chi), float(cutoff),
+                                    _stream_ptr(stream), C.byref(h)))
+    else:
+        cb = _PROGRESS(lambda done, total, _u: 1 if progress(int(done), int(total)) else 0)
+        _check(_load().mps_simulate_progress(C.c_void_p(x.data_ptr()), x.shape[0], C.byref(cs), int(chi),
+                                             float(cutoff), _stream_ptr(stream), cb, None, int(every),
+                                             C.byref(h)))
     return MPSBatch(h.value)
 
 

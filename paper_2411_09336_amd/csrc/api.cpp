@@ -97,7 +97,7 @@ static void batch_release(qk_mps_batch *b) {
 }
 
 qk_status batch_create(int64_t n, int32_t m, const std::vector<int32_t> &pad,
-                       hipStream_t stream, qk_mps_batch **out) {
+                       hipStream_t stream, qk_mps_batch **out, bool with_f64) {
   auto *b = new qk_mps_batch();
   QK_HIP_CHECK(hipGetDevice(&b->device));
   b->n = n;
@@ -110,7 +110,7 @@ qk_status batch_create(int64_t n, int32_t m, const std::vector<int32_t> &pad,
     return hipMemsetAsync(*p, 0, bytes, stream) == hipSuccess;
   };
   const size_t nn = size_t(std::max<int64_t>(n, 1));
-  bool good = alloc((void **)&b->f64, sizeof(double2) * nn * size_t(b->mps_stride)) &&
+  bool good = (!with_f64 || alloc((void **)&b->f64, sizeof(double2) * nn * size_t(b->mps_stride))) &&
               alloc((void **)&b->dims_dev, sizeof(int32_t) * nn * size_t(m + 1)) &&
               alloc((void **)&b->pad_dev, sizeof(int32_t) * size_t(m + 1)) &&
               alloc((void **)&b->site_off_dev, sizeof(int64_t) * size_t(m + 1)) &&
@@ -137,7 +137,12 @@ qk_status batch_create(int64_t n, int32_t m, const std::vector<int32_t> &pad,
 }
 
 qk_status batch_ensure_packed(qk_mps_batch *b, qk_precision prec, hipStream_t stream) {
-  if (prec == QK_FP64) return QK_OK;
+  if (prec == QK_FP64) {
+    if (!b->f64) return fail(QK_ENOTSUP, "batch holds no FP64 form");
+    return QK_OK;
+  }
+  if ((prec == QK_FP32 && b->f32) || (prec == QK_SPLIT_BF16 && b->sbf16)) return QK_OK;
+  if (!b->f64) return fail(QK_ENOTSUP, "batch holds no FP64 form to pack from");
   if (prec == QK_FP32) {
     if (b->f32) return QK_OK;
     size_t bytes = sizeof(float2) * size_t(std::max<int64_t>(b->n, 1)) * size_t(b->mps_stride);
@@ -197,6 +202,12 @@ qk_status qk_circuit_compile(const qk_circuit_spec *spec, qk_gate *out_host, int
 
 qk_status mps_simulate(const double *features_dev, int64_t n_points, const qk_circuit_spec *spec,
                        int32_t chi_max, double cutoff, void *hip_stream, qk_mps_batch **out) {
+  return mps_simulate_progress(features_dev, n_points, spec, chi_max, cutoff, hip_stream, nullptr, nullptr, 0, out);
+}
+
+qk_status mps_simulate_progress(const double *features_dev, int64_t n_points, const qk_circuit_spec *spec,
+                                int32_t chi_max, double cutoff, void *hip_stream, qk_progress_fn fn, void *user,
+                                int64_t every, qk_mps_batch **out) {
   if (!out) return fail(QK_EINVAL, "out is NULL");
   *out = nullptr;
   qk_status st = validate_spec(spec);
@@ -219,7 +230,7 @@ qk_status mps_simulate(const double *features_dev, int64_t n_points, const qk_ci
   st = batch_create(n_points, m, pad, stream, &b);
   if (st != QK_OK) return st;
   auto gates = compile_circuit(*spec);
-  st = run_simulation(b, features_dev, gates, *spec, chi_max, cutoff, stream);
+  st = run_simulation(b, features_dev, gates, *spec, chi_max, cutoff, stream, fn, user, every);
   if (st != QK_OK) {
     batch_release(b);
     return st;
@@ -411,7 +422,7 @@ qk_status mps_batch_info(const qk_mps_batch *b, qk_batch_info *info) {
     }
     info->mean_total_discarded = sum / double(n);
   }
-  info->bytes_f64 = int64_t(sizeof(double2)) * b->n * b->mps_stride;
+  info->bytes_f64 = b->f64 ? int64_t(sizeof(double2)) * b->n * b->mps_stride : 0;
   info->bytes_f32 = b->f32 ? int64_t(sizeof(float2)) * b->n * b->mps_stride : 0;
   info->bytes_split_bf16 = b->sbf16 ? b->n * b->split_stride : 0;
   return ok();
@@ -440,6 +451,7 @@ qk_status mps_batch_export(const qk_mps_batch *b, int64_t idx, double *host_buf,
                            int64_t *written) {
   if (!b || !written) return fail(QK_EINVAL, "NULL argument");
   if (idx < 0 || idx >= b->n) return fail(QK_EINVAL, "index out of range");
+  if (!b->f64) return fail(QK_ENOTSUP, "batch holds no FP64 form");
   const int m = b->m;
   std::vector<int32_t> d(m + 1);
   QK_HIP_CHECK(hipDeviceSynchronize());
@@ -486,34 +498,67 @@ qk_status mps_batch_drop(qk_mps_batch *b, qk_precision prec) {
   return ok();
 }
 
-qk_status mps_batch_gather(const qk_mps_batch *src, const int64_t *idx_host, int64_t count,
+qk_status mps_batch_gather(const qk_mps_batch *src, const int64_t *idx_host, int64_t count, uint32_t forms,
                            void *hip_stream, qk_mps_batch **out) {
   if (!src || !out) return fail(QK_EINVAL, "NULL argument");
   *out = nullptr;
   if (count < 0 || (count > 0 && !idx_host)) return fail(QK_EINVAL, "invalid index list");
+  if (forms == 0 || (forms & ~7u)) return fail(QK_EINVAL, "invalid forms mask");
+  if (((forms & QK_FORM_FP64) && !src->f64) || ((forms & QK_FORM_FP32) && !src->f32) ||
+      ((forms & QK_FORM_SPLIT_BF16) && !src->sbf16))
+    return fail(QK_EINVAL, "requested form is not present in the source batch");
   for (int64_t k = 0; k < count; ++k)
     if (idx_host[k] < 0 || idx_host[k] >= src->n) return fail(QK_EINVAL, "gather index out of range");
   hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
   qk_mps_batch *b = nullptr;
-  qk_status st = batch_create(count, src->m, src->pad, stream, &b);
+  qk_status st = batch_create(count, src->m, src->pad, stream, &b, (forms & QK_FORM_FP64) != 0);
   if (st != QK_OK) return st;
   b->n_two_qubit_gates = src->n_two_qubit_gates;
+  const size_t nn = size_t(std::max<int64_t>(count, 1));
+  if (forms & QK_FORM_FP32) {
+    if (hipMalloc(reinterpret_cast<void **>(&b->f32), sizeof(float2) * nn * size_t(b->mps_stride)) != hipSuccess) {
+      (void)hipGetLastError();
+      b->f32 = nullptr;
+      batch_release(b);
+      return fail(QK_ENOMEM, "device allocation of FP32 planes failed");
+    }
+  }
+  if (forms & QK_FORM_SPLIT_BF16) {
+    if (hipMalloc(reinterpret_cast<void **>(&b->sbf16), nn * size_t(b->split_stride)) != hipSuccess) {
+      (void)hipGetLastError();
+      b->sbf16 = nullptr;
+      batch_release(b);
+      return fail(QK_ENOMEM, "device allocation of split-BF16 planes failed");
+    }
+  }
   const int m1 = src->m + 1;
   for (int64_t k = 0; k < count; ++k) {
     const int64_t i = idx_host[k];
-    bool good =
-        hipMemcpyAsync(b->f64 + k * b->mps_stride, src->f64 + i * src->mps_stride,
-                       sizeof(double2) * src->mps_stride, hipMemcpyDeviceToDevice, stream) == hipSuccess &&
-        hipMemcpyAsync(b->dims_dev + k * m1, src->dims_dev + i * m1, sizeof(int32_t) * m1,
-                       hipMemcpyDeviceToDevice, stream) == hipSuccess &&
-        hipMemcpyAsync(b->disc_dev + k, src->disc_dev + i, sizeof(double), hipMemcpyDeviceToDevice, stream) == hipSuccess &&
-        hipMemcpyAsync(b->maxdisc_dev + k, src->maxdisc_dev + i, sizeof(double), hipMemcpyDeviceToDevice, stream) == hipSuccess &&
-        hipMemcpyAsync(b->degen_dev + k, src->degen_dev + i, sizeof(int32_t), hipMemcpyDeviceToDevice, stream) == hipSuccess &&
-        hipMemcpyAsync(b->unconv_dev + k, src->unconv_dev + i, sizeof(int32_t), hipMemcpyDeviceToDevice, stream) == hipSuccess;
+    bool good = true;
+    if (forms & QK_FORM_FP64)
+      good = good && hipMemcpyAsync(b->f64 + k * b->mps_stride, src->f64 + i * src->mps_stride,
+                                    sizeof(double2) * src->mps_stride, hipMemcpyDeviceToDevice, stream) == hipSuccess;
+    if (forms & QK_FORM_FP32)
+      good = good && hipMemcpyAsync(b->f32 + k * b->mps_stride, src->f32 + i * src->mps_stride,
+                                    sizeof(float2) * src->mps_stride, hipMemcpyDeviceToDevice, stream) == hipSuccess;
+    if (forms & QK_FORM_SPLIT_BF16)
+      good = good && hipMemcpyAsync(b->sbf16 + k * b->split_stride, src->sbf16 + i * src->split_stride,
+                                    size_t(src->split_stride), hipMemcpyDeviceToDevice, stream) == hipSuccess;
+    good = good &&
+           hipMemcpyAsync(b->dims_dev + k * m1, src->dims_dev + i * m1, sizeof(int32_t) * m1,
+                          hipMemcpyDeviceToDevice, stream) == hipSuccess &&
+           hipMemcpyAsync(b->disc_dev + k, src->disc_dev + i, sizeof(double), hipMemcpyDeviceToDevice, stream) == hipSuccess &&
+           hipMemcpyAsync(b->maxdisc_dev + k, src->maxdisc_dev + i, sizeof(double), hipMemcpyDeviceToDevice, stream) == hipSuccess &&
+           hipMemcpyAsync(b->degen_dev + k, src->degen_dev + i, sizeof(int32_t), hipMemcpyDeviceToDevice, stream) == hipSuccess &&
+           hipMemcpyAsync(b->unconv_dev + k, src->unconv_dev + i, sizeof(int32_t), hipMemcpyDeviceToDevice, stream) == hipSuccess;
     if (!good) {
       batch_release(b);
       return fail(QK_EDEVICE, "device copy failed in gather");
     }
+  }
+  if (hipStreamSynchronize(stream) != hipSuccess) {
+    batch_release(b);
+    return fail(QK_EDEVICE, "gather copies failed");
   }
   *out = b;
   return ok();

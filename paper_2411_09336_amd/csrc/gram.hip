@@ -319,21 +319,31 @@ __device__ inline Sl4 make_slices(const double (&xh)[8]) {
   return r;
 }
 
+// Work split per site (eight waves, MAXP = 64): wave w owns column block
+// c = w % 4 and row half h = w / 4.  GEMM1: T_s[rows 32h..32h+31][ket block c];
+// the exponent of each T^T row (ket column) combines both halves through LDS;
+// T is written to LDS as slices.  GEMM2: E'^T[rows (ket) 32h..][bra block c].
+// Each wave streams a quarter of each site tensor (shared with its sibling
+// through L1) and two waves per SIMD overlap MFMA with VALU and loads.
+constexpr int kSplitThreads = 512;
+
 template <int MAXP>
-__device__ void overlap_split(const GramJobDev &J, int64_t ia, int64_t ib, uint8_t *E, int *s_ea,
-                              double *s_rmax, double *s_wmax, double *s_ov, double &ov_re, double &ov_im,
-                              int &ov_exp) {
+__device__ void overlap_split(const GramJobDev &J, int64_t ia, int64_t ib, uint8_t *E, uint8_t *Tl, int *s_ea,
+                              int *s_eT, double *s_mx, double *s_ov, double &ov_re, double &ov_im, int &ov_exp) {
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int j = lane & 15, g = lane >> 4;
+  const int cb = wave & 3, hf = wave >> 2;
   const uint8_t *abase = reinterpret_cast<const uint8_t *>(J.a_base) + ia * J.a_stride;
   const uint8_t *bbase = reinterpret_cast<const uint8_t *>(J.b_base) + ib * J.b_stride;
-  // LDS E: fragment group (rt, kc) = [slice 4][plane 2][lane 64][16 B] = 8 KiB
-  auto egroup = [&](int rt, int kc, int nkc) -> uint8_t * { return E + size_t(rt * nkc + kc) * 8192; };
+  // LDS operand groups (row tile, k chunk) = [slice 4][plane 2][lane 64][16 B] = 8 KiB
+  auto lgroup = [&](uint8_t *base, int rt, int kc, int nkc) -> uint8_t * {
+    return base + size_t(rt * nkc + kc) * 8192;
+  };
   {
     const int nbytes = J.a_pad[0] * J.b_pad[0] * 16;
     uint32_t *E32 = reinterpret_cast<uint32_t *>(E);
-    for (int x = tid; x < nbytes / 4; x += kThreads) E32[x] = 0u;
-    for (int x = tid; x < MAXP; x += kThreads) s_ea[x] = 0;
+    for (int x = tid; x < nbytes / 4; x += kSplitThreads) E32[x] = 0u;
+    for (int x = tid; x < MAXP; x += kSplitThreads) s_ea[x] = 0;
     __syncthreads();
     // E_0 = [[1]]: row exponent 1, leading slice 64 (= 0.5 * 128)
     if (tid == 0) {
@@ -342,10 +352,8 @@ __device__ void overlap_split(const GramJobDev &J, int64_t ia, int64_t ib, uint8
     }
     __syncthreads();
   }
-  int expacc = 0;
   constexpr int NT = MAXP / 16;
-  constexpr int NK = MAXP / 32;
-  constexpr int CT_PER_WAVE = (NT + 3) / 4;
+  static_assert(NT == 4, "four 16-column blocks");
   for (int l = 0; l < J.m; ++l) {
     const int Da = J.a_pad[l], Dan = J.a_pad[l + 1], Db = J.b_pad[l], Dbn = J.b_pad[l + 1];
     const uint8_t *A = abase + J.a_off[l];
@@ -355,46 +363,45 @@ __device__ void overlap_split(const GramJobDev &J, int64_t ia, int64_t ib, uint8
     const int nrt = Da / 16, nkcb = Db / 32, nkca = Da / 32, nat = Dan / 16, nct = Dbn / 16;
     const int nkcn = Dbn / 32;
     const bool last = (l + 1 == J.m);
-    auto frag = [&](const uint8_t *site, int s, int k, int q, int kc, int ct, int nkc, int ncol) {
+    auto frag = [&](const uint8_t *site, int s, int k, int q, int kc, int c, int nkc, int ncol) {
       return *reinterpret_cast<const uint4 *>(
-          site + kSplitExpBytes +
-          ((size_t((((s * 4 + k) * 2 + q) * nkc + kc)) * ncol + ct) * 1024 + lane * 16));
+          site + kSplitExpBytes + ((size_t((((s * 4 + k) * 2 + q) * nkc + kc)) * ncol + c) * 1024 + lane * 16));
     };
-    double Epd[CT_PER_WAVE][NT][2][4];
-    double wmax = 0.0;
+    double Ep[2][2][4];   // E'^T[16 (2 hf + u) + 4 g + e][16 cb + j], summed over s
 #pragma unroll
-    for (int c = 0; c < CT_PER_WAVE; ++c) {
-      const int ct = wave + 4 * c;
+    for (int u = 0; u < 2; ++u)
 #pragma unroll
-      for (int at = 0; at < NT; ++at)
+      for (int q = 0; q < 2; ++q)
 #pragma unroll
-        for (int q = 0; q < 2; ++q)
+        for (int e = 0; e < 4; ++e) Ep[u][q][e] = 0.0;
 #pragma unroll
-          for (int e = 0; e < 4; ++e) Epd[c][at][q][e] = 0.0;
-      if (ct >= nct) continue;
+    for (int s = 0; s < 2; ++s) {
+      // ---- GEMM1: T_s[a][b'] = sum_b E[a][b] B_s[b][b'], b' in block cb, a in half hf
+      double Td[2][2][4];
+      double tmax = 0.0;
+      const bool g1 = cb < nct;
+      if (g1) {
+        f32x4 h1[2][2], l1[2][2];
 #pragma unroll
-      for (int s = 0; s < 2; ++s) {
-        // ---- GEMM1: T_s[a][b'] = sum_b E[a][b] B_s[b][b'], b' in block ct
-        f32x4 h1[NT][2], l1[NT][2];
-#pragma unroll
-        for (int rt = 0; rt < NT; ++rt)
+        for (int u = 0; u < 2; ++u)
 #pragma unroll
           for (int q = 0; q < 2; ++q) {
-            h1[rt][q] = f32x4{0, 0, 0, 0};
-            l1[rt][q] = f32x4{0, 0, 0, 0};
+            h1[u][q] = f32x4{0, 0, 0, 0};
+            l1[u][q] = f32x4{0, 0, 0, 0};
           }
         for (int kc = 0; kc < nkcb; ++kc) {
           Sl4 Br, Bi;
 #pragma unroll
           for (int k = 0; k < 4; ++k) {
-            Br.v[k] = frag(B, s, k, 0, kc, ct, nkcb, nct);
-            Bi.v[k] = frag(B, s, k, 1, kc, ct, nkcb, nct);
+            Br.v[k] = frag(B, s, k, 0, kc, cb, nkcb, nct);
+            Bi.v[k] = frag(B, s, k, 1, kc, cb, nkcb, nct);
           }
           const Sl4 Bin = neg4(Bi);
 #pragma unroll
-          for (int rt = 0; rt < NT; ++rt) {
+          for (int u = 0; u < 2; ++u) {
+            const int rt = 2 * hf + u;
             if (rt < nrt) {
-              const uint8_t *eg = egroup(rt, kc, nkcb) + lane * 16;
+              const uint8_t *eg = lgroup(E, rt, kc, nkcb) + lane * 16;
               Sl4 Er, Ei;
 #pragma unroll
               for (int k = 0; k < 4; ++k) {
@@ -402,155 +409,162 @@ __device__ void overlap_split(const GramJobDev &J, int64_t ia, int64_t ib, uint8
                 Ei.v[k] = *reinterpret_cast<const uint4 *>(eg + (k * 2 + 1) * 1024);
               }
               // re += Er Br - Ei Bi ; im += Er Bi + Ei Br
-              slice_mac(Er, Br, h1[rt][0], l1[rt][0]);
-              slice_mac(Ei, Bin, h1[rt][0], l1[rt][0]);
-              slice_mac(Er, Bi, h1[rt][1], l1[rt][1]);
-              slice_mac(Ei, Br, h1[rt][1], l1[rt][1]);
+              slice_mac(Er, Br, h1[u][0], l1[u][0]);
+              slice_mac(Ei, Bin, h1[u][0], l1[u][0]);
+              slice_mac(Er, Bi, h1[u][1], l1[u][1]);
+              slice_mac(Ei, Br, h1[u][1], l1[u][1]);
             }
           }
         }
-        // T in FP64; the row max of T^T (column b' = 16 ct + j) over a
-        double Td[NT][2][4];
-        double tmax = 0.0;
-        const int ebc = int(eB[s * 128 + 16 * ct + j]);
+        const int ebc = int(eB[s * 128 + 16 * cb + j]);
 #pragma unroll
-        for (int rt = 0; rt < NT; ++rt)
+        for (int u = 0; u < 2; ++u) {
+          const int rt = 2 * hf + u;
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
             const int ex = (rt < nrt ? s_ea[16 * rt + 4 * g + e] : 0) + ebc - 14;
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
-              const double v = rt < nrt ? ldexp(double(h1[rt][q][e]) + double(l1[rt][q][e]), ex) : 0.0;
-              Td[rt][q][e] = v;
+              const double v = rt < nrt ? ldexp(double(h1[u][q][e]) + double(l1[u][q][e]), ex) : 0.0;
+              Td[u][q][e] = v;
               tmax = fmax(tmax, fabs(v));
             }
           }
+        }
         tmax = fmax(tmax, __shfl_xor(tmax, 16, 64));
         tmax = fmax(tmax, __shfl_xor(tmax, 32, 64));
-        const int eT = exp_above(tmax);       // exponent of row b' = 16 ct + j
-        // ---- GEMM2: E'^T[b'][a'] += sum_a T_s[a][b'] conj(A_s[a][a'])
-        f32x4 h2[NT][2], l2[NT][2];
-#pragma unroll
-        for (int at = 0; at < NT; ++at)
-#pragma unroll
-          for (int q = 0; q < 2; ++q) {
-            h2[at][q] = f32x4{0, 0, 0, 0};
-            l2[at][q] = f32x4{0, 0, 0, 0};
-          }
-#pragma unroll
-        for (int kc = 0; kc < NK; ++kc) {
-          if (kc < nkca) {
-            double xr[8], xi[8];
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-              xr[v] = ldexp(Td[2 * kc][0][v], -eT);
-              xi[v] = ldexp(Td[2 * kc][1][v], -eT);
-              xr[4 + v] = ldexp(Td[2 * kc + 1][0][v], -eT);
-              xi[4 + v] = ldexp(Td[2 * kc + 1][1][v], -eT);
-            }
-            const Sl4 Tr = make_slices(xr), Ti = make_slices(xi);
-            const Sl4 Trn = neg4(Tr);
-#pragma unroll
-            for (int at = 0; at < NT; ++at) {
-              if (at < nat) {
-                Sl4 Ar, Ai;
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                  Ar.v[k] = frag(A, s, k, 0, kc, at, nkca, nat);
-                  Ai.v[k] = frag(A, s, k, 1, kc, at, nkca, nat);
-                }
-                // re += Tr Ar + Ti Ai ; im += Ti Ar - Tr Ai
-                slice_mac(Tr, Ar, h2[at][0], l2[at][0]);
-                slice_mac(Ti, Ai, h2[at][0], l2[at][0]);
-                slice_mac(Ti, Ar, h2[at][1], l2[at][1]);
-                slice_mac(Trn, Ai, h2[at][1], l2[at][1]);
-              }
-            }
-          }
-        }
-        // output row b' = 16 ct + 4 g + e takes the exponent of lane 4 g + e
-        int eTr[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) eTr[e] = __shfl(eT, 4 * g + e, 64);
-#pragma unroll
-        for (int at = 0; at < NT; ++at) {
-          if (at < nat) {
-            const int eac = int(eA[s * 128 + 16 * at + j]);
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-#pragma unroll
-              for (int q = 0; q < 2; ++q)
-                Epd[c][at][q][e] += ldexp(double(h2[at][q][e]) + double(l2[at][q][e]), eTr[e] + eac - 14);
-          }
-        }
+        if (g == 0) s_mx[hf * MAXP + 16 * cb + j] = tmax;
       }
-      // row maxima of E' rows a' = 16 at + j over this wave's columns
+      __syncthreads();  // both halves' T^T row maxima visible
+      if (g1) {
+        const int eT = exp_above(fmax(s_mx[16 * cb + j], s_mx[MAXP + 16 * cb + j]));
+        if (hf == 0 && g == 0) s_eT[16 * cb + j] = eT;
 #pragma unroll
-      for (int at = 0; at < NT; ++at) {
-        double rm = 0.0;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) rm = fmax(rm, fmax(fabs(Epd[c][at][0][e]), fabs(Epd[c][at][1][e])));
-        rm = fmax(rm, __shfl_xor(rm, 16, 64));
-        rm = fmax(rm, __shfl_xor(rm, 32, 64));
-        if (at < nat && g == 0) s_rmax[(wave + 4 * c) * MAXP + 16 * at + j] = rm;
-        wmax = fmax(wmax, rm);
-      }
-    }
-    // waves without a column block report zero rows
-    for (int c = 0; c < CT_PER_WAVE; ++c) {
-      const int ct = wave + 4 * c;
-      if (ct >= nct)
-        for (int x = lane; x < Dan; x += 64) s_rmax[(wave + 4 * c) * MAXP + x] = 0.0;
-    }
-    if (lane == 0) s_wmax[wave] = wmax;
-    if (last && wave == 0 && lane == 0) {
-      s_ov[0] = Epd[0][0][0][0];
-      s_ov[1] = Epd[0][0][1][0];
-    }
-    __syncthreads();  // every wave is done reading E and s_ea
-    if (!last) {
-      double gm = 0.0;
-      for (int w = 0; w < kThreads / 64; ++w) gm = fmax(gm, s_wmax[w]);
-      const int e2 = exp_above(gm);
-      expacc += e2;
-      const int nblk = (nct + 3) / 4 * 4;  // column blocks reported in s_rmax
-#pragma unroll
-      for (int c = 0; c < CT_PER_WAVE; ++c) {
-        const int ct = wave + 4 * c;
-        if (ct >= nct) continue;
-#pragma unroll
-        for (int at = 0; at < NT; ++at) {
-          if (at < nat) {
-            const int a_row = 16 * at + j;
-            double rm = 0.0;
-            for (int w = 0; w < nblk; ++w) rm = fmax(rm, s_rmax[w * MAXP + a_row]);
-            const int er = exp_above(rm);
-            uint8_t *eg = egroup(at, ct >> 1, nkcn) + lane * 16 + (ct & 1) * 8;
+        for (int u = 0; u < 2; ++u) {
+          const int rt = 2 * hf + u;
+          if (rt < nrt) {
+            uint8_t *tg = lgroup(Tl, cb, rt >> 1, nkca) + lane * 16 + (rt & 1) * 8;
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
               uint32_t sl[4][4];
 #pragma unroll
-              for (int e = 0; e < 4; ++e) slice4(ldexp(Epd[c][at][q][e], -er), sl[e]);
+              for (int e = 0; e < 4; ++e) slice4(ldexp(Td[u][q][e], -eT), sl[e]);
+#pragma unroll
+              for (int k = 0; k < 4; ++k)
+                *reinterpret_cast<uint2 *>(tg + (k * 2 + q) * 1024) =
+                    make_uint2(sl[0][k] | (sl[1][k] << 16), sl[2][k] | (sl[3][k] << 16));
+            }
+          }
+        }
+      }
+      __syncthreads();  // T_s complete in LDS
+      // ---- GEMM2: E'^T[b'][a'] += sum_a T_s[a][b'] conj(A_s[a][a']), a' in block cb, b' in half hf
+      if (cb < nat) {
+        f32x4 h2[2][2], l2[2][2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            h2[u][q] = f32x4{0, 0, 0, 0};
+            l2[u][q] = f32x4{0, 0, 0, 0};
+          }
+        for (int kc = 0; kc < nkca; ++kc) {
+          Sl4 Ar, Ai;
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            Ar.v[k] = frag(A, s, k, 0, kc, cb, nkca, nat);
+            Ai.v[k] = frag(A, s, k, 1, kc, cb, nkca, nat);
+          }
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            const int bt = 2 * hf + u;
+            if (bt < nct) {
+              const uint8_t *tg = lgroup(Tl, bt, kc, nkca) + lane * 16;
+              Sl4 Tr, Ti;
+#pragma unroll
+              for (int k = 0; k < 4; ++k) {
+                Tr.v[k] = *reinterpret_cast<const uint4 *>(tg + (k * 2 + 0) * 1024);
+                Ti.v[k] = *reinterpret_cast<const uint4 *>(tg + (k * 2 + 1) * 1024);
+              }
+              const Sl4 Trn = neg4(Tr);
+              // re += Tr Ar + Ti Ai ; im += Ti Ar - Tr Ai
+              slice_mac(Tr, Ar, h2[u][0], l2[u][0]);
+              slice_mac(Ti, Ai, h2[u][0], l2[u][0]);
+              slice_mac(Ti, Ar, h2[u][1], l2[u][1]);
+              slice_mac(Trn, Ai, h2[u][1], l2[u][1]);
+            }
+          }
+        }
+        const int eac = int(eA[s * 128 + 16 * cb + j]);
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const int bt = 2 * hf + u;
+          if (bt < nct) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const int ex = s_eT[16 * bt + 4 * g + e] + eac - 14;
+#pragma unroll
+              for (int q = 0; q < 2; ++q) Ep[u][q][e] += ldexp(double(h2[u][q][e]) + double(l2[u][q][e]), ex);
+            }
+          }
+        }
+      }
+      __syncthreads();  // T_s consumed (buffer, exponents and maxima reused)
+    }
+    if (last) {
+      // E_m[0][0] = E'^T[0][0]: wave 0 (block 0, half 0), lane 0, u = 0, e = 0
+      if (wave == 0 && lane == 0) {
+        s_ov[0] = Ep[0][0][0];
+        s_ov[1] = Ep[0][1][0];
+      }
+    } else {
+      // E' row a' = 16 cb + j: max over this wave's ket rows, combined with the sibling half
+      double rm = 0.0;
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) rm = fmax(rm, fmax(fabs(Ep[u][0][e]), fabs(Ep[u][1][e])));
+      rm = fmax(rm, __shfl_xor(rm, 16, 64));
+      rm = fmax(rm, __shfl_xor(rm, 32, 64));
+      if (g == 0) s_mx[hf * MAXP + 16 * cb + j] = rm;
+      __syncthreads();
+      if (cb < nat) {
+        const int er = exp_above(fmax(s_mx[16 * cb + j], s_mx[MAXP + 16 * cb + j]));
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const int bt = 2 * hf + u;
+          if (bt < nct) {
+            uint8_t *eg = lgroup(E, cb, bt >> 1, nkcn) + lane * 16 + (bt & 1) * 8;
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+              uint32_t sl[4][4];
+#pragma unroll
+              for (int e = 0; e < 4; ++e) slice4(ldexp(Ep[u][q][e], -er), sl[e]);
 #pragma unroll
               for (int k = 0; k < 4; ++k)
                 *reinterpret_cast<uint2 *>(eg + (k * 2 + q) * 1024) =
                     make_uint2(sl[0][k] | (sl[1][k] << 16), sl[2][k] | (sl[3][k] << 16));
             }
-            if (ct == 0 && g == 0) s_ea[a_row] = er - e2;
           }
         }
+        if (hf == 0 && g == 0) s_ea[16 * cb + j] = er;
       }
     }
     __syncthreads();
   }
   ov_re = s_ov[0];
   ov_im = s_ov[1];
-  ov_exp = expacc;
+  ov_exp = 0;
   __syncthreads();
 }
 
+template <int PREC>
+constexpr int threads_of() {
+  return PREC == QK_SPLIT_BF16 ? kSplitThreads : kThreads;
+}
+
 template <int PREC, int MAXP>
-__global__ __launch_bounds__(kThreads) void gram_kernel(const GramJobDev *__restrict__ jobs,
+__global__ __launch_bounds__(threads_of<PREC>()) void gram_kernel(const GramJobDev *__restrict__ jobs,
                                                         const GramTile *__restrict__ tiles,
                                                         int64_t total, unsigned long long *counter) {
   extern __shared__ __align__(16) uint8_t smem[];
@@ -558,7 +572,8 @@ __global__ __launch_bounds__(kThreads) void gram_kernel(const GramJobDev *__rest
   __shared__ double s_red[4];
   __shared__ double s_ov[2];
   __shared__ int s_ea[MAXP];
-  __shared__ double s_rmax[((MAXP / 16 + 3) / 4) * 4 * MAXP];
+  __shared__ int s_eT[MAXP];
+  __shared__ double s_mx[2 * MAXP];
   int job;
   int64_t i, j;
   bool valid;
@@ -581,7 +596,8 @@ __global__ __launch_bounds__(kThreads) void gram_kernel(const GramJobDev *__rest
     } else {
       double re, im;
       int ex;
-      overlap_split<MAXP>(J, J.a0 + i, J.b0 + j, smem, s_ea, s_rmax, s_red, s_ov, re, im, ex);
+      overlap_split<MAXP>(J, J.a0 + i, J.b0 + j, smem, smem + size_t(MAXP) * MAXP * 16, s_ea, s_eT, s_mx, s_ov,
+                          re, im, ex);
       k = ldexp(re * re + im * im, 2 * ex);
     }
     if (threadIdx.x == 0) write_k(J, i, j, k);
@@ -592,7 +608,7 @@ template <int PREC, int MAXP>
 size_t lds_bytes() {
   if (PREC == QK_FP64) return size_t(MAXP) * MAXP * 16;
   if (PREC == QK_FP32) return size_t(MAXP) * MAXP * 8;
-  return size_t(MAXP) * MAXP * 16;
+  return size_t(MAXP) * MAXP * 32;   // E slices + T slices
 }
 
 template <int PREC, int MAXP>
@@ -606,11 +622,11 @@ qk_status launch_one(const GramJobDev *jobs_dev, const GramTile *tiles_dev, int6
   QK_HIP_CHECK(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                    hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
   int per_cu = 0;
-  QK_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kThreads, lds));
+  QK_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads_of<PREC>(), lds));
   per_cu = std::max(per_cu, 1);
   int64_t grid = int64_t(cus) * per_cu;
   grid = std::min<int64_t>(grid, std::max<int64_t>(total, 1));
-  hipLaunchKernelGGL(kern, dim3(unsigned(grid)), dim3(kThreads), lds, stream, jobs_dev, tiles_dev, total,
+  hipLaunchKernelGGL(kern, dim3(unsigned(grid)), dim3(threads_of<PREC>()), lds, stream, jobs_dev, tiles_dev, total,
                      counter);
   QK_HIP_CHECK(hipGetLastError());
   return QK_OK;

@@ -89,7 +89,7 @@ namespace qk {
 
 // Allocate a batch with the given pad profile (device memory zeroed).
 qk_status batch_create(int64_t n, int32_t m, const std::vector<int32_t> &pad,
-                       hipStream_t stream, qk_mps_batch **out);
+                       hipStream_t stream, qk_mps_batch **out, bool with_f64 = true);
 qk_status batch_ensure_packed(qk_mps_batch *b, qk_precision prec, hipStream_t stream);
 
 // Launchers implemented in the .hip files.
@@ -120,7 +120,8 @@ qk_status launch_gram(const std::vector<GramJobDev> &jobs, int max_pad,
 qk_status run_simulation(qk_mps_batch *b, const double *features_dev,
                          const std::vector<qk_gate> &gates,
                          const qk_circuit_spec &spec, int chi, double cutoff,
-                         hipStream_t stream);
+                         hipStream_t stream, qk_progress_fn fn = nullptr,
+                         void *user = nullptr, int64_t every = 0);
 
 std::vector<qk_gate> compile_circuit(const qk_circuit_spec &spec);
 qk_status validate_spec(const qk_circuit_spec *spec);

@@ -79,6 +79,19 @@ struct SvParams {
   int64_t n;
 };
 
+// DPP wave shifts of a double: shr1 gives lane l the value of lane l-1, shl1
+// the value of lane l+1; lanes without a source keep their own value.
+__device__ inline double dpp_shr1(double x) {
+  const int lo = __double2loint(x), hi = __double2hiint(x);
+  return __hiloint2double(__builtin_amdgcn_update_dpp(hi, hi, 0x138, 0xf, 0xf, false),
+                          __builtin_amdgcn_update_dpp(lo, lo, 0x138, 0xf, 0xf, false));
+}
+__device__ inline double dpp_shl1(double x) {
+  const int lo = __double2loint(x), hi = __double2hiint(x);
+  return __hiloint2double(__builtin_amdgcn_update_dpp(hi, hi, 0x130, 0xf, 0xf, false),
+                          __builtin_amdgcn_update_dpp(lo, lo, 0x130, 0xf, 0xf, false));
+}
+
 __device__ inline double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
@@ -116,7 +129,8 @@ __global__ __launch_bounds__(kSvThreads) void svd_step_kernel(SvParams P) {
   if (ci >= P.n) return;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
 
-  __shared__ double s_part[64][17][4];
+  // partial sums [component][wave][pair], rows padded to 65 (bank spread)
+  __shared__ double s_part[4][kSvWaves][65];
   __shared__ double s_par[64][4];
   __shared__ double s_norm[kSvMaxN];
   __shared__ double s_sorted[kSvMaxN];
@@ -201,11 +215,11 @@ __global__ __launch_bounds__(kSvThreads) void svd_step_kernel(SvParams P) {
 #pragma unroll
     for (int rr = 0; rr < kSvRows; ++rr)
       w = fma(Ar[rr], Ar[rr], fma(Ai[rr], Ai[rr], fma(Br[rr], Br[rr], fma(Bi[rr], Bi[rr], w))));
-    s_part[lane][wave][0] = w;
+    s_part[0][wave][lane] = w;
     __syncthreads();
     if (tid < 64) {
       double t = 0.0;
-      for (int u = 0; u < kSvWaves; ++u) t += s_part[tid][u][0];
+      for (int u = 0; u < kSvWaves; ++u) t += s_part[0][u][tid];
       for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
       if (tid == 0) s_nrm = t;
     }
@@ -229,14 +243,14 @@ __global__ __launch_bounds__(kSvThreads) void svd_step_kernel(SvParams P) {
         gr = fma(Ar[rr], Br[rr], fma(Ai[rr], Bi[rr], gr));
         gi = fma(Ar[rr], Bi[rr], fma(-Ai[rr], Br[rr], gi));
       }
-      s_part[lane][wave][0] = al;
-      s_part[lane][wave][1] = be;
-      s_part[lane][wave][2] = gr;
-      s_part[lane][wave][3] = gi;
+      s_part[0][wave][lane] = al;
+      s_part[1][wave][lane] = be;
+      s_part[2][wave][lane] = gr;
+      s_part[3][wave][lane] = gi;
       __syncthreads();
       {
         const int pr = tid >> 4, w = tid & 15;
-        double a = s_part[pr][w][0], b = s_part[pr][w][1], x = s_part[pr][w][2], y = s_part[pr][w][3];
+        double a = s_part[0][w][pr], b = s_part[1][w][pr], x = s_part[2][w][pr], y = s_part[3][w][pr];
 #pragma unroll
         for (int o = 8; o > 0; o >>= 1) {
           a += __shfl_xor(a, o, 16);
@@ -281,20 +295,19 @@ __global__ __launch_bounds__(kSvThreads) void svd_step_kernel(SvParams P) {
         }
       }
       // circle ordering: A_1 -> A_2 -> ... -> A_{H-1} -> B_{H-1} -> ... -> B_0 -> A_1
+      // (A_0 fixed); lanes >= H hold empty positions and keep them.
       if (H > 1) {
-        const int srcA = lane > 0 ? lane - 1 : 0;
-        const int srcB = lane < 63 ? lane + 1 : 63;
 #pragma unroll
         for (int rr = 0; rr < kSvRows; ++rr) {
-          const double pa_r = __shfl(Ar[rr], srcA), pa_i = __shfl(Ai[rr], srcA);
-          const double nb_r = __shfl(Br[rr], srcB), nb_i = __shfl(Bi[rr], srcB);
-          const double b0_r = __shfl(Br[rr], 0), b0_i = __shfl(Bi[rr], 0);
+          const double sAr = dpp_shr1(Ar[rr]), sAi = dpp_shr1(Ai[rr]);
+          const double sBr = dpp_shr1(Br[rr]), sBi = dpp_shr1(Bi[rr]);
+          const double lBr = dpp_shl1(Br[rr]), lBi = dpp_shl1(Bi[rr]);
           if (lane < H) {
             const double oar = Ar[rr], oai = Ai[rr];
-            if (lane == 1) { Ar[rr] = b0_r; Ai[rr] = b0_i; }
-            else if (lane > 1) { Ar[rr] = pa_r; Ai[rr] = pa_i; }
+            if (lane == 1) { Ar[rr] = sBr; Ai[rr] = sBi; }
+            else if (lane > 1) { Ar[rr] = sAr; Ai[rr] = sAi; }
             if (lane == H - 1) { Br[rr] = oar; Bi[rr] = oai; }
-            else { Br[rr] = nb_r; Bi[rr] = nb_i; }
+            else { Br[rr] = lBr; Bi[rr] = lBi; }
           }
         }
       }
@@ -309,11 +322,11 @@ __global__ __launch_bounds__(kSvThreads) void svd_step_kernel(SvParams P) {
       na = fma(Ar[rr], Ar[rr], fma(Ai[rr], Ai[rr], na));
       nb = fma(Br[rr], Br[rr], fma(Bi[rr], Bi[rr], nb));
     }
-    s_part[lane][wave][0] = na;
-    s_part[lane][wave][1] = nb;
+    s_part[0][wave][lane] = na;
+    s_part[1][wave][lane] = nb;
     __syncthreads();
     const int pr = tid >> 4, w = tid & 15;
-    double a = s_part[pr][w][0], b = s_part[pr][w][1];
+    double a = s_part[0][w][pr], b = s_part[1][w][pr];
 #pragma unroll
     for (int o = 8; o > 0; o >>= 1) {
       a += __shfl_xor(a, o, 16);
@@ -507,7 +520,8 @@ __global__ void normalize_last_kernel(double2 *f64, int64_t mps_stride, const in
 }  // namespace
 
 qk_status run_simulation(qk_mps_batch *b, const double *features_dev, const std::vector<qk_gate> &gates,
-                         const qk_circuit_spec &spec, int chi, double cutoff, hipStream_t stream) {
+                         const qk_circuit_spec &spec, int chi, double cutoff, hipStream_t stream, qk_progress_fn fn,
+                         void *user, int64_t every) {
   const int64_t n = b->n;
   const int m = b->m;
   int n2q = 0;
@@ -585,6 +599,7 @@ qk_status run_simulation(qk_mps_batch *b, const double *features_dev, const std:
   int center = 0;
   qk_status st = QK_OK;
   size_t gi = 0;
+  int64_t done2q = 0;
   while (gi < gates.size() && st == QK_OK) {
     const qk_gate &g = gates[gi];
     if (g.op == OP_RZ) {
@@ -612,6 +627,14 @@ qk_status run_simulation(qk_mps_batch *b, const double *features_dev, const std:
     st = launch_step(p, absorb_right ? GATE_RIGHT : GATE_LEFT, g.op == 1 ? OP_RXX : OP_SWAP, g.feat_i, g.feat_j);
     center = absorb_right ? p + 1 : p;
     ++gi;
+    ++done2q;
+    if (st == QK_OK && fn && every > 0 && done2q % every == 0) {
+      if (hipStreamSynchronize(stream) != hipSuccess) {
+        st = fail(QK_EDEVICE, "simulation step failed");
+      } else if (fn(done2q, n2q, user) != 0) {
+        st = fail(QK_EABORTED, "simulation aborted by the progress callback");
+      }
+    }
   }
   while (st == QK_OK && center < m - 1) {
     st = launch_step(center, MOVE_RIGHT, OP_ID, -1, -1);
@@ -626,6 +649,7 @@ qk_status run_simulation(qk_mps_batch *b, const double *features_dev, const std:
   (void)hipFreeAsync(recs_dev, stream);
   if (st != QK_OK) return st;
   QK_HIP_CHECK(hipStreamSynchronize(stream));
+  if (fn && fn(n2q, n2q, user) != 0) return fail(QK_EABORTED, "simulation aborted by the progress callback");
   return QK_OK;
 }
 
