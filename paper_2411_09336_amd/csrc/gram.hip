@@ -265,17 +265,26 @@ __device__ inline int exp_above(double mx) {
 
 __device__ inline uint32_t bf16_bits_exact(float v) { return __float_as_uint(v) >> 16; }
 
-// Four pre-scaled slices n_k 2^-8k (k = 0..3) of xh in (-1, 1), bf16 bits.
-__device__ inline void slice4(double xh, uint32_t (&o)[4]) {
-  double r = xh * 128.0;
-  const float kp[4] = {1.0f, 0x1p-8f, 0x1p-16f, 0x1p-24f};
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const double nk = rint(r);
-    o[k] = bf16_bits_exact(float(nk) * kp[k]);
-    r = (r - nk) * 256.0;
-  }
+// Four pre-scaled slices n_k 2^-8k (k = 0..3) of x * 2^-e (|x| < 2^e), as
+// bf16 bits: X = round(x 2^(31-e)) (saturated to int32) is split into
+// balanced base-256 digits X = n0 2^24 + n1 2^16 + n2 2^8 + n3, with
+// n1..n3 in [-128, 127] and n0 in [-128, 128].
+__device__ inline void slice4e(double x, int e, uint32_t (&o)[4]) {
+  const int X = int(fmin(fmax(rint(ldexp(x, 31 - e)), -2147483647.0), 2147483647.0));
+  const int n3 = int(int8_t(X & 0xff));
+  int r = (X - n3) >> 8;
+  const int n2 = int(int8_t(r & 0xff));
+  r = (r - n2) >> 8;
+  const int n1 = int(int8_t(r & 0xff));
+  const int n0 = (r - n1) >> 8;
+  o[0] = bf16_bits_exact(float(n0));
+  o[1] = bf16_bits_exact(float(n1) * 0x1p-8f);
+  o[2] = bf16_bits_exact(float(n2) * 0x1p-16f);
+  o[3] = bf16_bits_exact(float(n3) * 0x1p-24f);
 }
+
+// Same slices for xh = x 2^-e already in (-1, 1).
+__device__ inline void slice4(double xh, uint32_t (&o)[4]) { slice4e(xh, 0, o); }
 
 struct Sl4 {
   uint4 v[4];
@@ -448,7 +457,7 @@ __device__ void overlap_split(const GramJobDev &J, int64_t ia, int64_t ib, uint8
             for (int q = 0; q < 2; ++q) {
               uint32_t sl[4][4];
 #pragma unroll
-              for (int e = 0; e < 4; ++e) slice4(ldexp(Td[u][q][e], -eT), sl[e]);
+              for (int e = 0; e < 4; ++e) slice4e(Td[u][q][e], eT, sl[e]);
 #pragma unroll
               for (int k = 0; k < 4; ++k)
                 *reinterpret_cast<uint2 *>(tg + (k * 2 + q) * 1024) =
@@ -509,7 +518,8 @@ __device__ void overlap_split(const GramJobDev &J, int64_t ia, int64_t ib, uint8
           }
         }
       }
-      __syncthreads();  // T_s consumed (buffer, exponents and maxima reused)
+      // no barrier here: the T buffer and s_eT are next written after the
+      // following barrier, which every wave reaches only after this GEMM2
     }
     if (last) {
       // E_m[0][0] = E'^T[0][0]: wave 0 (block 0, half 0), lane 0, u = 0, e = 0
@@ -539,7 +549,7 @@ __device__ void overlap_split(const GramJobDev &J, int64_t ia, int64_t ib, uint8
             for (int q = 0; q < 2; ++q) {
               uint32_t sl[4][4];
 #pragma unroll
-              for (int e = 0; e < 4; ++e) slice4(ldexp(Ep[u][q][e], -er), sl[e]);
+              for (int e = 0; e < 4; ++e) slice4e(Ep[u][q][e], er, sl[e]);
 #pragma unroll
               for (int k = 0; k < 4; ++k)
                 *reinterpret_cast<uint2 *>(eg + (k * 2 + q) * 1024) =
@@ -737,8 +747,8 @@ __global__ __launch_bounds__(256) void pack_split_kernel(const double2 *__restri
     for (int v = 0; v < 8; ++v) {
       const int row = 32 * kc + (v < 4 ? 4 * gg + v : 16 + 4 * gg + (v - 4));
       const double2 x = site[(size_t(s) * pl + row) * pr + col];
-      slice4(ldexp(x.x, -e), sl[0][v]);
-      slice4(ldexp(x.y, -e), sl[1][v]);
+      slice4e(x.x, e, sl[0][v]);
+      slice4e(x.y, e, sl[1][v]);
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k)

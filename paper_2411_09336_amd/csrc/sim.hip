@@ -92,6 +92,21 @@ __device__ inline double dpp_shl1(double x) {
                           __builtin_amdgcn_update_dpp(lo, lo, 0x130, 0xf, 0xf, false));
 }
 
+// Sum over the 16 lanes of a DPP row (all 16 lanes receive the total).
+template <int CTRL>
+__device__ inline double dpp_mov(double x) {
+  const int lo = __double2loint(x), hi = __double2hiint(x);
+  return __hiloint2double(__builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xf, 0xf, false),
+                          __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xf, 0xf, false));
+}
+__device__ inline double row_sum16(double x) {
+  x += dpp_mov<0x128>(x);   // row_ror:8
+  x += dpp_mov<0x124>(x);   // row_ror:4
+  x += dpp_mov<0x122>(x);   // row_ror:2
+  x += dpp_mov<0x121>(x);   // row_ror:1
+  return x;
+}
+
 __device__ inline double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
@@ -250,14 +265,8 @@ __global__ __launch_bounds__(kSvThreads) void svd_step_kernel(SvParams P) {
       __syncthreads();
       {
         const int pr = tid >> 4, w = tid & 15;
-        double a = s_part[0][w][pr], b = s_part[1][w][pr], x = s_part[2][w][pr], y = s_part[3][w][pr];
-#pragma unroll
-        for (int o = 8; o > 0; o >>= 1) {
-          a += __shfl_xor(a, o, 16);
-          b += __shfl_xor(b, o, 16);
-          x += __shfl_xor(x, o, 16);
-          y += __shfl_xor(y, o, 16);
-        }
+        const double a = row_sum16(s_part[0][w][pr]), b = row_sum16(s_part[1][w][pr]);
+        const double x = row_sum16(s_part[2][w][pr]), y = row_sum16(s_part[3][w][pr]);
         if (w == 0 && pr < H) {
           double c = 1.0, s = 0.0, ur = 1.0, ui = 0.0;
           const double gabs = sqrt(x * x + y * y);
@@ -326,12 +335,7 @@ __global__ __launch_bounds__(kSvThreads) void svd_step_kernel(SvParams P) {
     s_part[1][wave][lane] = nb;
     __syncthreads();
     const int pr = tid >> 4, w = tid & 15;
-    double a = s_part[0][w][pr], b = s_part[1][w][pr];
-#pragma unroll
-    for (int o = 8; o > 0; o >>= 1) {
-      a += __shfl_xor(a, o, 16);
-      b += __shfl_xor(b, o, 16);
-    }
+    const double a = row_sum16(s_part[0][w][pr]), b = row_sum16(s_part[1][w][pr]);
     if (w == 0) {
       s_norm[2 * pr] = (2 * pr < NP) ? a : 0.0;
       s_norm[2 * pr + 1] = (2 * pr + 1 < NP) ? b : 0.0;

@@ -85,3 +85,48 @@ def test_simulated_gram_invariants():
     assert np.array_equal(K, K.T)
     assert K.min() >= 0 and K.max() <= 1 + 1e-12
     assert np.linalg.eigvalsh(K).min() > -1e-10
+
+
+def test_routing1_truncated_vs_oracle():
+    w = sd.WORKLOADS["fp32"]
+    X = sd.workload_features(w, 3)
+    b = _sim(X, w, chi=16, routing=1)
+    dims = b.bond_dims()
+    for i in range(3):
+        r = omps.simulate(X[i], w.distance, w.reps, 16, w.cutoff, w.coef_z, w.coef_xx, routing=1)
+        f = fidelity(b.export(i), r.tensors)
+        print("routing 1", i, "fidelity", f)
+        if r.degenerate_cuts == 0:
+            assert f > 1 - 1e-10
+            assert list(dims[i]) == r.bond_dims
+
+
+def test_precision_workload_split_vs_fp64():
+    """100 qubits, d = 4, chi = 64 (GPU-simulated) plus near-duplicates:
+    split-BF16 vs FP64 on the GPU and both vs the oracle on the same MPS."""
+    import paper_2411_09336_amd as q
+    w = sd.WORKLOADS["precision"]
+    X = sd.workload_features(w, 3)
+    X = np.vstack([X, sd.perturb_near_duplicates(X[:2])])
+    b = _sim(X, w)
+    Kd = q.gram(b, precision="fp64").cpu().numpy()
+    Ks = q.gram(b, precision="split_bf16").cpu().numpy()
+    Kf = q.gram(b, precision="fp32").cpu().numpy()
+    Ko = ogram.gram([b.export(i) for i in range(len(X))])
+    print("split vs fp64", np.abs(Ks - Kd).max(), "fp32 vs fp64", np.abs(Kf - Kd).max(),
+          "fp64 vs oracle", np.abs(Kd - Ko).max(), "K near-dup", Kd[0, 3], Kd[1, 4])
+    assert np.abs(Kd - Ko).max() < 1e-12
+    assert np.abs(Ks - Kd).max() < 1e-7
+    assert Kd[0, 3] > 0.05 and Kd[1, 4] > 0.05
+
+
+def test_tiny_gpu_gram_matches_golden():
+    import os
+    import paper_2411_09336_amd as q
+    K_gold = np.load(os.path.join(os.path.dirname(__file__), "golden", "tiny_gram_statevector.npy"))
+    w = sd.WORKLOADS["tiny"]
+    b = _sim(sd.workload_features(w), w)
+    for prec, tol in (("fp64", 1e-12), ("split_bf16", 1e-7), ("fp32", 1e-5)):
+        K = q.gram(b, precision=prec).cpu().numpy()
+        print(prec, "max|dK| vs golden", np.abs(K - K_gold).max())
+        assert np.abs(K - K_gold).max() < tol

@@ -210,3 +210,16 @@ def test_truncated_gram_invariants():
     assert np.linalg.eigvalsh(K).min() > -1e-12
     # the near-duplicates give mid-range kernel values
     assert K[np.arange(4), 12 + np.arange(4)].min() > 0.05
+
+
+def test_tiny_workload_matches_golden_statevector_gram():
+    """The stored statevector Gram (tests/golden/make_golden.py) pins the MPS
+    oracle on the tiny workload end to end."""
+    import os
+    K_gold = np.load(os.path.join(os.path.dirname(__file__), "golden", "tiny_gram_statevector.npy"))
+    w = sd.WORKLOADS["tiny"]
+    X = sd.workload_features(w)
+    res = [mps.simulate(x, w.distance, w.reps, w.chi, w.cutoff, w.coef_z, w.coef_xx) for x in X[:16]]
+    K = gram.gram([r.tensors for r in res])
+    assert np.abs(K - K_gold[:16, :16]).max() < 1e-12
+    assert np.allclose(np.diag(K_gold), 1.0, atol=1e-12)
