@@ -272,7 +272,9 @@ def run(args):
     fpe = flops_per_entry(d0, d0)
     flops_launch = fpe * n_comp
     achieved_tf = flops_launch / t_split / 1e12
-    issued_tf = achieved_tf * 44 / 8     # 11 slice pairs x 4 real products per complex MAC
+    # a complex MAC is 8 algorithmic flops; the split form issues 11 slice
+    # products x 4 real products = 44 real MACs = 88 flops for it
+    issued_tf = achieved_tf * 11
     traffic, crec = counter_traffic()
     roof = {"bound": "mfma", "achieved": round(achieved_tf, 3), "peak": PEAK_TFLOPS["bf16"], "unit": "TFLOP/s",
             "frac": round(achieved_tf / PEAK_TFLOPS["bf16"], 5), "traffic": traffic,

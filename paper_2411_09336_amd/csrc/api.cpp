@@ -77,7 +77,7 @@ static void compute_layout(qk_mps_batch *b) {
   b->split_off.assign(m + 1, 0);
   for (int l = 0; l < m; ++l) {
     b->site_off[l + 1] = b->site_off[l] + int64_t(2) * b->pad[l] * b->pad[l + 1];
-    b->split_off[l + 1] = b->split_off[l] + split_site_bytes(b->pad[l], b->pad[l + 1]);
+    b->split_off[l + 1] = b->split_off[l] + split_site_bytes();
   }
   b->mps_stride = b->site_off[m];
   b->split_stride = b->split_off[m];
@@ -155,6 +155,8 @@ qk_status batch_ensure_packed(qk_mps_batch *b, qk_precision prec, hipStream_t st
   }
   if (prec == QK_SPLIT_BF16) {
     if (b->sbf16) return QK_OK;
+    if (*std::max_element(b->pad.begin(), b->pad.end()) > kSplitMaxPad)
+      return fail(QK_ENOTSUP, "the split-BF16 form supports bond dimensions up to 64");
     size_t bytes = size_t(std::max<int64_t>(b->n, 1)) * size_t(b->split_stride);
     if (hipMalloc((void **)&b->sbf16, bytes) != hipSuccess) {
       (void)hipGetLastError();

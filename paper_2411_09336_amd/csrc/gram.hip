@@ -259,8 +259,11 @@ __device__ void overlap_plain(const GramJobDev &J, int64_t ia, int64_t ib, T2 *E
 // E lives in LDS as slices plus one exponent per row; T and E' are formed in
 // FP64 registers and re-sliced for the next GEMM.
 __device__ inline int exp_above(double mx) {
-  // smallest e with mx < 2^e (0 for mx == 0)
-  return mx > 0.0 ? ilogb(mx) + 1 : 0;
+  // Smallest e with mx (1 + 2^-30) < 2^e (0 for mx == 0).  The margin keeps
+  // |x| 2^(31-e) below 2^31 - 1 after rounding for every |x| <= mx, so the
+  // 31-bit fixed-point code never saturates (saturation would bias values
+  // just below a power of two, e.g. the unit diagonal of a self-overlap).
+  return mx > 0.0 ? ilogb(mx * (1.0 + 0x1p-30)) + 1 : 0;
 }
 
 __device__ inline uint32_t bf16_bits_exact(float v) { return __float_as_uint(v) >> 16; }
@@ -268,15 +271,22 @@ __device__ inline uint32_t bf16_bits_exact(float v) { return __float_as_uint(v) 
 // Four pre-scaled slices n_k 2^-8k (k = 0..3) of x * 2^-e (|x| < 2^e), as
 // bf16 bits: X = round(x 2^(31-e)) (saturated to int32) is split into
 // balanced base-256 digits X = n0 2^24 + n1 2^16 + n2 2^8 + n3, with
-// n1..n3 in [-128, 127] and n0 in [-128, 128].
+// n1..n3 in [-128, 127] and n0 in [-128, 128].  Each step takes the low byte
+// as a signed digit and carries one when it is negative; the carry is formed
+// from the shifted value, never from X - digit, which overflows int32 for X
+// near 2^31 (values just below the top of their exponent range).
+__device__ inline int balanced_digit(int &r) {
+  const int d = int(int8_t(r & 0xff));
+  r = (r >> 8) + ((r >> 7) & 1);
+  return d;
+}
+
 __device__ inline void slice4e(double x, int e, uint32_t (&o)[4]) {
-  const int X = int(fmin(fmax(rint(ldexp(x, 31 - e)), -2147483647.0), 2147483647.0));
-  const int n3 = int(int8_t(X & 0xff));
-  int r = (X - n3) >> 8;
-  const int n2 = int(int8_t(r & 0xff));
-  r = (r - n2) >> 8;
-  const int n1 = int(int8_t(r & 0xff));
-  const int n0 = (r - n1) >> 8;
+  int r = int(fmin(fmax(rint(ldexp(x, 31 - e)), -2147483647.0), 2147483647.0));
+  const int n3 = balanced_digit(r);
+  const int n2 = balanced_digit(r);
+  const int n1 = balanced_digit(r);
+  const int n0 = r;
   o[0] = bf16_bits_exact(float(n0));
   o[1] = bf16_bits_exact(float(n1) * 0x1p-8f);
   o[2] = bf16_bits_exact(float(n2) * 0x1p-16f);
@@ -328,207 +338,224 @@ __device__ inline Sl4 make_slices(const double (&xh)[8]) {
   return r;
 }
 
-// Work split per site (eight waves, MAXP = 64): wave w owns column block
-// c = w % 4 and row half h = w / 4.  GEMM1: T_s[rows 32h..32h+31][ket block c];
-// the exponent of each T^T row (ket column) combines both halves through LDS;
-// T is written to LDS as slices.  GEMM2: E'^T[rows (ket) 32h..][bra block c].
-// Each wave streams a quarter of each site tensor (shared with its sibling
-// through L1) and two waves per SIMD overlap MFMA with VALU and loads.
+// Work split per site (eight waves): wave w owns column block c = w % 4 and
+// row half h = w / 4.  GEMM1 produces T_s[rows 32h..32h+31][ket block c]; the
+// exponent of each T^T row (ket column) combines both halves through LDS and
+// T is stored in LDS as slices.  GEMM2 produces E'^T[ket rows 32h..][bra
+// block c].  Two 64 KiB LDS buffers alternate roles so that slicing one
+// operand overlaps the MFMAs of the next GEMM:
+//   1. GEMM1(s=0) reads E (buffer X)                     -> T0 in registers
+//   2. slice T0 -> Y            ||  GEMM1(s=1) reads X    -> T1 in registers
+//   3. slice T1 -> X            ||  GEMM2(s=0) reads Y    (E no longer needed)
+//   4. GEMM2(s=1) reads X; E' row exponents
+//   5. slice E' -> Y, which holds E for the next site (X and Y swap).
+// The split form is stored with 64 x 64 blocks at every site, so the body is
+// straight-line code.
 constexpr int kSplitThreads = 512;
+constexpr int kSP = 64;
+
+struct SplitCtx {
+  int lane, j, g, cb, hf;
+};
+
+__device__ inline uint4 split_frag(const uint8_t *site, int s, int k, int q, int kc, int c, int lane) {
+  return *reinterpret_cast<const uint4 *>(
+      site + kSplitExpBytes + (size_t(((((s * 4 + k) * 2 + q) * 2 + kc) * 4 + c)) * 1024 + lane * 16));
+}
+
+// GEMM1 for physical index s: T[a][b'] (a in rows 32h.., b' in block c) in
+// FP64, and the local max |T| over this wave's part of each T^T row.
+__device__ inline void split_gemm1(const SplitCtx &C, const uint8_t *B, const uint8_t *Ebuf, const int *s_ea, int s,
+                                   double (&Td)[2][2][4], double &tmax) {
+  f32x4 h1[2][2], l1[2][2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      h1[u][q] = f32x4{0, 0, 0, 0};
+      l1[u][q] = f32x4{0, 0, 0, 0};
+    }
+#pragma unroll
+  for (int kc = 0; kc < 2; ++kc) {
+    Sl4 Br, Bi;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      Br.v[k] = split_frag(B, s, k, 0, kc, C.cb, C.lane);
+      Bi.v[k] = split_frag(B, s, k, 1, kc, C.cb, C.lane);
+    }
+    const Sl4 Bin = neg4(Bi);
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int rt = 2 * C.hf + u;
+      const uint8_t *eg = Ebuf + size_t(rt * 2 + kc) * 8192 + C.lane * 16;
+      Sl4 Er, Ei;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        Er.v[k] = *reinterpret_cast<const uint4 *>(eg + (k * 2 + 0) * 1024);
+        Ei.v[k] = *reinterpret_cast<const uint4 *>(eg + (k * 2 + 1) * 1024);
+      }
+      // re += Er Br - Ei Bi ; im += Er Bi + Ei Br
+      slice_mac(Er, Br, h1[u][0], l1[u][0]);
+      slice_mac(Ei, Bin, h1[u][0], l1[u][0]);
+      slice_mac(Er, Bi, h1[u][1], l1[u][1]);
+      slice_mac(Ei, Br, h1[u][1], l1[u][1]);
+    }
+  }
+  const int ebc = int(reinterpret_cast<const int8_t *>(B)[s * 128 + 16 * C.cb + C.j]);
+  tmax = 0.0;
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int rt = 2 * C.hf + u;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int ex = s_ea[16 * rt + 4 * C.g + e] + ebc - 14;
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const double v = ldexp(double(h1[u][q][e]) + double(l1[u][q][e]), ex);
+        Td[u][q][e] = v;
+        tmax = fmax(tmax, fabs(v));
+      }
+    }
+  }
+  tmax = fmax(tmax, __shfl_xor(tmax, 16, 64));
+  tmax = fmax(tmax, __shfl_xor(tmax, 32, 64));
+}
+
+// Slice four 4-value rows (u = 0, 1; q = re, im) with exponent ex into LDS
+// group row `grow` of buffer `buf`: A-operand group (grow, kc = u2 >> 1) where
+// u2 = 2 h + u is the 16-row tile of the contraction index.
+__device__ inline void split_store(const SplitCtx &C, uint8_t *buf, int grow, const double (&V)[2][2][4], int ex) {
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int t = 2 * C.hf + u;
+    uint8_t *dst = buf + size_t(grow * 2 + (t >> 1)) * 8192 + C.lane * 16 + (t & 1) * 8;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      uint32_t sl[4][4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) slice4e(V[u][q][e], ex, sl[e]);
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        *reinterpret_cast<uint2 *>(dst + (k * 2 + q) * 1024) =
+            make_uint2(sl[0][k] | (sl[1][k] << 16), sl[2][k] | (sl[3][k] << 16));
+    }
+  }
+}
+
+// GEMM2 for physical index s: E'^T[b'][a'] += sum_a T_s[a][b'] conj(A_s[a][a'])
+// with b' in rows 32h.., a' in bra block c.
+__device__ inline void split_gemm2(const SplitCtx &C, const uint8_t *A, const uint8_t *Tbuf, const int *s_eTs, int s,
+                                   double (&Ep)[2][2][4]) {
+  f32x4 h2[2][2], l2[2][2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      h2[u][q] = f32x4{0, 0, 0, 0};
+      l2[u][q] = f32x4{0, 0, 0, 0};
+    }
+#pragma unroll
+  for (int kc = 0; kc < 2; ++kc) {
+    Sl4 Ar, Ai;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      Ar.v[k] = split_frag(A, s, k, 0, kc, C.cb, C.lane);
+      Ai.v[k] = split_frag(A, s, k, 1, kc, C.cb, C.lane);
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int bt = 2 * C.hf + u;
+      const uint8_t *tg = Tbuf + size_t(bt * 2 + kc) * 8192 + C.lane * 16;
+      Sl4 Tr, Ti;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        Tr.v[k] = *reinterpret_cast<const uint4 *>(tg + (k * 2 + 0) * 1024);
+        Ti.v[k] = *reinterpret_cast<const uint4 *>(tg + (k * 2 + 1) * 1024);
+      }
+      const Sl4 Trn = neg4(Tr);
+      // re += Tr Ar + Ti Ai ; im += Ti Ar - Tr Ai
+      slice_mac(Tr, Ar, h2[u][0], l2[u][0]);
+      slice_mac(Ti, Ai, h2[u][0], l2[u][0]);
+      slice_mac(Ti, Ar, h2[u][1], l2[u][1]);
+      slice_mac(Trn, Ai, h2[u][1], l2[u][1]);
+    }
+  }
+  const int eac = int(reinterpret_cast<const int8_t *>(A)[s * 128 + 16 * C.cb + C.j]);
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int bt = 2 * C.hf + u;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int ex = s_eTs[16 * bt + 4 * C.g + e] + eac - 14;
+#pragma unroll
+      for (int q = 0; q < 2; ++q) Ep[u][q][e] += ldexp(double(h2[u][q][e]) + double(l2[u][q][e]), ex);
+    }
+  }
+}
 
 template <int MAXP>
-__device__ void overlap_split(const GramJobDev &J, int64_t ia, int64_t ib, uint8_t *E, uint8_t *Tl, int *s_ea,
-                              int *s_eT, double *s_mx, double *s_ov, double &ov_re, double &ov_im, int &ov_exp) {
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int j = lane & 15, g = lane >> 4;
-  const int cb = wave & 3, hf = wave >> 2;
+__device__ void overlap_split(const GramJobDev &J, int64_t ia, int64_t ib, uint8_t *buf0, uint8_t *buf1,
+                              int *s_ea, int *s_eT, double *s_mx, double *s_ov, double &ov_re, double &ov_im,
+                              int &ov_exp) {
+  static_assert(MAXP == kSP, "the split form uses 64 x 64 site blocks");
+  const int tid = threadIdx.x, wave = tid >> 6;
+  SplitCtx C;
+  C.lane = tid & 63;
+  C.j = C.lane & 15;
+  C.g = C.lane >> 4;
+  C.cb = wave & 3;
+  C.hf = wave >> 2;
   const uint8_t *abase = reinterpret_cast<const uint8_t *>(J.a_base) + ia * J.a_stride;
   const uint8_t *bbase = reinterpret_cast<const uint8_t *>(J.b_base) + ib * J.b_stride;
-  // LDS operand groups (row tile, k chunk) = [slice 4][plane 2][lane 64][16 B] = 8 KiB
-  auto lgroup = [&](uint8_t *base, int rt, int kc, int nkc) -> uint8_t * {
-    return base + size_t(rt * nkc + kc) * 8192;
-  };
+  uint8_t *X = buf0, *Y = buf1;
   {
-    const int nbytes = J.a_pad[0] * J.b_pad[0] * 16;
-    uint32_t *E32 = reinterpret_cast<uint32_t *>(E);
-    for (int x = tid; x < nbytes / 4; x += kSplitThreads) E32[x] = 0u;
-    for (int x = tid; x < MAXP; x += kSplitThreads) s_ea[x] = 0;
+    uint4 *X16 = reinterpret_cast<uint4 *>(X);
+    for (int x = tid; x < kSP * kSP; x += kSplitThreads) X16[x] = make_uint4(0, 0, 0, 0);
+    for (int x = tid; x < kSP; x += kSplitThreads) s_ea[x] = 0;
     __syncthreads();
     // E_0 = [[1]]: row exponent 1, leading slice 64 (= 0.5 * 128)
     if (tid == 0) {
-      reinterpret_cast<uint16_t *>(E)[0] = uint16_t(bf16_bits_exact(64.0f));
+      reinterpret_cast<uint16_t *>(X)[0] = uint16_t(bf16_bits_exact(64.0f));
       s_ea[0] = 1;
     }
     __syncthreads();
   }
-  constexpr int NT = MAXP / 16;
-  static_assert(NT == 4, "four 16-column blocks");
+  const int col = 16 * C.cb + C.j;
   for (int l = 0; l < J.m; ++l) {
-    const int Da = J.a_pad[l], Dan = J.a_pad[l + 1], Db = J.b_pad[l], Dbn = J.b_pad[l + 1];
     const uint8_t *A = abase + J.a_off[l];
     const uint8_t *B = bbase + J.b_off[l];
-    const int8_t *eA = reinterpret_cast<const int8_t *>(A);
-    const int8_t *eB = reinterpret_cast<const int8_t *>(B);
-    const int nrt = Da / 16, nkcb = Db / 32, nkca = Da / 32, nat = Dan / 16, nct = Dbn / 16;
-    const int nkcn = Dbn / 32;
-    const bool last = (l + 1 == J.m);
-    auto frag = [&](const uint8_t *site, int s, int k, int q, int kc, int c, int nkc, int ncol) {
-      return *reinterpret_cast<const uint4 *>(
-          site + kSplitExpBytes + ((size_t((((s * 4 + k) * 2 + q) * nkc + kc)) * ncol + c) * 1024 + lane * 16));
-    };
-    double Ep[2][2][4];   // E'^T[16 (2 hf + u) + 4 g + e][16 cb + j], summed over s
+    double Td0[2][2][4], Td1[2][2][4], Ep[2][2][4];
+    double tmax;
 #pragma unroll
     for (int u = 0; u < 2; ++u)
 #pragma unroll
       for (int q = 0; q < 2; ++q)
 #pragma unroll
         for (int e = 0; e < 4; ++e) Ep[u][q][e] = 0.0;
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      // ---- GEMM1: T_s[a][b'] = sum_b E[a][b] B_s[b][b'], b' in block cb, a in half hf
-      double Td[2][2][4];
-      double tmax = 0.0;
-      const bool g1 = cb < nct;
-      if (g1) {
-        f32x4 h1[2][2], l1[2][2];
-#pragma unroll
-        for (int u = 0; u < 2; ++u)
-#pragma unroll
-          for (int q = 0; q < 2; ++q) {
-            h1[u][q] = f32x4{0, 0, 0, 0};
-            l1[u][q] = f32x4{0, 0, 0, 0};
-          }
-        for (int kc = 0; kc < nkcb; ++kc) {
-          Sl4 Br, Bi;
-#pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            Br.v[k] = frag(B, s, k, 0, kc, cb, nkcb, nct);
-            Bi.v[k] = frag(B, s, k, 1, kc, cb, nkcb, nct);
-          }
-          const Sl4 Bin = neg4(Bi);
-#pragma unroll
-          for (int u = 0; u < 2; ++u) {
-            const int rt = 2 * hf + u;
-            if (rt < nrt) {
-              const uint8_t *eg = lgroup(E, rt, kc, nkcb) + lane * 16;
-              Sl4 Er, Ei;
-#pragma unroll
-              for (int k = 0; k < 4; ++k) {
-                Er.v[k] = *reinterpret_cast<const uint4 *>(eg + (k * 2 + 0) * 1024);
-                Ei.v[k] = *reinterpret_cast<const uint4 *>(eg + (k * 2 + 1) * 1024);
-              }
-              // re += Er Br - Ei Bi ; im += Er Bi + Ei Br
-              slice_mac(Er, Br, h1[u][0], l1[u][0]);
-              slice_mac(Ei, Bin, h1[u][0], l1[u][0]);
-              slice_mac(Er, Bi, h1[u][1], l1[u][1]);
-              slice_mac(Ei, Br, h1[u][1], l1[u][1]);
-            }
-          }
-        }
-        const int ebc = int(eB[s * 128 + 16 * cb + j]);
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-          const int rt = 2 * hf + u;
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int ex = (rt < nrt ? s_ea[16 * rt + 4 * g + e] : 0) + ebc - 14;
-#pragma unroll
-            for (int q = 0; q < 2; ++q) {
-              const double v = rt < nrt ? ldexp(double(h1[u][q][e]) + double(l1[u][q][e]), ex) : 0.0;
-              Td[u][q][e] = v;
-              tmax = fmax(tmax, fabs(v));
-            }
-          }
-        }
-        tmax = fmax(tmax, __shfl_xor(tmax, 16, 64));
-        tmax = fmax(tmax, __shfl_xor(tmax, 32, 64));
-        if (g == 0) s_mx[hf * MAXP + 16 * cb + j] = tmax;
-      }
-      __syncthreads();  // both halves' T^T row maxima visible
-      if (g1) {
-        const int eT = exp_above(fmax(s_mx[16 * cb + j], s_mx[MAXP + 16 * cb + j]));
-        if (hf == 0 && g == 0) s_eT[16 * cb + j] = eT;
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-          const int rt = 2 * hf + u;
-          if (rt < nrt) {
-            uint8_t *tg = lgroup(Tl, cb, rt >> 1, nkca) + lane * 16 + (rt & 1) * 8;
-#pragma unroll
-            for (int q = 0; q < 2; ++q) {
-              uint32_t sl[4][4];
-#pragma unroll
-              for (int e = 0; e < 4; ++e) slice4e(Td[u][q][e], eT, sl[e]);
-#pragma unroll
-              for (int k = 0; k < 4; ++k)
-                *reinterpret_cast<uint2 *>(tg + (k * 2 + q) * 1024) =
-                    make_uint2(sl[0][k] | (sl[1][k] << 16), sl[2][k] | (sl[3][k] << 16));
-            }
-          }
-        }
-      }
-      __syncthreads();  // T_s complete in LDS
-      // ---- GEMM2: E'^T[b'][a'] += sum_a T_s[a][b'] conj(A_s[a][a']), a' in block cb, b' in half hf
-      if (cb < nat) {
-        f32x4 h2[2][2], l2[2][2];
-#pragma unroll
-        for (int u = 0; u < 2; ++u)
-#pragma unroll
-          for (int q = 0; q < 2; ++q) {
-            h2[u][q] = f32x4{0, 0, 0, 0};
-            l2[u][q] = f32x4{0, 0, 0, 0};
-          }
-        for (int kc = 0; kc < nkca; ++kc) {
-          Sl4 Ar, Ai;
-#pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            Ar.v[k] = frag(A, s, k, 0, kc, cb, nkca, nat);
-            Ai.v[k] = frag(A, s, k, 1, kc, cb, nkca, nat);
-          }
-#pragma unroll
-          for (int u = 0; u < 2; ++u) {
-            const int bt = 2 * hf + u;
-            if (bt < nct) {
-              const uint8_t *tg = lgroup(Tl, bt, kc, nkca) + lane * 16;
-              Sl4 Tr, Ti;
-#pragma unroll
-              for (int k = 0; k < 4; ++k) {
-                Tr.v[k] = *reinterpret_cast<const uint4 *>(tg + (k * 2 + 0) * 1024);
-                Ti.v[k] = *reinterpret_cast<const uint4 *>(tg + (k * 2 + 1) * 1024);
-              }
-              const Sl4 Trn = neg4(Tr);
-              // re += Tr Ar + Ti Ai ; im += Ti Ar - Tr Ai
-              slice_mac(Tr, Ar, h2[u][0], l2[u][0]);
-              slice_mac(Ti, Ai, h2[u][0], l2[u][0]);
-              slice_mac(Ti, Ar, h2[u][1], l2[u][1]);
-              slice_mac(Trn, Ai, h2[u][1], l2[u][1]);
-            }
-          }
-        }
-        const int eac = int(eA[s * 128 + 16 * cb + j]);
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-          const int bt = 2 * hf + u;
-          if (bt < nct) {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-              const int ex = s_eT[16 * bt + 4 * g + e] + eac - 14;
-#pragma unroll
-              for (int q = 0; q < 2; ++q) Ep[u][q][e] += ldexp(double(h2[u][q][e]) + double(l2[u][q][e]), ex);
-            }
-          }
-        }
-      }
-      // no barrier here: the T buffer and s_eT are next written after the
-      // following barrier, which every wave reaches only after this GEMM2
+    // 1. GEMM1(s = 0)
+    split_gemm1(C, B, X, s_ea, 0, Td0, tmax);
+    if (C.g == 0) s_mx[(0 * 2 + C.hf) * kSP + col] = tmax;
+    __syncthreads();
+    // 2. slice T0 -> Y  ||  GEMM1(s = 1)
+    {
+      const int eT0 = exp_above(fmax(s_mx[(0 * 2 + 0) * kSP + col], s_mx[(0 * 2 + 1) * kSP + col]));
+      if (C.hf == 0 && C.g == 0) s_eT[0 * kSP + col] = eT0;
+      split_store(C, Y, C.cb, Td0, eT0);
+      split_gemm1(C, B, X, s_ea, 1, Td1, tmax);
+      if (C.g == 0) s_mx[(1 * 2 + C.hf) * kSP + col] = tmax;
     }
-    if (last) {
-      // E_m[0][0] = E'^T[0][0]: wave 0 (block 0, half 0), lane 0, u = 0, e = 0
-      if (wave == 0 && lane == 0) {
-        s_ov[0] = Ep[0][0][0];
-        s_ov[1] = Ep[0][1][0];
-      }
-    } else {
-      // E' row a' = 16 cb + j: max over this wave's ket rows, combined with the sibling half
+    __syncthreads();
+    // 3. slice T1 -> X  ||  GEMM2(s = 0)
+    {
+      const int eT1 = exp_above(fmax(s_mx[(1 * 2 + 0) * kSP + col], s_mx[(1 * 2 + 1) * kSP + col]));
+      if (C.hf == 0 && C.g == 0) s_eT[1 * kSP + col] = eT1;
+      split_store(C, X, C.cb, Td1, eT1);
+      split_gemm2(C, A, Y, s_eT, 0, Ep);
+    }
+    __syncthreads();
+    // 4. GEMM2(s = 1) and the row maxima of E' (rows a' = 16 c + j)
+    split_gemm2(C, A, X, s_eT + kSP, 1, Ep);
+    {
       double rm = 0.0;
 #pragma unroll
       for (int u = 0; u < 2; ++u)
@@ -536,31 +563,25 @@ __device__ void overlap_split(const GramJobDev &J, int64_t ia, int64_t ib, uint8
         for (int e = 0; e < 4; ++e) rm = fmax(rm, fmax(fabs(Ep[u][0][e]), fabs(Ep[u][1][e])));
       rm = fmax(rm, __shfl_xor(rm, 16, 64));
       rm = fmax(rm, __shfl_xor(rm, 32, 64));
-      if (g == 0) s_mx[hf * MAXP + 16 * cb + j] = rm;
-      __syncthreads();
-      if (cb < nat) {
-        const int er = exp_above(fmax(s_mx[16 * cb + j], s_mx[MAXP + 16 * cb + j]));
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-          const int bt = 2 * hf + u;
-          if (bt < nct) {
-            uint8_t *eg = lgroup(E, cb, bt >> 1, nkcn) + lane * 16 + (bt & 1) * 8;
-#pragma unroll
-            for (int q = 0; q < 2; ++q) {
-              uint32_t sl[4][4];
-#pragma unroll
-              for (int e = 0; e < 4; ++e) slice4e(Ep[u][q][e], er, sl[e]);
-#pragma unroll
-              for (int k = 0; k < 4; ++k)
-                *reinterpret_cast<uint2 *>(eg + (k * 2 + q) * 1024) =
-                    make_uint2(sl[0][k] | (sl[1][k] << 16), sl[2][k] | (sl[3][k] << 16));
-            }
-          }
-        }
-        if (hf == 0 && g == 0) s_ea[16 * cb + j] = er;
-      }
+      if (C.g == 0) s_mx[(0 * 2 + C.hf) * kSP + col] = rm;
     }
     __syncthreads();
+    // 5. E' -> Y (E of the next site)
+    if (l + 1 == J.m) {
+      // E_m[0][0] = E'^T[0][0]: block 0, half 0, lane 0, u = 0, e = 0
+      if (wave == 0 && C.lane == 0) {
+        s_ov[0] = Ep[0][0][0];
+        s_ov[1] = Ep[0][1][0];
+      }
+    } else {
+      const int er = exp_above(fmax(s_mx[(0 * 2 + 0) * kSP + col], s_mx[(0 * 2 + 1) * kSP + col]));
+      split_store(C, Y, C.cb, Ep, er);
+      if (C.hf == 0 && C.g == 0) s_ea[col] = er;
+    }
+    __syncthreads();
+    uint8_t *t = X;
+    X = Y;
+    Y = t;
   }
   ov_re = s_ov[0];
   ov_im = s_ov[1];
@@ -582,8 +603,8 @@ __global__ __launch_bounds__(threads_of<PREC>()) void gram_kernel(const GramJobD
   __shared__ double s_red[4];
   __shared__ double s_ov[2];
   __shared__ int s_ea[MAXP];
-  __shared__ int s_eT[MAXP];
-  __shared__ double s_mx[2 * MAXP];
+  __shared__ int s_eT[2 * MAXP];
+  __shared__ double s_mx[4 * MAXP];
   int job;
   int64_t i, j;
   bool valid;
@@ -704,7 +725,8 @@ __global__ void pack_f32_kernel(const double2 *__restrict__ src, float2 *__restr
 
 // One block per (site, mps): column exponents e[s][c] (max |x| < 2^e over the
 // column's rows and both planes), then the four fixed-point slices of every
-// value, in B-operand fragment order.
+// value, in B-operand fragment order, on a 64 x 64 block (zero beyond the
+// batch's pads).
 __global__ __launch_bounds__(256) void pack_split_kernel(const double2 *__restrict__ src, uint8_t *__restrict__ dst,
                                                          const int32_t *__restrict__ pad,
                                                          const int64_t *__restrict__ site_off,
@@ -715,7 +737,6 @@ __global__ __launch_bounds__(256) void pack_split_kernel(const double2 *__restri
   if (i >= n || l >= m) return;
   __shared__ int s_e[2 * 128];
   const int pl = pad[l], pr = pad[l + 1];
-  const int nkc = pl / 32, nct = pr / 16;
   const double2 *site = src + i * mps_stride + site_off[l];
   uint8_t *out = dst + i * split_stride + split_off[l];
   for (int t = threadIdx.x; t < 2 * 128; t += blockDim.x) {
@@ -727,18 +748,18 @@ __global__ __launch_bounds__(256) void pack_split_kernel(const double2 *__restri
         const double2 x = site[(size_t(s) * pl + r) * pr + c];
         mx = fmax(mx, fmax(fabs(x.x), fabs(x.y)));
       }
-      e = exp_above(mx);
+      e = max(exp_above(mx), -127);   // int8 storage; |x| < 2^e still holds
     }
     s_e[t] = e;
     out[t] = uint8_t(int8_t(e));
   }
   __syncthreads();
-  const int work = 2 * nkc * nct * 64;
+  const int work = 2 * 2 * 4 * 64;   // (s, kc, ct, lane)
   for (int w = threadIdx.x; w < work; w += blockDim.x) {
     const int lane = w % 64;
-    const int ct = (w / 64) % nct;
-    const int kc = (w / (64 * nct)) % nkc;
-    const int s = w / (64 * nct * nkc);
+    const int ct = (w / 64) % 4;
+    const int kc = (w / 256) % 2;
+    const int s = w / 512;
     const int jj = lane & 15, gg = lane >> 4;
     const int col = 16 * ct + jj;
     const int e = s_e[s * 128 + col];
@@ -746,7 +767,8 @@ __global__ __launch_bounds__(256) void pack_split_kernel(const double2 *__restri
 #pragma unroll
     for (int v = 0; v < 8; ++v) {
       const int row = 32 * kc + (v < 4 ? 4 * gg + v : 16 + 4 * gg + (v - 4));
-      const double2 x = site[(size_t(s) * pl + row) * pr + col];
+      double2 x = make_double2(0.0, 0.0);
+      if (row < pl && col < pr) x = site[(size_t(s) * pl + row) * pr + col];
       slice4e(x.x, e, sl[0][v]);
       slice4e(x.y, e, sl[1][v]);
     }
@@ -759,8 +781,8 @@ __global__ __launch_bounds__(256) void pack_split_kernel(const double2 *__restri
         o.y = sl[q][2][k] | (sl[q][3][k] << 16);
         o.z = sl[q][4][k] | (sl[q][5][k] << 16);
         o.w = sl[q][6][k] | (sl[q][7][k] << 16);
-        *reinterpret_cast<uint4 *>(out + kSplitExpBytes +
-                                   ((size_t(((s * 4 + k) * 2 + q) * nkc + kc) * nct + ct) * 1024 + lane * 16)) = o;
+        *reinterpret_cast<uint4 *>(out + kSplitExpBytes + ((size_t(((s * 4 + k) * 2 + q) * 2 + kc) * 4 + ct) * 1024 +
+                                                           lane * 16)) = o;
       }
   }
 }

@@ -31,7 +31,8 @@ inline int pad_of(int d) { return ((d + kPadQuantum - 1) / kPadQuantum) * kPadQu
 // Split-BF16 operand form (fixed-point slices).  Every real value x of a
 // site tensor column c (per physical index s) is written as
 //   x = 2^(e[s][c] - 7) * (n0 + n1 2^-8 + n2 2^-16 + n3 2^-24) + O(2^(e-32))
-// with a shared column exponent e[s][c] (max |x| of the column < 2^e) and
+// with a shared column exponent e[s][c] (max |x| of the column times
+// 1 + 2^-30 is below 2^e, so codes never saturate; e >= -127) and
 // integers |n_k| <= 128; slice k is stored as the bf16 value n_k 2^(-8k),
 // which is exact.  Products of leading slices are integers below 2^14, so
 // the (0,0) slice product accumulates exactly in an FP32 MFMA accumulator.
@@ -47,8 +48,11 @@ constexpr int kFragBytes = 64 * 8 * 2;   // 1 KiB
 constexpr int kSlices = 4;
 constexpr int kSplitExpBytes = 256;
 
-inline int64_t split_site_bytes(int pl, int pr) {
-  return kSplitExpBytes + int64_t(2) * kSlices * 2 * (pl / 32) * (pr / 16) * kFragBytes;
+// Every site of the split form is a 64 x 64 block (zero beyond the batch's
+// pads); batches with pads above 64 have no split form.
+constexpr int kSplitMaxPad = 64;
+inline int64_t split_site_bytes() {
+  return kSplitExpBytes + int64_t(2) * kSlices * 2 * (kSplitMaxPad / 32) * (kSplitMaxPad / 16) * kFragBytes;
 }
 
 }  // namespace qk

@@ -115,3 +115,34 @@ def test_gram_deterministic(small_sets):
         k1 = q.gram(b, precision=prec).cpu().numpy()
         k2 = q.gram(b, precision=prec).cpu().numpy()
         assert (k1 == k2).all()
+
+
+@pytest.mark.gpu
+def test_split_values_at_top_of_exponent_range():
+    """Product states whose amplitudes sit just below 1 (and just below 1/2):
+    after fixed-point rounding they reach the largest slice code, the case in
+    which a carry mistake would flip their sign.  Self-overlaps must be 1 and
+    every entry must match the oracle."""
+    import paper_2411_09336_amd as q
+    require_gpu()
+    m = 24
+    mps = []
+    for k, top in enumerate([1.0 - 2.0 ** -40, 1.0 - 2.0 ** -33, 0.5 - 2.0 ** -45, 1.0 - 2.0 ** -31]):
+        site = []
+        for l in range(m):
+            a = top if (l + k) % 3 else np.sqrt(0.5)
+            b = np.sqrt(max(1.0 - a * a, 0.0)) * np.exp(1j * 0.3 * (l + 1) * (k + 1))
+            if (l + k) % 3 and top < 0.75:
+                # amplitude just below 1/2 on |0>, the rest on |1>
+                a, b = top, np.sqrt(1.0 - top * top)
+            t = np.zeros((1, 2, 1), dtype=np.complex128)
+            t[0, 0, 0], t[0, 1, 0] = a, b
+            site.append(t)
+        mps.append(site)
+    b = q.import_batch(mps)
+    K = q.gram(b, precision="split_bf16").cpu().numpy()
+    Kref = ogram.gram(mps)
+    # fixed-point resolution 2^-31 relative per value and site: 24 sites,
+    # two operands, |K| = |<a|b>|^2 -> below 4 * 24 * 2^-31 = 4.5e-8
+    assert np.abs(np.diag(K) - 1.0).max() < 4.5e-8
+    assert np.abs(K - Kref).max() < 4.5e-8
