@@ -133,6 +133,8 @@ def main():
                     help="run only the first K slabs of the timed Gram (hardware-counter passes); 0 = all")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES bytes (hardware-counter scale), then exit")
     ap.add_argument("--routing", type=int, default=1,
                     help="0: 2(k-1) SWAPs per Rxx (paper); 1: cancelled inverse SWAP pairs (same circuit)")
     args = ap.parse_args()
@@ -142,7 +144,23 @@ def main():
               "a design in DESIGN.md, not a measured path.", file=sys.stderr)
         sys.exit(2)
 
+    if args.calibrate_copy > 0:
+        calibrate_copy(args.calibrate_copy)
+        return
     run(args)
+
+
+def calibrate_copy(nbytes):
+    """One elementwise copy kernel reading and writing nbytes each: the
+    reference dispatch for scaling FETCH_SIZE / WRITE_SIZE to bytes."""
+    import torch
+    n = nbytes // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    torch.mul(x, 1.0, out=y)       # the calibration dispatch
+    torch.cuda.synchronize()
+    log(f"[bench] copy calibration: {4 * n} bytes read, {4 * n} bytes written")
 
 
 def run(args):
@@ -289,7 +307,7 @@ def run(args):
     cpu = None
     dk_oracle = None
     if not args.no_cpu:
-        n_exp = min(S, 32)
+        n_exp = min(S, 48)
         log(f"[bench] exporting {n_exp} MPS for the CPU oracle")
         mps_np = [sim.export(i) for i in range(n_exp)]
         try:

@@ -534,33 +534,35 @@ qk_status mps_batch_gather(const qk_mps_batch *src, const int64_t *idx_host, int
     }
   }
   const int m1 = src->m + 1;
-  for (int64_t k = 0; k < count; ++k) {
-    const int64_t i = idx_host[k];
-    bool good = true;
-    if (forms & QK_FORM_FP64)
-      good = good && hipMemcpyAsync(b->f64 + k * b->mps_stride, src->f64 + i * src->mps_stride,
-                                    sizeof(double2) * src->mps_stride, hipMemcpyDeviceToDevice, stream) == hipSuccess;
-    if (forms & QK_FORM_FP32)
-      good = good && hipMemcpyAsync(b->f32 + k * b->mps_stride, src->f32 + i * src->mps_stride,
-                                    sizeof(float2) * src->mps_stride, hipMemcpyDeviceToDevice, stream) == hipSuccess;
-    if (forms & QK_FORM_SPLIT_BF16)
-      good = good && hipMemcpyAsync(b->sbf16 + k * b->split_stride, src->sbf16 + i * src->split_stride,
-                                    size_t(src->split_stride), hipMemcpyDeviceToDevice, stream) == hipSuccess;
-    good = good &&
-           hipMemcpyAsync(b->dims_dev + k * m1, src->dims_dev + i * m1, sizeof(int32_t) * m1,
-                          hipMemcpyDeviceToDevice, stream) == hipSuccess &&
-           hipMemcpyAsync(b->disc_dev + k, src->disc_dev + i, sizeof(double), hipMemcpyDeviceToDevice, stream) == hipSuccess &&
-           hipMemcpyAsync(b->maxdisc_dev + k, src->maxdisc_dev + i, sizeof(double), hipMemcpyDeviceToDevice, stream) == hipSuccess &&
-           hipMemcpyAsync(b->degen_dev + k, src->degen_dev + i, sizeof(int32_t), hipMemcpyDeviceToDevice, stream) == hipSuccess &&
-           hipMemcpyAsync(b->unconv_dev + k, src->unconv_dev + i, sizeof(int32_t), hipMemcpyDeviceToDevice, stream) == hipSuccess;
-    if (!good) {
+  if (count > 0) {
+    int64_t *idx_dev = nullptr;
+    if (hipMallocAsync(reinterpret_cast<void **>(&idx_dev), sizeof(int64_t) * size_t(count), stream) != hipSuccess) {
+      (void)hipGetLastError();
       batch_release(b);
-      return fail(QK_EDEVICE, "device copy failed in gather");
+      return fail(QK_ENOMEM, "device allocation of the gather index failed");
     }
-  }
-  if (hipStreamSynchronize(stream) != hipSuccess) {
-    batch_release(b);
-    return fail(QK_EDEVICE, "gather copies failed");
+    const qk_mps_batch_meta ms{src->dims_dev, src->disc_dev, src->maxdisc_dev, src->degen_dev, src->unconv_dev};
+    const qk_mps_batch_meta md{b->dims_dev, b->disc_dev, b->maxdisc_dev, b->degen_dev, b->unconv_dev};
+    qk_status gs = QK_OK;
+    if (hipMemcpyAsync(idx_dev, idx_host, sizeof(int64_t) * size_t(count), hipMemcpyHostToDevice, stream) !=
+        hipSuccess)
+      gs = fail(QK_EDEVICE, "copy of the gather index failed");
+    if (gs == QK_OK && (forms & QK_FORM_FP64))
+      gs = launch_gather_records(src->f64, b->f64, idx_dev, int64_t(sizeof(double2)) * src->mps_stride, count,
+                                 stream);
+    if (gs == QK_OK && (forms & QK_FORM_FP32))
+      gs = launch_gather_records(src->f32, b->f32, idx_dev, int64_t(sizeof(float2)) * src->mps_stride, count,
+                                 stream);
+    if (gs == QK_OK && (forms & QK_FORM_SPLIT_BF16))
+      gs = launch_gather_records(src->sbf16, b->sbf16, idx_dev, src->split_stride, count, stream);
+    if (gs == QK_OK) gs = launch_gather_meta(ms, md, idx_dev, m1, count, stream);
+    // the host index list must stay valid until the copy has run
+    const bool synced = hipStreamSynchronize(stream) == hipSuccess;
+    (void)hipFreeAsync(idx_dev, stream);
+    if (gs != QK_OK || !synced) {
+      batch_release(b);
+      return gs != QK_OK ? gs : fail(QK_EDEVICE, "gather failed");
+    }
   }
   *out = b;
   return ok();

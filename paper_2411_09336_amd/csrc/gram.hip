@@ -787,6 +787,58 @@ __global__ __launch_bounds__(256) void pack_split_kernel(const double2 *__restri
   }
 }
 
+// ------------------------------------------------------------------------
+// Gather: record k of the destination is record idx[k] of the source.  One
+// launch per form instead of one copy per MPS.
+
+__global__ __launch_bounds__(256) void gather_records_kernel(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
+                                                             const int64_t *__restrict__ idx, int64_t rec_vecs,
+                                                             int64_t k0, int64_t count) {
+  const int64_t k = k0 + blockIdx.y;
+  if (k >= count) return;
+  const uint4 *s = src + idx[k] * rec_vecs;
+  uint4 *d = dst + k * rec_vecs;
+  for (int64_t x = int64_t(blockIdx.x) * 256 + threadIdx.x; x < rec_vecs; x += int64_t(gridDim.x) * 256) d[x] = s[x];
+}
+
+__global__ __launch_bounds__(256) void gather_meta_kernel(const qk_mps_batch_meta src, qk_mps_batch_meta dst,
+                                                          const int64_t *__restrict__ idx, int32_t m1,
+                                                          int64_t count) {
+  const int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (k >= count) return;
+  const int64_t i = idx[k];
+  for (int t = 0; t < m1; ++t) dst.dims[k * m1 + t] = src.dims[i * m1 + t];
+  dst.disc[k] = src.disc[i];
+  dst.maxdisc[k] = src.maxdisc[i];
+  dst.degen[k] = src.degen[i];
+  dst.unconv[k] = src.unconv[i];
+}
+
+qk_status launch_gather_records(const void *src, void *dst, const int64_t *idx_dev, int64_t rec_bytes,
+                                int64_t count, hipStream_t stream) {
+  if (count == 0 || rec_bytes == 0) return QK_OK;
+  if (rec_bytes % 16) return fail(QK_EINVAL, "gather record size is not a multiple of 16 bytes");
+  const int64_t vecs = rec_bytes / 16;
+  const unsigned gx = unsigned(std::min<int64_t>((vecs + 255) / 256, 64));
+  for (int64_t k0 = 0; k0 < count; k0 += 65535) {
+    const unsigned gy = unsigned(std::min<int64_t>(65535, count - k0));
+    hipLaunchKernelGGL(gather_records_kernel, dim3(gx, gy), dim3(256), 0, stream,
+                       reinterpret_cast<const uint4 *>(src), reinterpret_cast<uint4 *>(dst), idx_dev, vecs, k0,
+                       count);
+    QK_HIP_CHECK(hipGetLastError());
+  }
+  return QK_OK;
+}
+
+qk_status launch_gather_meta(const qk_mps_batch_meta &src, const qk_mps_batch_meta &dst, const int64_t *idx_dev,
+                             int32_t m1, int64_t count, hipStream_t stream) {
+  if (count == 0) return QK_OK;
+  hipLaunchKernelGGL(gather_meta_kernel, dim3(unsigned((count + 255) / 256)), dim3(256), 0, stream, src, dst,
+                     idx_dev, m1, count);
+  QK_HIP_CHECK(hipGetLastError());
+  return QK_OK;
+}
+
 qk_status launch_pack_f32(const qk_mps_batch *b, hipStream_t stream) {
   const int64_t count = b->n * b->mps_stride;
   if (count == 0) return QK_OK;

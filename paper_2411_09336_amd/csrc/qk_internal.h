@@ -96,7 +96,18 @@ qk_status batch_create(int64_t n, int32_t m, const std::vector<int32_t> &pad,
                        hipStream_t stream, qk_mps_batch **out, bool with_f64 = true);
 qk_status batch_ensure_packed(qk_mps_batch *b, qk_precision prec, hipStream_t stream);
 
+// Per-MPS metadata arrays of a batch (device pointers).
+struct qk_mps_batch_meta {
+  int32_t *dims;
+  double *disc, *maxdisc;
+  int32_t *degen, *unconv;
+};
+
 // Launchers implemented in the .hip files.
+qk_status launch_gather_records(const void *src, void *dst, const int64_t *idx_dev, int64_t rec_bytes,
+                                int64_t count, hipStream_t stream);
+qk_status launch_gather_meta(const qk_mps_batch_meta &src, const qk_mps_batch_meta &dst, const int64_t *idx_dev,
+                             int32_t m1, int64_t count, hipStream_t stream);
 qk_status launch_pack_f32(const qk_mps_batch *b, hipStream_t stream);
 qk_status launch_pack_split(const qk_mps_batch *b, hipStream_t stream);
 
