@@ -135,6 +135,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes (hardware-counter scale), then exit")
+    ap.add_argument("--kernel-probe", type=int, default=0, metavar="N",
+                    help="only time the symmetric Gram of N random saturated 165-site chi=64 MPS in every "
+                         "form (kernel microbenchmark, no simulation), then exit")
     ap.add_argument("--routing", type=int, default=1,
                     help="0: 2(k-1) SWAPs per Rxx (paper); 1: cancelled inverse SWAP pairs (same circuit)")
     args = ap.parse_args()
@@ -147,7 +150,52 @@ def main():
     if args.calibrate_copy > 0:
         calibrate_copy(args.calibrate_copy)
         return
+    if args.kernel_probe > 0:
+        kernel_probe(args.kernel_probe)
+        return
     run(args)
+
+
+def random_saturated_mps(m, chi, rng):
+    """Left-canonical MPS with the saturated bond profile min(chi, 2^min(l, m-l))
+    (QR of complex Gaussian matrices), last site normalised."""
+    import numpy as np
+    dims = [min(chi, 2 ** min(l, m - l)) for l in range(m + 1)]
+    sites = []
+    for l in range(m):
+        dl, dr = dims[l], dims[l + 1]
+        z = rng.standard_normal((dl * 2, dr)) + 1j * rng.standard_normal((dl * 2, dr))
+        qm, _ = np.linalg.qr(z)
+        sites.append(qm.reshape(dl, 2, dr))
+    sites[-1] = sites[-1] / np.linalg.norm(sites[-1])
+    return sites
+
+
+def kernel_probe(n):
+    """Symmetric Gram of n MPS (8 distinct random saturated states, repeated)
+    in every form: one warm and one timed dispatch each."""
+    import numpy as np
+    import torch
+
+    import paper_2411_09336_amd as q
+    rng = np.random.default_rng(0)
+    base = [random_saturated_mps(165, 64, rng) for _ in range(8)]
+    b = q.import_batch([base[i % 8] for i in range(n)])
+    pairs = n * (n + 1) // 2
+    ref = None
+    for prec in ("fp64", "split_i8", "split_bf16", "fp32"):
+        b.pack(prec)
+        torch.cuda.synchronize()
+        q.gram(b, precision=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        K = q.gram(b, precision=prec)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        if ref is None:
+            ref = K.clone()
+        log(f"[bench] probe {prec}: n={n}, {pairs} entries in {dt:.3f} s -> {pairs / dt:.1f} entries/s; "
+            f"max|dK| vs fp64 {(K - ref).abs().max().item():.3e}")
 
 
 def calibrate_copy(nbytes):

@@ -56,9 +56,14 @@ typedef enum {
 typedef enum {
   QK_FP64 = 0,        /* complex128 operands, FP64 MFMA                        */
   QK_FP32 = 1,        /* complex64 operands, FP32 MFMA, per-site 2^e rescale   */
-  QK_SPLIT_BF16 = 2   /* each real operand split into three bf16 pieces        */
-                      /* (hi + mid + lo); the six products of order >= 2^-16   */
-                      /* go into one FP32 MFMA accumulator; 2^e rescale        */
+  QK_SPLIT_BF16 = 2,  /* each real operand as a 31-bit fixed-point code with   */
+                      /* one exponent per row / column, cut into four 8-bit    */
+                      /* digits carried as bf16; the leading digit product     */
+                      /* accumulates exactly in one FP32 MFMA accumulator, ten */
+                      /* smaller digit products in a second; FP64 combine      */
+  QK_SPLIT_I8 = 3     /* the same four digits as int8 MFMA operands; the      */
+                      /* eleven digit products accumulate exactly in int32,   */
+                      /* grouped by weight; FP64 combine                       */
 } qk_precision;
 
 /* Circuit of Sec. II-C.  Rotation angles: Rz on qubit i uses coef_z * x_i;
@@ -98,6 +103,7 @@ typedef struct {
   int64_t degenerate_cuts;   /* truncations whose kept/discarded gap < 1e-10   */
   int64_t unconverged_svds;  /* SVDs that hit the sweep limit                  */
   int64_t bytes_f64, bytes_f32, bytes_split_bf16; /* device bytes per form     */
+  int64_t bytes_split_i8;
 } qk_batch_info;
 
 /* ---------------------------------------------------------------- setup */
@@ -157,7 +163,8 @@ qk_status mps_simulate_progress(const double *features_dev, int64_t n_points,
  * If b == NULL or b == a the matrix is symmetric: only i <= j is contracted
  * and mirrored (the diagonal is computed, not assumed).
  * `a` and `b` must have the same m.  The precision's packed form is built
- * (and kept) on first use. */
+ * (and kept) on first use.  The MFMA kernels support bond pads up to 64
+ * (bond dimensions up to 64): QK_ENOTSUP for larger batches. */
 qk_status mps_gram(const qk_mps_batch *a, const qk_mps_batch *b,
                    qk_precision prec, double *K_dev, int64_t ldk,
                    void *hip_stream);
@@ -226,6 +233,7 @@ qk_status mps_batch_drop(qk_mps_batch *b, qk_precision prec);
 #define QK_FORM_FP64 1u
 #define QK_FORM_FP32 2u
 #define QK_FORM_SPLIT_BF16 4u
+#define QK_FORM_SPLIT_I8 8u
 
 /* New batch holding copies of MPS idx[0..count) of `src` (indices may
  * repeat), in the forms selected by `forms` (QK_FORM_* bits; each must be

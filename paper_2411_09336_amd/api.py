@@ -31,14 +31,18 @@ class Precision:
     FP64 = 0
     FP32 = 1
     SPLIT_BF16 = 2
-    _names = {"fp64": 0, "fp32": 1, "split_bf16": 2, "sbf16": 2, "bf16x6": 2}
+    SPLIT_I8 = 3
+    _names = {"fp64": 0, "fp32": 1, "split_bf16": 2, "split_i8": 3}
 
     @classmethod
     def of(cls, p) -> int:
         if isinstance(p, str):
-            return cls._names[p.lower()]
-        if int(p) not in (0, 1, 2):
-            raise ValueError("precision must be fp64, fp32 or split_bf16")
+            try:
+                return cls._names[p.lower()]
+            except KeyError:
+                raise ValueError(f"unknown precision {p!r}: use one of {sorted(cls._names)}") from None
+        if int(p) not in (0, 1, 2, 3):
+            raise ValueError("precision must be fp64, fp32, split_bf16 or split_i8")
         return int(p)
 
 
@@ -58,7 +62,7 @@ class _Info(C.Structure):
                 ("n_two_qubit_gates", C.c_int32), ("max_discarded", C.c_double),
                 ("mean_total_discarded", C.c_double), ("degenerate_cuts", C.c_int64),
                 ("unconverged_svds", C.c_int64), ("bytes_f64", C.c_int64), ("bytes_f32", C.c_int64),
-                ("bytes_split_bf16", C.c_int64)]
+                ("bytes_split_bf16", C.c_int64), ("bytes_split_i8", C.c_int64)]
 
 
 class _Job(C.Structure):
@@ -225,7 +229,7 @@ class MPSBatch:
         _check(_load().mps_batch_drop(self._h, Precision.of(precision)))
 
     def gather(self, indices: Sequence[int], forms=("fp64",), stream=None) -> "MPSBatch":
-        """Copies of MPS ``indices`` in the given forms ("fp64", "fp32", "split_bf16")."""
+        """Copies of MPS ``indices`` in the given forms ("fp64", "fp32", "split_bf16", "split_i8")."""
         idx = np.ascontiguousarray(np.asarray(indices, dtype=np.int64))
         mask = 0
         for f in forms:

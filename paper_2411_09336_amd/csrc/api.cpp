@@ -75,12 +75,15 @@ static void compute_layout(qk_mps_batch *b) {
   const int m = b->m;
   b->site_off.assign(m + 1, 0);
   b->split_off.assign(m + 1, 0);
+  b->i8_off.assign(m + 1, 0);
   for (int l = 0; l < m; ++l) {
     b->site_off[l + 1] = b->site_off[l] + int64_t(2) * b->pad[l] * b->pad[l + 1];
     b->split_off[l + 1] = b->split_off[l] + split_site_bytes();
+    b->i8_off[l + 1] = b->i8_off[l] + kI8SiteBytes;
   }
   b->mps_stride = b->site_off[m];
   b->split_stride = b->split_off[m];
+  b->i8_stride = b->i8_off[m];
 }
 
 static void batch_release(qk_mps_batch *b) {
@@ -88,8 +91,9 @@ static void batch_release(qk_mps_batch *b) {
   int cur = 0;
   (void)hipGetDevice(&cur);
   (void)hipSetDevice(b->device);
-  void *ptrs[] = {b->f64, b->f32, b->sbf16, b->dims_dev, b->pad_dev, b->site_off_dev,
-                  b->split_off_dev, b->disc_dev, b->maxdisc_dev, b->degen_dev, b->unconv_dev};
+  void *ptrs[] = {b->f64,          b->f32,        b->sbf16,       b->si8,       b->dims_dev,
+                  b->pad_dev,      b->site_off_dev, b->split_off_dev, b->i8_off_dev, b->disc_dev,
+                  b->maxdisc_dev,  b->degen_dev,   b->unconv_dev};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   (void)hipSetDevice(cur);
@@ -115,6 +119,7 @@ qk_status batch_create(int64_t n, int32_t m, const std::vector<int32_t> &pad,
               alloc((void **)&b->pad_dev, sizeof(int32_t) * size_t(m + 1)) &&
               alloc((void **)&b->site_off_dev, sizeof(int64_t) * size_t(m + 1)) &&
               alloc((void **)&b->split_off_dev, sizeof(int64_t) * size_t(m + 1)) &&
+              alloc((void **)&b->i8_off_dev, sizeof(int64_t) * size_t(m + 1)) &&
               alloc((void **)&b->disc_dev, sizeof(double) * nn) &&
               alloc((void **)&b->maxdisc_dev, sizeof(double) * nn) &&
               alloc((void **)&b->degen_dev, sizeof(int32_t) * nn) &&
@@ -128,6 +133,7 @@ qk_status batch_create(int64_t n, int32_t m, const std::vector<int32_t> &pad,
   if (hipMemcpyAsync(b->pad_dev, pad.data(), sizeof(int32_t) * (m + 1), hipMemcpyHostToDevice, stream) != hipSuccess ||
       hipMemcpyAsync(b->site_off_dev, b->site_off.data(), sizeof(int64_t) * (m + 1), hipMemcpyHostToDevice, stream) != hipSuccess ||
       hipMemcpyAsync(b->split_off_dev, b->split_off.data(), sizeof(int64_t) * (m + 1), hipMemcpyHostToDevice, stream) != hipSuccess ||
+      hipMemcpyAsync(b->i8_off_dev, b->i8_off.data(), sizeof(int64_t) * (m + 1), hipMemcpyHostToDevice, stream) != hipSuccess ||
       hipStreamSynchronize(stream) != hipSuccess) {
     batch_release(b);
     return fail(QK_EDEVICE, "copy of batch layout failed");
@@ -141,7 +147,8 @@ qk_status batch_ensure_packed(qk_mps_batch *b, qk_precision prec, hipStream_t st
     if (!b->f64) return fail(QK_ENOTSUP, "batch holds no FP64 form");
     return QK_OK;
   }
-  if ((prec == QK_FP32 && b->f32) || (prec == QK_SPLIT_BF16 && b->sbf16)) return QK_OK;
+  if ((prec == QK_FP32 && b->f32) || (prec == QK_SPLIT_BF16 && b->sbf16) || (prec == QK_SPLIT_I8 && b->si8))
+    return QK_OK;
   if (!b->f64) return fail(QK_ENOTSUP, "batch holds no FP64 form to pack from");
   if (prec == QK_FP32) {
     if (b->f32) return QK_OK;
@@ -164,6 +171,17 @@ qk_status batch_ensure_packed(qk_mps_batch *b, qk_precision prec, hipStream_t st
       return fail(QK_ENOMEM, "device allocation of split-BF16 planes failed");
     }
     return launch_pack_split(b, stream);
+  }
+  if (prec == QK_SPLIT_I8) {
+    if (*std::max_element(b->pad.begin(), b->pad.end()) > kSplitMaxPad)
+      return fail(QK_ENOTSUP, "the split-int8 form supports bond dimensions up to 64");
+    size_t bytes = size_t(std::max<int64_t>(b->n, 1)) * size_t(b->i8_stride);
+    if (hipMalloc((void **)&b->si8, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      b->si8 = nullptr;
+      return fail(QK_ENOMEM, "device allocation of split-int8 planes failed");
+    }
+    return launch_pack_i8(b, stream);
   }
   return fail(QK_EINVAL, "unknown precision");
 }
@@ -263,7 +281,7 @@ static qk_status make_job(const qk_mps_batch *a, int64_t a0, int64_t na, const q
   if (na > 0 && nb > 0 && !K) return fail(QK_EINVAL, "K_dev is NULL");
   if (ldk < nb) return fail(QK_EINVAL, "ldk < number of columns");
   if (upper && a != b) return fail(QK_EINVAL, "upper_only requires a == b");
-  if (prec != QK_FP64 && prec != QK_FP32 && prec != QK_SPLIT_BF16)
+  if (prec != QK_FP64 && prec != QK_FP32 && prec != QK_SPLIT_BF16 && prec != QK_SPLIT_I8)
     return fail(QK_EINVAL, "unknown precision");
   auto *am = const_cast<qk_mps_batch *>(a);
   auto *bm = const_cast<qk_mps_batch *>(b);
@@ -272,18 +290,27 @@ static qk_status make_job(const qk_mps_batch *a, int64_t a0, int64_t na, const q
   st = batch_ensure_packed(bm, prec, stream);
   if (st != QK_OK) return st;
   auto base = [&](qk_mps_batch *x) -> const void * {
-    return prec == QK_FP64 ? (const void *)x->f64
-                           : prec == QK_FP32 ? (const void *)x->f32 : (const void *)x->sbf16;
+    switch (prec) {
+      case QK_FP64: return x->f64;
+      case QK_FP32: return x->f32;
+      case QK_SPLIT_BF16: return x->sbf16;
+      default: return x->si8;
+    }
   };
-  const bool split = prec == QK_SPLIT_BF16;
+  auto offsets = [&](qk_mps_batch *x) -> const int64_t * {
+    return prec == QK_SPLIT_BF16 ? x->split_off_dev : prec == QK_SPLIT_I8 ? x->i8_off_dev : x->site_off_dev;
+  };
+  auto stride = [&](qk_mps_batch *x) -> int64_t {
+    return prec == QK_SPLIT_BF16 ? x->split_stride : prec == QK_SPLIT_I8 ? x->i8_stride : x->mps_stride;
+  };
   job->a_base = base(am);
   job->b_base = base(bm);
-  job->a_off = split ? am->split_off_dev : am->site_off_dev;
-  job->b_off = split ? bm->split_off_dev : bm->site_off_dev;
+  job->a_off = offsets(am);
+  job->b_off = offsets(bm);
   job->a_pad = am->pad_dev;
   job->b_pad = bm->pad_dev;
-  job->a_stride = split ? am->split_stride : am->mps_stride;
-  job->b_stride = split ? bm->split_stride : bm->mps_stride;
+  job->a_stride = stride(am);
+  job->b_stride = stride(bm);
   job->a0 = a0;
   job->na = na;
   job->b0 = b0;
@@ -427,6 +454,7 @@ qk_status mps_batch_info(const qk_mps_batch *b, qk_batch_info *info) {
   info->bytes_f64 = b->f64 ? int64_t(sizeof(double2)) * b->n * b->mps_stride : 0;
   info->bytes_f32 = b->f32 ? int64_t(sizeof(float2)) * b->n * b->mps_stride : 0;
   info->bytes_split_bf16 = b->sbf16 ? b->n * b->split_stride : 0;
+  info->bytes_split_i8 = b->si8 ? b->n * b->i8_stride : 0;
   return ok();
 }
 
@@ -494,6 +522,9 @@ qk_status mps_batch_drop(qk_mps_batch *b, qk_precision prec) {
   } else if (prec == QK_SPLIT_BF16 && b->sbf16) {
     QK_HIP_CHECK(hipFree(b->sbf16));
     b->sbf16 = nullptr;
+  } else if (prec == QK_SPLIT_I8 && b->si8) {
+    QK_HIP_CHECK(hipFree(b->si8));
+    b->si8 = nullptr;
   } else if (prec == QK_FP64) {
     return fail(QK_EINVAL, "the FP64 form cannot be dropped");
   }
@@ -505,9 +536,9 @@ qk_status mps_batch_gather(const qk_mps_batch *src, const int64_t *idx_host, int
   if (!src || !out) return fail(QK_EINVAL, "NULL argument");
   *out = nullptr;
   if (count < 0 || (count > 0 && !idx_host)) return fail(QK_EINVAL, "invalid index list");
-  if (forms == 0 || (forms & ~7u)) return fail(QK_EINVAL, "invalid forms mask");
+  if (forms == 0 || (forms & ~15u)) return fail(QK_EINVAL, "invalid forms mask");
   if (((forms & QK_FORM_FP64) && !src->f64) || ((forms & QK_FORM_FP32) && !src->f32) ||
-      ((forms & QK_FORM_SPLIT_BF16) && !src->sbf16))
+      ((forms & QK_FORM_SPLIT_BF16) && !src->sbf16) || ((forms & QK_FORM_SPLIT_I8) && !src->si8))
     return fail(QK_EINVAL, "requested form is not present in the source batch");
   for (int64_t k = 0; k < count; ++k)
     if (idx_host[k] < 0 || idx_host[k] >= src->n) return fail(QK_EINVAL, "gather index out of range");
@@ -533,6 +564,14 @@ qk_status mps_batch_gather(const qk_mps_batch *src, const int64_t *idx_host, int
       return fail(QK_ENOMEM, "device allocation of split-BF16 planes failed");
     }
   }
+  if (forms & QK_FORM_SPLIT_I8) {
+    if (hipMalloc(reinterpret_cast<void **>(&b->si8), nn * size_t(b->i8_stride)) != hipSuccess) {
+      (void)hipGetLastError();
+      b->si8 = nullptr;
+      batch_release(b);
+      return fail(QK_ENOMEM, "device allocation of split-int8 planes failed");
+    }
+  }
   const int m1 = src->m + 1;
   if (count > 0) {
     int64_t *idx_dev = nullptr;
@@ -555,6 +594,8 @@ qk_status mps_batch_gather(const qk_mps_batch *src, const int64_t *idx_host, int
                                  stream);
     if (gs == QK_OK && (forms & QK_FORM_SPLIT_BF16))
       gs = launch_gather_records(src->sbf16, b->sbf16, idx_dev, src->split_stride, count, stream);
+    if (gs == QK_OK && (forms & QK_FORM_SPLIT_I8))
+      gs = launch_gather_records(src->si8, b->si8, idx_dev, src->i8_stride, count, stream);
     if (gs == QK_OK) gs = launch_gather_meta(ms, md, idx_dev, m1, count, stream);
     // the host index list must stay valid until the copy has run
     const bool synced = hipStreamSynchronize(stream) == hipSuccess;

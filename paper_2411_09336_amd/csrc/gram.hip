@@ -589,9 +589,296 @@ __device__ void overlap_split(const GramJobDev &J, int64_t ia, int64_t ib, uint8
   __syncthreads();
 }
 
+// ------------------------------------------------------------------------
+// Split-int8 form: the same 31-bit fixed-point codes with one exponent per
+// row (E, T^T) or column (site tensors), cut into four balanced base-256
+// digits that are int8 MFMA operands (v_mfma_i32_16x16x64_i8, twice the
+// bf16 rate).  Digit products accumulate EXACTLY in int32, grouped by weight
+// 2^(-8 c), c = a + b for digit pair (a, b): c = 0..3 (ten pairs) and the
+// (2, 2) pair.  A product with a negated operand uses ~x = -x - 1: the
+// accumulator then lacks a column digit sum of the other operand, which the
+// packed site block carries and the combination adds back.
+//
+// Code of x with exponent e: X = round(x 2^(31-e)), formed by one FMA with
+// 1.5 * 2^52 (the low word of the sum is X).  The margin of exp_above_i8
+// keeps |X| <= 2^31 * 128/129, so the leading digit lies in [-127, 127].
+// Digit word (X + 0x808080) ^ 0x808080 holds the digits d3, d2, d1, d0 as
+// two's-complement bytes 0..3 (X = d0 2^24 + d1 2^16 + d2 2^8 + d3).
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+
+__device__ inline i32x4 mma_i8(const uint4 &a, const uint4 &b, const i32x4 &c) {
+  return __builtin_amdgcn_mfma_i32_16x16x64_i8(*reinterpret_cast<const i32x4 *>(&a),
+                                               *reinterpret_cast<const i32x4 *>(&b), c, 0, 0, 0);
+}
+
+__device__ inline int exp_above_i8(double mx) {
+  // smallest e with mx (1 + 2^-7) < 2^e (0 for mx == 0)
+  return mx > 0.0 ? ilogb(mx * (1.0 + 0x1p-7)) + 1 : 0;
+}
+
+__device__ inline uint32_t digit_word(double x, double scale) {
+  const double w = fma(x, scale, 0x1.8p52);
+  const uint32_t X = uint32_t(__double_as_longlong(w));
+  return (X + 0x808080u) ^ 0x808080u;
+}
+
+// Byte transpose of four digit words (values e = 0..3) into four slice words:
+// byte e of slice k is digit k of value e (slice 0 = leading digit).
+__device__ inline void transpose_digits(uint32_t d0, uint32_t d1, uint32_t d2, uint32_t d3, uint32_t (&s)[4]) {
+  const uint32_t lo01 = __builtin_amdgcn_perm(d1, d0, 0x05010400u);
+  const uint32_t hi01 = __builtin_amdgcn_perm(d1, d0, 0x07030602u);
+  const uint32_t lo23 = __builtin_amdgcn_perm(d3, d2, 0x05010400u);
+  const uint32_t hi23 = __builtin_amdgcn_perm(d3, d2, 0x07030602u);
+  s[3] = __builtin_amdgcn_perm(lo23, lo01, 0x05040100u);
+  s[2] = __builtin_amdgcn_perm(lo23, lo01, 0x07060302u);
+  s[1] = __builtin_amdgcn_perm(hi23, hi01, 0x05040100u);
+  s[0] = __builtin_amdgcn_perm(hi23, hi01, 0x07060302u);
+}
+
+__device__ inline uint4 not4(const uint4 &v) { return make_uint4(~v.x, ~v.y, ~v.z, ~v.w); }
+
+// Fragment (s, slice k, plane q, column block ct) of a packed int8 site block.
+__device__ inline uint4 i8_frag(const uint8_t *site, int s, int k, int q, int ct, int lane) {
+  return *reinterpret_cast<const uint4 *>(site + kI8ExpBytes + kI8SumBytes +
+                                          size_t(((s * 4 + k) * 2 + q) * 4 + ct) * kI8FragBytes + lane * 16);
+}
+
+// Digit-pair products of one complex 16 x 16 x 64 block, grouped by weight.
+// re += Xr Yr + Xs Ys' and im += Xr Yi + Xi Yr style sums are chosen by the
+// caller through the operand roles (P, Q, R, S): c_re += P Y0 + Q Y1,
+// c_im += R Y1 + S Y0.
+struct I8Acc {
+  i32x4 re[5], im[5];
+};
+
+__device__ inline void i8_block(const uint4 (&P)[4], const uint4 (&Q)[4], const uint4 (&R)[4], const uint4 (&S)[4],
+                                const uint4 (&Y0)[4], const uint4 (&Y1)[4], I8Acc &acc) {
+#pragma unroll
+  for (int c = 0; c < 5; ++c) {
+    acc.re[c] = i32x4{0, 0, 0, 0};
+    acc.im[c] = i32x4{0, 0, 0, 0};
+  }
+  // (a, b, class): consecutive pairs mostly feed different accumulators
+  constexpr int pa[11] = {0, 0, 0, 0, 2, 1, 1, 1, 2, 2, 3};
+  constexpr int pb[11] = {0, 1, 2, 3, 2, 0, 1, 2, 0, 1, 0};
+  constexpr int pc[11] = {0, 1, 2, 3, 4, 1, 2, 3, 2, 3, 3};
+#pragma unroll
+  for (int t = 0; t < 11; ++t) {
+    const int a = pa[t], b = pb[t], c = pc[t];
+    acc.re[c] = mma_i8(P[a], Y0[b], acc.re[c]);
+    acc.im[c] = mma_i8(R[a], Y1[b], acc.im[c]);
+    acc.re[c] = mma_i8(Q[a], Y1[b], acc.re[c]);
+    acc.im[c] = mma_i8(S[a], Y0[b], acc.im[c]);
+  }
+}
+
+// Exact digit sum of element e of a class accumulator set, plus correction
+// words, as a double times 2^-32 of the code product scale.
+__device__ inline double i8_value(const i32x4 (&a)[5], int e, uint32_t chi, uint32_t clo, uint32_t c4) {
+  const int hiw = int((uint32_t(a[0][e]) << 8) + uint32_t(a[1][e]) + chi);
+  const int low = int((uint32_t(a[2][e]) << 8) + uint32_t(a[3][e]) + clo);
+  const int w4 = int(uint32_t(a[4][e]) + c4);
+  return fma(fma(double(hiw), 65536.0, double(low)), 256.0, double(w4));
+}
+
+// Class corrections from the column digit sums cs0..cs3 of the operand that
+// was multiplied by a complemented one: class c gets the sum over its pairs
+// (a, b) of cs_b, packed like the accumulator words of i8_value.
+__device__ inline void i8_corrections(const int *cs, uint32_t &chi, uint32_t &clo, uint32_t &c4) {
+  const int c0 = cs[0], c1 = cs[64], c2 = cs[128], c3 = cs[192];
+  const int k0 = c0, k1 = c0 + c1, k2 = c0 + c1 + c2, k3 = k2 + c3;
+  chi = (uint32_t(k0) << 8) + uint32_t(k1);
+  clo = (uint32_t(k2) << 8) + uint32_t(k3);
+  c4 = uint32_t(c2);
+}
+
+// GEMM1 (int8): T_s[a][b'] for a in rows 32h.., b' in block c.
+__device__ inline void i8_gemm1(const SplitCtx &C, const uint8_t *B, const uint8_t *Ebuf, const int *s_ea, int s,
+                                double (&Td)[2][2][4], double &tmax) {
+  uint4 Br[4], Bi[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    Br[k] = i8_frag(B, s, k, 0, C.cb, C.lane);
+    Bi[k] = i8_frag(B, s, k, 1, C.cb, C.lane);
+  }
+  const int col = 16 * C.cb + C.j;
+  uint32_t chi, clo, c4;
+  i8_corrections(reinterpret_cast<const int *>(B + kI8ExpBytes) + s * 256 + col, chi, clo, c4);
+  const int ebc = int(reinterpret_cast<const int8_t *>(B)[s * 128 + col]);
+  tmax = 0.0;
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int rt = 2 * C.hf + u;
+    const uint8_t *eg = Ebuf + size_t(rt * 8) * kI8FragBytes + C.lane * 16;
+    uint4 Er[4], Ei[4], En[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      Er[k] = *reinterpret_cast<const uint4 *>(eg + (k * 2 + 0) * kI8FragBytes);
+      Ei[k] = *reinterpret_cast<const uint4 *>(eg + (k * 2 + 1) * kI8FragBytes);
+      En[k] = not4(Ei[k]);
+    }
+    // re = Er Br - Ei Bi = Er Br + (~Ei) Bi + colsum(Bi) ; im = Er Bi + Ei Br
+    I8Acc acc;
+    i8_block(Er, En, Er, Ei, Br, Bi, acc);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int ex = s_ea[16 * rt + 4 * C.g + e] + ebc - 46;
+      const double vr = ldexp(i8_value(acc.re, e, chi, clo, c4), ex);
+      const double vi = ldexp(i8_value(acc.im, e, 0u, 0u, 0u), ex);
+      Td[u][0][e] = vr;
+      Td[u][1][e] = vi;
+      tmax = fmax(tmax, fmax(fabs(vr), fabs(vi)));
+    }
+  }
+  tmax = fmax(tmax, __shfl_xor(tmax, 16, 64));
+  tmax = fmax(tmax, __shfl_xor(tmax, 32, 64));
+}
+
+// Slice a wave's 4 x 4 values per plane (rows 16 c + j of the A operand,
+// contraction 16 (2 h + u) + 4 g + e) with row exponent ex into buffer buf:
+// fragment (row tile c, slice k, plane q), bytes 8 h .. 8 h + 7 of the lane.
+__device__ inline void i8_store(const SplitCtx &C, uint8_t *buf, const double (&V)[2][2][4], int ex) {
+  const double scale = ldexp(1.0, 31 - ex);
+  uint8_t *dst = buf + size_t(C.cb * 8) * kI8FragBytes + C.lane * 16 + C.hf * 8;
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    uint32_t w[2][4];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+      transpose_digits(digit_word(V[u][q][0], scale), digit_word(V[u][q][1], scale),
+                       digit_word(V[u][q][2], scale), digit_word(V[u][q][3], scale), w[u]);
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      *reinterpret_cast<uint2 *>(dst + (k * 2 + q) * kI8FragBytes) = make_uint2(w[0][k], w[1][k]);
+  }
+}
+
+// GEMM2 (int8): E'^T[b'][a'] += sum_a T_s[a][b'] conj(A_s[a][a']).
+__device__ inline void i8_gemm2(const SplitCtx &C, const uint8_t *A, const uint8_t *Tbuf, const int *s_eTs, int s,
+                                double (&Ep)[2][2][4]) {
+  uint4 Ar[4], Ai[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    Ar[k] = i8_frag(A, s, k, 0, C.cb, C.lane);
+    Ai[k] = i8_frag(A, s, k, 1, C.cb, C.lane);
+  }
+  const int col = 16 * C.cb + C.j;
+  uint32_t chi, clo, c4;
+  i8_corrections(reinterpret_cast<const int *>(A + kI8ExpBytes) + s * 256 + col, chi, clo, c4);
+  const int eac = int(reinterpret_cast<const int8_t *>(A)[s * 128 + col]);
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int bt = 2 * C.hf + u;
+    const uint8_t *tg = Tbuf + size_t(bt * 8) * kI8FragBytes + C.lane * 16;
+    uint4 Tr[4], Ti[4], Tn[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      Tr[k] = *reinterpret_cast<const uint4 *>(tg + (k * 2 + 0) * kI8FragBytes);
+      Ti[k] = *reinterpret_cast<const uint4 *>(tg + (k * 2 + 1) * kI8FragBytes);
+      Tn[k] = not4(Tr[k]);
+    }
+    // re = Tr Ar + Ti Ai ; im = Ti Ar - Tr Ai = Ti Ar + (~Tr) Ai + colsum(Ai)
+    I8Acc acc;
+    i8_block(Tr, Ti, Tn, Ti, Ar, Ai, acc);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int ex = s_eTs[16 * bt + 4 * C.g + e] + eac - 46;
+      Ep[u][0][e] += ldexp(i8_value(acc.re, e, 0u, 0u, 0u), ex);
+      Ep[u][1][e] += ldexp(i8_value(acc.im, e, chi, clo, c4), ex);
+    }
+  }
+}
+
+// Same five-phase schedule as overlap_split, on 32 KiB int8 buffers.
+__device__ void overlap_i8(const GramJobDev &J, int64_t ia, int64_t ib, uint8_t *buf0, uint8_t *buf1, int *s_ea,
+                           int *s_eT, double *s_mx, double *s_ov, double &ov_re, double &ov_im) {
+  const int tid = threadIdx.x, wave = tid >> 6;
+  SplitCtx C;
+  C.lane = tid & 63;
+  C.j = C.lane & 15;
+  C.g = C.lane >> 4;
+  C.cb = wave & 3;
+  C.hf = wave >> 2;
+  const uint8_t *abase = reinterpret_cast<const uint8_t *>(J.a_base) + ia * J.a_stride;
+  const uint8_t *bbase = reinterpret_cast<const uint8_t *>(J.b_base) + ib * J.b_stride;
+  uint8_t *X = buf0, *Y = buf1;
+  {
+    uint4 *X16 = reinterpret_cast<uint4 *>(X);
+    for (int x = tid; x < kI8BufBytes / 16; x += kSplitThreads) X16[x] = make_uint4(0, 0, 0, 0);
+    for (int x = tid; x < kSP; x += kSplitThreads) s_ea[x] = 0;
+    __syncthreads();
+    // E_0 = [[1]]: exponent 1, code 2^30, leading digit 64
+    if (tid == 0) {
+      X[0] = 64;
+      s_ea[0] = 1;
+    }
+    __syncthreads();
+  }
+  const int col = 16 * C.cb + C.j;
+  for (int l = 0; l < J.m; ++l) {
+    const uint8_t *A = abase + J.a_off[l];
+    const uint8_t *B = bbase + J.b_off[l];
+    double Td0[2][2][4], Td1[2][2][4], Ep[2][2][4];
+    double tmax;
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) Ep[u][q][e] = 0.0;
+    i8_gemm1(C, B, X, s_ea, 0, Td0, tmax);
+    if (C.g == 0) s_mx[(0 * 2 + C.hf) * kSP + col] = tmax;
+    __syncthreads();
+    {
+      const int eT0 = exp_above_i8(fmax(s_mx[(0 * 2 + 0) * kSP + col], s_mx[(0 * 2 + 1) * kSP + col]));
+      if (C.hf == 0 && C.g == 0) s_eT[0 * kSP + col] = eT0;
+      i8_store(C, Y, Td0, eT0);
+      i8_gemm1(C, B, X, s_ea, 1, Td1, tmax);
+      if (C.g == 0) s_mx[(1 * 2 + C.hf) * kSP + col] = tmax;
+    }
+    __syncthreads();
+    {
+      const int eT1 = exp_above_i8(fmax(s_mx[(1 * 2 + 0) * kSP + col], s_mx[(1 * 2 + 1) * kSP + col]));
+      if (C.hf == 0 && C.g == 0) s_eT[1 * kSP + col] = eT1;
+      i8_store(C, X, Td1, eT1);
+      i8_gemm2(C, A, Y, s_eT, 0, Ep);
+    }
+    __syncthreads();
+    i8_gemm2(C, A, X, s_eT + kSP, 1, Ep);
+    {
+      double rm = 0.0;
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) rm = fmax(rm, fmax(fabs(Ep[u][0][e]), fabs(Ep[u][1][e])));
+      rm = fmax(rm, __shfl_xor(rm, 16, 64));
+      rm = fmax(rm, __shfl_xor(rm, 32, 64));
+      if (C.g == 0) s_mx[(0 * 2 + C.hf) * kSP + col] = rm;
+    }
+    __syncthreads();
+    if (l + 1 == J.m) {
+      if (wave == 0 && C.lane == 0) {
+        s_ov[0] = Ep[0][0][0];
+        s_ov[1] = Ep[0][1][0];
+      }
+    } else {
+      const int er = exp_above_i8(fmax(s_mx[(0 * 2 + 0) * kSP + col], s_mx[(0 * 2 + 1) * kSP + col]));
+      i8_store(C, Y, Ep, er);
+      if (C.hf == 0 && C.g == 0) s_ea[col] = er;
+    }
+    __syncthreads();
+    uint8_t *t = X;
+    X = Y;
+    Y = t;
+  }
+  ov_re = s_ov[0];
+  ov_im = s_ov[1];
+  __syncthreads();
+}
+
 template <int PREC>
 constexpr int threads_of() {
-  return PREC == QK_SPLIT_BF16 ? kSplitThreads : kThreads;
+  return (PREC == QK_SPLIT_BF16 || PREC == QK_SPLIT_I8) ? kSplitThreads : kThreads;
 }
 
 template <int PREC, int MAXP>
@@ -624,12 +911,17 @@ __global__ __launch_bounds__(threads_of<PREC>()) void gram_kernel(const GramJobD
       overlap_plain<float, f32x4, float2, MAXP>(J, J.a0 + i, J.b0 + j, reinterpret_cast<float2 *>(smem),
                                                 reinterpret_cast<float *>(s_red), re, im, ex);
       k = ldexp(double(re) * re + double(im) * im, 2 * ex);
-    } else {
+    } else if constexpr (PREC == QK_SPLIT_BF16) {
       double re, im;
       int ex;
       overlap_split<MAXP>(J, J.a0 + i, J.b0 + j, smem, smem + size_t(MAXP) * MAXP * 16, s_ea, s_eT, s_mx, s_ov,
                           re, im, ex);
       k = ldexp(re * re + im * im, 2 * ex);
+    } else {
+      static_assert(MAXP == kSP, "the split-int8 form uses 64 x 64 site blocks");
+      double re, im;
+      overlap_i8(J, J.a0 + i, J.b0 + j, smem, smem + kI8BufBytes, s_ea, s_eT, s_mx, s_ov, re, im);
+      k = re * re + im * im;
     }
     if (threadIdx.x == 0) write_k(J, i, j, k);
   }
@@ -639,7 +931,8 @@ template <int PREC, int MAXP>
 size_t lds_bytes() {
   if (PREC == QK_FP64) return size_t(MAXP) * MAXP * 16;
   if (PREC == QK_FP32) return size_t(MAXP) * MAXP * 8;
-  return size_t(MAXP) * MAXP * 32;   // E slices + T slices
+  if (PREC == QK_SPLIT_BF16) return size_t(MAXP) * MAXP * 32;   // E slices + T slices
+  return size_t(2) * kI8BufBytes;                                  // two int8 operand buffers
 }
 
 template <int PREC, int MAXP>
@@ -706,8 +999,10 @@ qk_status launch_gram(const std::vector<GramJobDev> &jobs_in, int max_pad, qk_pr
     st = launch_one<QK_FP64, 64>(jobs_dev, tiles_dev, total, counter, stream);
   else if (prec == QK_FP32)
     st = launch_one<QK_FP32, 64>(jobs_dev, tiles_dev, total, counter, stream);
-  else
+  else if (prec == QK_SPLIT_BF16)
     st = launch_one<QK_SPLIT_BF16, 64>(jobs_dev, tiles_dev, total, counter, stream);
+  else
+    st = launch_one<QK_SPLIT_I8, 64>(jobs_dev, tiles_dev, total, counter, stream);
   (void)hipFreeAsync(ws, stream);
   return st;
 }
@@ -836,6 +1131,91 @@ qk_status launch_gather_meta(const qk_mps_batch_meta &src, const qk_mps_batch_me
   hipLaunchKernelGGL(gather_meta_kernel, dim3(unsigned((count + 255) / 256)), dim3(256), 0, stream, src, dst,
                      idx_dev, m1, count);
   QK_HIP_CHECK(hipGetLastError());
+  return QK_OK;
+}
+
+// One block per (site, mps) for the split-int8 form: column exponents (with
+// the int8 margin), the int8 digit fragments in B-operand order and the
+// column digit sums of the imaginary plane.
+__global__ __launch_bounds__(256) void pack_i8_kernel(const double2 *__restrict__ src, uint8_t *__restrict__ dst,
+                                                      const int32_t *__restrict__ pad,
+                                                      const int64_t *__restrict__ site_off, int64_t mps_stride,
+                                                      int64_t i8_stride, int32_t m, int64_t n) {
+  const int l = blockIdx.x;
+  const int64_t i = blockIdx.y;
+  if (i >= n || l >= m) return;
+  __shared__ int s_e[2 * 128];
+  const int pl = pad[l], pr = pad[l + 1];
+  const double2 *site = src + i * mps_stride + site_off[l];
+  uint8_t *out = dst + i * i8_stride + int64_t(l) * kI8SiteBytes;
+  auto value = [&](int s, int row, int col, int q) -> double {
+    if (row >= pl || col >= pr) return 0.0;
+    const double2 x = site[(size_t(s) * pl + row) * pr + col];
+    return q ? x.y : x.x;
+  };
+  for (int t = threadIdx.x; t < 2 * 128; t += blockDim.x) {
+    const int s = t / 128, c = t % 128;
+    int e = 0;
+    if (c < pr) {
+      double mx = 0.0;
+      for (int r = 0; r < pl; ++r) {
+        const double2 x = site[(size_t(s) * pl + r) * pr + c];
+        mx = fmax(mx, fmax(fabs(x.x), fabs(x.y)));
+      }
+      e = max(exp_above_i8(mx), -127);   // int8 storage; |x| < 2^e still holds
+    }
+    s_e[t] = e;
+    out[t] = uint8_t(int8_t(e));
+  }
+  __syncthreads();
+  // fragments: work item (s, q, ct, lane), 16 rows each
+  for (int w = threadIdx.x; w < 2 * 2 * 4 * 64; w += blockDim.x) {
+    const int lane = w % 64;
+    const int ct = (w / 64) % 4;
+    const int q = (w / 256) % 2;
+    const int s = w / 512;
+    const int jj = lane & 15, gg = lane >> 4;
+    const int col = 16 * ct + jj;
+    const double scale = ldexp(1.0, 31 - s_e[s * 128 + col]);
+    uint32_t sl[4][4];   // [group of four rows][digit]
+#pragma unroll
+    for (int vv = 0; vv < 4; ++vv) {
+      uint32_t d[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int v = 4 * vv + r;
+        const int row = 16 * (2 * (v >> 3) + ((v >> 2) & 1)) + 4 * gg + (v & 3);
+        d[r] = digit_word(value(s, row, col, q), scale);
+      }
+      transpose_digits(d[0], d[1], d[2], d[3], sl[vv]);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      *reinterpret_cast<uint4 *>(out + kI8ExpBytes + kI8SumBytes +
+                                 size_t(((s * 4 + k) * 2 + q) * 4 + ct) * kI8FragBytes + lane * 16) =
+          make_uint4(sl[0][k], sl[1][k], sl[2][k], sl[3][k]);
+  }
+  // column digit sums of the imaginary plane: item (s, k, c)
+  int *cs = reinterpret_cast<int *>(out + kI8ExpBytes);
+  for (int t = threadIdx.x; t < 2 * 4 * 64; t += blockDim.x) {
+    const int c = t % 64, k = (t / 64) % 4, s = t / 256;
+    const double scale = ldexp(1.0, 31 - s_e[s * 128 + c]);
+    int sum = 0;
+    for (int r = 0; r < 64; ++r) sum += int(int8_t(digit_word(value(s, r, c, 1), scale) >> (8 * (3 - k))));
+    cs[(s * 4 + k) * 64 + c] = sum;
+  }
+}
+
+qk_status launch_pack_i8(const qk_mps_batch *b, hipStream_t stream) {
+  if (b->n == 0) return QK_OK;
+  const int64_t chunk = 65535;
+  for (int64_t i0 = 0; i0 < b->n; i0 += chunk) {
+    const int64_t cnt = std::min(chunk, b->n - i0);
+    hipLaunchKernelGGL(pack_i8_kernel, dim3(unsigned(b->m), unsigned(cnt)), dim3(256), 0, stream,
+                       b->f64 + i0 * b->mps_stride, b->si8 + i0 * b->i8_stride, b->pad_dev, b->site_off_dev,
+                       b->mps_stride, b->i8_stride, b->m, cnt);
+    QK_HIP_CHECK(hipGetLastError());
+  }
   return QK_OK;
 }
 

@@ -55,6 +55,23 @@ inline int64_t split_site_bytes() {
   return kSplitExpBytes + int64_t(2) * kSlices * 2 * (kSplitMaxPad / 32) * (kSplitMaxPad / 16) * kFragBytes;
 }
 
+// Split-int8 operand form: the same 31-bit codes (row / column exponent e
+// with max |x| (1 + 2^-7) < 2^e, so the leading digit is in [-127, 127]) cut
+// into four balanced base-256 digits stored as int8.  A site block is:
+//   [int8 exponents e[s][c], s in {0,1}, c < 128 : 256 bytes]
+//   [int32 column digit sums of the imaginary plane cs[s][k][c], c < 64 :
+//    2048 bytes]
+//   [fragments [s][digit k 0..3][plane 0..1][ct 0..3][lane][16 int8]]
+// where fragment ct is the B operand of v_mfma_i32_16x16x64_i8 for columns
+// 16 ct .. 16 ct + 15: lane l = j + 16 g, byte v holds row
+//   perm(g, v) = 16 (2 (v >> 3) + ((v >> 2) & 1)) + 4 g + (v & 3)
+// of column 16 ct + j.  Every site is a 64 x 64 block (zero beyond the pads).
+constexpr int kI8ExpBytes = 256;
+constexpr int kI8SumBytes = 2 * 4 * 64 * 4;
+constexpr int kI8FragBytes = 64 * 16;
+constexpr int kI8BufBytes = 4 * 4 * 2 * kI8FragBytes;   // one A-operand buffer (64 rows)
+constexpr int64_t kI8SiteBytes = kI8ExpBytes + kI8SumBytes + int64_t(2) * 4 * 2 * 4 * kI8FragBytes;
+
 }  // namespace qk
 
 // Opaque batch.  Every MPS of a batch has m sites with the pad profile
@@ -72,15 +89,19 @@ struct qk_mps_batch {
   int64_t mps_stride = 0;          // complex elements per MPS
   std::vector<int64_t> split_off;  // m + 1 entries, bytes
   int64_t split_stride = 0;        // bytes per MPS
+  std::vector<int64_t> i8_off;     // m + 1 entries, bytes (split-int8 form)
+  int64_t i8_stride = 0;           // bytes per MPS
 
   double2 *f64 = nullptr;          // n * mps_stride
   float2 *f32 = nullptr;           // packed on demand
   uint8_t *sbf16 = nullptr;        // packed on demand
+  uint8_t *si8 = nullptr;          // packed on demand
 
   int32_t *dims_dev = nullptr;     // n * (m + 1)
   int32_t *pad_dev = nullptr;      // m + 1
   int64_t *site_off_dev = nullptr; // m + 1
   int64_t *split_off_dev = nullptr;// m + 1
+  int64_t *i8_off_dev = nullptr;   // m + 1
   double *disc_dev = nullptr;      // n: summed discarded weight
   double *maxdisc_dev = nullptr;   // n: largest single discarded weight
   int32_t *degen_dev = nullptr;    // n: near-degenerate cuts
@@ -110,6 +131,7 @@ qk_status launch_gather_meta(const qk_mps_batch_meta &src, const qk_mps_batch_me
                              int32_t m1, int64_t count, hipStream_t stream);
 qk_status launch_pack_f32(const qk_mps_batch *b, hipStream_t stream);
 qk_status launch_pack_split(const qk_mps_batch *b, hipStream_t stream);
+qk_status launch_pack_i8(const qk_mps_batch *b, hipStream_t stream);
 
 struct GramJobDev {
   const void *a_base;              // form-specific base pointer of batch a

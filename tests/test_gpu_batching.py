@@ -35,13 +35,16 @@ def test_gather_forms_and_errors():
     mpss = _oracle_mps(sd.WORKLOADS["fp32"], 4, chi=16)
     b = q.import_batch(mpss)
     b.pack("split_bf16")
-    g = b.gather([2, 0, 2, 3], forms=("split_bf16",))
-    Kg = q.gram(g, precision="split_bf16").cpu().numpy()
-    Kb = q.gram_block(b, 0, 4, b, 0, 4, precision="split_bf16").cpu().numpy()
+    b.pack("split_i8")
+    g = b.gather([2, 0, 2, 3], forms=("split_bf16", "split_i8"))
     idx = [2, 0, 2, 3]
-    for r in range(4):
-        for c in range(r, 4):
-            assert Kg[r, c] == Kb[idx[r], idx[c]]        # same inputs, same bits
+    for prec in ("split_bf16", "split_i8"):
+        Kg = q.gram(g, precision=prec).cpu().numpy()
+        Kb = q.gram_block(b, 0, 4, b, 0, 4, precision=prec).cpu().numpy()
+        for r in range(4):
+            for c in range(r, 4):
+                assert Kg[r, c] == Kb[idx[r], idx[c]]    # same inputs, same bits
+    assert g.info()["bytes_split_i8"] == 4 * 50 * 67840      # 4 MPS x 50 sites x site block
     with pytest.raises(q.QKError) as e:
         q.gram(g, precision="fp64")
     assert e.value.status == -4                            # QK_ENOTSUP: no FP64 form
@@ -62,7 +65,7 @@ def test_gram_multi_mixed_batches_one_launch():
     mb = _oracle_mps(wb, 7)
     A = q.import_batch(ma)
     Bb = q.import_batch(mb)
-    for prec, tol in (("fp64", 1e-12), ("split_bf16", 1e-7)):
+    for prec, tol in (("fp64", 1e-12), ("split_bf16", 1e-7), ("split_i8", 1e-7)):
         K1 = torch.zeros((9, 9), dtype=torch.float64, device="cuda")
         K2 = torch.zeros((3, 6), dtype=torch.float64, device="cuda")
         K3 = torch.zeros((7, 7), dtype=torch.float64, device="cuda")

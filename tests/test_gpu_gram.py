@@ -44,7 +44,7 @@ def test_gram_fp64_matches_oracle(small_sets, which):
     assert np.allclose(np.diag(K), 1.0, atol=1e-12)
 
 
-@pytest.mark.parametrize("prec,tol", [("fp32", 2e-5), ("split_bf16", 1e-7)])
+@pytest.mark.parametrize("prec,tol", [("fp32", 2e-5), ("split_bf16", 1e-7), ("split_i8", 1e-7)])
 def test_gram_reduced_precision(small_sets, prec, tol):
     """FP32: plain complex64 operands and FP32 accumulation (error grows with
     chain length; 2e-5 bounds 50 sites).  Split-BF16: fixed-point slices with
@@ -111,23 +111,28 @@ def test_gauge_invariance_fp64():
 def test_gram_deterministic(small_sets):
     import paper_2411_09336_amd as q
     b = q.import_batch(small_sets[1])
-    for prec in ("fp64", "split_bf16"):
+    for prec in ("fp64", "split_bf16", "split_i8"):
         k1 = q.gram(b, precision=prec).cpu().numpy()
         k2 = q.gram(b, precision=prec).cpu().numpy()
         assert (k1 == k2).all()
 
 
 @pytest.mark.gpu
-def test_split_values_at_top_of_exponent_range():
-    """Product states whose amplitudes sit just below 1 (and just below 1/2):
-    after fixed-point rounding they reach the largest slice code, the case in
-    which a carry mistake would flip their sign.  Self-overlaps must be 1 and
-    every entry must match the oracle."""
+@pytest.mark.parametrize("prec", ["split_bf16", "split_i8"])
+def test_split_values_at_top_of_exponent_range(prec):
+    """Product states whose amplitudes sit just below 1, just below 1/2 and
+    at the int8 form's exponent margin 128/129: after fixed-point rounding
+    they reach the largest codes, where a carry mistake would flip a sign or
+    overflow the leading digit.  Self-overlaps must be 1 and every entry must
+    match the oracle."""
     import paper_2411_09336_amd as q
     require_gpu()
     m = 24
     mps = []
-    for k, top in enumerate([1.0 - 2.0 ** -40, 1.0 - 2.0 ** -33, 0.5 - 2.0 ** -45, 1.0 - 2.0 ** -31]):
+    r = 128.0 / 129.0
+    tops = [1.0 - 2.0 ** -40, 1.0 - 2.0 ** -33, 0.5 - 2.0 ** -45, 1.0 - 2.0 ** -31,
+            r * (1.0 - 2.0 ** -35), r * (1.0 + 2.0 ** -35), 0.5 * r]
+    for k, top in enumerate(tops):
         site = []
         for l in range(m):
             a = top if (l + k) % 3 else np.sqrt(0.5)
@@ -140,7 +145,7 @@ def test_split_values_at_top_of_exponent_range():
             site.append(t)
         mps.append(site)
     b = q.import_batch(mps)
-    K = q.gram(b, precision="split_bf16").cpu().numpy()
+    K = q.gram(b, precision=prec).cpu().numpy()
     Kref = ogram.gram(mps)
     # fixed-point resolution 2^-31 relative per value and site: 24 sites,
     # two operands, |K| = |<a|b>|^2 -> below 4 * 24 * 2^-31 = 4.5e-8

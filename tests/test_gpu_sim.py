@@ -111,12 +111,15 @@ def test_precision_workload_split_vs_fp64():
     b = _sim(X, w)
     Kd = q.gram(b, precision="fp64").cpu().numpy()
     Ks = q.gram(b, precision="split_bf16").cpu().numpy()
+    Ki = q.gram(b, precision="split_i8").cpu().numpy()
     Kf = q.gram(b, precision="fp32").cpu().numpy()
     Ko = ogram.gram([b.export(i) for i in range(len(X))])
-    print("split vs fp64", np.abs(Ks - Kd).max(), "fp32 vs fp64", np.abs(Kf - Kd).max(),
+    print("split vs fp64", np.abs(Ks - Kd).max(), "split_i8 vs fp64", np.abs(Ki - Kd).max(),
+          "fp32 vs fp64", np.abs(Kf - Kd).max(),
           "fp64 vs oracle", np.abs(Kd - Ko).max(), "K near-dup", Kd[0, 3], Kd[1, 4])
     assert np.abs(Kd - Ko).max() < 1e-12
     assert np.abs(Ks - Kd).max() < 1e-7
+    assert np.abs(Ki - Ko).max() < 1e-7
     assert Kd[0, 3] > 0.05 and Kd[1, 4] > 0.05
 
 
@@ -126,7 +129,7 @@ def test_tiny_gpu_gram_matches_golden():
     K_gold = np.load(os.path.join(os.path.dirname(__file__), "golden", "tiny_gram_statevector.npy"))
     w = sd.WORKLOADS["tiny"]
     b = _sim(sd.workload_features(w), w)
-    for prec, tol in (("fp64", 1e-12), ("split_bf16", 1e-7), ("fp32", 1e-5)):
+    for prec, tol in (("fp64", 1e-12), ("split_bf16", 1e-7), ("split_i8", 1e-7), ("fp32", 1e-5)):
         K = q.gram(b, precision=prec).cpu().numpy()
         print(prec, "max|dK| vs golden", np.abs(K - K_gold).max())
         assert np.abs(K - K_gold).max() < tol
