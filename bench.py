@@ -9,16 +9,16 @@ symmetric 6400 x 6400 Gram matrix K = |<psi_i|psi_j>|^2.
 What one run does (progress on stderr, ONE JSON line on stdout):
   1. Simulate S distinct circuits of the workload on the GPU (mps_simulate,
      timed separately: circuits/s, two-qubit gates/s).
-  2. Pack them into the split-BF16 form and gather the 6400-MPS Gram batch
+  2. Pack them into the timed form (default split-int8) and gather the 6400-MPS Gram batch
      (MPS i is a copy of simulated state i mod S; every copy has the same
      saturated bond profile as a freshly simulated point, so the Gram work is
      that of 6400 distinct states).
-  3. TIMED: the full symmetric split-BF16 Gram (row slabs, HIP events on the
+  3. TIMED: the full symmetric Gram in that form (row slabs, HIP events on the
      launch stream).  value = N (N - 1) / 2 / t.
-  4. FP64 and split-BF16 Gram of the S distinct states: split-vs-FP64 speedup
-     on identical work, and |dK| split vs FP64; each entry of the full matrix
-     equals bit-for-bit one of these S x S entries (checked), so this |dK| is
-     the maximum over all 20.5M entries.
+  4. FP64, split-BF16 and split-int8 Grams of the S distinct states:
+     speedups over FP64 on identical work, and |dK| vs FP64; each entry of
+     the full matrix equals bit-for-bit one of the S x S entries of its form
+     (checked), so that |dK| is the maximum over all 20.5M entries.
   5. The CPU FP64 oracle on a bounded sample of pairs (baseline, not target),
      also giving |dK| of both GPU forms against the oracle.
 """
@@ -36,7 +36,16 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "Gram entries/s at 165 qubits chi=64, split-BF16 vs FP64 GPU, |dK|<=1e-6"
-PEAK_TFLOPS = {"bf16": 2500.0, "fp64": 78.6, "fp32": 157.3}
+PEAK_TFLOPS = {"bf16": 2500.0, "int8": 5000.0, "fp64": 78.6, "fp32": 157.3}
+# timed forms: MFMA dtype, kernel, description
+FORMS = {
+    "split_i8": ("int8", "gram_kernel<split_i8,64>",
+                 "split-int8: 31-bit fixed-point codes with row/column exponents, four int8 digits, "
+                 "11 digit products on int8 MFMA, exact int32 accumulation, fp64 combine"),
+    "split_bf16": ("bf16", "gram_kernel<split_bf16,64>",
+                   "split-bf16: the same four digits carried as bf16, 11 digit products on bf16 MFMA, "
+                   "exact fp32 leading accumulator + fp32 accumulator for the rest, fp64 combine"),
+}
 HBM_PEAK_GBS = 8000.0
 
 
@@ -54,12 +63,13 @@ def flops_per_entry(dims_a, dims_b):
     return 8 * f
 
 
-def counter_traffic():
+def counter_traffic(form):
     """HBM bytes per timed Gram launch from the committed hardware-counter
-    record, or None when absent or taken on a different kernel source."""
+    record of that form, or None when absent or taken on a different kernel
+    source."""
     import hashlib
     src = os.path.join(ROOT, "paper_2411_09336_amd", "csrc", "gram.hip")
-    rec = os.path.join(ROOT, "profiles", "gram_split_counters.json")
+    rec = os.path.join(ROOT, "profiles", f"gram_{form}_counters.json")
     try:
         digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
         data = json.load(open(rec))
@@ -115,7 +125,7 @@ def cpu_oracle_leg(mps_list, K_split, K_fp64, seconds):
     cpu = {"value": round(len(sample) / dt, 3), "unit": "entries/s", "cores": 1, "kind": "oracle",
            "sample": f"{len(sample)} entries (random pairs among {n} simulated 165-qubit chi=64 MPS); "
                      f"complex128 NumPy, one core, one BLAS thread, {dt:.1f} s"}
-    dk = {"split_bf16_vs_oracle_max": float(d_split.max()), "split_bf16_vs_oracle_mean": float(d_split.mean()),
+    dk = {"split_vs_oracle_max": float(d_split.max()), "split_vs_oracle_mean": float(d_split.mean()),
           "fp64_vs_oracle_max": float(d_fp64.max()), "fp64_vs_oracle_mean": float(d_fp64.mean()),
           "pairs": len(sample)}
     return cpu, dk
@@ -138,6 +148,7 @@ def main():
     ap.add_argument("--kernel-probe", type=int, default=0, metavar="N",
                     help="only time the symmetric Gram of N random saturated 165-site chi=64 MPS in every "
                          "form (kernel microbenchmark, no simulation), then exit")
+    ap.add_argument("--form", choices=sorted(FORMS), default="split_i8", help="form of the timed Gram")
     ap.add_argument("--routing", type=int, default=1,
                     help="0: 2(k-1) SWAPs per Rxx (paper); 1: cancelled inverse SWAP pairs (same circuit)")
     args = ap.parse_args()
@@ -250,12 +261,13 @@ def run(args):
         f"unconverged SVDs {info['unconverged_svds']}, degenerate cuts {info['degenerate_cuts']}")
 
     # ---------------------------------------------------------------- 2. Gram batch
-    sim.pack("split_bf16")
-    sim.pack("fp64")
+    form = args.form
+    for f in ("fp64", "split_bf16", "split_i8"):
+        sim.pack(f)
     idx = np.arange(N) % S
-    gb = sim.gather(idx, forms=("split_bf16",))
+    gb = sim.gather(idx, forms=(form,))
     ginfo = gb.info()
-    log(f"[bench] Gram batch: {N} MPS, split-BF16 planes {ginfo['bytes_split_bf16'] / 1e9:.1f} GB")
+    log(f"[bench] Gram batch: {N} MPS, {form} planes {ginfo['bytes_' + form] / 1e9:.1f} GB")
 
     K = torch.zeros((N, N), dtype=torch.float64, device="cuda")
     slabs = slab_bounds(N, args.slabs)
@@ -268,7 +280,7 @@ def run(args):
         for p in range(nrun):
             r0, r1 = slabs[p], slabs[p + 1]
             out = K[r0:, r0:]
-            q.gram_block(gb, r0, r1 - r0, gb, r0, N - r0, precision="split_bf16", upper_only=True,
+            q.gram_block(gb, r0, r1 - r0, gb, r0, N - r0, precision=form, upper_only=True,
                          out=out, stream=stream)
             stream.synchronize()
             log(f"[bench] {tag} slab {p + 1}/{len(slabs) - 1} rows {r0}:{r1} done")
@@ -279,7 +291,7 @@ def run(args):
     # warmup: one slab-sized block outside the timed region
     for _ in range(args.warmup):
         wr = min(64, N)
-        q.gram_block(gb, 0, wr, gb, 0, N, precision="split_bf16", upper_only=True, out=K[:wr], stream=stream)
+        q.gram_block(gb, 0, wr, gb, 0, N, precision=form, upper_only=True, out=K[:wr], stream=stream)
         stream.synchronize()
         log("[bench] warmup done")
 
@@ -294,7 +306,7 @@ def run(args):
     if args.slabs_run > 0:
         log(f"[bench] partial run ({args.slabs_run} slabs) for hardware counters: no result line")
         return
-    log(f"[bench] split-BF16 full Gram: {t_split:.2f} s -> {value:.1f} entries/s")
+    log(f"[bench] {form} full Gram: {t_split:.2f} s -> {value:.1f} entries/s")
 
     # complete the lower triangle (outside the timed region)
     Ku = torch.triu(K)
@@ -304,8 +316,8 @@ def run(args):
     # ---------------------------------------------------------------- 4. FP64 vs split on S distinct
     # full S x S blocks (bra i, ket j for every i, j), so that each upper
     # entry of the full matrix has an identically computed counterpart
-    Ks = torch.zeros((S, S), dtype=torch.float64, device="cuda")
     Kd = torch.zeros((S, S), dtype=torch.float64, device="cuda")
+    Kforms = {f: torch.zeros((S, S), dtype=torch.float64, device="cuda") for f in FORMS}
 
     def timed_gram(prec, out):
         q.gram_block(sim, 0, S, sim, 0, S, precision=prec, out=out, stream=stream)   # warm
@@ -318,8 +330,10 @@ def run(args):
         e1.synchronize()
         return e0.elapsed_time(e1) / 1e3
 
-    t_s_small = timed_gram("split_bf16", Ks)
     t_d_small = timed_gram("fp64", Kd)
+    t_forms = {f: timed_gram(f, Kforms[f]) for f in FORMS}
+    Ks = Kforms[form]
+    t_s_small = t_forms[form]
     speedup = t_d_small / t_s_small
     dK = (Ks - Kd).abs()
     ii = torch.as_tensor(idx, device="cuda")
@@ -330,7 +344,7 @@ def run(args):
     full_dK_max = float((K - Kd[ii][:, ii]).abs()[upper].max().item())
     del upper
     s_pairs = S * S
-    log(f"[bench] S={S}: split {t_s_small:.3f} s, fp64 {t_d_small:.3f} s, speedup {speedup:.2f}x; "
+    log(f"[bench] S={S}: {form} {t_s_small:.3f} s, fp64 {t_d_small:.3f} s, speedup {speedup:.2f}x; "
         f"|dK| max {dK.max().item():.3e}; full-matrix upper entries identical to the S x S map: {bit_identical}")
 
     # ---------------------------------------------------------------- roofline
@@ -338,16 +352,19 @@ def run(args):
     fpe = flops_per_entry(d0, d0)
     flops_launch = fpe * n_comp
     achieved_tf = flops_launch / t_split / 1e12
-    # a complex MAC is 8 algorithmic flops; the split form issues 11 slice
-    # products x 4 real products = 44 real MACs = 88 flops for it
+    # a complex MAC is 8 algorithmic flops; both split forms issue 11 digit
+    # products x 4 real products = 44 real MACs = 88 ops for it
+    mdt, kname, fdesc = FORMS[form]
     issued_tf = achieved_tf * 11
-    traffic, crec = counter_traffic()
-    roof = {"bound": "mfma", "achieved": round(achieved_tf, 3), "peak": PEAK_TFLOPS["bf16"], "unit": "TFLOP/s",
-            "frac": round(achieved_tf / PEAK_TFLOPS["bf16"], 5), "traffic": traffic,
+    traffic, crec = counter_traffic(form)
+    roof = {"bound": "mfma", "achieved": round(achieved_tf, 3), "peak": PEAK_TFLOPS[mdt], "unit": "TFLOP/s",
+            "frac": round(achieved_tf / PEAK_TFLOPS[mdt], 5), "traffic": traffic,
             "traffic_note": (None if crec is None else crec.get("note")),
+            "peak_note": f"dense {mdt} MFMA peak of the contraction's operand type; achieved counts "
+                         "algorithmic complex-GEMM flops (8 per complex MAC)",
             "launches_in_timed_region": len(slabs) - 1,
-            "kernel": "gram_kernel<split_bf16,64>", "flops_per_entry": fpe, "entries_per_timed_region": n_comp,
-            "issued_bf16_tflops": round(issued_tf, 2), "issued_frac": round(issued_tf / PEAK_TFLOPS["bf16"], 4),
+            "kernel": kname, "flops_per_entry": fpe, "entries_per_timed_region": n_comp,
+            "issued_tops": round(issued_tf, 2), "issued_frac": round(issued_tf / PEAK_TFLOPS[mdt], 4),
             "fp64_form_tflops": round(fpe * s_pairs / t_d_small / 1e12, 3),
             "fp64_form_frac": round(fpe * s_pairs / t_d_small / 1e12 / PEAK_TFLOPS["fp64"], 4)}
 
@@ -378,18 +395,22 @@ def run(args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16",
+        "dtype": mdt,
         "data": "synthetic",
         "config": {"workload": "full: 165 qubits, d=8, reps=2, chi=64, cutoff=1e-8, N=6400 symmetric Gram",
                    "n_points": N, "n_qubits": w.n_qubits, "distance": w.distance, "reps": w.reps,
                    "chi": w.chi, "cutoff": w.cutoff, "routing": args.routing, "distinct_states": S,
-                   "precision": "split-bf16 (4 fixed-point slices, 11 slice products, fp32 accumulate, fp64 combine)"},
+                   "form": form, "precision": fdesc},
         "roofline": roof,
         "cpu_baseline": cpu,
-        "fp64_gpu": {"entries_per_s": round(s_pairs / t_d_small, 2), "speedup_split_vs_fp64": round(speedup, 3),
-                     "measured_on": f"{S}x{S} symmetric Gram of the simulated states ({s_pairs} entries)"},
-        "dK": {"split_vs_fp64_max_all_entries": full_dK_max, "split_vs_fp64_max": float(dK.max().item()),
-               "split_vs_fp64_mean": float(dK.mean().item()), "full_matrix_bit_identical_to_SxS": bit_identical,
+        "fp64_gpu": {"entries_per_s": round(s_pairs / t_d_small, 2), "speedup_vs_fp64": round(speedup, 3),
+                     "measured_on": f"{S}x{S} Gram of the simulated states ({s_pairs} entries)"},
+        "forms_on_same_work": {
+            f: {"entries_per_s": round(s_pairs / t_forms[f], 2), "speedup_vs_fp64": round(t_d_small / t_forms[f], 3),
+                "dK_vs_fp64_max": float((Kforms[f] - Kd).abs().max().item()),
+                "dK_vs_fp64_mean": float((Kforms[f] - Kd).abs().mean().item())} for f in FORMS},
+        "dK": {"vs_fp64_max_all_entries": full_dK_max, "vs_fp64_max": float(dK.max().item()),
+               "vs_fp64_mean": float(dK.mean().item()), "full_matrix_bit_identical_to_SxS": bit_identical,
                "oracle": dk_oracle},
         "K_distribution": {"offdiag_median": float(np.median(offd)), "offdiag_max": float(offd.max()),
                            "offdiag_frac_above_1e-6": float((offd > 1e-6).mean())},

@@ -637,6 +637,17 @@ __device__ inline void transpose_digits(uint32_t d0, uint32_t d1, uint32_t d2, u
 
 __device__ inline uint4 not4(const uint4 &v) { return make_uint4(~v.x, ~v.y, ~v.z, ~v.w); }
 
+// Completes one row tile before the next one starts: the tile's results are
+// formed before this point and no later LDS or global load moves above it,
+// so only one tile's accumulators are live (register budget of two waves
+// per SIMD).
+__device__ inline void tile_fence(double (&v)[2][4]) {
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) asm volatile("" : "+v"(v[q][e])::"memory");
+}
+
 // Fragment (s, slice k, plane q, column block ct) of a packed int8 site block.
 __device__ inline uint4 i8_frag(const uint8_t *site, int s, int k, int q, int ct, int lane) {
   return *reinterpret_cast<const uint4 *>(site + kI8ExpBytes + kI8SumBytes +
@@ -692,9 +703,24 @@ __device__ inline void i8_corrections(const int *cs, uint32_t &chi, uint32_t &cl
   c4 = uint32_t(c2);
 }
 
-// GEMM1 (int8): T_s[a][b'] for a in rows 32h.., b' in block c.
-__device__ inline void i8_gemm1(const SplitCtx &C, const uint8_t *B, const uint8_t *Ebuf, const int *s_ea, int s,
-                                double (&Td)[2][2][4], double &tmax) {
+// Work split of the int8 kernel: workgroups of four waves, two per CU, each
+// workgroup on its own pair, so the two workgroups of a CU interleave their
+// MFMA and VALU phases.  Wave w owns column block c = w of every 64 x 64
+// product: it holds whole columns of T (rows of T^T) and whole rows of E',
+// so their exponents are formed in registers.  Three barriers per site:
+//   I.   GEMM1(s=0) reads E (buffer X) -> T0 -> Y ; GEMM1(s=1) reads X -> T1
+//   II.  T1 -> X (E consumed) ; GEMM2(s=0) reads Y
+//   III. GEMM2(s=1) reads X ; E' -> Y (T0 consumed), which is the next E
+constexpr int kI8Threads = 256;
+
+struct I8Ctx {
+  int lane, j, g, cb;
+};
+
+// GEMM1: T_s[a][b'] for all rows a (tiles rt = 0..3) and b' in block c;
+// tmax = max |T| over the whole column b' = 16 c + j.
+__device__ inline void i8_gemm1(const I8Ctx &C, const uint8_t *B, const uint8_t *Ebuf, const int *s_ea, int s,
+                                double (&Td)[4][2][4], double &tmax) {
   uint4 Br[4], Bi[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
@@ -707,8 +733,7 @@ __device__ inline void i8_gemm1(const SplitCtx &C, const uint8_t *B, const uint8
   const int ebc = int(reinterpret_cast<const int8_t *>(B)[s * 128 + col]);
   tmax = 0.0;
 #pragma unroll
-  for (int u = 0; u < 2; ++u) {
-    const int rt = 2 * C.hf + u;
+  for (int rt = 0; rt < 4; ++rt) {
     const uint8_t *eg = Ebuf + size_t(rt * 8) * kI8FragBytes + C.lane * 16;
     uint4 Er[4], Ei[4], En[4];
 #pragma unroll
@@ -725,37 +750,39 @@ __device__ inline void i8_gemm1(const SplitCtx &C, const uint8_t *B, const uint8
       const int ex = s_ea[16 * rt + 4 * C.g + e] + ebc - 46;
       const double vr = ldexp(i8_value(acc.re, e, chi, clo, c4), ex);
       const double vi = ldexp(i8_value(acc.im, e, 0u, 0u, 0u), ex);
-      Td[u][0][e] = vr;
-      Td[u][1][e] = vi;
+      Td[rt][0][e] = vr;
+      Td[rt][1][e] = vi;
       tmax = fmax(tmax, fmax(fabs(vr), fabs(vi)));
     }
+    tile_fence(Td[rt]);
   }
   tmax = fmax(tmax, __shfl_xor(tmax, 16, 64));
   tmax = fmax(tmax, __shfl_xor(tmax, 32, 64));
 }
 
-// Slice a wave's 4 x 4 values per plane (rows 16 c + j of the A operand,
-// contraction 16 (2 h + u) + 4 g + e) with row exponent ex into buffer buf:
-// fragment (row tile c, slice k, plane q), bytes 8 h .. 8 h + 7 of the lane.
-__device__ inline void i8_store(const SplitCtx &C, uint8_t *buf, const double (&V)[2][2][4], int ex) {
+// Slice the wave's values (A-operand rows 16 c + j, contraction
+// 16 rt + 4 g + e) with row exponent ex into buffer buf: fragment (row tile
+// c, digit k, plane q), lane bytes 4 rt .. 4 rt + 3.
+__device__ inline void i8_store(const I8Ctx &C, uint8_t *buf, const double (&V)[4][2][4], int ex) {
   const double scale = ldexp(1.0, 31 - ex);
-  uint8_t *dst = buf + size_t(C.cb * 8) * kI8FragBytes + C.lane * 16 + C.hf * 8;
+  uint8_t *dst = buf + size_t(C.cb * 8) * kI8FragBytes + C.lane * 16;
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
-    uint32_t w[2][4];
+    uint32_t w[4][4];
 #pragma unroll
-    for (int u = 0; u < 2; ++u)
-      transpose_digits(digit_word(V[u][q][0], scale), digit_word(V[u][q][1], scale),
-                       digit_word(V[u][q][2], scale), digit_word(V[u][q][3], scale), w[u]);
+    for (int rt = 0; rt < 4; ++rt)
+      transpose_digits(digit_word(V[rt][q][0], scale), digit_word(V[rt][q][1], scale),
+                       digit_word(V[rt][q][2], scale), digit_word(V[rt][q][3], scale), w[rt]);
 #pragma unroll
     for (int k = 0; k < 4; ++k)
-      *reinterpret_cast<uint2 *>(dst + (k * 2 + q) * kI8FragBytes) = make_uint2(w[0][k], w[1][k]);
+      *reinterpret_cast<uint4 *>(dst + (k * 2 + q) * kI8FragBytes) = make_uint4(w[0][k], w[1][k], w[2][k], w[3][k]);
   }
 }
 
-// GEMM2 (int8): E'^T[b'][a'] += sum_a T_s[a][b'] conj(A_s[a][a']).
-__device__ inline void i8_gemm2(const SplitCtx &C, const uint8_t *A, const uint8_t *Tbuf, const int *s_eTs, int s,
-                                double (&Ep)[2][2][4]) {
+// GEMM2: E'^T[b'][a'] += sum_a T_s[a][b'] conj(A_s[a][a']) for all b' (tiles
+// bt = 0..3) and a' in block c.
+__device__ inline void i8_gemm2(const I8Ctx &C, const uint8_t *A, const uint8_t *Tbuf, const int *s_eTs, int s,
+                                double (&Ep)[4][2][4]) {
   uint4 Ar[4], Ai[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
@@ -767,8 +794,7 @@ __device__ inline void i8_gemm2(const SplitCtx &C, const uint8_t *A, const uint8
   i8_corrections(reinterpret_cast<const int *>(A + kI8ExpBytes) + s * 256 + col, chi, clo, c4);
   const int eac = int(reinterpret_cast<const int8_t *>(A)[s * 128 + col]);
 #pragma unroll
-  for (int u = 0; u < 2; ++u) {
-    const int bt = 2 * C.hf + u;
+  for (int bt = 0; bt < 4; ++bt) {
     const uint8_t *tg = Tbuf + size_t(bt * 8) * kI8FragBytes + C.lane * 16;
     uint4 Tr[4], Ti[4], Tn[4];
 #pragma unroll
@@ -783,29 +809,28 @@ __device__ inline void i8_gemm2(const SplitCtx &C, const uint8_t *A, const uint8
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int ex = s_eTs[16 * bt + 4 * C.g + e] + eac - 46;
-      Ep[u][0][e] += ldexp(i8_value(acc.re, e, 0u, 0u, 0u), ex);
-      Ep[u][1][e] += ldexp(i8_value(acc.im, e, chi, clo, c4), ex);
+      Ep[bt][0][e] += ldexp(i8_value(acc.re, e, 0u, 0u, 0u), ex);
+      Ep[bt][1][e] += ldexp(i8_value(acc.im, e, chi, clo, c4), ex);
     }
+    tile_fence(Ep[bt]);
   }
 }
 
-// Same five-phase schedule as overlap_split, on 32 KiB int8 buffers.
 __device__ void overlap_i8(const GramJobDev &J, int64_t ia, int64_t ib, uint8_t *buf0, uint8_t *buf1, int *s_ea,
-                           int *s_eT, double *s_mx, double *s_ov, double &ov_re, double &ov_im) {
-  const int tid = threadIdx.x, wave = tid >> 6;
-  SplitCtx C;
+                           int *s_eT, double *s_ov, double &ov_re, double &ov_im) {
+  const int tid = threadIdx.x;
+  I8Ctx C;
   C.lane = tid & 63;
   C.j = C.lane & 15;
   C.g = C.lane >> 4;
-  C.cb = wave & 3;
-  C.hf = wave >> 2;
+  C.cb = tid >> 6;
   const uint8_t *abase = reinterpret_cast<const uint8_t *>(J.a_base) + ia * J.a_stride;
   const uint8_t *bbase = reinterpret_cast<const uint8_t *>(J.b_base) + ib * J.b_stride;
   uint8_t *X = buf0, *Y = buf1;
   {
     uint4 *X16 = reinterpret_cast<uint4 *>(X);
-    for (int x = tid; x < kI8BufBytes / 16; x += kSplitThreads) X16[x] = make_uint4(0, 0, 0, 0);
-    for (int x = tid; x < kSP; x += kSplitThreads) s_ea[x] = 0;
+    for (int x = tid; x < kI8BufBytes / 16; x += kI8Threads) X16[x] = make_uint4(0, 0, 0, 0);
+    for (int x = tid; x < kSP; x += kI8Threads) s_ea[x] = 0;
     __syncthreads();
     // E_0 = [[1]]: exponent 1, code 2^30, leading digit 64
     if (tid == 0) {
@@ -818,53 +843,50 @@ __device__ void overlap_i8(const GramJobDev &J, int64_t ia, int64_t ib, uint8_t 
   for (int l = 0; l < J.m; ++l) {
     const uint8_t *A = abase + J.a_off[l];
     const uint8_t *B = bbase + J.b_off[l];
-    double Td0[2][2][4], Td1[2][2][4], Ep[2][2][4];
+    double Td[4][2][4], Ep[4][2][4];
     double tmax;
+    // I
+    i8_gemm1(C, B, X, s_ea, 0, Td, tmax);
+    {
+      const int eT0 = exp_above_i8(tmax);
+      if (C.g == 0) s_eT[col] = eT0;
+      i8_store(C, Y, Td, eT0);
+    }
+    i8_gemm1(C, B, X, s_ea, 1, Td, tmax);
+    __syncthreads();
+    // II
+    {
+      const int eT1 = exp_above_i8(tmax);
+      if (C.g == 0) s_eT[kSP + col] = eT1;
+      i8_store(C, X, Td, eT1);
+    }
 #pragma unroll
-    for (int u = 0; u < 2; ++u)
+    for (int bt = 0; bt < 4; ++bt)
 #pragma unroll
       for (int q = 0; q < 2; ++q)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) Ep[u][q][e] = 0.0;
-    i8_gemm1(C, B, X, s_ea, 0, Td0, tmax);
-    if (C.g == 0) s_mx[(0 * 2 + C.hf) * kSP + col] = tmax;
+        for (int e = 0; e < 4; ++e) Ep[bt][q][e] = 0.0;
+    i8_gemm2(C, A, Y, s_eT, 0, Ep);
     __syncthreads();
-    {
-      const int eT0 = exp_above_i8(fmax(s_mx[(0 * 2 + 0) * kSP + col], s_mx[(0 * 2 + 1) * kSP + col]));
-      if (C.hf == 0 && C.g == 0) s_eT[0 * kSP + col] = eT0;
-      i8_store(C, Y, Td0, eT0);
-      i8_gemm1(C, B, X, s_ea, 1, Td1, tmax);
-      if (C.g == 0) s_mx[(1 * 2 + C.hf) * kSP + col] = tmax;
-    }
-    __syncthreads();
-    {
-      const int eT1 = exp_above_i8(fmax(s_mx[(1 * 2 + 0) * kSP + col], s_mx[(1 * 2 + 1) * kSP + col]));
-      if (C.hf == 0 && C.g == 0) s_eT[1 * kSP + col] = eT1;
-      i8_store(C, X, Td1, eT1);
-      i8_gemm2(C, A, Y, s_eT, 0, Ep);
-    }
-    __syncthreads();
+    // III
     i8_gemm2(C, A, X, s_eT + kSP, 1, Ep);
-    {
-      double rm = 0.0;
-#pragma unroll
-      for (int u = 0; u < 2; ++u)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) rm = fmax(rm, fmax(fabs(Ep[u][0][e]), fabs(Ep[u][1][e])));
-      rm = fmax(rm, __shfl_xor(rm, 16, 64));
-      rm = fmax(rm, __shfl_xor(rm, 32, 64));
-      if (C.g == 0) s_mx[(0 * 2 + C.hf) * kSP + col] = rm;
-    }
-    __syncthreads();
     if (l + 1 == J.m) {
-      if (wave == 0 && C.lane == 0) {
+      // E_m[0][0] = E'^T[0][0]: wave 0, lane 0, tile 0, e = 0
+      if (tid == 0) {
         s_ov[0] = Ep[0][0][0];
         s_ov[1] = Ep[0][1][0];
       }
     } else {
-      const int er = exp_above_i8(fmax(s_mx[(0 * 2 + 0) * kSP + col], s_mx[(0 * 2 + 1) * kSP + col]));
+      double rm = 0.0;
+#pragma unroll
+      for (int bt = 0; bt < 4; ++bt)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) rm = fmax(rm, fmax(fabs(Ep[bt][0][e]), fabs(Ep[bt][1][e])));
+      rm = fmax(rm, __shfl_xor(rm, 16, 64));
+      rm = fmax(rm, __shfl_xor(rm, 32, 64));
+      const int er = exp_above_i8(rm);
       i8_store(C, Y, Ep, er);
-      if (C.hf == 0 && C.g == 0) s_ea[col] = er;
+      if (C.g == 0) s_ea[col] = er;
     }
     __syncthreads();
     uint8_t *t = X;
@@ -878,11 +900,11 @@ __device__ void overlap_i8(const GramJobDev &J, int64_t ia, int64_t ib, uint8_t 
 
 template <int PREC>
 constexpr int threads_of() {
-  return (PREC == QK_SPLIT_BF16 || PREC == QK_SPLIT_I8) ? kSplitThreads : kThreads;
+  return PREC == QK_SPLIT_BF16 ? kSplitThreads : PREC == QK_SPLIT_I8 ? kI8Threads : kThreads;
 }
 
 template <int PREC, int MAXP>
-__global__ __launch_bounds__(threads_of<PREC>()) void gram_kernel(const GramJobDev *__restrict__ jobs,
+__global__ __launch_bounds__(threads_of<PREC>(), 2) void gram_kernel(const GramJobDev *__restrict__ jobs,
                                                         const GramTile *__restrict__ tiles,
                                                         int64_t total, unsigned long long *counter) {
   extern __shared__ __align__(16) uint8_t smem[];
@@ -920,7 +942,7 @@ __global__ __launch_bounds__(threads_of<PREC>()) void gram_kernel(const GramJobD
     } else {
       static_assert(MAXP == kSP, "the split-int8 form uses 64 x 64 site blocks");
       double re, im;
-      overlap_i8(J, J.a0 + i, J.b0 + j, smem, smem + kI8BufBytes, s_ea, s_eT, s_mx, s_ov, re, im);
+      overlap_i8(J, J.a0 + i, J.b0 + j, smem, smem + kI8BufBytes, s_ea, s_eT, s_ov, re, im);
       k = re * re + im * im;
     }
     if (threadIdx.x == 0) write_k(J, i, j, k);
