@@ -654,32 +654,39 @@ __device__ inline uint4 i8_frag(const uint8_t *site, int s, int k, int q, int ct
                                           size_t(((s * 4 + k) * 2 + q) * 4 + ct) * kI8FragBytes + lane * 16);
 }
 
-// Digit-pair products of one complex 16 x 16 x 64 block, grouped by weight.
-// re += Xr Yr + Xs Ys' and im += Xr Yi + Xi Yr style sums are chosen by the
-// caller through the operand roles (P, Q, R, S): c_re += P Y0 + Q Y1,
-// c_im += R Y1 + S Y0.
+// Class accumulators of one complex 16 x 16 tile: class c holds the digit
+// products of weight 2^(-8 c) (c = 0..3) and class 4 the (2, 2) product.
 struct I8Acc {
   i32x4 re[5], im[5];
 };
 
-__device__ inline void i8_block(const uint4 (&P)[4], const uint4 (&Q)[4], const uint4 (&R)[4], const uint4 (&S)[4],
-                                const uint4 (&Y0)[4], const uint4 (&Y1)[4], I8Acc &acc) {
+// Same products with the LDS operand read one digit at a time (tile base tg:
+// fragments (digit a, plane 0 / 1) at (2 a + q) KiB).  CPL1: complement plane 1
+// in the real part (GEMM1: re += X0 Y0 + (~X1) Y1, im += X0 Y1 + X1 Y0);
+// otherwise complement plane 0 in the imaginary part (GEMM2: re += X0 Y0 +
+// X1 Y1, im += (~X0) Y1 + X1 Y0).  Only one digit's operands are live.
+template <bool CPL1>
+__device__ inline void i8_block_lds(const uint8_t *tg, const uint4 (&Y0)[4], const uint4 (&Y1)[4], I8Acc &acc) {
 #pragma unroll
   for (int c = 0; c < 5; ++c) {
     acc.re[c] = i32x4{0, 0, 0, 0};
     acc.im[c] = i32x4{0, 0, 0, 0};
   }
-  // (a, b, class): consecutive pairs mostly feed different accumulators
-  constexpr int pa[11] = {0, 0, 0, 0, 2, 1, 1, 1, 2, 2, 3};
-  constexpr int pb[11] = {0, 1, 2, 3, 2, 0, 1, 2, 0, 1, 0};
-  constexpr int pc[11] = {0, 1, 2, 3, 4, 1, 2, 3, 2, 3, 3};
 #pragma unroll
-  for (int t = 0; t < 11; ++t) {
-    const int a = pa[t], b = pb[t], c = pc[t];
-    acc.re[c] = mma_i8(P[a], Y0[b], acc.re[c]);
-    acc.im[c] = mma_i8(R[a], Y1[b], acc.im[c]);
-    acc.re[c] = mma_i8(Q[a], Y1[b], acc.re[c]);
-    acc.im[c] = mma_i8(S[a], Y0[b], acc.im[c]);
+  for (int a = 0; a < 4; ++a) {
+    const uint4 x0 = *reinterpret_cast<const uint4 *>(tg + (a * 2 + 0) * kI8FragBytes);
+    const uint4 x1 = *reinterpret_cast<const uint4 *>(tg + (a * 2 + 1) * kI8FragBytes);
+    const uint4 P = x0, Q = CPL1 ? not4(x1) : x1, R = CPL1 ? x0 : not4(x0), S = x1;
+    // digit pairs (a, b) with a + b <= 3, plus (2, 2) in class 4
+    const int nb = a == 0 ? 4 : a == 1 ? 3 : a == 2 ? 3 : 1;
+#pragma unroll
+    for (int b = 0; b < nb; ++b) {
+      const int c = (a == 2 && b == 2) ? 4 : a + b;
+      acc.re[c] = mma_i8(P, Y0[b], acc.re[c]);
+      acc.im[c] = mma_i8(R, Y1[b], acc.im[c]);
+      acc.re[c] = mma_i8(Q, Y1[b], acc.re[c]);
+      acc.im[c] = mma_i8(S, Y0[b], acc.im[c]);
+    }
   }
 }
 
@@ -695,8 +702,8 @@ __device__ inline double i8_value(const i32x4 (&a)[5], int e, uint32_t chi, uint
 // Class corrections from the column digit sums cs0..cs3 of the operand that
 // was multiplied by a complemented one: class c gets the sum over its pairs
 // (a, b) of cs_b, packed like the accumulator words of i8_value.
-__device__ inline void i8_corrections(const int *cs, uint32_t &chi, uint32_t &clo, uint32_t &c4) {
-  const int c0 = cs[0], c1 = cs[64], c2 = cs[128], c3 = cs[192];
+__device__ inline void i8_corrections(const int (&cs)[4], uint32_t &chi, uint32_t &clo, uint32_t &c4) {
+  const int c0 = cs[0], c1 = cs[1], c2 = cs[2], c3 = cs[3];
   const int k0 = c0, k1 = c0 + c1, k2 = c0 + c1 + c2, k3 = k2 + c3;
   chi = (uint32_t(k0) << 8) + uint32_t(k1);
   clo = (uint32_t(k2) << 8) + uint32_t(k3);
@@ -717,34 +724,51 @@ struct I8Ctx {
   int lane, j, g, cb;
 };
 
-// GEMM1: T_s[a][b'] for all rows a (tiles rt = 0..3) and b' in block c;
-// tmax = max |T| over the whole column b' = 16 c + j.
-__device__ inline void i8_gemm1(const I8Ctx &C, const uint8_t *B, const uint8_t *Ebuf, const int *s_ea, int s,
-                                double (&Td)[4][2][4], double &tmax) {
-  uint4 Br[4], Bi[4];
+// This lane's digit fragments of column block c of one physical index of a
+// packed site block (real plane, then imaginary plane), loaded one GEMM
+// ahead of their use so that global latency overlaps the current GEMM; the
+// column exponent and digit sums are read at the start of the GEMM itself
+// (first needed after its first tile of MFMAs).
+struct I8Operand {
+  uint4 f[8];
+  const uint8_t *site;
+  int s;
+};
+
+__device__ inline void i8_load(const I8Ctx &C, const uint8_t *site, int s, I8Operand &o) {
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    Br[k] = i8_frag(B, s, k, 0, C.cb, C.lane);
-    Bi[k] = i8_frag(B, s, k, 1, C.cb, C.lane);
+    o.f[k] = i8_frag(site, s, k, 0, C.cb, C.lane);
+    o.f[4 + k] = i8_frag(site, s, k, 1, C.cb, C.lane);
   }
+  o.site = site;
+  o.s = s;
+}
+
+__device__ inline void i8_column_meta(const I8Ctx &C, const I8Operand &o, int &e, int (&cs)[4]) {
   const int col = 16 * C.cb + C.j;
+  e = int(reinterpret_cast<const int8_t *>(o.site)[o.s * 128 + col]);
+  const int *p = reinterpret_cast<const int *>(o.site + kI8ExpBytes) + o.s * 256 + col;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) cs[k] = p[64 * k];
+}
+
+// GEMM1: T_s[a][b'] for all rows a (tiles rt = 0..3) and b' in block c;
+// tmax = max |T| over the whole column b' = 16 c + j.
+__device__ inline void i8_gemm1(const I8Ctx &C, const I8Operand &Bs, const uint8_t *Ebuf, const int *s_ea,
+                                double (&Td)[4][2][4], double &tmax) {
+  const uint4(&Br)[4] = *reinterpret_cast<const uint4(*)[4]>(&Bs.f[0]);
+  const uint4(&Bi)[4] = *reinterpret_cast<const uint4(*)[4]>(&Bs.f[4]);
+  int ebc, cs[4];
+  i8_column_meta(C, Bs, ebc, cs);
   uint32_t chi, clo, c4;
-  i8_corrections(reinterpret_cast<const int *>(B + kI8ExpBytes) + s * 256 + col, chi, clo, c4);
-  const int ebc = int(reinterpret_cast<const int8_t *>(B)[s * 128 + col]);
+  i8_corrections(cs, chi, clo, c4);
   tmax = 0.0;
 #pragma unroll
   for (int rt = 0; rt < 4; ++rt) {
-    const uint8_t *eg = Ebuf + size_t(rt * 8) * kI8FragBytes + C.lane * 16;
-    uint4 Er[4], Ei[4], En[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      Er[k] = *reinterpret_cast<const uint4 *>(eg + (k * 2 + 0) * kI8FragBytes);
-      Ei[k] = *reinterpret_cast<const uint4 *>(eg + (k * 2 + 1) * kI8FragBytes);
-      En[k] = not4(Ei[k]);
-    }
     // re = Er Br - Ei Bi = Er Br + (~Ei) Bi + colsum(Bi) ; im = Er Bi + Ei Br
     I8Acc acc;
-    i8_block(Er, En, Er, Ei, Br, Bi, acc);
+    i8_block_lds<true>(Ebuf + size_t(rt * 8) * kI8FragBytes + C.lane * 16, Br, Bi, acc);
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int ex = s_ea[16 * rt + 4 * C.g + e] + ebc - 46;
@@ -781,31 +805,19 @@ __device__ inline void i8_store(const I8Ctx &C, uint8_t *buf, const double (&V)[
 
 // GEMM2: E'^T[b'][a'] += sum_a T_s[a][b'] conj(A_s[a][a']) for all b' (tiles
 // bt = 0..3) and a' in block c.
-__device__ inline void i8_gemm2(const I8Ctx &C, const uint8_t *A, const uint8_t *Tbuf, const int *s_eTs, int s,
+__device__ inline void i8_gemm2(const I8Ctx &C, const I8Operand &As, const uint8_t *Tbuf, const int *s_eTs,
                                 double (&Ep)[4][2][4]) {
-  uint4 Ar[4], Ai[4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    Ar[k] = i8_frag(A, s, k, 0, C.cb, C.lane);
-    Ai[k] = i8_frag(A, s, k, 1, C.cb, C.lane);
-  }
-  const int col = 16 * C.cb + C.j;
+  const uint4(&Ar)[4] = *reinterpret_cast<const uint4(*)[4]>(&As.f[0]);
+  const uint4(&Ai)[4] = *reinterpret_cast<const uint4(*)[4]>(&As.f[4]);
+  int eac, cs[4];
+  i8_column_meta(C, As, eac, cs);
   uint32_t chi, clo, c4;
-  i8_corrections(reinterpret_cast<const int *>(A + kI8ExpBytes) + s * 256 + col, chi, clo, c4);
-  const int eac = int(reinterpret_cast<const int8_t *>(A)[s * 128 + col]);
+  i8_corrections(cs, chi, clo, c4);
 #pragma unroll
   for (int bt = 0; bt < 4; ++bt) {
-    const uint8_t *tg = Tbuf + size_t(bt * 8) * kI8FragBytes + C.lane * 16;
-    uint4 Tr[4], Ti[4], Tn[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      Tr[k] = *reinterpret_cast<const uint4 *>(tg + (k * 2 + 0) * kI8FragBytes);
-      Ti[k] = *reinterpret_cast<const uint4 *>(tg + (k * 2 + 1) * kI8FragBytes);
-      Tn[k] = not4(Tr[k]);
-    }
     // re = Tr Ar + Ti Ai ; im = Ti Ar - Tr Ai = Ti Ar + (~Tr) Ai + colsum(Ai)
     I8Acc acc;
-    i8_block(Tr, Ti, Tn, Ti, Ar, Ai, acc);
+    i8_block_lds<false>(Tbuf + size_t(bt * 8) * kI8FragBytes + C.lane * 16, Ar, Ai, acc);
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int ex = s_eTs[16 * bt + 4 * C.g + e] + eac - 46;
@@ -840,21 +852,26 @@ __device__ void overlap_i8(const GramJobDev &J, int64_t ia, int64_t ib, uint8_t 
     __syncthreads();
   }
   const int col = 16 * C.cb + C.j;
+  I8Operand P0, P1;   // operands of the current and the next GEMM
+  i8_load(C, bbase + J.b_off[0], 0, P0);
   for (int l = 0; l < J.m; ++l) {
     const uint8_t *A = abase + J.a_off[l];
     const uint8_t *B = bbase + J.b_off[l];
     double Td[4][2][4], Ep[4][2][4];
     double tmax;
     // I
-    i8_gemm1(C, B, X, s_ea, 0, Td, tmax);
+    i8_load(C, B, 1, P1);
+    i8_gemm1(C, P0, X, s_ea, Td, tmax);
     {
       const int eT0 = exp_above_i8(tmax);
       if (C.g == 0) s_eT[col] = eT0;
       i8_store(C, Y, Td, eT0);
     }
-    i8_gemm1(C, B, X, s_ea, 1, Td, tmax);
+    i8_load(C, A, 0, P0);
+    i8_gemm1(C, P1, X, s_ea, Td, tmax);
     __syncthreads();
     // II
+    i8_load(C, A, 1, P1);
     {
       const int eT1 = exp_above_i8(tmax);
       if (C.g == 0) s_eT[kSP + col] = eT1;
@@ -866,10 +883,11 @@ __device__ void overlap_i8(const GramJobDev &J, int64_t ia, int64_t ib, uint8_t 
       for (int q = 0; q < 2; ++q)
 #pragma unroll
         for (int e = 0; e < 4; ++e) Ep[bt][q][e] = 0.0;
-    i8_gemm2(C, A, Y, s_eT, 0, Ep);
+    i8_gemm2(C, P0, Y, s_eT, Ep);
     __syncthreads();
     // III
-    i8_gemm2(C, A, X, s_eT + kSP, 1, Ep);
+    if (l + 1 < J.m) i8_load(C, bbase + J.b_off[l + 1], 0, P0);
+    i8_gemm2(C, P1, X, s_eT + kSP, Ep);
     if (l + 1 == J.m) {
       // E_m[0][0] = E'^T[0][0]: wave 0, lane 0, tile 0, e = 0
       if (tid == 0) {
