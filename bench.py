@@ -63,21 +63,67 @@ def flops_per_entry(dims_a, dims_b):
     return 8 * f
 
 
+def kernel_source_digest():
+    """SHA-256 of the Gram kernel sources with comments and whitespace removed:
+    it changes when the compiled kernels can change, not when comments do."""
+    import hashlib
+    import re
+    h = hashlib.sha256()
+    for name in ("gram.hip", "qk_internal.h"):
+        text = open(os.path.join(ROOT, "paper_2411_09336_amd", "csrc", name)).read()
+        text = re.sub(r"//[^\n]*", "", text)
+        h.update(re.sub(r"\s+", "", text).encode())
+    return h.hexdigest()
+
+
+def counter_record_path(form):
+    return os.path.join(ROOT, "profiles", f"gram_{form}_counters.json")
+
+
 def counter_traffic(form):
     """HBM bytes per timed Gram launch from the committed hardware-counter
-    record of that form, or None when absent or taken on a different kernel
-    source."""
-    import hashlib
-    src = os.path.join(ROOT, "paper_2411_09336_amd", "csrc", "gram.hip")
-    rec = os.path.join(ROOT, "profiles", f"gram_{form}_counters.json")
+    record of that form, or None when absent or taken on other kernel
+    sources."""
     try:
-        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
-        data = json.load(open(rec))
+        data = json.load(open(counter_record_path(form)))
     except (OSError, ValueError):
         return None, None
-    if data.get("gram_hip_sha256") != digest:
+    if data.get("kernel_source_sha256") != kernel_source_digest():
         return None, data
     return data.get("traffic_bytes_per_launch"), data
+
+
+def write_counter_record(form, fetch_csv, write_csv, fetch_scale, write_scale, command):
+    """Record of the FETCH_SIZE / WRITE_SIZE runs of one timed launch (the
+    first dispatch of the form's kernel after the warmup-free partial run),
+    scaled to bytes by the copy-kernel factors."""
+    import csv
+    kname = {"split_i8": "gram_kernel<3, 64>", "split_bf16": "gram_kernel<2, 64>"}[form]
+
+    def first(path, counter):
+        rows = [r for r in csv.DictReader(open(path))
+                if kname in r["Kernel_Name"] and r["Counter_Name"] == counter]
+        by_dispatch = {}
+        for r in rows:
+            by_dispatch.setdefault(int(r["Dispatch_Id"]), 0.0)
+            by_dispatch[int(r["Dispatch_Id"])] += float(r["Counter_Value"])
+        d = min(by_dispatch)
+        return by_dispatch[d]
+
+    fetch_kib = first(fetch_csv, "FETCH_SIZE")
+    write_kib = first(write_csv, "WRITE_SIZE")
+    fetch_b = fetch_kib * fetch_scale
+    write_b = write_kib * write_scale
+    rec = {"form": form, "kernel": kname, "kernel_source_sha256": kernel_source_digest(),
+           "fetch_size_kib": fetch_kib, "write_size_kib": write_kib,
+           "fetch_bytes_per_counted_kib": fetch_scale, "write_bytes_per_counted_kib": write_scale,
+           "traffic_bytes_per_launch": fetch_b + write_b,
+           "note": "HBM bytes of one timed slab launch (rows 0..r1 of 8 equal-work slabs of the 6400 x 6400 "
+                   "Gram): FETCH_SIZE and WRITE_SIZE in separate runs, scaled by a plain copy kernel",
+           "command": command}
+    with open(counter_record_path(form), "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec))
 
 
 def slab_bounds(n, parts):
@@ -149,6 +195,11 @@ def main():
                     help="only time the symmetric Gram of N random saturated 165-site chi=64 MPS in every "
                          "form (kernel microbenchmark, no simulation), then exit")
     ap.add_argument("--form", choices=sorted(FORMS), default="split_i8", help="form of the timed Gram")
+    ap.add_argument("--counter-record", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="only write profiles/gram_<form>_counters.json from rocprofv3 counter CSVs of "
+                         "'--slabs-run 1' runs (no GPU use), then exit")
+    ap.add_argument("--counter-scale", nargs=2, type=float, default=(2047.93, 1024.0),
+                    metavar=("FETCH", "WRITE"), help="bytes per counted KiB (plain copy kernel)")
     ap.add_argument("--routing", type=int, default=1,
                     help="0: 2(k-1) SWAPs per Rxx (paper); 1: cancelled inverse SWAP pairs (same circuit)")
     args = ap.parse_args()
@@ -158,6 +209,12 @@ def main():
               "a design in DESIGN.md, not a measured path.", file=sys.stderr)
         sys.exit(2)
 
+    if args.counter_record:
+        write_counter_record(args.form, args.counter_record[0], args.counter_record[1], args.counter_scale[0],
+                             args.counter_scale[1],
+                             f"rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) --output-format csv -- python3 "
+                             f"bench.py --form {args.form} --slabs-run 1 --no-cpu --sim-sample 16 --warmup 0")
+        return
     if args.calibrate_copy > 0:
         calibrate_copy(args.calibrate_copy)
         return
@@ -241,7 +298,10 @@ def run(args):
 
     # ---------------------------------------------------------------- 1. simulation
     log(f"[bench] simulating {S} circuits: m={w.n_qubits} d={w.distance} reps={w.reps} chi={w.chi} cutoff={w.cutoff}")
-    xs = torch.tensor(X[:S], dtype=torch.float64, device="cuda")
+    # D near-duplicates of the first D points ride along in the same batch
+    # (same launches): pairs (x, x') have mid-range K for the precision check
+    D = min(16, S)
+    xs = torch.tensor(np.vstack([X[:S], sd.perturb_near_duplicates(X[:D])]), dtype=torch.float64, device="cuda")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     t_last = [time.perf_counter()]
@@ -257,7 +317,8 @@ def run(args):
     t_sim = time.perf_counter() - t0
     info = sim.info()
     dims = sim.bond_dims()
-    log(f"[bench] simulation {t_sim:.1f} s ({S / t_sim:.2f} circuits/s); max bond {info['max_bond']}, "
+    n_sim = S + D
+    log(f"[bench] simulation {t_sim:.1f} s ({n_sim / t_sim:.2f} circuits/s); max bond {info['max_bond']}, "
         f"unconverged SVDs {info['unconverged_svds']}, degenerate cuts {info['degenerate_cuts']}")
 
     # ---------------------------------------------------------------- 2. Gram batch
@@ -368,6 +429,43 @@ def run(args):
             "fp64_form_tflops": round(fpe * s_pairs / t_d_small / 1e12, 3),
             "fp64_form_frac": round(fpe * s_pairs / t_d_small / 1e12 / PEAK_TFLOPS["fp64"], 4)}
 
+    # ---------------------------------------------------------------- 4b. stress sets and inference
+    # (i) near-duplicate block: rows = D points, columns = their near-duplicates
+    Knd = {}
+    for f in ("fp64",) + tuple(FORMS):
+        out = torch.zeros((D, D), dtype=torch.float64, device="cuda")
+        q.gram_block(sim, 0, D, sim, S, D, precision=f, out=out, stream=stream)
+        Knd[f] = out
+    stream.synchronize()
+    nd_diag = Knd["fp64"].diagonal()
+    log(f"[bench] near-duplicate block: K(x, x') in [{nd_diag.min().item():.3f}, {nd_diag.max().item():.3f}]; "
+        + ", ".join(f"{f} max|dK| {(Knd[f] - Knd['fp64']).abs().max().item():.2e}" for f in FORMS))
+    # (ii) the paper's own 165-qubit bandwidth (gamma = 0.1, d = 1): K = O(0.1 .. 1)
+    wp = sd.WORKLOADS["paper_d1"]
+    P = min(64, S)
+    specp = q.CircuitSpec(wp.n_qubits, wp.distance, wp.reps, wp.coef_z, wp.coef_xx, args.routing)
+    xp = torch.tensor(sd.workload_features(wp, P), dtype=torch.float64, device="cuda")
+    simp = q.simulate(xp, specp, wp.chi, wp.cutoff)
+    Kp = {}
+    for f in ("fp64",) + tuple(FORMS):
+        Kp[f] = q.gram(simp, precision=f)
+    stream.synchronize()
+    offp = Kp["fp64"].cpu().numpy()[~np.eye(P, dtype=bool)]
+    log(f"[bench] paper bandwidth (gamma 0.1, d 1): max bond {simp.info()['max_bond']}, off-diagonal K median "
+        f"{np.median(offp):.3f}; " + ", ".join(f"{f} max|dK| {(Kp[f] - Kp['fp64']).abs().max().item():.2e}"
+                                               for f in FORMS))
+    # (iii) inference: one new point's kernel row against the N-point training batch
+    q.gram_block(gb, 0, 1, gb, 0, N, precision=form, stream=stream)
+    stream.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    q.gram_block(gb, 0, 1, gb, 0, N, precision=form, stream=stream)
+    e1.record(stream)
+    e1.synchronize()
+    t_row = e0.elapsed_time(e1) / 1e3
+    log(f"[bench] inference row (1 x {N}, {form}): {t_row * 1e3:.2f} ms")
+
     # ---------------------------------------------------------------- 5. CPU oracle
     cpu = None
     dk_oracle = None
@@ -377,6 +475,16 @@ def run(args):
         mps_np = [sim.export(i) for i in range(n_exp)]
         try:
             cpu, dk_oracle = cpu_oracle_leg(mps_np, Ks.cpu().numpy(), Kd.cpu().numpy(), args.cpu_seconds)
+            # the oracle on the two stress sets (all pairs; the paper-bandwidth states have small bonds)
+            from oracle import gram as ogram
+            nd_o = np.array([[abs(ogram.overlap(sim.export(i), sim.export(S + j))) ** 2 for j in range(D)]
+                             for i in range(D)])
+            mp = [simp.export(i) for i in range(P)]
+            kp_o = ogram.gram(mp)
+            for f in ("fp64",) + tuple(FORMS):
+                dk_oracle[f"near_duplicates_{f}_max"] = float(np.abs(Knd[f].cpu().numpy() - nd_o).max())
+                dk_oracle[f"paper_bandwidth_{f}_max"] = float(np.abs(Kp[f].cpu().numpy() - kp_o).max())
+            log(f"[bench] oracle on stress sets: {dk_oracle}")
             log(f"[bench] oracle: {cpu['value']:.2f} entries/s on {cpu['cores']} cores; {dk_oracle}")
         except Exception as e:   # the baseline must not cost the measurement
             log(f"[bench] CPU oracle leg failed: {e!r}")
@@ -412,11 +520,21 @@ def run(args):
         "dK": {"vs_fp64_max_all_entries": full_dK_max, "vs_fp64_max": float(dK.max().item()),
                "vs_fp64_mean": float(dK.mean().item()), "full_matrix_bit_identical_to_SxS": bit_identical,
                "oracle": dk_oracle},
+        "stress": {
+            "near_duplicates": {"points": D, "K_range": [float(nd_diag.min().item()), float(nd_diag.max().item())],
+                                **{f"{f}_vs_fp64_max": float((Knd[f] - Knd["fp64"]).abs().max().item())
+                                   for f in FORMS}},
+            "paper_bandwidth": {"workload": "165 qubits, d=1, reps=2, coef_z=0.2, coef_xx=0.01*pi (gamma 0.1), chi 64",
+                                "points": P, "max_bond": simp.info()["max_bond"],
+                                "offdiag_K_median": float(np.median(offp)), "offdiag_K_min": float(offp.min()),
+                                **{f"{f}_vs_fp64_max": float((Kp[f] - Kp["fp64"]).abs().max().item())
+                                   for f in FORMS}}},
+        "inference": {"row_entries": N, "ms": round(t_row * 1e3, 3), "entries_per_s": round(N / t_row, 1)},
         "K_distribution": {"offdiag_median": float(np.median(offd)), "offdiag_max": float(offd.max()),
                            "offdiag_frac_above_1e-6": float((offd > 1e-6).mean())},
-        "simulation": {"circuits": S, "seconds": round(t_sim, 2), "circuits_per_s": round(S / t_sim, 3),
+        "simulation": {"circuits": n_sim, "seconds": round(t_sim, 2), "circuits_per_s": round(n_sim / t_sim, 3),
                        "two_qubit_gates_per_circuit": info["n_two_qubit_gates"],
-                       "two_qubit_gates_per_s": round(S * info["n_two_qubit_gates"] / t_sim, 1),
+                       "two_qubit_gates_per_s": round(n_sim * info["n_two_qubit_gates"] / t_sim, 1),
                        "max_bond": info["max_bond"], "unconverged_svds": info["unconverged_svds"],
                        "degenerate_cuts": info["degenerate_cuts"],
                        "mean_total_discarded": info["mean_total_discarded"]},

@@ -6,20 +6,23 @@
 // and K[i][j] = |E_m|^2 (Eq. (1)).  Each site update is two complex GEMMs:
 //     GEMM1  T_s  = E A_b[s]              (contract the ket's left bond)
 //     GEMM2  E'^T = sum_s T_s^T conj(A_a[s])   (contract the bra's left bond)
-// One workgroup of four waves owns a pair at a time; E lives in LDS and wave
-// w computes E' for the 16-column block w of the ket's right bond.  Site
-// tensors stream from HBM (re-used across concurrently running pairs through
-// L2); the T accumulators of GEMM1 feed GEMM2 directly as MFMA A-operands:
-// the accumulator rows become the contraction index, and the bra operand is
-// laid out with the matching row order.
+// E (and T) live in LDS; MFMA accumulator rows of one GEMM are laid out so
+// that they feed the next GEMM as A-operand rows, and the site tensors stream
+// from HBM / L2 in MFMA fragment order.
 //
-// After every site E' is rescaled by a power of two (exact) so that FP32 and
-// BF16 operands never underflow; the exponents are summed in an integer and
-// K = |E_m|^2 * 2^(2 * sum e) is formed in FP64.
+// Four arithmetic forms:
+//  * FP64 and FP32: plain operands, v_mfma_f64_16x16x4 / v_mfma_f32_16x16x4,
+//    E rescaled by a power of two after every site (exact) against underflow;
+//    four waves per pair, wave w computes E' for the ket column block w.
+//  * split-BF16 and split-int8: 31-bit fixed-point codes with one exponent
+//    per row (E, T^T) or column (site tensors), cut into four 8-bit digits;
+//    the digit products are carried by bf16 MFMAs (exact leading-digit
+//    accumulator, FP64 combination) or by int8 MFMAs (all products exact in
+//    int32).  These forms reach FP64-level accuracy (|dK| ~ 1e-8) on
+//    low-precision matrix cores.
 //
-// Pairs are taken from a device work queue (one atomic per pair) over a list
-// of 16 x 16 pair tiles that may span several jobs (batches with different
-// qubit counts and pads).
+// Pairs are taken from device work queues over 16 x 16 pair tiles that may
+// span several jobs (batches with different qubit counts and pads).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
