@@ -183,7 +183,9 @@ def main():
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=6400, help="Gram size (points)")
-    ap.add_argument("--sim-sample", type=int, default=64, help="distinct circuits simulated on the GPU")
+    ap.add_argument("--sim-sample", type=int, default=240,
+                    help="distinct circuits simulated on the GPU, plus 16 near-duplicates (one workgroup per "
+                         "circuit: up to one per CU, 256, costs the same time)")
     ap.add_argument("--slabs", type=int, default=8)
     ap.add_argument("--slabs-run", type=int, default=0,
                     help="run only the first K slabs of the timed Gram (hardware-counter passes); 0 = all")

@@ -133,3 +133,26 @@ def test_tiny_gpu_gram_matches_golden():
         K = q.gram(b, precision=prec).cpu().numpy()
         print(prec, "max|dK| vs golden", np.abs(K - K_gold).max())
         assert np.abs(K - K_gold).max() < tol
+
+
+def test_paper_bandwidth_165_qubits_vs_oracle():
+    """The paper's own 165-qubit setting (gamma = 0.1, d = 1): GPU simulation
+    vs the oracle's (fidelity, bond dimensions) and every Gram form vs the
+    oracle Gram of the oracle's states; off-diagonal K is O(0.1 .. 1) here, so
+    the precision forms are tested on mid-range values."""
+    import paper_2411_09336_amd as q
+    w = sd.WORKLOADS["paper_d1"]
+    X = sd.workload_features(w, 12)
+    b = _sim(X, w, routing=1)
+    dims = b.bond_dims()
+    ref = [omps.simulate(x, w.distance, w.reps, w.chi, w.cutoff, w.coef_z, w.coef_xx, routing=1) for x in X]
+    for i, r in enumerate(ref):
+        assert fidelity(b.export(i), r.tensors) > 1 - 1e-12
+        assert list(dims[i]) == r.bond_dims
+    Ko = ogram.gram([r.tensors for r in ref])
+    off = Ko[~np.eye(len(X), dtype=bool)]
+    assert off.min() > 0.1
+    for prec, tol in (("fp64", 1e-12), ("split_i8", 1e-7), ("split_bf16", 1e-7), ("fp32", 2e-5)):
+        K = q.gram(b, precision=prec).cpu().numpy()
+        print(prec, "max|dK| vs oracle", np.abs(K - Ko).max(), "K offdiag range", off.min(), off.max())
+        assert np.abs(K - Ko).max() < tol
