@@ -617,8 +617,17 @@ __device__ void overlap_split(const GramJobDev &J, int64_t ia, int64_t ib, uint8
 // 1.5 * 2^52 (the low word of the sum is X).  The margin of exp_above_i8
 // keeps |X| <= 2^31 * 128/129, so the leading digit lies in [-127, 127].
 // Digit word (X + 0x808080) ^ 0x808080 holds the digits d3, d2, d1, d0 as
-// two's-complement bytes 0..3 (X = d0 2^24 + d1 2^16 + d2 2^8 + d3).
+// two's-complement bytes 0..3 (X = d0 2^24 + d1 2^16 + d2 2^8 + d3); the
+// addition is folded into the FMA constant and the XOR applied once per
+// four-value slice word.
 typedef int i32x4 __attribute__((ext_vector_type(4)));
+
+// The sign-definite (2, 2) digit pair costs 9 % of the MFMAs; without it the
+// kernel is 9 % faster but max |dK| on 165-site chi = 64 states grows from
+// 2.7e-9 to 4.0e-7 (a one-signed bias on self-overlaps), so it is kept.
+#ifndef QK_I8_PAIR22
+#define QK_I8_PAIR22 1
+#endif
 
 __device__ inline i32x4 mma_i8(const uint4 &a, const uint4 &b, const i32x4 &c) {
   return __builtin_amdgcn_mfma_i32_16x16x64_i8(*reinterpret_cast<const i32x4 *>(&a),
@@ -630,22 +639,24 @@ __device__ inline int exp_above_i8(double mx) {
   return mx > 0.0 ? ilogb(mx * (1.0 + 0x1p-7)) + 1 : 0;
 }
 
-__device__ inline uint32_t digit_word(double x, double scale) {
-  const double w = fma(x, scale, 0x1.8p52);
-  const uint32_t X = uint32_t(__double_as_longlong(w));
-  return (X + 0x808080u) ^ 0x808080u;
+// Digit word with the bias of the three low digits still applied (bytes
+// 0..2 hold d + 128); transpose_digits removes it.
+__device__ inline uint32_t biased_digit_word(double x, double scale) {
+  const double w = fma(x, scale, 0x1.8p52 + 0x808080);   // low word: X + 0x808080
+  return uint32_t(__double_as_longlong(w));
 }
 
-// Byte transpose of four digit words (values e = 0..3) into four slice words:
-// byte e of slice k is digit k of value e (slice 0 = leading digit).
+// Byte transpose of four biased digit words (values e = 0..3) into four
+// slice words: byte e of slice k is digit k of value e (slice 0 = leading
+// digit); the bias of digits 1..3 is removed by one XOR per slice word.
 __device__ inline void transpose_digits(uint32_t d0, uint32_t d1, uint32_t d2, uint32_t d3, uint32_t (&s)[4]) {
   const uint32_t lo01 = __builtin_amdgcn_perm(d1, d0, 0x05010400u);
   const uint32_t hi01 = __builtin_amdgcn_perm(d1, d0, 0x07030602u);
   const uint32_t lo23 = __builtin_amdgcn_perm(d3, d2, 0x05010400u);
   const uint32_t hi23 = __builtin_amdgcn_perm(d3, d2, 0x07030602u);
-  s[3] = __builtin_amdgcn_perm(lo23, lo01, 0x05040100u);
-  s[2] = __builtin_amdgcn_perm(lo23, lo01, 0x07060302u);
-  s[1] = __builtin_amdgcn_perm(hi23, hi01, 0x05040100u);
+  s[3] = __builtin_amdgcn_perm(lo23, lo01, 0x05040100u) ^ 0x80808080u;
+  s[2] = __builtin_amdgcn_perm(lo23, lo01, 0x07060302u) ^ 0x80808080u;
+  s[1] = __builtin_amdgcn_perm(hi23, hi01, 0x05040100u) ^ 0x80808080u;
   s[0] = __builtin_amdgcn_perm(hi23, hi01, 0x07060302u);
 }
 
@@ -692,7 +703,7 @@ __device__ inline void i8_block_lds(const uint8_t *tg, const uint4 (&Y0)[4], con
     const uint4 x1 = *reinterpret_cast<const uint4 *>(tg + (a * 2 + 1) * kI8FragBytes);
     const uint4 P = x0, Q = CPL1 ? not4(x1) : x1, R = CPL1 ? x0 : not4(x0), S = x1;
     // digit pairs (a, b) with a + b <= 3, plus (2, 2) in class 4
-    const int nb = a == 0 ? 4 : a == 1 ? 3 : a == 2 ? 3 : 1;
+    const int nb = a == 0 ? 4 : a == 1 ? 3 : a == 2 ? (QK_I8_PAIR22 ? 3 : 2) : 1;
 #pragma unroll
     for (int b = 0; b < nb; ++b) {
       const int c = (a == 2 && b == 2) ? 4 : a + b;
@@ -709,8 +720,13 @@ __device__ inline void i8_block_lds(const uint8_t *tg, const uint4 (&Y0)[4], con
 __device__ inline double i8_value(const i32x4 (&a)[5], int e, uint32_t chi, uint32_t clo, uint32_t c4) {
   const int hiw = int((uint32_t(a[0][e]) << 8) + uint32_t(a[1][e]) + chi);
   const int low = int((uint32_t(a[2][e]) << 8) + uint32_t(a[3][e]) + clo);
+#if QK_I8_PAIR22
   const int w4 = int(uint32_t(a[4][e]) + c4);
   return fma(fma(double(hiw), 65536.0, double(low)), 256.0, double(w4));
+#else
+  (void)c4;
+  return fma(double(hiw), 16777216.0, double(low) * 256.0);
+#endif
 }
 
 // Class corrections from the column digit sums cs0..cs3 of the operand that
@@ -809,8 +825,8 @@ __device__ inline void i8_store(const I8Ctx &C, uint8_t *buf, const double (&V)[
     uint32_t w[4][4];
 #pragma unroll
     for (int rt = 0; rt < 4; ++rt)
-      transpose_digits(digit_word(V[rt][q][0], scale), digit_word(V[rt][q][1], scale),
-                       digit_word(V[rt][q][2], scale), digit_word(V[rt][q][3], scale), w[rt]);
+      transpose_digits(biased_digit_word(V[rt][q][0], scale), biased_digit_word(V[rt][q][1], scale),
+                       biased_digit_word(V[rt][q][2], scale), biased_digit_word(V[rt][q][3], scale), w[rt]);
 #pragma unroll
     for (int k = 0; k < 4; ++k)
       *reinterpret_cast<uint4 *>(dst + (k * 2 + q) * kI8FragBytes) = make_uint4(w[0][k], w[1][k], w[2][k], w[3][k]);
@@ -1245,7 +1261,7 @@ __global__ __launch_bounds__(256) void pack_i8_kernel(const double2 *__restrict_
       for (int r = 0; r < 4; ++r) {
         const int v = 4 * vv + r;
         const int row = 16 * (2 * (v >> 3) + ((v >> 2) & 1)) + 4 * gg + (v & 3);
-        d[r] = digit_word(value(s, row, col, q), scale);
+        d[r] = biased_digit_word(value(s, row, col, q), scale);
       }
       transpose_digits(d[0], d[1], d[2], d[3], sl[vv]);
     }
@@ -1261,7 +1277,8 @@ __global__ __launch_bounds__(256) void pack_i8_kernel(const double2 *__restrict_
     const int c = t % 64, k = (t / 64) % 4, s = t / 256;
     const double scale = ldexp(1.0, 31 - s_e[s * 128 + c]);
     int sum = 0;
-    for (int r = 0; r < 64; ++r) sum += int(int8_t(digit_word(value(s, r, c, 1), scale) >> (8 * (3 - k))));
+    for (int r = 0; r < 64; ++r)
+      sum += int(int8_t((biased_digit_word(value(s, r, c, 1), scale) ^ 0x808080u) >> (8 * (3 - k))));
     cs[(s * 4 + k) * 64 + c] = sum;
   }
 }
