@@ -155,6 +155,19 @@ qk_status mps_simulate_progress(const double *features_dev, int64_t n_points,
                                 qk_progress_fn fn, void *user, int64_t every,
                                 qk_mps_batch **out);
 
+/* mps_simulate with the kernel launches recorded as HIP graphs: the launches
+ * of every `gates_per_graph` two-qubit gates (0: the whole circuit) are
+ * captured on a private stream, instantiated and launched as one graph,
+ * ordered after earlier work on hip_stream and before later work on it.  The
+ * kernels and their order are those of mps_simulate, so the batch is
+ * bit-identical.  Removes per-launch host overhead for circuits whose gates
+ * are short; returns QK_EDEVICE if capture or instantiation fails.  The call
+ * returns after the simulation has finished. */
+qk_status mps_simulate_graph(const double *features_dev, int64_t n_points,
+                             const qk_circuit_spec *spec, int32_t chi_max,
+                             double cutoff, int64_t gates_per_graph,
+                             void *hip_stream, qk_mps_batch **out);
+
 /* ---------------------------------------------------------------- Gram */
 
 /* K[i][j] = |<a_i | b_j>|^2 for i < na, j < nb, written to K_dev (row-major,

@@ -89,6 +89,7 @@ def _load():
         "qk_circuit_compile": (S, [C.POINTER(_Spec), P, I64, C.POINTER(I64)]),
         "mps_simulate": (S, [P, I64, C.POINTER(_Spec), I32, D, P, C.POINTER(P)]),
         "mps_simulate_progress": (S, [P, I64, C.POINTER(_Spec), I32, D, P, _PROGRESS, P, I64, C.POINTER(P)]),
+        "mps_simulate_graph": (S, [P, I64, C.POINTER(_Spec), I32, D, I64, P, C.POINTER(P)]),
         "mps_gram": (S, [P, P, C.c_int, P, I64, P]),
         "mps_gram_block": (S, [P, I64, I64, P, I64, I64, I32, C.c_int, P, I64, P]),
         "mps_gram_multi": (S, [C.POINTER(_Job), I32, C.c_int, P]),
@@ -262,11 +263,13 @@ def import_batch(mps_list: Sequence[Sequence[np.ndarray]], stream=None) -> MPSBa
 
 
 def simulate(features, spec: CircuitSpec, chi: int, cutoff: float, stream=None, progress=None,
-             every: int = 0) -> MPSBatch:
+             every: int = 0, graph_gates=None) -> MPSBatch:
     """Truncated MPS simulation of every row of ``features`` (a CUDA float64 tensor, n x m).
 
     ``progress(done, total)`` (optional) is called every ``every`` two-qubit
-    gates; returning True aborts."""
+    gates; returning True aborts.  ``graph_gates`` (not with ``progress``)
+    records the launches of that many two-qubit gates per HIP graph (0: one
+    graph for the whole circuit)."""
     import torch
     if not isinstance(features, torch.Tensor) or features.device.type != "cuda":
         raise TypeError("features must be a CUDA tensor")
@@ -275,7 +278,12 @@ def simulate(features, spec: CircuitSpec, chi: int, cutoff: float, stream=None, 
         raise ValueError("features must be n x n_qubits")
     cs = spec._c()
     h = C.c_void_p(0)
-    if progress is None:
+    if graph_gates is not None:
+        if progress is not None:
+            raise ValueError("progress callbacks are not available with graph capture")
+        _check(_load().mps_simulate_graph(C.c_void_p(x.data_ptr()), x.shape[0], C.byref(cs), int(chi),
+                                          float(cutoff), int(graph_gates), _stream_ptr(stream), C.byref(h)))
+    elif progress is None:
         _check(_load().mps_simulate(C.c_void_p(x.data_ptr()), x.shape[0], C.byref(cs), int(chi), float(cutoff),
                                     _stream_ptr(stream), C.byref(h)))
     else:

@@ -225,9 +225,27 @@ qk_status mps_simulate(const double *features_dev, int64_t n_points, const qk_ci
   return mps_simulate_progress(features_dev, n_points, spec, chi_max, cutoff, hip_stream, nullptr, nullptr, 0, out);
 }
 
+static qk_status simulate_impl(const double *features_dev, int64_t n_points, const qk_circuit_spec *spec,
+                               int32_t chi_max, double cutoff, void *hip_stream, qk_progress_fn fn, void *user,
+                               int64_t every, int64_t graph_gates, qk_mps_batch **out);
+
 qk_status mps_simulate_progress(const double *features_dev, int64_t n_points, const qk_circuit_spec *spec,
                                 int32_t chi_max, double cutoff, void *hip_stream, qk_progress_fn fn, void *user,
                                 int64_t every, qk_mps_batch **out) {
+  return simulate_impl(features_dev, n_points, spec, chi_max, cutoff, hip_stream, fn, user, every, 0, out);
+}
+
+qk_status mps_simulate_graph(const double *features_dev, int64_t n_points, const qk_circuit_spec *spec,
+                             int32_t chi_max, double cutoff, int64_t gates_per_graph, void *hip_stream,
+                             qk_mps_batch **out) {
+  if (gates_per_graph < 0) return fail(QK_EINVAL, "gates_per_graph < 0");
+  return simulate_impl(features_dev, n_points, spec, chi_max, cutoff, hip_stream, nullptr, nullptr, 0,
+                       gates_per_graph == 0 ? INT64_MAX : gates_per_graph, out);
+}
+
+static qk_status simulate_impl(const double *features_dev, int64_t n_points, const qk_circuit_spec *spec,
+                               int32_t chi_max, double cutoff, void *hip_stream, qk_progress_fn fn, void *user,
+                               int64_t every, int64_t graph_gates, qk_mps_batch **out) {
   if (!out) return fail(QK_EINVAL, "out is NULL");
   *out = nullptr;
   qk_status st = validate_spec(spec);
@@ -250,7 +268,7 @@ qk_status mps_simulate_progress(const double *features_dev, int64_t n_points, co
   st = batch_create(n_points, m, pad, stream, &b);
   if (st != QK_OK) return st;
   auto gates = compile_circuit(*spec);
-  st = run_simulation(b, features_dev, gates, *spec, chi_max, cutoff, stream, fn, user, every);
+  st = run_simulation(b, features_dev, gates, *spec, chi_max, cutoff, stream, fn, user, every, graph_gates);
   if (st != QK_OK) {
     batch_release(b);
     return st;

@@ -524,8 +524,8 @@ __global__ void normalize_last_kernel(double2 *f64, int64_t mps_stride, const in
 }  // namespace
 
 qk_status run_simulation(qk_mps_batch *b, const double *features_dev, const std::vector<qk_gate> &gates,
-                         const qk_circuit_spec &spec, int chi, double cutoff, hipStream_t stream, qk_progress_fn fn,
-                         void *user, int64_t every) {
+                         const qk_circuit_spec &spec, int chi, double cutoff, hipStream_t stream_in, qk_progress_fn fn,
+                         void *user, int64_t every, int64_t graph_gates) {
   const int64_t n = b->n;
   const int m = b->m;
   int n2q = 0;
@@ -533,6 +533,7 @@ qk_status run_simulation(qk_mps_batch *b, const double *features_dev, const std:
   b->n_two_qubit_gates = n2q;
   if (n == 0) return QK_OK;
   if (n > 0x7fffffff) return fail(QK_EINVAL, "too many points for one launch");
+  hipStream_t stream = stream_in;
 
   // reject non-finite features before any launch
   {
@@ -591,6 +592,48 @@ qk_status run_simulation(qk_mps_batch *b, const double *features_dev, const std:
     return QK_OK;
   };
 
+  // HIP-graph mode: the launches of every `graph_gates` two-qubit gates are
+  // recorded by stream capture on a private stream (the caller's stream may
+  // be the legacy null stream, which cannot be captured), then instantiated
+  // and launched as one graph.  Events order the private stream after the
+  // caller's work and the caller's stream after the graphs.  The captured
+  // launches are exactly the eager ones, so results are bit-identical.
+  hipStream_t cap = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  bool capturing = false;
+  if (graph_gates > 0) {
+    QK_HIP_CHECK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    if (hipEventCreateWithFlags(&ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ev_out, hipEventDisableTiming) != hipSuccess ||
+        hipEventRecord(ev_in, stream_in) != hipSuccess || hipStreamWaitEvent(cap, ev_in, 0) != hipSuccess) {
+      if (ev_in) (void)hipEventDestroy(ev_in);
+      if (ev_out) (void)hipEventDestroy(ev_out);
+      (void)hipStreamDestroy(cap);
+      return fail(QK_EDEVICE, "graph stream set-up failed");
+    }
+  }
+  auto begin_segment = [&]() -> qk_status {
+    if (graph_gates <= 0 || capturing) return QK_OK;
+    QK_HIP_CHECK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+    stream = cap;
+    capturing = true;
+    return QK_OK;
+  };
+  auto end_segment = [&]() -> qk_status {
+    if (!capturing) return QK_OK;
+    capturing = false;
+    hipGraph_t graph = nullptr;
+    QK_HIP_CHECK(hipStreamEndCapture(cap, &graph));
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    hipError_t le = ie == hipSuccess ? hipGraphLaunch(exec, cap) : ie;
+    if (exec) (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    if (le != hipSuccess) return fail(QK_EDEVICE, std::string("graph launch failed: ") + hipGetErrorString(le));
+    return QK_OK;
+  };
+  int64_t seg2q = 0;
+
   // next two-qubit gate position after each gate
   std::vector<int> next2q(gates.size(), -1);
   {
@@ -606,6 +649,8 @@ qk_status run_simulation(qk_mps_batch *b, const double *features_dev, const std:
   int64_t done2q = 0;
   while (gi < gates.size() && st == QK_OK) {
     const qk_gate &g = gates[gi];
+    st = begin_segment();
+    if (st != QK_OK) break;
     if (g.op == OP_RZ) {
       size_t ge = gi;
       while (ge < gates.size() && gates[ge].op == OP_RZ) ++ge;
@@ -632,7 +677,17 @@ qk_status run_simulation(qk_mps_batch *b, const double *features_dev, const std:
     center = absorb_right ? p + 1 : p;
     ++gi;
     ++done2q;
+    ++seg2q;
+    if (st == QK_OK && graph_gates > 0 && seg2q == graph_gates) {
+      st = end_segment();
+      seg2q = 0;
+    }
     if (st == QK_OK && fn && every > 0 && done2q % every == 0) {
+      if (capturing) {
+        st = end_segment();
+        seg2q = 0;
+        if (st != QK_OK) break;
+      }
       if (hipStreamSynchronize(stream) != hipSuccess) {
         st = fail(QK_EDEVICE, "simulation step failed");
       } else if (fn(done2q, n2q, user) != 0) {
@@ -640,6 +695,7 @@ qk_status run_simulation(qk_mps_batch *b, const double *features_dev, const std:
       }
     }
   }
+  if (st == QK_OK) st = begin_segment();
   while (st == QK_OK && center < m - 1) {
     st = launch_step(center, MOVE_RIGHT, OP_ID, -1, -1);
     ++center;
@@ -649,8 +705,25 @@ qk_status run_simulation(qk_mps_batch *b, const double *features_dev, const std:
                        b->site_off_dev, b->pad_dev, m, n);
     if (hipGetLastError() != hipSuccess) st = fail(QK_EDEVICE, "normalisation launch failed");
   }
+  if (capturing) {
+    // on an earlier error, still close the capture so the stream is usable
+    const qk_status se = end_segment();
+    if (st == QK_OK) st = se;
+  }
+  if (graph_gates > 0) {
+    // the caller's stream continues after the graphs
+    (void)hipEventRecord(ev_out, cap);
+    (void)hipStreamWaitEvent(stream_in, ev_out, 0);
+    stream = stream_in;
+  }
   (void)hipFreeAsync(scratch, stream);
   (void)hipFreeAsync(recs_dev, stream);
+  if (graph_gates > 0) {
+    (void)hipStreamSynchronize(stream_in);
+    (void)hipEventDestroy(ev_in);
+    (void)hipEventDestroy(ev_out);
+    (void)hipStreamDestroy(cap);
+  }
   if (st != QK_OK) return st;
   QK_HIP_CHECK(hipStreamSynchronize(stream));
   if (fn && fn(n2q, n2q, user) != 0) return fail(QK_EABORTED, "simulation aborted by the progress callback");

@@ -156,3 +156,39 @@ def test_paper_bandwidth_165_qubits_vs_oracle():
         K = q.gram(b, precision=prec).cpu().numpy()
         print(prec, "max|dK| vs oracle", np.abs(K - Ko).max(), "K offdiag range", off.min(), off.max())
         assert np.abs(K - Ko).max() < tol
+
+
+def test_graph_captured_simulation_bit_identical():
+    """mps_simulate_graph records the same launches as HIP graphs (segments of
+    64 two-qubit gates, and the whole circuit as one graph): every run gives
+    the eager batch bit for bit, including runs interleaved with other eager
+    GPU work on the same stream."""
+    import time
+    import paper_2411_09336_amd as q
+    torch = require_gpu()
+    w = sd.WORKLOADS["fp32"]
+    X = sd.workload_features(w, 6)
+    xt = torch.tensor(X, dtype=torch.float64, device="cuda")
+    spec = q.CircuitSpec(w.n_qubits, w.distance, w.reps, w.coef_z, w.coef_xx, 0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ref = q.simulate(xt, spec, w.chi, w.cutoff)
+    torch.cuda.synchronize()
+    t_eager = time.perf_counter() - t0
+    ref_mps = [ref.export(i) for i in range(len(X))]
+    ref_dims = ref.bond_dims()
+    for run, seg in enumerate((64, 0, 64)):
+        junk = torch.randn(1 << 20, device="cuda").sum()       # eager work between runs
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g = q.simulate(xt, spec, w.chi, w.cutoff, graph_gates=seg)
+        torch.cuda.synchronize()
+        t_graph = time.perf_counter() - t0
+        print("graph segment", seg, "eager", t_eager, "s graph", t_graph, "s", float(junk) * 0)
+        assert np.array_equal(g.bond_dims(), ref_dims)
+        for i in range(len(X)):
+            for a, b in zip(g.export(i), ref_mps[i]):
+                assert np.array_equal(a, b)
+        K1 = q.gram(g, precision="fp64")
+        K0 = q.gram(ref, precision="fp64")
+        assert torch.equal(K1, K0)
