@@ -209,6 +209,31 @@ typedef struct {
 qk_status mps_gram_multi(const qk_gram_job *jobs, int32_t n_jobs,
                          qk_precision prec, void *hip_stream);
 
+/* Autotuner of the Gram kernels' tile shapes.  For `prec` and the bond-pad
+ * bucket of batch `b` (pads <= 32 or <= 64), every valid configuration (block
+ * size 32 or 64 for the FP64 / FP32 forms when the pads allow, pair-tile
+ * side 8 / 16 / 32, one work queue or one per XCD) computes the symmetric
+ * Gram of the first min(sample, n) MPS of `b` (one warm-up run, then the
+ * best of two timed runs, wall clock including the launch's host work).
+ * The fastest configuration is stored for this device, precision and pad
+ * bucket and used by every later mps_gram* call on this process; `report`
+ * (may be NULL) receives it with its time and the default configuration's
+ * time.  Not thread-safe with concurrent Gram calls of the same bucket. */
+typedef struct {
+  int32_t maxp;           /* block size of the winning configuration        */
+  int32_t tile_side;      /* pair-tile side                                  */
+  int32_t queues;         /* 1 or one per XCD                                */
+  int32_t n_candidates;   /* configurations timed                            */
+  double best_ms;         /* wall time of the winner on the sample           */
+  double default_ms;      /* wall time of the default configuration          */
+} qk_tune_report;
+
+qk_status mps_gram_autotune(qk_mps_batch *b, qk_precision prec, int64_t sample,
+                            void *hip_stream, qk_tune_report *report);
+
+/* Forget every stored configuration (back to the defaults). */
+qk_status mps_gram_tune_reset(void);
+
 /* ---------------------------------------------------------------- batches */
 
 /* Build an MPS batch from host FP64 tensors.  `dims_host` holds n x (m+1)

@@ -9,6 +9,6 @@ raises ``RuntimeError`` if the library has not been built
 (``python -m paper_2411_09336_amd.build``).
 """
 from .api import (  # noqa: F401
-    CircuitSpec, MPSBatch, QKError, Precision, circuit_compile, gram, gram_block, gram_multi,
-    import_batch, library_path, simulate, version,
+    CircuitSpec, MPSBatch, QKError, Precision, autotune, autotune_reset, circuit_compile, gram, gram_block,
+    gram_multi, import_batch, library_path, simulate, version,
 )

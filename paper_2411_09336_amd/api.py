@@ -71,6 +71,11 @@ class _Job(C.Structure):
                 ("K_dev", C.c_void_p), ("ldk", C.c_int64)]
 
 
+class _Tune(C.Structure):
+    _fields_ = [("maxp", C.c_int32), ("tile_side", C.c_int32), ("queues", C.c_int32),
+                ("n_candidates", C.c_int32), ("best_ms", C.c_double), ("default_ms", C.c_double)]
+
+
 _PROGRESS = C.CFUNCTYPE(C.c_int, C.c_int64, C.c_int64, C.c_void_p)
 
 
@@ -102,6 +107,8 @@ def _load():
         "mps_batch_drop": (S, [P, C.c_int]),
         "mps_batch_gather": (S, [P, P, I64, C.c_uint32, P, C.POINTER(P)]),
         "mps_batch_free": (None, [P]),
+        "mps_gram_autotune": (S, [P, C.c_int, I64, P, C.POINTER(_Tune)]),
+        "mps_gram_tune_reset": (S, []),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -292,6 +299,21 @@ def simulate(features, spec: CircuitSpec, chi: int, cutoff: float, stream=None, 
                                              float(cutoff), _stream_ptr(stream), cb, None, int(every),
                                              C.byref(h)))
     return MPSBatch(h.value)
+
+
+def autotune(batch: MPSBatch, precision="fp64", sample: int = 64, stream=None) -> dict:
+    """Time every Gram kernel configuration of ``precision`` on the symmetric
+    Gram of the first ``sample`` MPS of ``batch`` and keep the fastest for
+    later Gram calls on batches with the same pad bucket."""
+    r = _Tune()
+    _check(_load().mps_gram_autotune(batch.handle, Precision.of(precision), int(sample), _stream_ptr(stream),
+                                     C.byref(r)))
+    return {f: getattr(r, f) for f, _ in _Tune._fields_}
+
+
+def autotune_reset() -> None:
+    """Back to the default Gram kernel configurations."""
+    _check(_load().mps_gram_tune_reset())
 
 
 def gram(a: MPSBatch, b: Optional[MPSBatch] = None, precision="fp64", out=None, stream=None):

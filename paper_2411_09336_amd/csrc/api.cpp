@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -366,6 +367,64 @@ qk_status mps_gram(const qk_mps_batch *a, const qk_mps_batch *b, qk_precision pr
   if (!a) return fail(QK_EINVAL, "batch a is NULL");
   if (b == nullptr || b == a) return mps_gram_block(a, 0, a->n, a, 0, a->n, 1, prec, K_dev, ldk, hip_stream);
   return mps_gram_block(a, 0, a->n, b, 0, b->n, 0, prec, K_dev, ldk, hip_stream);
+}
+
+qk_status mps_gram_autotune(qk_mps_batch *b, qk_precision prec, int64_t sample, void *hip_stream,
+                            qk_tune_report *report) {
+  if (!b) return fail(QK_EINVAL, "NULL batch");
+  if (sample < 1) return fail(QK_EINVAL, "sample must be >= 1");
+  hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+  const int64_t n = std::min<int64_t>(sample, b->n);
+  if (n < 1) return fail(QK_EINVAL, "empty batch");
+  double *K = nullptr;
+  QK_HIP_CHECK(hipMallocAsync(reinterpret_cast<void **>(&K), sizeof(double) * size_t(n) * size_t(n), stream));
+  GramJobDev job;
+  qk_status st = make_job(b, 0, n, b, 0, n, 1, K, n, prec, stream, &job);
+  const int max_pad = max_pad_of(b);
+  std::vector<GramJobDev> jobs{job};
+  auto run_ms = [&](const GramConfig &c, double &ms) -> qk_status {
+    double best = 1e300;
+    for (int rep = 0; rep < 3; ++rep) {
+      const auto t0 = std::chrono::steady_clock::now();
+      qk_status s2 = launch_gram_cfg(jobs, max_pad, prec, c, stream);
+      if (s2 != QK_OK) return s2;
+      QK_HIP_CHECK(hipStreamSynchronize(stream));
+      const double dt = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+      if (rep > 0) best = std::min(best, dt);   // rep 0 warms up
+    }
+    ms = best;
+    return QK_OK;
+  };
+  GramConfig best_cfg = default_gram_config(prec, max_pad);
+  double default_ms = 0.0, best_ms = 1e300;
+  const auto cands = gram_config_candidates(prec, max_pad);
+  if (st == QK_OK) st = run_ms(best_cfg, default_ms);
+  best_ms = default_ms;
+  for (size_t k = 0; k < cands.size() && st == QK_OK; ++k) {
+    double ms = 0.0;
+    st = run_ms(cands[k], ms);
+    if (st == QK_OK && ms < best_ms) {
+      best_ms = ms;
+      best_cfg = cands[k];
+    }
+  }
+  (void)hipFreeAsync(K, stream);
+  if (st != QK_OK) return st;
+  store_gram_config(prec, max_pad, best_cfg);
+  if (report) {
+    report->maxp = best_cfg.maxp;
+    report->tile_side = best_cfg.tile_side;
+    report->queues = best_cfg.queues;
+    report->n_candidates = int32_t(cands.size());
+    report->best_ms = best_ms;
+    report->default_ms = default_ms;
+  }
+  return ok();
+}
+
+qk_status mps_gram_tune_reset(void) {
+  clear_gram_configs();
+  return ok();
 }
 
 qk_status mps_gram_multi(const qk_gram_job *jobs, int32_t n_jobs, qk_precision prec, void *hip_stream) {

@@ -26,6 +26,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "qk_internal.h"
@@ -34,8 +37,7 @@ namespace qk {
 
 namespace {
 
-constexpr int kTileSide = 16;
-constexpr int kTilePairs = kTileSide * kTileSide;
+constexpr int kDefaultTileSide = 16;   // pair tiles are side x side entries
 constexpr int kThreads = 256;
 
 struct GramTile {
@@ -86,21 +88,22 @@ constexpr int kCounterStride = 8;   // unsigned long long elements
 // Decode the next pair of this workgroup's queue.  Returns false when the
 // queue is empty; *valid is false for pairs outside the job's range or below
 // the diagonal.
-__device__ inline bool next_pair(const GramJobDev *jobs, const GramTile *tiles, int64_t n_tiles, int nq,
+__device__ inline bool next_pair(const GramJobDev *jobs, const GramTile *tiles, int64_t n_tiles, int nq, int side,
                                  unsigned long long *counters, int64_t *s_slot, int *job, int64_t *i,
                                  int64_t *j, bool *valid) {
+  const int tile_pairs = side * side;
   const int x = int(blockIdx.x % unsigned(nq));
   if (threadIdx.x == 0) *s_slot = int64_t(atomicAdd(counters + x * kCounterStride, 1ull));
   __syncthreads();
   const int64_t p = *s_slot;
   __syncthreads();
-  const int64_t tile = x + int64_t(nq) * (p / kTilePairs);
+  const int64_t tile = x + int64_t(nq) * (p / tile_pairs);
   if (tile >= n_tiles) return false;
   const GramTile t = tiles[tile];
-  const int q = int(p % kTilePairs);
+  const int q = int(p % tile_pairs);
   const GramJobDev &J = jobs[t.job];
-  const int64_t li = int64_t(t.ti) * kTileSide + q / kTileSide;
-  const int64_t lj = int64_t(t.tj) * kTileSide + q % kTileSide;
+  const int64_t li = int64_t(t.ti) * side + q / side;
+  const int64_t lj = int64_t(t.tj) * side + q % side;
   *job = t.job;
   *i = li;
   *j = lj;
@@ -954,7 +957,8 @@ constexpr int threads_of() {
 template <int PREC, int MAXP>
 __global__ __launch_bounds__(threads_of<PREC>(), 2) void gram_kernel(const GramJobDev *__restrict__ jobs,
                                                         const GramTile *__restrict__ tiles,
-                                                        int64_t n_tiles, int nq, unsigned long long *counters) {
+                                                        int64_t n_tiles, int nq, int side,
+                                                        unsigned long long *counters) {
   extern __shared__ __align__(16) uint8_t smem[];
   __shared__ int64_t s_slot;
   __shared__ double s_red[4];
@@ -965,7 +969,7 @@ __global__ __launch_bounds__(threads_of<PREC>(), 2) void gram_kernel(const GramJ
   int job;
   int64_t i, j;
   bool valid;
-  while (next_pair(jobs, tiles, n_tiles, nq, counters, &s_slot, &job, &i, &j, &valid)) {
+  while (next_pair(jobs, tiles, n_tiles, nq, side, counters, &s_slot, &job, &i, &j, &valid)) {
     if (!valid) continue;
     const GramJobDev &J = jobs[job];
     double k;
@@ -1007,7 +1011,7 @@ size_t lds_bytes() {
 
 template <int PREC, int MAXP>
 qk_status launch_one(const GramJobDev *jobs_dev, const GramTile *tiles_dev, int64_t n_tiles,
-                     unsigned long long *counters, hipStream_t stream) {
+                     unsigned long long *counters, const GramConfig &cfg, hipStream_t stream) {
   int dev = 0, cus = 256;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -1019,36 +1023,35 @@ qk_status launch_one(const GramJobDev *jobs_dev, const GramTile *tiles_dev, int6
   QK_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads_of<PREC>(), lds));
   per_cu = std::max(per_cu, 1);
   int64_t grid = int64_t(cus) * per_cu;
-  grid = std::min<int64_t>(grid, std::max<int64_t>(n_tiles * kTilePairs, 1));
-  // every queue needs workgroups: at most one queue per workgroup.  The
-  // split-int8 form runs one queue per XCD (L2 hit rate 40 % -> 70 % on
-  // 165-site chi = 64 states); the FP64 / FP32 / split-BF16 kernels measured
-  // no gain (FP64 and FP32 lost 6-8 %) and keep one queue.
-  const int nq = PREC == QK_SPLIT_I8 ? int(std::min<int64_t>(kQueues, grid)) : 1;
+  grid = std::min<int64_t>(grid, std::max<int64_t>(n_tiles * cfg.tile_side * cfg.tile_side, 1));
+  // every queue needs workgroups: at most one queue per workgroup
+  const int nq = int(std::min<int64_t>(cfg.queues, grid));
   hipLaunchKernelGGL(kern, dim3(unsigned(grid)), dim3(threads_of<PREC>()), lds, stream, jobs_dev, tiles_dev,
-                     n_tiles, nq, counters);
+                     n_tiles, nq, cfg.tile_side, counters);
   QK_HIP_CHECK(hipGetLastError());
   return QK_OK;
 }
 
 }  // namespace
 
-qk_status launch_gram(const std::vector<GramJobDev> &jobs_in, int max_pad, qk_precision prec,
-                      hipStream_t stream) {
+qk_status launch_gram_cfg(const std::vector<GramJobDev> &jobs_in, int max_pad, qk_precision prec,
+                          const GramConfig &cfg, hipStream_t stream) {
   if (max_pad > 64) return fail(QK_ENOTSUP, "Gram kernels support bond pads up to 64");
+  if (cfg.maxp < max_pad) return fail(QK_EINVAL, "tile configuration smaller than the batch's bond pads");
+  const int side = cfg.tile_side;
   std::vector<GramJobDev> jobs = jobs_in;
   std::vector<GramTile> tiles;
   for (size_t k = 0; k < jobs.size(); ++k) {
     GramJobDev &J = jobs[k];
-    J.tiles_i = (J.na + kTileSide - 1) / kTileSide;
-    J.tiles_j = (J.nb + kTileSide - 1) / kTileSide;
-    J.pair_begin = int64_t(tiles.size()) * kTilePairs;
+    J.tiles_i = (J.na + side - 1) / side;
+    J.tiles_j = (J.nb + side - 1) / side;
+    J.pair_begin = int64_t(tiles.size()) * (side * side);
     for (int64_t ti = 0; ti < J.tiles_i; ++ti)
       for (int64_t tj = 0; tj < J.tiles_j; ++tj) {
         if (J.upper) {
           // skip tiles entirely below the global diagonal
-          const int64_t max_col = J.b0 + std::min(J.nb, (tj + 1) * kTileSide) - 1;
-          const int64_t min_row = J.a0 + ti * kTileSide;
+          const int64_t max_col = J.b0 + std::min(J.nb, (tj + 1) * side) - 1;
+          const int64_t min_row = J.a0 + ti * side;
           if (max_col < min_row) continue;
         }
         tiles.push_back(GramTile{int32_t(k), int32_t(ti), int32_t(tj), 0});
@@ -1072,15 +1075,81 @@ qk_status launch_gram(const std::vector<GramJobDev> &jobs_in, int max_pad, qk_pr
   QK_HIP_CHECK(hipStreamSynchronize(stream));
   qk_status st;
   if (prec == QK_FP64)
-    st = launch_one<QK_FP64, 64>(jobs_dev, tiles_dev, n_tiles, counters, stream);
+    st = cfg.maxp == 32 ? launch_one<QK_FP64, 32>(jobs_dev, tiles_dev, n_tiles, counters, cfg, stream)
+                        : launch_one<QK_FP64, 64>(jobs_dev, tiles_dev, n_tiles, counters, cfg, stream);
   else if (prec == QK_FP32)
-    st = launch_one<QK_FP32, 64>(jobs_dev, tiles_dev, n_tiles, counters, stream);
+    st = cfg.maxp == 32 ? launch_one<QK_FP32, 32>(jobs_dev, tiles_dev, n_tiles, counters, cfg, stream)
+                        : launch_one<QK_FP32, 64>(jobs_dev, tiles_dev, n_tiles, counters, cfg, stream);
   else if (prec == QK_SPLIT_BF16)
-    st = launch_one<QK_SPLIT_BF16, 64>(jobs_dev, tiles_dev, n_tiles, counters, stream);
+    st = launch_one<QK_SPLIT_BF16, 64>(jobs_dev, tiles_dev, n_tiles, counters, cfg, stream);
   else
-    st = launch_one<QK_SPLIT_I8, 64>(jobs_dev, tiles_dev, n_tiles, counters, stream);
+    st = launch_one<QK_SPLIT_I8, 64>(jobs_dev, tiles_dev, n_tiles, counters, cfg, stream);
   (void)hipFreeAsync(ws, stream);
   return st;
+}
+
+
+// ------------------------------------------------------------------------
+// Kernel configurations and the autotuner.  A configuration is the block
+// size of the plain forms (32 or 64), the pair-tile side and the number of
+// work queues.  Defaults were chosen by measurement on 165-site chi = 64
+// batches; mps_gram_autotune times every valid configuration on a sample of
+// the caller's batch and stores the fastest per (device, form, pad bucket).
+
+namespace {
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int>, GramConfig> g_tuned;
+
+int pad_bucket(int max_pad) { return max_pad <= 32 ? 32 : 64; }
+}  // namespace
+
+GramConfig default_gram_config(qk_precision prec, int max_pad) {
+  (void)max_pad;
+  GramConfig c;
+  c.maxp = 64;
+  c.tile_side = kDefaultTileSide;
+  c.queues = prec == QK_SPLIT_I8 ? kQueues : 1;
+  return c;
+}
+
+std::vector<GramConfig> gram_config_candidates(qk_precision prec, int max_pad) {
+  std::vector<GramConfig> out;
+  std::vector<int> maxps{64};
+  if ((prec == QK_FP64 || prec == QK_FP32) && max_pad <= 32) maxps.push_back(32);
+  for (int mp : maxps)
+    for (int side : {8, 16, 32})
+      for (int nq : {1, kQueues}) {
+        GramConfig c;
+        c.maxp = mp;
+        c.tile_side = side;
+        c.queues = nq;
+        out.push_back(c);
+      }
+  return out;
+}
+
+GramConfig current_gram_config(qk_precision prec, int max_pad) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tuned.find(std::make_tuple(dev, int(prec), pad_bucket(max_pad)));
+  return it != g_tuned.end() ? it->second : default_gram_config(prec, max_pad);
+}
+
+void store_gram_config(qk_precision prec, int max_pad, const GramConfig &c) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tuned[std::make_tuple(dev, int(prec), pad_bucket(max_pad))] = c;
+}
+
+void clear_gram_configs() {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tuned.clear();
+}
+
+qk_status launch_gram(const std::vector<GramJobDev> &jobs, int max_pad, qk_precision prec, hipStream_t stream) {
+  return launch_gram_cfg(jobs, max_pad, prec, current_gram_config(prec, max_pad), stream);
 }
 
 // ------------------------------------------------------------------------

@@ -150,8 +150,23 @@ struct GramJobDev {
   int64_t pair_begin;              // first flat pair index of this job
 };
 
+// Gram kernel configuration: block size of the plain forms (32 or 64), pair
+// tile side, number of work queues (1, or one per XCD).
+struct GramConfig {
+  int maxp = 64;
+  int tile_side = 16;
+  int queues = 1;
+};
+
 qk_status launch_gram(const std::vector<GramJobDev> &jobs, int max_pad,
                       qk_precision prec, hipStream_t stream);
+qk_status launch_gram_cfg(const std::vector<GramJobDev> &jobs, int max_pad,
+                          qk_precision prec, const GramConfig &cfg, hipStream_t stream);
+GramConfig default_gram_config(qk_precision prec, int max_pad);
+GramConfig current_gram_config(qk_precision prec, int max_pad);
+std::vector<GramConfig> gram_config_candidates(qk_precision prec, int max_pad);
+void store_gram_config(qk_precision prec, int max_pad, const GramConfig &c);
+void clear_gram_configs();
 
 // Simulation launchers.
 qk_status run_simulation(qk_mps_batch *b, const double *features_dev,

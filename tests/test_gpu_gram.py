@@ -151,3 +151,27 @@ def test_split_values_at_top_of_exponent_range(prec):
     # two operands, |K| = |<a|b>|^2 -> below 4 * 24 * 2^-31 = 4.5e-8
     assert np.abs(np.diag(K) - 1.0).max() < 4.5e-8
     assert np.abs(K - Kref).max() < 4.5e-8
+
+
+@pytest.mark.gpu
+def test_autotune_keeps_results_and_uses_choice(small_sets):
+    """The autotuner times every configuration (block size 32 / 64 for the
+    plain forms when the pads allow, pair-tile side, queues) and stores the
+    fastest; Gram results afterwards are bit-identical to the defaults (the
+    configuration changes scheduling, not arithmetic)."""
+    import paper_2411_09336_amd as q
+    torch = require_gpu()
+    b = q.import_batch(small_sets[0])            # bond dims <= 32: pads 32
+    assert b.info()["pad_max"] == 32
+    try:
+        for prec, ncand in (("fp64", 12), ("fp32", 12), ("split_i8", 6), ("split_bf16", 6)):
+            k0 = q.gram(b, precision=prec)
+            rep = q.autotune(b, precision=prec, sample=16)
+            print(prec, rep)
+            assert rep["n_candidates"] == ncand
+            assert rep["maxp"] in (32, 64) and rep["tile_side"] in (8, 16, 32) and rep["queues"] in (1, 8)
+            assert rep["best_ms"] <= rep["default_ms"]
+            k1 = q.gram(b, precision=prec)
+            assert torch.equal(k0, k1)
+    finally:
+        q.autotune_reset()
