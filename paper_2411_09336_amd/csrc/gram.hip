@@ -38,6 +38,38 @@ namespace qk {
 namespace {
 
 constexpr int kDefaultTileSide = 16;   // pair tiles are side x side entries
+
+// Site tensors and K live in global memory, but their pointers come from the
+// job table, so the compiler cannot infer the address space and would emit
+// flat accesses, which also count against the LDS wait counter (an LDS wait
+// then waits for every global load in flight).  Accesses go through these
+// global-address-space views instead.
+template <typename T>
+__device__ inline const T __attribute__((address_space(1))) *gview(const T *p) {
+  return (const T __attribute__((address_space(1))) *)p;
+}
+template <typename T>
+__device__ inline T __attribute__((address_space(1))) *gview_rw(T *p) {
+  return (T __attribute__((address_space(1))) *)p;
+}
+
+// 16-byte and complex loads through global views (native vector types: the
+// HIP vector structs cannot be copied from address-space-qualified lvalues).
+__device__ inline uint4 gload_u4(const void *p) {
+  typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+  const v4u v = *gview(reinterpret_cast<const v4u *>(p));
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
+template <typename T2>
+__device__ inline T2 gload_c(const T2 *p) {
+  typedef decltype(T2().x) T;
+  typedef T v2 __attribute__((ext_vector_type(2)));
+  const v2 v = *gview(reinterpret_cast<const v2 *>(p));
+  T2 r;
+  r.x = v.x;
+  r.y = v.y;
+  return r;
+}
 constexpr int kThreads = 256;
 
 struct GramTile {
@@ -95,7 +127,12 @@ __device__ inline bool next_pair(const GramJobDev *jobs, const GramTile *tiles, 
   const int x = int(blockIdx.x % unsigned(nq));
   if (threadIdx.x == 0) *s_slot = int64_t(atomicAdd(counters + x * kCounterStride, 1ull));
   __syncthreads();
-  const int64_t p = *s_slot;
+  // the slot is the same for the whole workgroup: make it wave-uniform so
+  // that the job, pair and site addresses derived from it live in scalar
+  // registers
+  const uint64_t pv = uint64_t(*s_slot);
+  const int64_t p = int64_t((uint64_t(uint32_t(__builtin_amdgcn_readfirstlane(uint32_t(pv >> 32)))) << 32) |
+                            uint32_t(__builtin_amdgcn_readfirstlane(uint32_t(pv))));
   __syncthreads();
   const int64_t tile = x + int64_t(nq) * (p / tile_pairs);
   if (tile >= n_tiles) return false;
@@ -114,12 +151,13 @@ __device__ inline bool next_pair(const GramJobDev *jobs, const GramTile *tiles, 
 }
 
 __device__ inline void write_k(const GramJobDev &J, int64_t li, int64_t lj, double k) {
-  J.K[li * J.ldk + lj] = k;
+  const auto K = gview_rw(J.K);
+  K[li * J.ldk + lj] = k;
   if (J.upper) {
     // mirror inside the written block when the transposed entry is in range
     const int64_t gi = J.a0 + li, gj = J.b0 + lj;
     const int64_t mi = gj - J.a0, mj = gi - J.b0;
-    if (gi != gj && mi >= 0 && mi < J.na && mj >= 0 && mj < J.nb) J.K[mi * J.ldk + mj] = k;
+    if (gi != gj && mi >= 0 && mi < J.na && mj >= 0 && mj < J.nb) K[mi * J.ldk + mj] = k;
   }
 }
 
@@ -143,7 +181,7 @@ __device__ void overlap_plain(const GramJobDev &J, int64_t ia, int64_t ib, T2 *E
   const T2 *abase = reinterpret_cast<const T2 *>(J.a_base) + ia * J.a_stride;
   const T2 *bbase = reinterpret_cast<const T2 *>(J.b_base) + ib * J.b_stride;
   {
-    const int n0 = J.a_pad[0] * J.b_pad[0];
+    const int n0 = gview(J.a_pad)[0] * gview(J.b_pad)[0];
     for (int x = tid; x < n0; x += kThreads) {
       T2 z;
       z.x = T(0);
@@ -158,9 +196,9 @@ __device__ void overlap_plain(const GramJobDev &J, int64_t ia, int64_t ib, T2 *E
   constexpr int NT = MAXP / 16;
   constexpr int CT_PER_WAVE = (NT + 3) / 4;
   for (int l = 0; l < J.m; ++l) {
-    const int Da = J.a_pad[l], Dan = J.a_pad[l + 1], Db = J.b_pad[l], Dbn = J.b_pad[l + 1];
-    const T2 *A = abase + J.a_off[l];
-    const T2 *B = bbase + J.b_off[l];
+    const int Da = gview(J.a_pad)[l], Dan = gview(J.a_pad)[l + 1], Db = gview(J.b_pad)[l], Dbn = gview(J.b_pad)[l + 1];
+    const T2 *A = abase + gview(J.a_off)[l];
+    const T2 *B = bbase + gview(J.b_off)[l];
     const int nrt = Da / 16, nkq = Db / 4, nat = Dan / 16, nct = Dbn / 16, nkqn = Dbn / 4;
     V4 Ep[CT_PER_WAVE][NT][2];
     T lmax = T(0);
@@ -183,7 +221,7 @@ __device__ void overlap_plain(const GramJobDev &J, int64_t ia, int64_t ib, T2 *E
         }
         // GEMM1: T_s[a][b'] = sum_b E[a][b] B_s[b][b'],  b' in block ct
         for (int kq = 0; kq < nkq; ++kq) {
-          const T2 bv = B[(size_t(s) * Db + 4 * kq + g) * Dbn + 16 * ct + j];
+          const T2 bv = gload_c(B + (size_t(s) * Db + 4 * kq + g) * Dbn + 16 * ct + j);
           const T bneg = -bv.y;
 #pragma unroll
           for (int rt = 0; rt < NT; ++rt) {
@@ -208,7 +246,7 @@ __device__ void overlap_plain(const GramJobDev &J, int64_t ia, int64_t ib, T2 *E
 #pragma unroll
               for (int at = 0; at < NT; ++at) {
                 if (at < nat) {
-                  const T2 av = arow[16 * at];
+                  const T2 av = gload_c(arow + 16 * at);
                   Ep[c][at][0] = mma(tr, av.x, Ep[c][at][0]);
                   Ep[c][at][0] = mma(ti, av.y, Ep[c][at][0]);
                   Ep[c][at][1] = mma(ti, av.x, Ep[c][at][1]);
@@ -376,8 +414,7 @@ struct SplitCtx {
 };
 
 __device__ inline uint4 split_frag(const uint8_t *site, int s, int k, int q, int kc, int c, int lane) {
-  return *reinterpret_cast<const uint4 *>(
-      site + kSplitExpBytes + (size_t(((((s * 4 + k) * 2 + q) * 2 + kc) * 4 + c)) * 1024 + lane * 16));
+  return gload_u4(site + kSplitExpBytes + (size_t(((((s * 4 + k) * 2 + q) * 2 + kc) * 4 + c)) * 1024 + lane * 16));
 }
 
 // GEMM1 for physical index s: T[a][b'] (a in rows 32h.., b' in block c) in
@@ -418,7 +455,7 @@ __device__ inline void split_gemm1(const SplitCtx &C, const uint8_t *B, const ui
       slice_mac(Ei, Br, h1[u][1], l1[u][1]);
     }
   }
-  const int ebc = int(reinterpret_cast<const int8_t *>(B)[s * 128 + 16 * C.cb + C.j]);
+  const int ebc = int(gview(reinterpret_cast<const int8_t *>(B))[s * 128 + 16 * C.cb + C.j]);
   tmax = 0.0;
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
@@ -497,7 +534,7 @@ __device__ inline void split_gemm2(const SplitCtx &C, const uint8_t *A, const ui
       slice_mac(Trn, Ai, h2[u][1], l2[u][1]);
     }
   }
-  const int eac = int(reinterpret_cast<const int8_t *>(A)[s * 128 + 16 * C.cb + C.j]);
+  const int eac = int(gview(reinterpret_cast<const int8_t *>(A))[s * 128 + 16 * C.cb + C.j]);
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
     const int bt = 2 * C.hf + u;
@@ -539,8 +576,8 @@ __device__ void overlap_split(const GramJobDev &J, int64_t ia, int64_t ib, uint8
   }
   const int col = 16 * C.cb + C.j;
   for (int l = 0; l < J.m; ++l) {
-    const uint8_t *A = abase + J.a_off[l];
-    const uint8_t *B = bbase + J.b_off[l];
+    const uint8_t *A = abase + gview(J.a_off)[l];
+    const uint8_t *B = bbase + gview(J.b_off)[l];
     double Td0[2][2][4], Td1[2][2][4], Ep[2][2][4];
     double tmax;
 #pragma unroll
@@ -678,8 +715,8 @@ __device__ inline void tile_fence(double (&v)[2][4]) {
 
 // Fragment (s, slice k, plane q, column block ct) of a packed int8 site block.
 __device__ inline uint4 i8_frag(const uint8_t *site, int s, int k, int q, int ct, int lane) {
-  return *reinterpret_cast<const uint4 *>(site + kI8ExpBytes + kI8SumBytes +
-                                          size_t(((s * 4 + k) * 2 + q) * 4 + ct) * kI8FragBytes + lane * 16);
+  return gload_u4(site + kI8ExpBytes + kI8SumBytes + size_t(((s * 4 + k) * 2 + q) * 4 + ct) * kI8FragBytes +
+                  lane * 16);
 }
 
 // Class accumulators of one complex 16 x 16 tile: class c holds the digit
@@ -780,8 +817,8 @@ __device__ inline void i8_load(const I8Ctx &C, const uint8_t *site, int s, I8Ope
 
 __device__ inline void i8_column_meta(const I8Ctx &C, const I8Operand &o, int &e, int (&cs)[4]) {
   const int col = 16 * C.cb + C.j;
-  e = int(reinterpret_cast<const int8_t *>(o.site)[o.s * 128 + col]);
-  const int *p = reinterpret_cast<const int *>(o.site + kI8ExpBytes) + o.s * 256 + col;
+  e = int(gview(reinterpret_cast<const int8_t *>(o.site))[o.s * 128 + col]);
+  const auto p = gview(reinterpret_cast<const int *>(o.site + kI8ExpBytes) + o.s * 256 + col);
 #pragma unroll
   for (int k = 0; k < 4; ++k) cs[k] = p[64 * k];
 }
@@ -868,7 +905,7 @@ __device__ void overlap_i8(const GramJobDev &J, int64_t ia, int64_t ib, uint8_t 
   C.lane = tid & 63;
   C.j = C.lane & 15;
   C.g = C.lane >> 4;
-  C.cb = tid >> 6;
+  C.cb = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform: scalar addressing
   const uint8_t *abase = reinterpret_cast<const uint8_t *>(J.a_base) + ia * J.a_stride;
   const uint8_t *bbase = reinterpret_cast<const uint8_t *>(J.b_base) + ib * J.b_stride;
   uint8_t *X = buf0, *Y = buf1;
@@ -886,10 +923,10 @@ __device__ void overlap_i8(const GramJobDev &J, int64_t ia, int64_t ib, uint8_t 
   }
   const int col = 16 * C.cb + C.j;
   I8Operand P0, P1;   // operands of the current and the next GEMM
-  i8_load(C, bbase + J.b_off[0], 0, P0);
+  i8_load(C, bbase + gview(J.b_off)[0], 0, P0);
   for (int l = 0; l < J.m; ++l) {
-    const uint8_t *A = abase + J.a_off[l];
-    const uint8_t *B = bbase + J.b_off[l];
+    const uint8_t *A = abase + gview(J.a_off)[l];
+    const uint8_t *B = bbase + gview(J.b_off)[l];
     double Td[4][2][4], Ep[4][2][4];
     double tmax;
     // I
@@ -919,7 +956,7 @@ __device__ void overlap_i8(const GramJobDev &J, int64_t ia, int64_t ib, uint8_t 
     i8_gemm2(C, P0, Y, s_eT, Ep);
     __syncthreads();
     // III
-    if (l + 1 < J.m) i8_load(C, bbase + J.b_off[l + 1], 0, P0);
+    if (l + 1 < J.m) i8_load(C, bbase + gview(J.b_off)[l + 1], 0, P0);
     i8_gemm2(C, P1, X, s_eT + kSP, Ep);
     if (l + 1 == J.m) {
       // E_m[0][0] = E'^T[0][0]: wave 0, lane 0, tile 0, e = 0
