@@ -80,44 +80,51 @@ def counter_record_path(form):
     return os.path.join(ROOT, "profiles", f"gram_{form}_counters.json")
 
 
-def counter_traffic(form):
+def counter_traffic(form, config):
     """HBM bytes per timed Gram launch from the committed hardware-counter
-    record of that form, or None when absent or taken on other kernel
-    sources."""
+    record of that form, or None when absent, taken on other kernel sources
+    or with another kernel configuration (block size, tile side, queues)."""
     try:
         data = json.load(open(counter_record_path(form)))
     except (OSError, ValueError):
         return None, None
     if data.get("kernel_source_sha256") != kernel_source_digest():
         return None, data
+    rc = data.get("config") or {}
+    if any(rc.get(k) != config.get(k) for k in ("maxp", "tile_side", "queues")):
+        return None, data
     return data.get("traffic_bytes_per_launch"), data
 
 
-def write_counter_record(form, fetch_csv, write_csv, fetch_scale, write_scale, command):
+def write_counter_record(form, fetch_csv, write_csv, fetch_scale, write_scale, command, config):
     """Record of the FETCH_SIZE / WRITE_SIZE runs of one timed launch (the
     first dispatch of the form's kernel after the warmup-free partial run),
     scaled to bytes by the copy-kernel factors."""
     import csv
     kname = {"split_i8": "gram_kernel<3, 64>", "split_bf16": "gram_kernel<2, 64>"}[form]
 
-    def first(path, counter):
+    def slab(path, counter):
+        # the timed slab is the longest dispatch of the kernel (autotuning
+        # and warm-up dispatches are short)
         rows = [r for r in csv.DictReader(open(path))
                 if kname in r["Kernel_Name"] and r["Counter_Name"] == counter]
-        by_dispatch = {}
+        value, dur = {}, {}
         for r in rows:
-            by_dispatch.setdefault(int(r["Dispatch_Id"]), 0.0)
-            by_dispatch[int(r["Dispatch_Id"])] += float(r["Counter_Value"])
-        d = min(by_dispatch)
-        return by_dispatch[d]
+            d = int(r["Dispatch_Id"])
+            value[d] = value.get(d, 0.0) + float(r["Counter_Value"])
+            dur[d] = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+        d = max(dur, key=dur.get)
+        return value[d], dur[d] / 1e9
 
-    fetch_kib = first(fetch_csv, "FETCH_SIZE")
-    write_kib = first(write_csv, "WRITE_SIZE")
+    fetch_kib, fetch_s = slab(fetch_csv, "FETCH_SIZE")
+    write_kib, write_s = slab(write_csv, "WRITE_SIZE")
     fetch_b = fetch_kib * fetch_scale
     write_b = write_kib * write_scale
-    rec = {"form": form, "kernel": kname, "kernel_source_sha256": kernel_source_digest(),
+    rec = {"form": form, "kernel": kname, "kernel_source_sha256": kernel_source_digest(), "config": config,
            "fetch_size_kib": fetch_kib, "write_size_kib": write_kib,
            "fetch_bytes_per_counted_kib": fetch_scale, "write_bytes_per_counted_kib": write_scale,
            "traffic_bytes_per_launch": fetch_b + write_b,
+           "slab_seconds_in_counter_runs": [fetch_s, write_s],
            "note": "HBM bytes of one timed slab launch (rows 0..r1 of 8 equal-work slabs of the 6400 x 6400 "
                    "Gram): FETCH_SIZE and WRITE_SIZE in separate runs, scaled by a plain copy kernel",
            "command": command}
@@ -200,6 +207,8 @@ def main():
     ap.add_argument("--counter-record", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="only write profiles/gram_<form>_counters.json from rocprofv3 counter CSVs of "
                          "'--slabs-run 1' runs (no GPU use), then exit")
+    ap.add_argument("--counter-config", default="maxp=64,tile_side=16,queues=1",
+                    help="kernel configuration of the counter runs (as reported by their autotune line)")
     ap.add_argument("--counter-scale", nargs=2, type=float, default=(2047.93, 1024.0),
                     metavar=("FETCH", "WRITE"), help="bytes per counted KiB (plain copy kernel)")
     ap.add_argument("--routing", type=int, default=1,
@@ -215,7 +224,8 @@ def main():
         write_counter_record(args.form, args.counter_record[0], args.counter_record[1], args.counter_scale[0],
                              args.counter_scale[1],
                              f"rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) --output-format csv -- python3 "
-                             f"bench.py --form {args.form} --slabs-run 1 --no-cpu --sim-sample 16 --warmup 0")
+                             f"bench.py --form {args.form} --slabs-run 1 --no-cpu --warmup 0",
+                             {k: int(v) for k, v in (kv.split("=") for kv in args.counter_config.split(","))})
         return
     if args.calibrate_copy > 0:
         calibrate_copy(args.calibrate_copy)
@@ -430,7 +440,7 @@ def run(args):
     # products x 4 real products = 44 real MACs = 88 ops for it
     mdt, kname, fdesc = FORMS[form]
     issued_tf = achieved_tf * 11
-    traffic, crec = counter_traffic(form)
+    traffic, crec = counter_traffic(form, tune)
     roof = {"bound": "mfma", "achieved": round(achieved_tf, 3), "peak": PEAK_TFLOPS[mdt], "unit": "TFLOP/s",
             "frac": round(achieved_tf / PEAK_TFLOPS[mdt], 5), "traffic": traffic,
             "traffic_note": (None if crec is None else crec.get("note")),
