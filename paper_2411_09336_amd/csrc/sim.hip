@@ -25,10 +25,12 @@
 //
 // Register layout of the Jacobi matrix M (<= 128 x 128 complex): wave w of
 // 16 owns rows 8w .. 8w+7; lane l owns column positions 2l and 2l+1 (slots A
-// and B), so every rotation pair is local to a lane.  Each round the partial
-// inner products of the 16 waves are reduced through LDS, rotations are
-// applied, and the columns move one step along the round-robin (circle)
-// ordering, so n-1 rounds visit every pair once per sweep.
+// and B).  Rounds alternate between pairs inside a lane and pairs across
+// neighbouring lanes (odd-even transposition ordering, each pair exchanged
+// after its rotation), so n rounds visit every pair once per sweep and the
+// only data movement is one DPP lane shift each way in every second round.
+// Each round the partial inner products of the 16 waves go through LDS to
+// four waves that form the rotation parameters, which all waves then apply.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -79,26 +81,20 @@ struct SvParams {
   int64_t n;
 };
 
-// DPP wave shifts of a double: shr1 gives lane l the value of lane l-1, shl1
-// the value of lane l+1; lanes without a source keep their own value.
-__device__ inline double dpp_shr1(double x) {
-  const int lo = __double2loint(x), hi = __double2hiint(x);
-  return __hiloint2double(__builtin_amdgcn_update_dpp(hi, hi, 0x138, 0xf, 0xf, false),
-                          __builtin_amdgcn_update_dpp(lo, lo, 0x138, 0xf, 0xf, false));
-}
-__device__ inline double dpp_shl1(double x) {
-  const int lo = __double2loint(x), hi = __double2hiint(x);
-  return __hiloint2double(__builtin_amdgcn_update_dpp(hi, hi, 0x130, 0xf, 0xf, false),
-                          __builtin_amdgcn_update_dpp(lo, lo, 0x130, 0xf, 0xf, false));
-}
-
-// Sum over the 16 lanes of a DPP row (all 16 lanes receive the total).
+// DPP lane moves of a double.  Lanes without a source lane receive zero
+// (bound_ctrl), so no copy of the source is needed as the fallback value.
 template <int CTRL>
 __device__ inline double dpp_mov(double x) {
   const int lo = __double2loint(x), hi = __double2hiint(x);
-  return __hiloint2double(__builtin_amdgcn_update_dpp(hi, hi, CTRL, 0xf, 0xf, false),
-                          __builtin_amdgcn_update_dpp(lo, lo, CTRL, 0xf, 0xf, false));
+  return __hiloint2double(__builtin_amdgcn_mov_dpp(hi, CTRL, 0xf, 0xf, true),
+                          __builtin_amdgcn_mov_dpp(lo, CTRL, 0xf, 0xf, true));
 }
+// shr1: lane l receives lane l-1 (lane 0: zero); shl1: lane l receives lane
+// l+1 (lane 63: zero)
+__device__ inline double dpp_shr1(double x) { return dpp_mov<0x138>(x); }
+__device__ inline double dpp_shl1(double x) { return dpp_mov<0x130>(x); }
+
+// Sum over the 16 lanes of a DPP row (all 16 lanes receive the total).
 __device__ inline double row_sum16(double x) {
   x += dpp_mov<0x128>(x);   // row_ror:8
   x += dpp_mov<0x124>(x);   // row_ror:4
@@ -139,6 +135,111 @@ __device__ inline double2 theta_elem(const SvParams &P, const double2 *Ap, const
   return pair_prod(Ap, Aq, Pp, Pm, Pn, Dm, s, a, t, b);
 }
 
+struct JacobiShared {
+  double2 (*red)[kSvWaves][64];  // [0]: (|X|^2, |Y|^2), [1]: <X, Y>; per wave and lane
+  double (*upd)[64][8];          // per round type and lane: pa, wa, -, -, pb, wb, -, -
+};
+
+// Sum over the 4 lanes of a DPP quad (every lane receives the same total).
+__device__ inline double quad_sum(double x) {
+  x += dpp_mov<0xB1>(x);   // quad_perm [1,0,3,2]
+  x += dpp_mov<0x4E>(x);   // quad_perm [2,3,0,1]
+  return x;
+}
+
+// One round of the parallel Jacobi sweep.  The pair of a lane is (X, Y) =
+// (A, B) for TYPE 0 and (B_l, A_{l+1}) for TYPE 1.  Its rotation
+// X' = c X - s u Y, Y' = s X + c u Y (u = conj<X,Y> / |<X,Y>|, the
+// Hermitian 2x2 Jacobi rotation of the Gram block of the pair) zeroes
+// <X', Y'>; the outputs are stored exchanged, Y' in the slot of X and X' in
+// the slot of Y.  Every lane then forms A' = pa P + wa Q, B' = pb R + wb S
+// with (P, Q, R, S) = (A, B, A, B) for TYPE 0 and (B_{l-1}, A, B, A_{l+1})
+// for TYPE 1.  Returns whether this wave rotated some pair.
+template <int TYPE>
+__device__ __forceinline__ bool jacobi_round(double (&Ar)[kSvRows], double (&Ai)[kSvRows], double (&Br)[kSvRows],
+                                             double (&Bi)[kSvRows], const JacobiShared &sh, int wave, int lane,
+                                             int H, double zero_w) {
+  // A_{l+1} is shifted in where it is used (once for the inner products and
+  // once for the update) rather than held across the barriers
+  {
+    double al = 0.0, be = 0.0, gr = 0.0, gi = 0.0;
+#pragma unroll
+    for (int rr = 0; rr < kSvRows; ++rr) {
+      const double xr = TYPE == 0 ? Ar[rr] : Br[rr], xi = TYPE == 0 ? Ai[rr] : Bi[rr];
+      const double yr = TYPE == 0 ? Br[rr] : dpp_shl1(Ar[rr]), yi = TYPE == 0 ? Bi[rr] : dpp_shl1(Ai[rr]);
+      al = fma(xr, xr, fma(xi, xi, al));
+      be = fma(yr, yr, fma(yi, yi, be));
+      gr = fma(xr, yr, fma(xi, yi, gr));
+      gi = fma(xr, yi, fma(-xi, yr, gi));
+    }
+    sh.red[0][wave][lane] = make_double2(al, be);
+    sh.red[1][wave][lane] = make_double2(gr, gi);
+  }
+  __syncthreads();
+  // rotation parameters: waves 0..3, lane = 4 j + q sums the partials of
+  // pair 16 wave + j over waves 4q..4q+3, then over the quad
+  const int npairs = TYPE == 0 ? H : H - 1;
+  bool rotated = false;
+  if (wave < 4 && 16 * wave < npairs) {
+    const int j = lane >> 2, q = lane & 3, pr = 16 * wave + j;
+    double a = 0.0, b = 0.0, x = 0.0, y = 0.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const double2 n = sh.red[0][4 * q + u][pr], g = sh.red[1][4 * q + u][pr];
+      a += n.x;
+      b += n.y;
+      x += g.x;
+      y += g.y;
+    }
+    a = quad_sum(a);
+    b = quad_sum(b);
+    x = quad_sum(x);
+    y = quad_sum(y);
+    const double g2 = fma(x, x, y * y);
+    const bool rot = pr < npairs && a > zero_w && b > zero_w && g2 > (kJacobiTol * kJacobiTol) * (a * b);
+    rotated = __any(rot);
+    if (pr < npairs && q < 2) {
+      double c = 1.0, s = 0.0, ur = 1.0, ui = 0.0;
+      if (rot) {
+        const double rg = 1.0 / sqrt(g2);
+        const double zeta = 0.5 * (b - a) * rg;
+        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(fma(zeta, zeta, 1.0)));
+        c = 1.0 / sqrt(fma(t, t, 1.0));
+        s = c * t;
+        ur = x * rg;
+        ui = -y * rg;
+      }
+      // q == 0 stores Y' = s X + (c u) Y, q == 1 stores X' = c X - (s u) Y
+      const double p0 = q == 0 ? s : c, w = q == 0 ? c : -s;
+      const int slot_lane = (TYPE == 1 && q == 1) ? pr + 1 : pr;
+      const int slot = (TYPE == 0) == (q == 0) ? 0 : 4;
+      double *o = sh.upd[TYPE][slot_lane] + slot;
+      o[0] = p0;
+      o[1] = w * ur;
+      o[2] = w * ui;
+    }
+  }
+  __syncthreads();
+  const double *up = sh.upd[TYPE][lane];
+  const double pa = up[0], war = up[1], wai = up[2], pb = up[4], wbr = up[5], wbi = up[6];
+#pragma unroll
+  for (int rr = 0; rr < kSvRows; ++rr) {
+    double pr_, pi_, qr, qi, rr_, ri, sr, si;
+    if (TYPE == 0) {
+      pr_ = Ar[rr]; pi_ = Ai[rr]; qr = Br[rr]; qi = Bi[rr];
+      rr_ = Ar[rr]; ri = Ai[rr]; sr = Br[rr]; si = Bi[rr];
+    } else {
+      pr_ = dpp_shr1(Br[rr]); pi_ = dpp_shr1(Bi[rr]); qr = Ar[rr]; qi = Ai[rr];
+      rr_ = Br[rr]; ri = Bi[rr]; sr = dpp_shl1(Ar[rr]); si = dpp_shl1(Ai[rr]);
+    }
+    Ar[rr] = fma(pa, pr_, fma(war, qr, -wai * qi));
+    Ai[rr] = fma(pa, pi_, fma(war, qi, wai * qr));
+    Br[rr] = fma(pb, rr_, fma(wbr, sr, -wbi * si));
+    Bi[rr] = fma(pb, ri, fma(wbr, si, wbi * sr));
+  }
+  return rotated;
+}
+
 __global__ __launch_bounds__(kSvThreads) void svd_step_kernel(SvParams P) {
   const int64_t ci = blockIdx.x;
   if (ci >= P.n) return;
@@ -146,7 +247,8 @@ __global__ __launch_bounds__(kSvThreads) void svd_step_kernel(SvParams P) {
 
   // partial sums [component][wave][pair], rows padded to 65 (bank spread)
   __shared__ double s_part[4][kSvWaves][65];
-  __shared__ double s_par[64][4];
+  __shared__ double2 s_red[2][kSvWaves][64];
+  __shared__ double s_upd[2][64][8];
   __shared__ double s_norm[kSvMaxN];
   __shared__ double s_sorted[kSvMaxN];
   __shared__ int s_rank[kSvMaxN];
@@ -244,83 +346,37 @@ __global__ __launch_bounds__(kSvThreads) void svd_step_kernel(SvParams P) {
   __syncthreads();
 
   // ---------------------------------------------------------- Jacobi sweeps
+  // Odd-even transposition ordering of the positions 0..NP-1 (A_l = 2l,
+  // B_l = 2l+1): type-0 rounds pair (A_l, B_l) inside each lane, type-1
+  // rounds pair (B_l, A_{l+1}) across neighbouring lanes, and each pair is
+  // exchanged after its rotation, so every two columns meet exactly once in
+  // the NP rounds of a sweep.  Lanes >= H hold empty positions and keep them.
+  for (int e = tid; e < 2 * 64; e += kSvThreads) {
+    // identity updates (slots that no pair of the round writes)
+    const int type = e >> 6;
+    double *u = s_upd[type][e & 63];
+    u[0] = type == 0 ? 1.0 : 0.0;  // A' = pa P + wa Q
+    u[1] = type == 0 ? 0.0 : 1.0;
+    u[2] = 0.0;
+    u[3] = 0.0;
+    u[4] = type == 0 ? 0.0 : 1.0;  // B' = pb R + wb S
+    u[5] = type == 0 ? 1.0 : 0.0;
+    u[6] = 0.0;
+    u[7] = 0.0;
+  }
+  __syncthreads();
   const int NP = (nc + (nc & 1)) < 2 ? 2 : (nc + (nc & 1));
   const int H = NP / 2;
+  const JacobiShared sh{s_red, s_upd};
   bool converged = false;
   int sweep = 0;
   for (; sweep < kMaxSweeps && !converged; ++sweep) {
-    for (int round = 0; round < NP - 1; ++round) {
-      double al = 0.0, be = 0.0, gr = 0.0, gi = 0.0;
-#pragma unroll
-      for (int rr = 0; rr < kSvRows; ++rr) {
-        al = fma(Ar[rr], Ar[rr], fma(Ai[rr], Ai[rr], al));
-        be = fma(Br[rr], Br[rr], fma(Bi[rr], Bi[rr], be));
-        gr = fma(Ar[rr], Br[rr], fma(Ai[rr], Bi[rr], gr));
-        gi = fma(Ar[rr], Bi[rr], fma(-Ai[rr], Br[rr], gi));
-      }
-      s_part[0][wave][lane] = al;
-      s_part[1][wave][lane] = be;
-      s_part[2][wave][lane] = gr;
-      s_part[3][wave][lane] = gi;
-      __syncthreads();
-      {
-        const int pr = tid >> 4, w = tid & 15;
-        const double a = row_sum16(s_part[0][w][pr]), b = row_sum16(s_part[1][w][pr]);
-        const double x = row_sum16(s_part[2][w][pr]), y = row_sum16(s_part[3][w][pr]);
-        if (w == 0 && pr < H) {
-          double c = 1.0, s = 0.0, ur = 1.0, ui = 0.0;
-          const double gabs = sqrt(x * x + y * y);
-          if (a > zero_w && b > zero_w && gabs > kJacobiTol * sqrt(a) * sqrt(b)) {
-            const double zeta = (b - a) / (2.0 * gabs);
-            const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-            c = 1.0 / sqrt(1.0 + t * t);
-            s = c * t;
-            ur = x / gabs;   // u = conj(gamma) / |gamma|
-            ui = -y / gabs;
-            s_flag[sweep & 1] = 1;
-          }
-          s_par[pr][0] = c;
-          s_par[pr][1] = s;
-          s_par[pr][2] = ur;
-          s_par[pr][3] = ui;
-        }
-        if (round == 0 && tid == 0) s_flag[(sweep + 1) & 1] = 0;
-      }
-      __syncthreads();
-      if (round == NP - 2) converged = (s_flag[sweep & 1] == 0);
-      if (lane < H) {
-        const double c = s_par[lane][0], s = s_par[lane][1], ur = s_par[lane][2], ui = s_par[lane][3];
-#pragma unroll
-        for (int rr = 0; rr < kSvRows; ++rr) {
-          // uB = u * B ; A' = c A - s uB ; B' = s A + c uB
-          const double ubr = ur * Br[rr] - ui * Bi[rr];
-          const double ubi = ur * Bi[rr] + ui * Br[rr];
-          const double nar = c * Ar[rr] - s * ubr, nai = c * Ai[rr] - s * ubi;
-          const double nbr = s * Ar[rr] + c * ubr, nbi = s * Ai[rr] + c * ubi;
-          Ar[rr] = nar;
-          Ai[rr] = nai;
-          Br[rr] = nbr;
-          Bi[rr] = nbi;
-        }
-      }
-      // circle ordering: A_1 -> A_2 -> ... -> A_{H-1} -> B_{H-1} -> ... -> B_0 -> A_1
-      // (A_0 fixed); lanes >= H hold empty positions and keep them.
-      if (H > 1) {
-#pragma unroll
-        for (int rr = 0; rr < kSvRows; ++rr) {
-          const double sAr = dpp_shr1(Ar[rr]), sAi = dpp_shr1(Ai[rr]);
-          const double sBr = dpp_shr1(Br[rr]), sBi = dpp_shr1(Bi[rr]);
-          const double lBr = dpp_shl1(Br[rr]), lBi = dpp_shl1(Bi[rr]);
-          if (lane < H) {
-            const double oar = Ar[rr], oai = Ai[rr];
-            if (lane == 1) { Ar[rr] = sBr; Ai[rr] = sBi; }
-            else if (lane > 1) { Ar[rr] = sAr; Ai[rr] = sAi; }
-            if (lane == H - 1) { Br[rr] = oar; Bi[rr] = oai; }
-            else { Br[rr] = lBr; Bi[rr] = lBi; }
-          }
-        }
-      }
+    bool rotated = false;  // wave-uniform
+    for (int half = 0; half < H; ++half) {
+      rotated |= jacobi_round<0>(Ar, Ai, Br, Bi, sh, wave, lane, H, zero_w);
+      if (H > 1) rotated |= jacobi_round<1>(Ar, Ai, Br, Bi, sh, wave, lane, H, zero_w);
     }
+    converged = __syncthreads_or(rotated ? 1 : 0) == 0;
   }
 
   // ---------------------------------------------------------- norms, order, k
