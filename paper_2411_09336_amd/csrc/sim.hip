@@ -138,6 +138,7 @@ __device__ inline double2 theta_elem(const SvParams &P, const double2 *Ap, const
 struct JacobiShared {
   double2 (*red)[kSvWaves][64];  // [0]: (|X|^2, |Y|^2), [1]: <X, Y>; per wave and lane
   double (*upd)[64][8];          // per round type and lane: pa, wa, -, -, pb, wb, -, -
+  double *w;                     // squared norm of the column at each position
 };
 
 // Sum over the 4 lanes of a DPP quad (every lane receives the same total).
@@ -155,7 +156,13 @@ __device__ inline double quad_sum(double x) {
 // the slot of Y.  Every lane then forms A' = pa P + wa Q, B' = pb R + wb S
 // with (P, Q, R, S) = (A, B, A, B) for TYPE 0 and (B_{l-1}, A, B, A_{l+1})
 // for TYPE 1.  Returns whether this wave rotated some pair.
-template <int TYPE>
+//
+// Column norms: a FULL round reduces |X|^2 and |Y|^2 with <X, Y> and stores
+// them; the other rounds reduce <X, Y> only and update the stored norms by
+// |X'|^2 = |X|^2 - t |<X,Y>|, |Y'|^2 = |Y|^2 + t |<X,Y>| (t = s / c), which
+// holds exactly for the rotation above.  The first round of every sweep is
+// FULL, so rounding in the updates never outlives a sweep.
+template <int TYPE, bool FULL>
 __device__ __forceinline__ bool jacobi_round(double (&Ar)[kSvRows], double (&Ai)[kSvRows], double (&Br)[kSvRows],
                                              double (&Bi)[kSvRows], const JacobiShared &sh, int wave, int lane,
                                              int H, double zero_w) {
@@ -167,12 +174,14 @@ __device__ __forceinline__ bool jacobi_round(double (&Ar)[kSvRows], double (&Ai)
     for (int rr = 0; rr < kSvRows; ++rr) {
       const double xr = TYPE == 0 ? Ar[rr] : Br[rr], xi = TYPE == 0 ? Ai[rr] : Bi[rr];
       const double yr = TYPE == 0 ? Br[rr] : dpp_shl1(Ar[rr]), yi = TYPE == 0 ? Bi[rr] : dpp_shl1(Ai[rr]);
-      al = fma(xr, xr, fma(xi, xi, al));
-      be = fma(yr, yr, fma(yi, yi, be));
+      if (FULL) {
+        al = fma(xr, xr, fma(xi, xi, al));
+        be = fma(yr, yr, fma(yi, yi, be));
+      }
       gr = fma(xr, yr, fma(xi, yi, gr));
       gi = fma(xr, yi, fma(-xi, yr, gi));
     }
-    sh.red[0][wave][lane] = make_double2(al, be);
+    if (FULL) sh.red[0][wave][lane] = make_double2(al, be);
     sh.red[1][wave][lane] = make_double2(gr, gi);
   }
   __syncthreads();
@@ -182,24 +191,34 @@ __device__ __forceinline__ bool jacobi_round(double (&Ar)[kSvRows], double (&Ai)
   bool rotated = false;
   if (wave < 4 && 16 * wave < npairs) {
     const int j = lane >> 2, q = lane & 3, pr = 16 * wave + j;
+    // positions of X and Y
+    const int px = TYPE == 0 ? 2 * pr : 2 * pr + 1, py = px + 1;
     double a = 0.0, b = 0.0, x = 0.0, y = 0.0;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const double2 n = sh.red[0][4 * q + u][pr], g = sh.red[1][4 * q + u][pr];
-      a += n.x;
-      b += n.y;
+      if (FULL) {
+        const double2 n = sh.red[0][4 * q + u][pr];
+        a += n.x;
+        b += n.y;
+      }
+      const double2 g = sh.red[1][4 * q + u][pr];
       x += g.x;
       y += g.y;
     }
-    a = quad_sum(a);
-    b = quad_sum(b);
+    if (FULL) {
+      a = quad_sum(a);
+      b = quad_sum(b);
+    } else {
+      a = sh.w[px];
+      b = sh.w[py];
+    }
     x = quad_sum(x);
     y = quad_sum(y);
     const double g2 = fma(x, x, y * y);
     const bool rot = pr < npairs && a > zero_w && b > zero_w && g2 > (kJacobiTol * kJacobiTol) * (a * b);
     rotated = __any(rot);
     if (pr < npairs && q < 2) {
-      double c = 1.0, s = 0.0, ur = 1.0, ui = 0.0;
+      double c = 1.0, s = 0.0, ur = 1.0, ui = 0.0, tg = 0.0;
       if (rot) {
         const double rg = 1.0 / sqrt(g2);
         const double zeta = 0.5 * (b - a) * rg;
@@ -208,7 +227,11 @@ __device__ __forceinline__ bool jacobi_round(double (&Ar)[kSvRows], double (&Ai)
         s = c * t;
         ur = x * rg;
         ui = -y * rg;
+        tg = t * (g2 * rg);
       }
+      // exchanged: the slot of X receives |Y'|^2, the slot of Y |X'|^2
+      if (q == 0) sh.w[px] = b + tg;
+      else sh.w[py] = fmax(a - tg, 0.0);
       // q == 0 stores Y' = s X + (c u) Y, q == 1 stores X' = c X - (s u) Y
       const double p0 = q == 0 ? s : c, w = q == 0 ? c : -s;
       const int slot_lane = (TYPE == 1 && q == 1) ? pr + 1 : pr;
@@ -236,6 +259,9 @@ __device__ __forceinline__ bool jacobi_round(double (&Ar)[kSvRows], double (&Ai)
     Ai[rr] = fma(pa, pi_, fma(war, qi, wai * qr));
     Br[rr] = fma(pb, rr_, fma(wbr, sr, -wbi * si));
     Bi[rr] = fma(pb, ri, fma(wbr, si, wbi * sr));
+    // one row at a time: hoisting the lane shifts of later rows would need
+    // more registers than a wave of this 1024-thread block has
+    if (TYPE == 1) __builtin_amdgcn_sched_barrier(0);
   }
   return rotated;
 }
@@ -249,10 +275,10 @@ __global__ __launch_bounds__(kSvThreads) void svd_step_kernel(SvParams P) {
   __shared__ double s_part[4][kSvWaves][65];
   __shared__ double2 s_red[2][kSvWaves][64];
   __shared__ double s_upd[2][64][8];
+  __shared__ double s_w[kSvMaxN];
   __shared__ double s_norm[kSvMaxN];
   __shared__ double s_sorted[kSvMaxN];
   __shared__ int s_rank[kSvMaxN];
-  __shared__ int s_flag[2];
   __shared__ int s_k;
   __shared__ double s_nrm;
 
@@ -322,10 +348,6 @@ __global__ __launch_bounds__(kSvThreads) void svd_step_kernel(SvParams P) {
     Br[rr] = vb.x;
     Bi[rr] = vb.y;
   }
-  if (tid == 0) {
-    s_flag[0] = 0;
-    s_flag[1] = 0;
-  }
   // ||M||_F^2 (invariant under the rotations)
   {
     double w = 0.0;
@@ -367,14 +389,15 @@ __global__ __launch_bounds__(kSvThreads) void svd_step_kernel(SvParams P) {
   __syncthreads();
   const int NP = (nc + (nc & 1)) < 2 ? 2 : (nc + (nc & 1));
   const int H = NP / 2;
-  const JacobiShared sh{s_red, s_upd};
+  const JacobiShared sh{s_red, s_upd, s_w};
   bool converged = false;
   int sweep = 0;
   for (; sweep < kMaxSweeps && !converged; ++sweep) {
-    bool rotated = false;  // wave-uniform
-    for (int half = 0; half < H; ++half) {
-      rotated |= jacobi_round<0>(Ar, Ai, Br, Bi, sh, wave, lane, H, zero_w);
-      if (H > 1) rotated |= jacobi_round<1>(Ar, Ai, Br, Bi, sh, wave, lane, H, zero_w);
+    bool rotated = jacobi_round<0, true>(Ar, Ai, Br, Bi, sh, wave, lane, H, zero_w);  // wave-uniform
+    if (H > 1) rotated |= jacobi_round<1, false>(Ar, Ai, Br, Bi, sh, wave, lane, H, zero_w);
+    for (int half = 1; half < H; ++half) {
+      rotated |= jacobi_round<0, false>(Ar, Ai, Br, Bi, sh, wave, lane, H, zero_w);
+      rotated |= jacobi_round<1, false>(Ar, Ai, Br, Bi, sh, wave, lane, H, zero_w);
     }
     converged = __syncthreads_or(rotated ? 1 : 0) == 0;
   }
