@@ -108,31 +108,68 @@ __device__ inline double2 cmul(double2 a, double2 b) {
 }
 __device__ inline double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
 
-// P(s', t')[a][b] = sum_c A_p[s'][a][c] A_{p+1}[t'][c][b]
-__device__ inline double2 pair_prod(const double2 *Ap, const double2 *Aq, int Pp, int Pm, int Pn, int Dm,
-                                    int s1, int a, int t1, int b) {
-  double re = 0.0, im = 0.0;
-  const double2 *x = Ap + (size_t(s1) * Pp + a) * Pm;
-  const double2 *y = Aq + size_t(t1) * Pm * Pn + b;
-  for (int c = 0; c < Dm; ++c) {
-    const double2 u = x[c], v = y[size_t(c) * Pn];
-    re = fma(u.x, v.x, fma(-u.y, v.y, re));
-    im = fma(u.x, v.y, fma(u.y, v.x, im));
+constexpr int kKC = 16;  // contraction chunk of the pair product staged in LDS
+
+// Pair product of the two sites, the two-site tensor before the gate
+// (Fig. 1b): P[(s', a)][(t', b)] = sum_c A_p[s'][a][c] A_{p+1}[t'][c][b],
+// rows y = s' Dp + a, columns x = t' Dn + b.  Thread (wave w, lane l) forms
+// rows 8w .. 8w+7 and columns 2l, 2l+1 (zero outside 2 Dp x 2 Dn); chunks
+// of kKC contraction indices of both sites are staged in LDS, the row
+// operand read by the whole wave at one address.
+__device__ inline void pair_product_tile(const double2 *Ap, const double2 *Aq, int Dp, int Dm, int Dn, int Pp,
+                                         int Pm, int Pn, double2 (*sL)[kSvMaxN], double2 (*sR)[kSvMaxN],
+                                         double2 (&acc)[kSvRows][2]) {
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+#pragma unroll
+  for (int rr = 0; rr < kSvRows; ++rr) {
+    acc[rr][0] = make_double2(0.0, 0.0);
+    acc[rr][1] = make_double2(0.0, 0.0);
   }
-  return make_double2(re, im);
+  for (int k0 = 0; k0 < Dm; k0 += kKC) {
+    __syncthreads();  // the previous chunk is consumed
+    for (int e = tid; e < kKC * kSvMaxN; e += kSvThreads) {
+      {
+        // consecutive threads walk the contraction index of one row of A_p
+        const int kk = e % kKC, y = e / kKC;
+        double2 v = make_double2(0.0, 0.0);
+        if (y < 2 * Dp && k0 + kk < Dm) v = Ap[(size_t(y / Dp) * Pp + y % Dp) * Pm + k0 + kk];
+        sL[kk][y] = v;
+      }
+      {
+        const int x = e % kSvMaxN, kk = e / kSvMaxN;
+        double2 v = make_double2(0.0, 0.0);
+        if (x < 2 * Dn && k0 + kk < Dm) v = Aq[(size_t(x / Dn) * Pm + k0 + kk) * Pn + x % Dn];
+        sR[kk][x] = v;
+      }
+    }
+    __syncthreads();
+    const int kc = min(kKC, Dm - k0);
+    for (int kk = 0; kk < kc; ++kk) {
+      const double2 r0 = sR[kk][2 * lane], r1 = sR[kk][2 * lane + 1];
+#pragma unroll
+      for (int rr = 0; rr < kSvRows; ++rr) {
+        const double2 l = sL[kk][wave * kSvRows + rr];
+        acc[rr][0].x = fma(l.x, r0.x, fma(-l.y, r0.y, acc[rr][0].x));
+        acc[rr][0].y = fma(l.x, r0.y, fma(l.y, r0.x, acc[rr][0].y));
+        acc[rr][1].x = fma(l.x, r1.x, fma(-l.y, r1.y, acc[rr][1].x));
+        acc[rr][1].y = fma(l.x, r1.y, fma(l.y, r1.x, acc[rr][1].y));
+      }
+    }
+  }
 }
 
-// Two-site theta element for the gate of this step (identity for moves).
-__device__ inline double2 theta_elem(const SvParams &P, const double2 *Ap, const double2 *Aq, int Pp, int Pm,
-                                     int Pn, int Dm, double cg, double sg, int s, int a, int t, int b) {
-  if (P.op == OP_SWAP) return pair_prod(Ap, Aq, Pp, Pm, Pn, Dm, t, a, s, b);
-  if (P.op == OP_RXX) {
+// Two-site theta element theta[(s, a), (t, b)] of this step's gate from the
+// pair product P (row stride kSvMaxN).
+__device__ inline double2 theta_from_pair(const double2 *Pp2, int op, double cg, double sg, int Dp, int Dn, int s,
+                                          int a, int t, int b) {
+  if (op == OP_SWAP) return Pp2[(t * Dp + a) * kSvMaxN + s * Dn + b];
+  const double2 d = Pp2[(s * Dp + a) * kSvMaxN + t * Dn + b];
+  if (op == OP_RXX) {
     // Rxx = cos(phi/2) I - i sin(phi/2) X(x)X
-    const double2 d = pair_prod(Ap, Aq, Pp, Pm, Pn, Dm, s, a, t, b);
-    const double2 x = pair_prod(Ap, Aq, Pp, Pm, Pn, Dm, 1 - s, a, 1 - t, b);
+    const double2 x = Pp2[((1 - s) * Dp + a) * kSvMaxN + (1 - t) * Dn + b];
     return make_double2(cg * d.x + sg * x.y, cg * d.y - sg * x.x);
   }
-  return pair_prod(Ap, Aq, Pp, Pm, Pn, Dm, s, a, t, b);
+  return d;
 }
 
 struct JacobiShared {
@@ -271,9 +308,20 @@ __global__ __launch_bounds__(kSvThreads) void svd_step_kernel(SvParams P) {
   if (ci >= P.n) return;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
 
-  // partial sums [component][wave][pair], rows padded to 65 (bank spread)
-  __shared__ double s_part[4][kSvWaves][65];
-  __shared__ double2 s_red[2][kSvWaves][64];
+  // the pair-product staging is dead once the Jacobi matrix is built; the
+  // reduction buffers are used from then on
+  __shared__ union {
+    struct {
+      double2 L[kKC][kSvMaxN];
+      double2 R[kKC][kSvMaxN];
+    } stage;
+    struct {
+      double part[4][kSvWaves][65];  // [component][wave][pair], rows padded (bank spread)
+      double2 red[2][kSvWaves][64];
+    } jac;
+  } s_u;
+  auto &s_part = s_u.jac.part;
+  auto &s_red = s_u.jac.red;
   __shared__ double s_upd[2][64][8];
   __shared__ double s_w[kSvMaxN];
   __shared__ double s_norm[kSvMaxN];
@@ -308,34 +356,43 @@ __global__ __launch_bounds__(kSvThreads) void svd_step_kernel(SvParams P) {
 
   // ---------------------------------------------------------- build M
   // M (Jacobi matrix) goes to scratch region SM, the projection source to S;
-  // for gates they coincide.
+  // for gates they coincide and the pair product is kept in region 2.
   double2 *SM = gate ? S : S + kSvMaxN * kSvMaxN;
-  for (int e = tid; e < nr * nc; e += kSvThreads) {
-    const int r = e / nc, c = e % nc;
-    double2 v;
-    if (P.mode == GATE_RIGHT)
-      v = theta_elem(P, Ap, Aq, Pp, Pm, Pn, Dm, cg, sg, r / Dp, r % Dp, c / Dn, c % Dn);
-    else if (P.mode == GATE_LEFT)
-      v = cconj(theta_elem(P, Ap, Aq, Pp, Pm, Pn, Dm, cg, sg, c / Dp, c % Dp, r / Dn, r % Dn));
-    else if (P.mode == MOVE_RIGHT)
-      v = Ap[(size_t(r / Dp) * Pp + r % Dp) * Pm + c];
-    else
-      v = cconj(Aq[(size_t(r / Dn) * Pm + c) * Pn + r % Dn]);
-    SM[r * kSvMaxN + c] = v;
+  {
+    double2 pt[kSvRows][2];
+    pair_product_tile(Ap, Aq, Dp, Dm, Dn, Pp, Pm, Pn, s_u.stage.L, s_u.stage.R, pt);
+    double2 *P2 = S + kSvMaxN * kSvMaxN;
+#pragma unroll
+    for (int rr = 0; rr < kSvRows; ++rr)
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int y = wave * kSvRows + rr, x = 2 * lane + q;
+        if (y < 2 * Dp && x < 2 * Dn) {
+          if (gate) P2[y * kSvMaxN + x] = pt[rr][q];
+          else if (P.mode == MOVE_RIGHT) S[y * kSvMaxN + x] = pt[rr][q];   // identity theta
+          else S[x * kSvMaxN + y] = cconj(pt[rr][q]);                        // its adjoint
+        }
+      }
   }
   if (!gate) {
-    // identity two-site theta (or its adjoint) as the projection source
-    for (int e = tid; e < nr * ncs; e += kSvThreads) {
-      const int y = e / ncs, x = e % ncs;
-      double2 v;
-      if (P.mode == MOVE_RIGHT)
-        v = pair_prod(Ap, Aq, Pp, Pm, Pn, Dm, y / Dp, y % Dp, x / Dn, x % Dn);
-      else
-        v = cconj(pair_prod(Ap, Aq, Pp, Pm, Pn, Dm, x / Dp, x % Dp, y / Dn, y % Dn));
-      S[y * kSvMaxN + x] = v;
+    // the site being orthogonalised, as a matrix
+    for (int e = tid; e < nr * nc; e += kSvThreads) {
+      const int r = e / nc, c = e % nc;
+      SM[r * kSvMaxN + c] = P.mode == MOVE_RIGHT ? Ap[(size_t(r / Dp) * Pp + r % Dp) * Pm + c]
+                                                 : cconj(Aq[(size_t(r / Dn) * Pm + c) * Pn + r % Dn]);
     }
   }
   __syncthreads();
+  if (gate) {
+    const double2 *P2 = S + kSvMaxN * kSvMaxN;
+    for (int e = tid; e < nr * nc; e += kSvThreads) {
+      const int r = e / nc, c = e % nc;
+      SM[r * kSvMaxN + c] = P.mode == GATE_RIGHT
+                                ? theta_from_pair(P2, P.op, cg, sg, Dp, Dn, r / Dp, r % Dp, c / Dn, c % Dn)
+                                : cconj(theta_from_pair(P2, P.op, cg, sg, Dp, Dn, c / Dp, c % Dp, r / Dn, r % Dn));
+    }
+    __syncthreads();
+  }
   double Ar[kSvRows], Ai[kSvRows], Br[kSvRows], Bi[kSvRows];
 #pragma unroll
   for (int rr = 0; rr < kSvRows; ++rr) {
