@@ -110,45 +110,39 @@ __device__ inline double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
 
 constexpr int kKC = 16;  // contraction chunk of the pair product staged in LDS
 
-// Pair product of the two sites, the two-site tensor before the gate
-// (Fig. 1b): P[(s', a)][(t', b)] = sum_c A_p[s'][a][c] A_{p+1}[t'][c][b],
-// rows y = s' Dp + a, columns x = t' Dn + b.  Thread (wave w, lane l) forms
-// rows 8w .. 8w+7 and columns 2l, 2l+1 (zero outside 2 Dp x 2 Dn); chunks
-// of kKC contraction indices of both sites are staged in LDS, the row
-// operand read by the whole wave at one address.
-__device__ inline void pair_product_tile(const double2 *Ap, const double2 *Aq, int Dp, int Dm, int Dn, int Pp,
-                                         int Pm, int Pn, double2 (*sL)[kSvMaxN], double2 (*sR)[kSvMaxN],
-                                         double2 (&acc)[kSvRows][2]) {
+// Block-wide complex product acc[rr][q] = sum_{k < K} L(y, k) R(k, x) with
+// y = ROWS w + rr (wave w) and x = 2 l + q (lane l); ldL / ldR return the
+// operands (zero outside the matrices).  Chunks of kKC contraction indices
+// of both operands are staged in LDS; the row operand is read by the whole
+// wave at one address.
+template <int ROWS, class FL, class FR>
+__device__ inline void staged_tile_gemm(int K, const FL &ldL, const FR &ldR, double2 (*sL)[kSvMaxN],
+                                        double2 (*sR)[kSvMaxN], double2 (&acc)[ROWS][2]) {
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  constexpr int kRowsAll = ROWS * kSvWaves;
 #pragma unroll
-  for (int rr = 0; rr < kSvRows; ++rr) {
+  for (int rr = 0; rr < ROWS; ++rr) {
     acc[rr][0] = make_double2(0.0, 0.0);
     acc[rr][1] = make_double2(0.0, 0.0);
   }
-  for (int k0 = 0; k0 < Dm; k0 += kKC) {
-    __syncthreads();  // the previous chunk is consumed
+  for (int k0 = 0; k0 < K; k0 += kKC) {
+    __syncthreads();  // the previous chunk (or earlier use of the buffers) is done
+    for (int e = tid; e < kKC * kRowsAll; e += kSvThreads) {
+      // consecutive threads walk the contraction index of one row
+      const int kk = e % kKC, y = e / kKC;
+      sL[kk][y] = k0 + kk < K ? ldL(y, k0 + kk) : make_double2(0.0, 0.0);
+    }
     for (int e = tid; e < kKC * kSvMaxN; e += kSvThreads) {
-      {
-        // consecutive threads walk the contraction index of one row of A_p
-        const int kk = e % kKC, y = e / kKC;
-        double2 v = make_double2(0.0, 0.0);
-        if (y < 2 * Dp && k0 + kk < Dm) v = Ap[(size_t(y / Dp) * Pp + y % Dp) * Pm + k0 + kk];
-        sL[kk][y] = v;
-      }
-      {
-        const int x = e % kSvMaxN, kk = e / kSvMaxN;
-        double2 v = make_double2(0.0, 0.0);
-        if (x < 2 * Dn && k0 + kk < Dm) v = Aq[(size_t(x / Dn) * Pm + k0 + kk) * Pn + x % Dn];
-        sR[kk][x] = v;
-      }
+      const int x = e % kSvMaxN, kk = e / kSvMaxN;
+      sR[kk][x] = k0 + kk < K ? ldR(k0 + kk, x) : make_double2(0.0, 0.0);
     }
     __syncthreads();
-    const int kc = min(kKC, Dm - k0);
+    const int kc = min(kKC, K - k0);
     for (int kk = 0; kk < kc; ++kk) {
       const double2 r0 = sR[kk][2 * lane], r1 = sR[kk][2 * lane + 1];
 #pragma unroll
-      for (int rr = 0; rr < kSvRows; ++rr) {
-        const double2 l = sL[kk][wave * kSvRows + rr];
+      for (int rr = 0; rr < ROWS; ++rr) {
+        const double2 l = sL[kk][wave * ROWS + rr];
         acc[rr][0].x = fma(l.x, r0.x, fma(-l.y, r0.y, acc[rr][0].x));
         acc[rr][0].y = fma(l.x, r0.y, fma(l.y, r0.x, acc[rr][0].y));
         acc[rr][1].x = fma(l.x, r1.x, fma(-l.y, r1.y, acc[rr][1].x));
@@ -359,8 +353,18 @@ __global__ __launch_bounds__(kSvThreads) void svd_step_kernel(SvParams P) {
   // for gates they coincide and the pair product is kept in region 2.
   double2 *SM = gate ? S : S + kSvMaxN * kSvMaxN;
   {
+    // pair product of the two sites, the two-site tensor before the gate
+    // (Fig. 1b): P[(s', a)][(t', b)] = sum_c A_p[s'][a][c] A_{p+1}[t'][c][b]
     double2 pt[kSvRows][2];
-    pair_product_tile(Ap, Aq, Dp, Dm, Dn, Pp, Pm, Pn, s_u.stage.L, s_u.stage.R, pt);
+    staged_tile_gemm<kSvRows>(
+        Dm,
+        [&](int y, int c) {
+          return y < 2 * Dp ? Ap[(size_t(y / Dp) * Pp + y % Dp) * Pm + c] : make_double2(0.0, 0.0);
+        },
+        [&](int c, int x) {
+          return x < 2 * Dn ? Aq[(size_t(x / Dn) * Pm + c) * Pn + x % Dn] : make_double2(0.0, 0.0);
+        },
+        s_u.stage.L, s_u.stage.R, pt);
     double2 *P2 = S + kSvMaxN * kSvMaxN;
 #pragma unroll
     for (int rr = 0; rr < kSvRows; ++rr)
@@ -562,40 +566,29 @@ __global__ __launch_bounds__(kSvThreads) void svd_step_kernel(SvParams P) {
     }
   }
   __syncthreads();
-  // projection: out[j][x] = sum_y conj(U[y][j]) S[y][x]
+  // projection: out[j][x] = sum_y conj(U[y][j]) S[y][x]; wave w forms rows
+  // j = 4w .. 4w+3
   {
-    const int x = tid & 127, jg = tid >> 7;
-    if (x < ncs) {
-      double2 acc[8];
+    double2 acc[4][2];
+    staged_tile_gemm<4>(
+        nr,
+        [&](int j, int y) {
+          if (j >= k) return make_double2(0.0, 0.0);
+          return right ? cconj(Ap[(size_t(y / Dp) * Pp + y % Dp) * Pm + j])
+                       : Aq[(size_t(y / Dn) * Pm + j) * Pn + y % Dn];
+        },
+        [&](int y, int x) { return x < ncs ? S[y * kSvMaxN + x] : make_double2(0.0, 0.0); },
+        s_u.stage.L, s_u.stage.R, acc);
 #pragma unroll
-      for (int u = 0; u < 8; ++u) acc[u] = make_double2(0.0, 0.0);
-      for (int y = 0; y < nr; ++y) {
-        const double2 sv = S[y * kSvMaxN + x];
+    for (int rr = 0; rr < 4; ++rr)
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int j = jg + 8 * u;
-          if (j < k) {
-            double2 uv;
-            if (right) uv = Ap[(size_t(y / Dp) * Pp + y % Dp) * Pm + j];
-            else uv = cconj(Aq[(size_t(y / Dn) * Pm + j) * Pn + y % Dn]);
-            // conj(uv) * sv
-            acc[u].x = fma(uv.x, sv.x, fma(uv.y, sv.y, acc[u].x));
-            acc[u].y = fma(uv.x, sv.y, fma(-uv.y, sv.x, acc[u].y));
-          }
+      for (int q = 0; q < 2; ++q) {
+        const int j = wave * 4 + rr, x = 2 * lane + q;
+        if (j < k && x < ncs) {
+          if (right) Aq[(size_t(x / Dn) * Pm + j) * Pn + x % Dn] = make_double2(nrm * acc[rr][q].x, nrm * acc[rr][q].y);
+          else Ap[(size_t(x / Dp) * Pp + x % Dp) * Pm + j] = make_double2(nrm * acc[rr][q].x, -nrm * acc[rr][q].y);
         }
       }
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int j = jg + 8 * u;
-        if (j < k) {
-          if (right) {
-            Aq[(size_t(x / Dn) * Pm + j) * Pn + x % Dn] = make_double2(nrm * acc[u].x, nrm * acc[u].y);
-          } else {
-            Ap[(size_t(x / Dp) * Pp + x % Dp) * Pm + j] = make_double2(nrm * acc[u].x, -nrm * acc[u].y);
-          }
-        }
-      }
-    }
   }
   if (tid == 0) dims[p + 1] = k;
 }
