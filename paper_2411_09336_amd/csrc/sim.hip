@@ -118,7 +118,7 @@ constexpr int kKC = 16;  // contraction chunk of the pair product staged in LDS
 template <int ROWS, class FL, class FR>
 __device__ inline void staged_tile_gemm(int K, const FL &ldL, const FR &ldR, double2 (*sL)[kSvMaxN],
                                         double2 (*sR)[kSvMaxN], double2 (&acc)[ROWS][2]) {
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   constexpr int kRowsAll = ROWS * kSvWaves;
 #pragma unroll
   for (int rr = 0; rr < ROWS; ++rr) {
@@ -195,8 +195,13 @@ __device__ inline double quad_sum(double x) {
 // FULL, so rounding in the updates never outlives a sweep.
 template <int TYPE, bool FULL>
 __device__ __forceinline__ bool jacobi_round(double (&Ar)[kSvRows], double (&Ai)[kSvRows], double (&Br)[kSvRows],
-                                             double (&Bi)[kSvRows], const JacobiShared &sh, int wave, int lane,
+                                             double (&Bi)[kSvRows], const JacobiShared &sh, int wave,
                                              int H, double zero_w) {
+  // The lane index is formed afresh every round (two instructions the
+  // compiler cannot hoist), so the LDS addresses derived from it are not
+  // held, or spilled, across the sweep loop.
+  int lane;
+  asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(lane));
   // A_{l+1} is shifted in where it is used (once for the inner products and
   // once for the update) rather than held across the barriers
   {
@@ -300,7 +305,8 @@ __device__ __forceinline__ bool jacobi_round(double (&Ar)[kSvRows], double (&Ai)
 __global__ __launch_bounds__(kSvThreads) void svd_step_kernel(SvParams P) {
   const int64_t ci = blockIdx.x;
   if (ci >= P.n) return;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: scalar register
 
   // the pair-product staging is dead once the Jacobi matrix is built; the
   // reduction buffers are used from then on
@@ -451,14 +457,17 @@ __global__ __launch_bounds__(kSvThreads) void svd_step_kernel(SvParams P) {
   const int NP = (nc + (nc & 1)) < 2 ? 2 : (nc + (nc & 1));
   const int H = NP / 2;
   const JacobiShared sh{s_red, s_upd, s_w};
+  // wave-uniform: kept in scalar registers
+  const double zw = __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(zero_w)),
+                                     __builtin_amdgcn_readfirstlane(__double2loint(zero_w)));
   bool converged = false;
   int sweep = 0;
   for (; sweep < kMaxSweeps && !converged; ++sweep) {
-    bool rotated = jacobi_round<0, true>(Ar, Ai, Br, Bi, sh, wave, lane, H, zero_w);  // wave-uniform
-    if (H > 1) rotated |= jacobi_round<1, false>(Ar, Ai, Br, Bi, sh, wave, lane, H, zero_w);
+    bool rotated = jacobi_round<0, true>(Ar, Ai, Br, Bi, sh, wave, H, zw);  // wave-uniform
+    if (H > 1) rotated |= jacobi_round<1, false>(Ar, Ai, Br, Bi, sh, wave, H, zw);
     for (int half = 1; half < H; ++half) {
-      rotated |= jacobi_round<0, false>(Ar, Ai, Br, Bi, sh, wave, lane, H, zero_w);
-      rotated |= jacobi_round<1, false>(Ar, Ai, Br, Bi, sh, wave, lane, H, zero_w);
+      rotated |= jacobi_round<0, false>(Ar, Ai, Br, Bi, sh, wave, H, zw);
+      rotated |= jacobi_round<1, false>(Ar, Ai, Br, Bi, sh, wave, H, zw);
     }
     converged = __syncthreads_or(rotated ? 1 : 0) == 0;
   }
