@@ -4,11 +4,12 @@
 // Every circuit of a batch shares one gate list, so each gate is one launch
 // over all circuits (one workgroup per circuit).  Rz layers are diagonal and
 // applied in place (Fig. 1a).  A two-qubit gate on sites (p, p+1) (Fig. 1b):
-//   * theta[(s,a),(t,b)] = sum_{s',t'} G[st,s't'] sum_c A_p[s'][a][c] A_{p+1}[t'][c][b]
-//     is built directly in registers;
+//   * theta[(s,a),(t,b)] = sum_{s',t'} G[st,s't'] P[(s',a),(t',b)] with the
+//     pair product P[(s',a),(t',b)] = sum_c A_p[s'][a][c] A_{p+1}[t'][c][b],
+//     formed once per step as a block-wide GEMM through LDS;
 //   * its SVD is taken by one-sided (Hestenes) Jacobi in FP64: pairs of
 //     columns are rotated until every pair is orthogonal to relative
-//     tolerance 1e-15; the columns then are U S.  To absorb S to the right
+//     tolerance 1e-14; the columns then are U S.  To absorb S to the right
 //     the columns of theta are orthogonalised (U = W / |W|, the new right
 //     tensor is U^H theta); to absorb it to the left the columns of theta^H
 //     are (giving V, the new left tensor is theta V).  The isometric factor
@@ -103,9 +104,6 @@ __device__ inline double row_sum16(double x) {
   return x;
 }
 
-__device__ inline double2 cmul(double2 a, double2 b) {
-  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
 __device__ inline double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
 
 constexpr int kKC = 16;  // contraction chunk of the pair product staged in LDS
@@ -298,9 +296,6 @@ __device__ __forceinline__ bool jacobi_round(double (&Ar)[kSvRows], double (&Ai)
     Ai[rr] = fma(pa, pi_, fma(war, qi, wai * qr));
     Br[rr] = fma(pb, rr_, fma(wbr, sr, -wbi * si));
     Bi[rr] = fma(pb, ri, fma(wbr, si, wbi * sr));
-    // one row at a time: hoisting the lane shifts of later rows would need
-    // more registers than a wave of this 1024-thread block has
-    if (TYPE == 1) __builtin_amdgcn_sched_barrier(0);
   }
   return rotated;
 }
