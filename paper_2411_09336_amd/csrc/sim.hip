@@ -106,6 +106,14 @@ __device__ inline double row_sum16(double x) {
 
 __device__ inline double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
 
+// Sum over the 64 lanes of the wave (every lane receives the total).
+__device__ inline double wave_sum(double x) {
+  x = row_sum16(x);
+  x += __shfl_xor(x, 16, 64);
+  x += __shfl_xor(x, 32, 64);
+  return x;
+}
+
 constexpr int kKC = 16;  // contraction chunk of the pair product staged in LDS
 
 // Block-wide complex product acc[rr][q] = sum_{k < K} L(y, k) R(k, x) with
@@ -431,6 +439,68 @@ __global__ __launch_bounds__(kSvThreads) void svd_step_kernel(SvParams P) {
   }
   const double zero_w = kZeroWeight * s_nrm;
   __syncthreads();
+
+  // ---------------------------------------------------------- LQ preconditioning
+  // M <- M H_0 H_1 ... (Householder reflections from the right, M = L Q): the
+  // Jacobi columns of M W are U S for any unitary W, so the factors are
+  // unchanged, while the lower-triangular L of these graded matrices needs
+  // about a third fewer sweeps than M itself.  Step i reflects row i onto
+  // its diagonal entry: with x = row i restricted to columns >= i and
+  // w = x + e^{i arg x_i} |x| e_i, every row r becomes r - beta (r . conj w) w,
+  // beta = 1 / (|x| (|x| + |x_i|)).  Row i lives in wave i / 8; the others
+  // read w from LDS (two buffers, one barrier per step); waves whose rows
+  // all lie above row i hold only rounding-level entries in columns >= i
+  // and skip the step.
+  {
+    double2(*lqw)[kSvMaxN] = reinterpret_cast<double2(*)[kSvMaxN]>(&s_red[0][0][0]);  // [2][kSvMaxN]
+    double *lqb = reinterpret_cast<double *>(&s_red[1][0][0]);                          // [2]
+    const int nref = min(nr, nc);
+    const int c0 = 2 * lane, c1 = 2 * lane + 1;
+    for (int i = 0; i < nref; ++i) {
+      const int buf = i & 1;
+      if (wave == (i >> 3)) {
+        const int ri = i & 7;
+        double xr0 = 0.0, xi0 = 0.0, xr1 = 0.0, xi1 = 0.0;
+#pragma unroll
+        for (int rr = 0; rr < kSvRows; ++rr)
+          if (rr == ri) {
+            xr0 = Ar[rr];
+            xi0 = Ai[rr];
+            xr1 = Br[rr];
+            xi1 = Bi[rr];
+          }
+        if (c0 < i) xr0 = xi0 = 0.0;
+        if (c1 < i) xr1 = xi1 = 0.0;
+        const double nx = sqrt(wave_sum(fma(xr0, xr0, fma(xi0, xi0, fma(xr1, xr1, xi1 * xi1)))));
+        const double dr = __shfl((i & 1) ? xr1 : xr0, i >> 1, 64);
+        const double di = __shfl((i & 1) ? xi1 : xi0, i >> 1, 64);
+        const double ax = sqrt(fma(dr, dr, di * di));
+        const double pr = ax > 0.0 ? dr / ax : 1.0, pi = ax > 0.0 ? di / ax : 0.0;
+        const double wdr = pr * (ax + nx), wdi = pi * (ax + nx);
+        lqw[buf][c0] = c0 == i ? make_double2(wdr, wdi) : make_double2(xr0, xi0);
+        lqw[buf][c1] = c1 == i ? make_double2(wdr, wdi) : make_double2(xr1, xi1);
+        if (lane == 0) lqb[buf] = nx > 0.0 ? 1.0 / (nx * (nx + ax)) : 0.0;
+      }
+      __syncthreads();
+      if (wave * kSvRows + kSvRows - 1 >= i) {
+        const double2 w0 = lqw[buf][c0], w1 = lqw[buf][c1];
+        const double beta = lqb[buf];
+#pragma unroll
+        for (int rr = 0; rr < kSvRows; ++rr) {
+          // d = r . conj(w)
+          double dr = fma(Ar[rr], w0.x, fma(Ai[rr], w0.y, fma(Br[rr], w1.x, Bi[rr] * w1.y)));
+          double di = fma(Ai[rr], w0.x, fma(-Ar[rr], w0.y, fma(Bi[rr], w1.x, -Br[rr] * w1.y)));
+          dr = beta * wave_sum(dr);
+          di = beta * wave_sum(di);
+          Ar[rr] -= dr * w0.x - di * w0.y;
+          Ai[rr] -= dr * w0.y + di * w0.x;
+          Br[rr] -= dr * w1.x - di * w1.y;
+          Bi[rr] -= dr * w1.y + di * w1.x;
+        }
+      }
+    }
+    __syncthreads();  // the reflector buffers alias the Jacobi reduction buffers
+  }
 
   // ---------------------------------------------------------- Jacobi sweeps
   // Odd-even transposition ordering of the positions 0..NP-1 (A_l = 2l,
