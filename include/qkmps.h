@@ -158,9 +158,10 @@ qk_status mps_simulate_progress(const double *features_dev, int64_t n_points,
 /* mps_simulate with the kernel launches recorded as HIP graphs: the launches
  * of every `gates_per_graph` two-qubit gates (0: the whole circuit) are
  * captured on a private stream, instantiated and launched as one graph,
- * ordered after earlier work on hip_stream and before later work on it.  The
- * kernels and their order are those of mps_simulate, so the batch is
- * bit-identical.  Removes per-launch host overhead for circuits whose gates
+ * ordered after earlier work on hip_stream and before later work on it.  Each
+ * circuit goes through the same steps with the same kernels as in
+ * mps_simulate (only the launch boundaries differ), so the batch is
+ * bit-identical.  Removes per-launch host overhead for circuits whose steps
  * are short; returns QK_EDEVICE if capture or instantiation fails.  The call
  * returns after the simulation has finished. */
 qk_status mps_simulate_graph(const double *features_dev, int64_t n_points,

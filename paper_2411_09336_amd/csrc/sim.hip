@@ -1,9 +1,11 @@
 // Batched truncated MPS simulation of the feature-map circuit (Sec. II-B,
 // Fig. 1; circuit of Sec. II-C).
 //
-// Every circuit of a batch shares one gate list, so each gate is one launch
-// over all circuits (one workgroup per circuit).  Rz layers are diagonal and
-// applied in place (Fig. 1a).  A two-qubit gate on sites (p, p+1) (Fig. 1b):
+// Every circuit of a batch shares one gate list, hence one step list (runs
+// of Rz records, centre moves and two-qubit gates); a launch runs a chunk of
+// steps with one workgroup per circuit, each walking its own circuit through
+// the chunk.  Rz layers are diagonal and applied in place (Fig. 1a).  A
+// two-qubit gate on sites (p, p+1) (Fig. 1b):
 //   * theta[(s,a),(t,b)] = sum_{s',t'} G[st,s't'] P[(s',a),(t',b)] with the
 //     pair product P[(s',a),(t',b)] = sum_c A_p[s'][a][c] A_{p+1}[t'][c][b],
 //     formed once per step as a block-wide GEMM through LDS;
@@ -64,12 +66,7 @@ struct SvParams {
   const int32_t *pad;
   int32_t *dims;
   int32_t m;
-  int32_t p;
-  int32_t mode;
-  int32_t op;
-  int32_t fi, fj;
   int32_t chi;
-  int32_t pad_unused;
   double coef_xx;
   double cutoff;
   const double *X;
@@ -308,9 +305,17 @@ __device__ __forceinline__ bool jacobi_round(double (&Ar)[kSvRows], double (&Ai)
   return rotated;
 }
 
-__global__ __launch_bounds__(kSvThreads) void svd_step_kernel(SvParams P) {
-  const int64_t ci = blockIdx.x;
-  if (ci >= P.n) return;
+// One entry of the step list shared by every circuit of a batch: a run of
+// Rz records, or a two-site step (a two-qubit gate or a centre move).
+enum StepKind { STEP_RZ = 0, STEP_TWO_SITE = 1 };
+struct SimStep {
+  int32_t kind;
+  int32_t p, mode, op, fi, fj;  // two-site step: sites (p, p+1), SvMode, GateOp, features of Rxx
+  int32_t r0, nr;               // Rz run: gate records [r0, r0 + nr)
+};
+
+// Two-site step of circuit ci (one 1024-thread workgroup).
+__device__ __attribute__((noinline)) void svd_step(const SvParams &P, const int64_t ci, const SimStep &st) {
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: scalar register
 
@@ -337,7 +342,7 @@ __global__ __launch_bounds__(kSvThreads) void svd_step_kernel(SvParams P) {
   __shared__ double s_nrm;
 
   int32_t *dims = P.dims + ci * (P.m + 1);
-  const int p = P.p;
+  const int p = st.p;
   const int Dp = dims[p], Dm = dims[p + 1], Dn = dims[p + 2];
   const int Pp = P.pad[p], Pm = P.pad[p + 1], Pn = P.pad[p + 2];
   double2 *Ap = P.f64 + ci * P.mps_stride + P.site_off[p];
@@ -345,19 +350,19 @@ __global__ __launch_bounds__(kSvThreads) void svd_step_kernel(SvParams P) {
   double2 *S = P.scratch + ci * (2 * kSvMaxN * kSvMaxN);
 
   double cg = 1.0, sg = 0.0;
-  if (P.op == OP_RXX) {
-    const double xi = P.X[ci * P.ldx + P.fi], xj = P.X[ci * P.ldx + P.fj];
+  if (st.op == OP_RXX) {
+    const double xi = P.X[ci * P.ldx + st.fi], xj = P.X[ci * P.ldx + st.fj];
     const double phi = P.coef_xx * (1.0 - xi) * (1.0 - xj);
     sincos(0.5 * phi, &sg, &cg);
   }
 
-  const bool right = (P.mode == GATE_RIGHT || P.mode == MOVE_RIGHT);
-  const bool gate = (P.mode == GATE_RIGHT || P.mode == GATE_LEFT);
+  const bool right = (st.mode == GATE_RIGHT || st.mode == MOVE_RIGHT);
+  const bool gate = (st.mode == GATE_RIGHT || st.mode == GATE_LEFT);
   // Jacobi matrix shape and projection-source width
   int nr, nc, ncs;
-  if (P.mode == GATE_RIGHT) { nr = 2 * Dp; nc = 2 * Dn; ncs = nc; }
-  else if (P.mode == GATE_LEFT) { nr = 2 * Dn; nc = 2 * Dp; ncs = nc; }
-  else if (P.mode == MOVE_RIGHT) { nr = 2 * Dp; nc = Dm; ncs = 2 * Dn; }
+  if (st.mode == GATE_RIGHT) { nr = 2 * Dp; nc = 2 * Dn; ncs = nc; }
+  else if (st.mode == GATE_LEFT) { nr = 2 * Dn; nc = 2 * Dp; ncs = nc; }
+  else if (st.mode == MOVE_RIGHT) { nr = 2 * Dp; nc = Dm; ncs = 2 * Dn; }
   else { nr = 2 * Dn; nc = Dm; ncs = 2 * Dp; }
 
   // ---------------------------------------------------------- build M
@@ -385,7 +390,7 @@ __global__ __launch_bounds__(kSvThreads) void svd_step_kernel(SvParams P) {
         const int y = wave * kSvRows + rr, x = 2 * lane + q;
         if (y < 2 * Dp && x < 2 * Dn) {
           if (gate) P2[y * kSvMaxN + x] = pt[rr][q];
-          else if (P.mode == MOVE_RIGHT) S[y * kSvMaxN + x] = pt[rr][q];   // identity theta
+          else if (st.mode == MOVE_RIGHT) S[y * kSvMaxN + x] = pt[rr][q];   // identity theta
           else S[x * kSvMaxN + y] = cconj(pt[rr][q]);                        // its adjoint
         }
       }
@@ -394,7 +399,7 @@ __global__ __launch_bounds__(kSvThreads) void svd_step_kernel(SvParams P) {
     // the site being orthogonalised, as a matrix
     for (int e = tid; e < nr * nc; e += kSvThreads) {
       const int r = e / nc, c = e % nc;
-      SM[r * kSvMaxN + c] = P.mode == MOVE_RIGHT ? Ap[(size_t(r / Dp) * Pp + r % Dp) * Pm + c]
+      SM[r * kSvMaxN + c] = st.mode == MOVE_RIGHT ? Ap[(size_t(r / Dp) * Pp + r % Dp) * Pm + c]
                                                  : cconj(Aq[(size_t(r / Dn) * Pm + c) * Pn + r % Dn]);
     }
   }
@@ -403,9 +408,9 @@ __global__ __launch_bounds__(kSvThreads) void svd_step_kernel(SvParams P) {
     const double2 *P2 = S + kSvMaxN * kSvMaxN;
     for (int e = tid; e < nr * nc; e += kSvThreads) {
       const int r = e / nc, c = e % nc;
-      SM[r * kSvMaxN + c] = P.mode == GATE_RIGHT
-                                ? theta_from_pair(P2, P.op, cg, sg, Dp, Dn, r / Dp, r % Dp, c / Dn, c % Dn)
-                                : cconj(theta_from_pair(P2, P.op, cg, sg, Dp, Dn, c / Dp, c % Dp, r / Dn, r % Dn));
+      SM[r * kSvMaxN + c] = st.mode == GATE_RIGHT
+                                ? theta_from_pair(P2, st.op, cg, sg, Dp, Dn, r / Dp, r % Dp, c / Dn, c % Dn)
+                                : cconj(theta_from_pair(P2, st.op, cg, sg, Dp, Dn, c / Dp, c % Dp, r / Dn, r % Dn));
     }
     __syncthreads();
   }
@@ -670,24 +675,39 @@ __global__ __launch_bounds__(kSvThreads) void svd_step_kernel(SvParams P) {
   if (tid == 0) dims[p + 1] = k;
 }
 
-// Rz on a run of gate records (Fig. 1a): A[site][s] *= exp(-/+ i theta / 2).
-__global__ void rz_kernel(double2 *f64, int64_t mps_stride, const int64_t *site_off, const int32_t *pad,
-                          const qk_gate *recs, int n_recs, const double *X, int64_t ldx, double coef_z,
-                          int64_t n) {
+// Rz on a run of gate records (Fig. 1a) for circuit ci: A[site][s] *=
+// exp(-/+ i theta / 2).  The records of a run act on distinct sites.
+__device__ inline void rz_run(const SvParams &P, int64_t ci, const qk_gate *recs, int n_recs, double coef_z) {
+  for (int r = 0; r < n_recs; ++r) {
+    const qk_gate g = recs[r];
+    const double th = coef_z * P.X[ci * P.ldx + g.feat_i];
+    double sn, cs;
+    sincos(0.5 * th, &sn, &cs);
+    const int pl = P.pad[g.site], pr = P.pad[g.site + 1];
+    double2 *A = P.f64 + ci * P.mps_stride + P.site_off[g.site];
+    const int half = pl * pr;
+    for (int e = threadIdx.x; e < 2 * half; e += kSvThreads) {
+      const double2 v = A[e];
+      const double ph = e < half ? -sn : sn;  // s = 0: exp(-i th/2), s = 1: exp(+i th/2)
+      A[e] = make_double2(cs * v.x - ph * v.y, cs * v.y + ph * v.x);
+    }
+  }
+}
+
+// Steps [s0, s1) of the step list for every circuit, one workgroup each.
+// Circuits do not wait for one another between steps, so a launch lasts as
+// long as the slowest circuit's total over the chunk rather than the sum,
+// over the steps, of each step's slowest SVD (whose sweep count varies from
+// circuit to circuit).
+__global__ __launch_bounds__(kSvThreads) void sim_steps_kernel(SvParams P, const SimStep *steps, int s0, int s1,
+                                                              const qk_gate *recs, double coef_z) {
   const int64_t ci = blockIdx.x;
-  const int r = blockIdx.y;
-  if (ci >= n || r >= n_recs) return;
-  const qk_gate g = recs[r];
-  const double th = coef_z * X[ci * ldx + g.feat_i];
-  double sn, cs;
-  sincos(0.5 * th, &sn, &cs);
-  const int pl = pad[g.site], pr = pad[g.site + 1];
-  double2 *A = f64 + ci * mps_stride + site_off[g.site];
-  const int half = pl * pr;
-  for (int e = threadIdx.x; e < 2 * half; e += blockDim.x) {
-    const double2 v = A[e];
-    const double ph = e < half ? -sn : sn;  // s = 0: exp(-i th/2), s = 1: exp(+i th/2)
-    A[e] = make_double2(cs * v.x - ph * v.y, cs * v.y + ph * v.x);
+  if (ci >= P.n) return;
+  for (int s = s0; s < s1; ++s) {
+    const SimStep st = steps[s];
+    if (st.kind == STEP_RZ) rz_run(P, ci, recs + st.r0, st.nr, coef_z);
+    else svd_step(P, ci, st);
+    __syncthreads();  // the next step reads the tensors and bond dims this one wrote
   }
 }
 
@@ -786,17 +806,6 @@ qk_status run_simulation(qk_mps_batch *b, const double *features_dev, const std:
   P.unconv = b->unconv_dev;
   P.n = n;
 
-  auto launch_step = [&](int p, int mode, int op, int fi, int fj) -> qk_status {
-    SvParams q = P;
-    q.p = p;
-    q.mode = mode;
-    q.op = op;
-    q.fi = fi;
-    q.fj = fj;
-    hipLaunchKernelGGL(svd_step_kernel, dim3(unsigned(n)), dim3(kSvThreads), 0, stream, q);
-    QK_HIP_CHECK(hipGetLastError());
-    return QK_OK;
-  };
 
   // HIP-graph mode: the launches of every `graph_gates` two-qubit gates are
   // recorded by stream capture on a private stream (the caller's stream may
@@ -838,57 +847,88 @@ qk_status run_simulation(qk_mps_batch *b, const double *features_dev, const std:
     if (le != hipSuccess) return fail(QK_EDEVICE, std::string("graph launch failed: ") + hipGetErrorString(le));
     return QK_OK;
   };
-  int64_t seg2q = 0;
-
-  // next two-qubit gate position after each gate
-  std::vector<int> next2q(gates.size(), -1);
+  // The step list shared by every circuit: runs of Rz records, centre moves
+  // and two-qubit gates in circuit order, then the final moves to the last
+  // site.  gate_no[i] is the number of two-qubit gates done after step i
+  // when step i is a gate, and 0 otherwise.
+  std::vector<SimStep> steps;
+  std::vector<int64_t> gate_no;
   {
+    std::vector<int> next2q(gates.size(), -1);  // site of the next two-qubit gate
     int nxt = -1;
     for (int gi = int(gates.size()) - 1; gi >= 0; --gi) {
       next2q[gi] = nxt;
       if (gates[gi].op != OP_RZ) nxt = gates[gi].site;
     }
+    auto push = [&](const SimStep &x, int64_t g) {
+      steps.push_back(x);
+      gate_no.push_back(g);
+    };
+    int center = 0;
+    int64_t d2q = 0;
+    size_t gi = 0;
+    while (gi < gates.size()) {
+      if (gates[gi].op == OP_RZ) {
+        size_t ge = gi;
+        while (ge < gates.size() && gates[ge].op == OP_RZ) ++ge;
+        push({STEP_RZ, 0, 0, 0, -1, -1, int32_t(gi), int32_t(ge - gi)}, 0);
+        gi = ge;
+        continue;
+      }
+      const int p = gates[gi].site;
+      for (; center < p; ++center) push({STEP_TWO_SITE, center, MOVE_RIGHT, OP_ID, -1, -1, 0, 0}, 0);
+      for (; center > p + 1; --center) push({STEP_TWO_SITE, center - 1, MOVE_LEFT, OP_ID, -1, -1, 0, 0}, 0);
+      const bool absorb_right = next2q[gi] < 0 || next2q[gi] > p;
+      push({STEP_TWO_SITE, p, absorb_right ? GATE_RIGHT : GATE_LEFT, gates[gi].op == 1 ? OP_RXX : OP_SWAP,
+            gates[gi].feat_i, gates[gi].feat_j, 0, 0},
+           ++d2q);
+      center = absorb_right ? p + 1 : p;
+      ++gi;
+    }
+    for (; center < m - 1; ++center) push({STEP_TWO_SITE, center, MOVE_RIGHT, OP_ID, -1, -1, 0, 0}, 0);
   }
-  int center = 0;
+  SimStep *steps_dev = nullptr;
   qk_status st = QK_OK;
-  size_t gi = 0;
-  int64_t done2q = 0;
-  while (gi < gates.size() && st == QK_OK) {
-    const qk_gate &g = gates[gi];
+  if (!steps.empty()) {
+    if (hipMallocAsync(reinterpret_cast<void **>(&steps_dev), sizeof(SimStep) * steps.size(), stream) != hipSuccess ||
+        hipMemcpyAsync(steps_dev, steps.data(), sizeof(SimStep) * steps.size(), hipMemcpyHostToDevice, stream) !=
+            hipSuccess) {
+      (void)hipGetLastError();
+      st = fail(QK_ENOMEM, "device allocation of the step list failed");
+    }
+  }
+
+  // Launches of at most kMaxChunkSteps steps, each ending where a progress
+  // callback or the end of a graph segment is due.
+  constexpr size_t kMaxChunkSteps = 256;
+  int64_t seg2q = 0;
+  size_t s0 = 0;
+  while (st == QK_OK && s0 < steps.size()) {
     st = begin_segment();
     if (st != QK_OK) break;
-    if (g.op == OP_RZ) {
-      size_t ge = gi;
-      while (ge < gates.size() && gates[ge].op == OP_RZ) ++ge;
-      hipLaunchKernelGGL(rz_kernel, dim3(unsigned(n), unsigned(ge - gi)), dim3(256), 0, stream, b->f64, b->mps_stride,
-                         b->site_off_dev, b->pad_dev, recs_dev + gi, int(ge - gi), features_dev, int64_t(m),
-                         spec.coef_z, n);
-      if (hipGetLastError() != hipSuccess) st = fail(QK_EDEVICE, "Rz launch failed");
-      gi = ge;
-      continue;
+    size_t s1 = s0;
+    bool seg_end = false, report = false;
+    while (s1 < steps.size() && s1 - s0 < kMaxChunkSteps) {
+      const int64_t g = gate_no[s1++];
+      if (g > 0) {
+        seg_end = graph_gates > 0 && ++seg2q == graph_gates;
+        report = fn && every > 0 && g % every == 0;
+        if (seg_end || report) break;
+      }
     }
-    const int p = g.site;
-    while (st == QK_OK && center < p) {
-      st = launch_step(center, MOVE_RIGHT, OP_ID, -1, -1);
-      ++center;
+    hipLaunchKernelGGL(sim_steps_kernel, dim3(unsigned(n)), dim3(kSvThreads), 0, stream, P, steps_dev, int(s0),
+                       int(s1), recs_dev, spec.coef_z);
+    if (hipGetLastError() != hipSuccess) {
+      st = fail(QK_EDEVICE, "simulation launch failed");
+      break;
     }
-    while (st == QK_OK && center > p + 1) {
-      st = launch_step(center - 1, MOVE_LEFT, OP_ID, -1, -1);
-      --center;
-    }
-    if (st != QK_OK) break;
-    const int nx = next2q[gi];
-    const bool absorb_right = nx < 0 || nx > p;
-    st = launch_step(p, absorb_right ? GATE_RIGHT : GATE_LEFT, g.op == 1 ? OP_RXX : OP_SWAP, g.feat_i, g.feat_j);
-    center = absorb_right ? p + 1 : p;
-    ++gi;
-    ++done2q;
-    ++seg2q;
-    if (st == QK_OK && graph_gates > 0 && seg2q == graph_gates) {
+    const int64_t done2q = gate_no[s1 - 1];
+    s0 = s1;
+    if (seg_end) {
       st = end_segment();
       seg2q = 0;
     }
-    if (st == QK_OK && fn && every > 0 && done2q % every == 0) {
+    if (st == QK_OK && report) {
       if (capturing) {
         st = end_segment();
         seg2q = 0;
@@ -902,10 +942,6 @@ qk_status run_simulation(qk_mps_batch *b, const double *features_dev, const std:
     }
   }
   if (st == QK_OK) st = begin_segment();
-  while (st == QK_OK && center < m - 1) {
-    st = launch_step(center, MOVE_RIGHT, OP_ID, -1, -1);
-    ++center;
-  }
   if (st == QK_OK) {
     hipLaunchKernelGGL(normalize_last_kernel, dim3(unsigned(n)), dim3(256), 0, stream, b->f64, b->mps_stride,
                        b->site_off_dev, b->pad_dev, m, n);
@@ -924,6 +960,7 @@ qk_status run_simulation(qk_mps_batch *b, const double *features_dev, const std:
   }
   (void)hipFreeAsync(scratch, stream);
   (void)hipFreeAsync(recs_dev, stream);
+  if (steps_dev) (void)hipFreeAsync(steps_dev, stream);
   if (graph_gates > 0) {
     (void)hipStreamSynchronize(stream_in);
     (void)hipEventDestroy(ev_in);
