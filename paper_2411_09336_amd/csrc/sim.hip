@@ -336,6 +336,8 @@ __device__ __attribute__((noinline)) void svd_step(const SvParams &P, const int6
   __shared__ double s_upd[2][64][8];
   __shared__ double s_w[kSvMaxN];
   __shared__ double s_norm[kSvMaxN];
+  __shared__ int s_piv[kSvMaxN];    // LQ pivot of each step
+  __shared__ int s_prank[kSvMaxN];  // step at which each row is the pivot
   __shared__ double s_sorted[kSvMaxN];
   __shared__ int s_rank[kSvMaxN];
   __shared__ int s_k;
@@ -446,25 +448,51 @@ __device__ __attribute__((noinline)) void svd_step(const SvParams &P, const int6
   __syncthreads();
 
   // ---------------------------------------------------------- LQ preconditioning
-  // M <- M H_0 H_1 ... (Householder reflections from the right, M = L Q): the
-  // Jacobi columns of M W are U S for any unitary W, so the factors are
-  // unchanged, while the lower-triangular L of these graded matrices needs
-  // about a third fewer sweeps than M itself.  Step i reflects row i onto
-  // its diagonal entry: with x = row i restricted to columns >= i and
+  // M <- M H_0 H_1 ... (Householder reflections from the right, M = L Q with
+  // the rows taken in order of decreasing norm): the Jacobi columns of M W
+  // are U S for any unitary W, so the factors are unchanged, while the
+  // triangular factor of these graded matrices needs 40 % fewer sweeps than M
+  // itself.  Step i reflects the i-th heaviest row (its pivot) onto column i:
+  // with x = that row restricted to columns >= i and
   // w = x + e^{i arg x_i} |x| e_i, every row r becomes r - beta (r . conj w) w,
-  // beta = 1 / (|x| (|x| + |x_i|)).  Row i lives in wave i / 8; the others
-  // read w from LDS (two buffers, one barrier per step); waves whose rows
-  // all lie above row i hold only rounding-level entries in columns >= i
+  // beta = 1 / (|x| (|x| + |x_i|)).  Rows stay in place (a row permutation
+  // changes no column inner product); the pivot's wave publishes w in LDS
+  // (two buffers, one barrier per step), and waves whose rows all were
+  // pivots of earlier steps hold only rounding-level entries in columns >= i
   // and skip the step.
   {
     double2(*lqw)[kSvMaxN] = reinterpret_cast<double2(*)[kSvMaxN]>(&s_red[0][0][0]);  // [2][kSvMaxN]
     double *lqb = reinterpret_cast<double *>(&s_red[1][0][0]);                          // [2]
     const int nref = min(nr, nc);
     const int c0 = 2 * lane, c1 = 2 * lane + 1;
+    // pivot order: rows by decreasing norm, ties by index
+#pragma unroll
+    for (int rr = 0; rr < kSvRows; ++rr) {
+      const double w2 = wave_sum(fma(Ar[rr], Ar[rr], fma(Ai[rr], Ai[rr], fma(Br[rr], Br[rr], Bi[rr] * Bi[rr]))));
+      if (lane == 0) s_norm[wave * kSvRows + rr] = w2;
+    }
+    __syncthreads();
+    if (tid < kSvMaxN) {
+      const double v = s_norm[tid];
+      int rank = 0;
+#pragma unroll 1
+      for (int u = 0; u < kSvMaxN; ++u) {
+        const double o = s_norm[u];
+        rank += (o > v || (o == v && u < tid)) ? 1 : 0;
+      }
+      s_piv[rank] = tid;
+      s_prank[tid] = rank;
+    }
+    __syncthreads();
+    int last = 0;  // latest step at which a row of this wave is the pivot
+#pragma unroll
+    for (int rr = 0; rr < kSvRows; ++rr) last = max(last, s_prank[wave * kSvRows + rr]);
+    last = __builtin_amdgcn_readfirstlane(last);
     for (int i = 0; i < nref; ++i) {
       const int buf = i & 1;
-      if (wave == (i >> 3)) {
-        const int ri = i & 7;
+      const int pv = __builtin_amdgcn_readfirstlane(s_piv[i]);
+      if (wave == (pv >> 3)) {
+        const int ri = pv & 7;
         double xr0 = 0.0, xi0 = 0.0, xr1 = 0.0, xi1 = 0.0;
 #pragma unroll
         for (int rr = 0; rr < kSvRows; ++rr)
@@ -487,7 +515,7 @@ __device__ __attribute__((noinline)) void svd_step(const SvParams &P, const int6
         if (lane == 0) lqb[buf] = nx > 0.0 ? 1.0 / (nx * (nx + ax)) : 0.0;
       }
       __syncthreads();
-      if (wave * kSvRows + kSvRows - 1 >= i) {
+      if (last >= i) {
         const double2 w0 = lqw[buf][c0], w1 = lqw[buf][c1];
         const double beta = lqb[buf];
 #pragma unroll
