@@ -111,6 +111,54 @@ __device__ inline double wave_sum(double x) {
   return x;
 }
 
+// Lane-half and row exchanges of two doubles (gfx950 permlane swaps):
+// swap32 leaves a = [a_lo, b_lo], b = [a_hi, b_hi] (32-lane halves);
+// swap16 leaves a = [a_0, b_0, a_2, b_2], b = [a_1, b_1, a_3, b_3] (rows).
+__device__ inline void swap32(double &a, double &b) {
+  const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(a), __double2loint(b), false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(a), __double2hiint(b), false, false);
+  a = __hiloint2double(int(hi[0]), int(lo[0]));
+  b = __hiloint2double(int(hi[1]), int(lo[1]));
+}
+__device__ inline void swap16(double &a, double &b) {
+  const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(a), __double2loint(b), false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(a), __double2hiint(b), false, false);
+  a = __hiloint2double(int(hi[0]), int(lo[0]));
+  b = __hiloint2double(int(hi[1]), int(lo[1]));
+}
+
+// Sixteen wave sums at once (every lane receives all sixteen totals): a
+// reduce-scatter over the lane halves and rows (each exchange halves the
+// values a lane carries), a row sum of the remaining four, then the reverse
+// exchanges to spread the totals.  About a third of the instructions of
+// sixteen separate wave sums.
+__device__ inline void wave_sum16(double (&v)[16]) {
+  double u[8], t[4];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    swap32(v[2 * k], v[2 * k + 1]);
+    u[k] = v[2 * k] + v[2 * k + 1];  // lanes 0-31: value 2k, lanes 32-63: value 2k+1
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    swap16(u[2 * k], u[2 * k + 1]);
+    // rows 0, 1, 2, 3: values 4k, 4k+2, 4k+1, 4k+3, each over 4 lanes
+    t[k] = row_sum16(u[2 * k] + u[2 * k + 1]);
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    double a = t[k], b = t[k];
+    swap16(a, b);  // rows 0, 1: a = value 4k, b = 4k+2; rows 2, 3: a = 4k+1, b = 4k+3
+    double a2 = a, b2 = b;
+    swap32(a, a2);
+    swap32(b, b2);
+    v[4 * k] = a;
+    v[4 * k + 1] = a2;
+    v[4 * k + 2] = b;
+    v[4 * k + 3] = b2;
+  }
+}
+
 constexpr int kKC = 16;  // contraction chunk of the pair product staged in LDS
 
 // Block-wide complex product acc[rr][q] = sum_{k < K} L(y, k) R(k, x) with
@@ -518,13 +566,16 @@ __device__ __attribute__((noinline)) void svd_step(const SvParams &P, const int6
       if (last >= i) {
         const double2 w0 = lqw[buf][c0], w1 = lqw[buf][c1];
         const double beta = lqb[buf];
+        double d[16];  // d = r . conj(w) for the wave's rows (re, im)
 #pragma unroll
         for (int rr = 0; rr < kSvRows; ++rr) {
-          // d = r . conj(w)
-          double dr = fma(Ar[rr], w0.x, fma(Ai[rr], w0.y, fma(Br[rr], w1.x, Bi[rr] * w1.y)));
-          double di = fma(Ai[rr], w0.x, fma(-Ar[rr], w0.y, fma(Bi[rr], w1.x, -Br[rr] * w1.y)));
-          dr = beta * wave_sum(dr);
-          di = beta * wave_sum(di);
+          d[2 * rr] = fma(Ar[rr], w0.x, fma(Ai[rr], w0.y, fma(Br[rr], w1.x, Bi[rr] * w1.y)));
+          d[2 * rr + 1] = fma(Ai[rr], w0.x, fma(-Ar[rr], w0.y, fma(Bi[rr], w1.x, -Br[rr] * w1.y)));
+        }
+        wave_sum16(d);
+#pragma unroll
+        for (int rr = 0; rr < kSvRows; ++rr) {
+          const double dr = beta * d[2 * rr], di = beta * d[2 * rr + 1];
           Ar[rr] -= dr * w0.x - di * w0.y;
           Ai[rr] -= dr * w0.y + di * w0.x;
           Br[rr] -= dr * w1.x - di * w1.y;
