@@ -217,7 +217,7 @@ def main():
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU sharding is "
-              "a design in DESIGN.md, not a measured path.", file=sys.stderr)
+              "described (ring exchange of MPS blocks over RCCL), not a measured path.", file=sys.stderr)
         sys.exit(2)
 
     if args.counter_record:
