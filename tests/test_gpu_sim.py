@@ -101,6 +101,32 @@ def test_routing1_truncated_vs_oracle():
             assert list(dims[i]) == r.bond_dims
 
 
+def test_saturated_chi64_vs_oracle():
+    """The full workload's circuit on its first 40 features (d = 8, reps = 2,
+    routing 1, chi = 64, cutoff 1e-8): the bond dimension saturates at 64, so
+    the gate steps take the SVD of full 128 x 128 thetas (every parameter
+    wave and LQ reflection of the SVD kernel in use).  Per circuit: fidelity
+    with the oracle's MPS >= 1 - 1e-10, equal bond dimensions and discarded
+    weights, and no unconverged SVD."""
+    w = sd.WORKLOADS["full"]
+    X = sd.workload_features(w, 2)[:, :40]
+    b = _sim(X, w, routing=1)
+    inf = b.info()
+    assert inf["max_bond"] == 64
+    assert inf["unconverged_svds"] == 0
+    dims = b.bond_dims()
+    disc, deg = b.trunc_stats()
+    for i in range(len(X)):
+        r = omps.simulate(X[i], w.distance, w.reps, w.chi, w.cutoff, w.coef_z, w.coef_xx, routing=1)
+        f = fidelity(b.export(i), r.tensors)
+        print("saturated", i, "fidelity", f, "disc", disc[i], r.discarded, "degenerate", deg[i], r.degenerate_cuts)
+        assert r.max_bond_seen == 64
+        if r.degenerate_cuts == 0 and deg[i] == 0:
+            assert f > 1 - 1e-10
+            assert list(dims[i]) == r.bond_dims
+            assert abs(disc[i] - r.discarded) <= 1e-9 * max(1.0, r.discarded)
+
+
 def test_precision_workload_split_vs_fp64():
     """100 qubits, d = 4, chi = 64 (GPU-simulated) plus near-duplicates:
     split-BF16 vs FP64 on the GPU and both vs the oracle on the same MPS."""
