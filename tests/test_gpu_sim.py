@@ -127,6 +127,32 @@ def test_saturated_chi64_vs_oracle():
             assert abs(disc[i] - r.discarded) <= 1e-9 * max(1.0, r.discarded)
 
 
+def test_full_size_gram_vs_oracle():
+    """The benchmark's workload at full size (165 qubits, d = 8, reps = 2,
+    chi = 64, cutoff 1e-8, routing 1): 6 points and near-duplicates of two
+    of them simulated on the GPU, then the Gram in FP64 and in the timed
+    split-int8 form with the kernel configuration the autotuner picks for
+    this batch (as the benchmark does).  Every entry against the oracle's
+    overlaps of the same MPS: FP64 to 1e-12, split-int8 to the 1e-6 bound."""
+    import paper_2411_09336_amd as q
+    w = sd.WORKLOADS["full"]
+    X = sd.workload_features(w, 6)
+    X = np.vstack([X, sd.perturb_near_duplicates(X[:2])])
+    b = _sim(X, w, routing=1)
+    inf = b.info()
+    assert inf["max_bond"] == 64 and inf["unconverged_svds"] == 0
+    Ko = ogram.gram([b.export(i) for i in range(len(X))])
+    Kd = q.gram(b, precision="fp64").cpu().numpy()
+    q.autotune(b, precision="split_i8", sample=len(X))
+    Ki = q.gram(b, precision="split_i8").cpu().numpy()
+    q.autotune_reset()
+    print("fp64 vs oracle", np.abs(Kd - Ko).max(), "split_i8 vs oracle", np.abs(Ki - Ko).max(),
+          "near-duplicate K", Ko[0, 6], Ko[1, 7])
+    assert Ko[0, 6] > 1e-3 and Ko[1, 7] > 1e-3   # the near-duplicate entries are not vacuous
+    assert np.abs(Kd - Ko).max() < 1e-12
+    assert np.abs(Ki - Ko).max() < 1e-6
+
+
 def test_precision_workload_split_vs_fp64():
     """100 qubits, d = 4, chi = 64 (GPU-simulated) plus near-duplicates:
     split-BF16 vs FP64 on the GPU and both vs the oracle on the same MPS."""
