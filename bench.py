@@ -488,6 +488,19 @@ def run(args):
     e1.synchronize()
     t_row = e0.elapsed_time(e1) / 1e3
     log(f"[bench] inference row (1 x {N}, {form}): {t_row * 1e3:.2f} ms")
+    # (iv) one new point end to end (features on the device): its simulation, then its kernel row
+    # against the training batch; one circuit occupies one CU for its whole step list
+    xn = torch.tensor(sd.workload_features(w, S + 1)[S:S + 1], dtype=torch.float64, device="cuda")
+    rown = torch.zeros((1, N), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.time()
+    simn = q.simulate(xn, spec, w.chi, w.cutoff, stream=stream)
+    stream.synchronize()
+    t_sim1 = time.time() - t0
+    q.gram_block(simn, 0, 1, gb, 0, N, precision=form, out=rown, stream=stream)
+    stream.synchronize()
+    t_point = time.time() - t0
+    log(f"[bench] new point end to end: simulation {t_sim1:.2f} s, with its 1 x {N} row {t_point:.2f} s")
 
     # ---------------------------------------------------------------- 5. CPU oracle
     cpu = None
@@ -553,7 +566,8 @@ def run(args):
                                 "offdiag_K_median": float(np.median(offp)), "offdiag_K_min": float(offp.min()),
                                 **{f"{f}_vs_fp64_max": float((Kp[f] - Kp["fp64"]).abs().max().item())
                                    for f in FORMS}}},
-        "inference": {"row_entries": N, "ms": round(t_row * 1e3, 3), "entries_per_s": round(N / t_row, 1)},
+        "inference": {"row_entries": N, "ms": round(t_row * 1e3, 3), "entries_per_s": round(N / t_row, 1),
+                      "new_point_simulation_s": round(t_sim1, 3), "new_point_end_to_end_s": round(t_point, 3)},
         "K_distribution": {"offdiag_median": float(np.median(offd)), "offdiag_max": float(offd.max()),
                            "offdiag_frac_above_1e-6": float((offd > 1e-6).mean())},
         "simulation": {"circuits": n_sim, "seconds": round(t_sim, 2), "circuits_per_s": round(n_sim / t_sim, 3),
