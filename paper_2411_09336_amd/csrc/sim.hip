@@ -253,14 +253,20 @@ __device__ __forceinline__ bool jacobi_round(double (&Ar)[kSvRows], double (&Ai)
   // held, or spilled, across the sweep loop.
   int lane;
   asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0\n\tv_mbcnt_hi_u32_b32 %0, -1, %0" : "=v"(lane));
-  // A_{l+1} is shifted in where it is used (once for the inner products and
-  // once for the update) rather than held across the barriers
+  double Nr[kSvRows], Ni[kSvRows];  // A_{l+1} (TYPE 1)
+  if (TYPE == 1) {
+#pragma unroll
+    for (int rr = 0; rr < kSvRows; ++rr) {
+      Nr[rr] = dpp_shl1(Ar[rr]);
+      Ni[rr] = dpp_shl1(Ai[rr]);
+    }
+  }
   {
     double al = 0.0, be = 0.0, gr = 0.0, gi = 0.0;
 #pragma unroll
     for (int rr = 0; rr < kSvRows; ++rr) {
       const double xr = TYPE == 0 ? Ar[rr] : Br[rr], xi = TYPE == 0 ? Ai[rr] : Bi[rr];
-      const double yr = TYPE == 0 ? Br[rr] : dpp_shl1(Ar[rr]), yi = TYPE == 0 ? Bi[rr] : dpp_shl1(Ai[rr]);
+      const double yr = TYPE == 0 ? Br[rr] : Nr[rr], yi = TYPE == 0 ? Bi[rr] : Ni[rr];
       if (FULL) {
         al = fma(xr, xr, fma(xi, xi, al));
         be = fma(yr, yr, fma(yi, yi, be));
@@ -343,7 +349,7 @@ __device__ __forceinline__ bool jacobi_round(double (&Ar)[kSvRows], double (&Ai)
       rr_ = Ar[rr]; ri = Ai[rr]; sr = Br[rr]; si = Bi[rr];
     } else {
       pr_ = dpp_shr1(Br[rr]); pi_ = dpp_shr1(Bi[rr]); qr = Ar[rr]; qi = Ai[rr];
-      rr_ = Br[rr]; ri = Bi[rr]; sr = dpp_shl1(Ar[rr]); si = dpp_shl1(Ai[rr]);
+      rr_ = Br[rr]; ri = Bi[rr]; sr = Nr[rr]; si = Ni[rr];
     }
     Ar[rr] = fma(pa, pr_, fma(war, qr, -wai * qi));
     Ai[rr] = fma(pa, pi_, fma(war, qi, wai * qr));
