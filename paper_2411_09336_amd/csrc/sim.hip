@@ -318,7 +318,14 @@ __device__ __forceinline__ bool jacobi_round(double (&Ar)[kSvRows], double (&Ai)
         // this per-round critical path
         const double rg = rsqrt(g2);
         const double zeta = 0.5 * (b - a) * rg;
-        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(fma(zeta, zeta, 1.0)));
+        // t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)); the denominator is >= 1, so
+        // its reciprocal is the hardware estimate refined by two Newton steps
+        // (the rotation is orthogonal for any t: c and s follow from t)
+        const double den = fabs(zeta) + sqrt(fma(zeta, zeta, 1.0));
+        double rd = __builtin_amdgcn_rcp(den);
+        rd = fma(rd, fma(-den, rd, 1.0), rd);
+        rd = fma(rd, fma(-den, rd, 1.0), rd);
+        const double t = zeta >= 0.0 ? rd : -rd;
         c = rsqrt(fma(t, t, 1.0));
         s = c * t;
         ur = x * rg;
