@@ -713,10 +713,30 @@ __device__ inline void tile_fence(double (&v)[2][4]) {
     for (int e = 0; e < 4; ++e) asm volatile("" : "+v"(v[q][e])::"memory");
 }
 
+// A pointer that is the same in every lane, moved to scalar registers.
+template <typename T>
+__device__ inline T *uniform_ptr(T *p) {
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  return reinterpret_cast<T *>((uint64_t(__builtin_amdgcn_readfirstlane(uint32_t(v >> 32))) << 32) |
+                               uint32_t(__builtin_amdgcn_readfirstlane(uint32_t(v))));
+}
+
+// Fragments are read with buffer loads through a descriptor of the whole
+// site block (scalar base, 32-bit lane offset, scalar fragment offset): no
+// 64-bit vector address arithmetic per fragment, and a read outside the
+// block's bytes returns zero.  Word 3 is the gfx9-family raw-buffer format.
+typedef __amdgpu_buffer_rsrc_t SiteRsrc;
+__device__ inline SiteRsrc site_rsrc(const uint8_t *site) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t *>(uniform_ptr(site)), 0, int(kI8SiteBytes),
+                                           0x00020000);
+}
+
 // Fragment (s, slice k, plane q, column block ct) of a packed int8 site block.
-__device__ inline uint4 i8_frag(const uint8_t *site, int s, int k, int q, int ct, int lane) {
-  return gload_u4(site + kI8ExpBytes + kI8SumBytes + size_t(((s * 4 + k) * 2 + q) * 4 + ct) * kI8FragBytes +
-                  lane * 16);
+__device__ inline uint4 i8_frag(SiteRsrc site, int s, int k, int q, int ct, int lane) {
+  const int frag = kI8ExpBytes + kI8SumBytes + (((s * 4 + k) * 2 + q) * 4 + ct) * kI8FragBytes;
+  typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+  const v4u v = __builtin_amdgcn_raw_buffer_load_b128(site, lane * 16, frag, 0);
+  return make_uint4(v.x, v.y, v.z, v.w);
 }
 
 // Class accumulators of one complex 16 x 16 tile: class c holds the digit
@@ -806,10 +826,11 @@ struct I8Operand {
 };
 
 __device__ inline void i8_load(const I8Ctx &C, const uint8_t *site, int s, I8Operand &o) {
+  const SiteRsrc r = site_rsrc(site);
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    o.f[k] = i8_frag(site, s, k, 0, C.cb, C.lane);
-    o.f[4 + k] = i8_frag(site, s, k, 1, C.cb, C.lane);
+    o.f[k] = i8_frag(r, s, k, 0, C.cb, C.lane);
+    o.f[4 + k] = i8_frag(r, s, k, 1, C.cb, C.lane);
   }
   o.site = site;
   o.s = s;
@@ -838,7 +859,9 @@ __device__ inline void i8_gemm1(const I8Ctx &C, const I8Operand &Bs, const uint8
   for (int rt = 0; rt < 4; ++rt) {
     // re = Er Br - Ei Bi = Er Br + (~Ei) Bi + colsum(Bi) ; im = Er Bi + Ei Br
     I8Acc acc;
+    __builtin_amdgcn_s_setprio(1);
     i8_block_lds<true>(Ebuf + size_t(rt * 8) * kI8FragBytes + C.lane * 16, Br, Bi, acc);
+    __builtin_amdgcn_s_setprio(0);
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int ex = s_ea[16 * rt + 4 * C.g + e] + ebc - 46;
@@ -887,7 +910,9 @@ __device__ inline void i8_gemm2(const I8Ctx &C, const I8Operand &As, const uint8
   for (int bt = 0; bt < 4; ++bt) {
     // re = Tr Ar + Ti Ai ; im = Ti Ar - Tr Ai = Ti Ar + (~Tr) Ai + colsum(Ai)
     I8Acc acc;
+    __builtin_amdgcn_s_setprio(1);
     i8_block_lds<false>(Tbuf + size_t(bt * 8) * kI8FragBytes + C.lane * 16, Ar, Ai, acc);
+    __builtin_amdgcn_s_setprio(0);
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int ex = s_eTs[16 * bt + 4 * C.g + e] + eac - 46;
@@ -923,10 +948,10 @@ __device__ void overlap_i8(const GramJobDev &J, int64_t ia, int64_t ib, uint8_t 
   }
   const int col = 16 * C.cb + C.j;
   I8Operand P0, P1;   // operands of the current and the next GEMM
-  i8_load(C, bbase + gview(J.b_off)[0], 0, P0);
+  i8_load(C, uniform_ptr(bbase + gview(J.b_off)[0]), 0, P0);
   for (int l = 0; l < J.m; ++l) {
-    const uint8_t *A = abase + gview(J.a_off)[l];
-    const uint8_t *B = bbase + gview(J.b_off)[l];
+    const uint8_t *A = uniform_ptr(abase + gview(J.a_off)[l]);
+    const uint8_t *B = uniform_ptr(bbase + gview(J.b_off)[l]);
     double Td[4][2][4], Ep[4][2][4];
     double tmax;
     // I
@@ -956,7 +981,7 @@ __device__ void overlap_i8(const GramJobDev &J, int64_t ia, int64_t ib, uint8_t 
     i8_gemm2(C, P0, Y, s_eT, Ep);
     __syncthreads();
     // III
-    if (l + 1 < J.m) i8_load(C, bbase + gview(J.b_off)[l + 1], 0, P0);
+    if (l + 1 < J.m) i8_load(C, uniform_ptr(bbase + gview(J.b_off)[l + 1]), 0, P0);
     i8_gemm2(C, P1, X, s_eT + kSP, Ep);
     if (l + 1 == J.m) {
       // E_m[0][0] = E'^T[0][0]: wave 0, lane 0, tile 0, e = 0
