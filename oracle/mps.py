@@ -23,6 +23,11 @@ discarded relative weight.
 
 Finally the centre is swept to the last site (left-canonical form) and the
 last tensor is normalised to unit norm.
+
+Memory trace (the memory evolution of Sec. III-A, Fig. 6): after every
+two-qubit gate the result records the bond dimension at the gate's cut and
+sum_l D_l D_{l+1} over all sites, so the FP64 tensors take 32 bytes times
+that sum (two physical values, 16-byte complex entries).
 """
 from __future__ import annotations
 
@@ -45,6 +50,7 @@ class MPSResult:
     degenerate_cuts: int = 0          # truncations with a near-degenerate cut
     n_svd: int = 0
     max_bond_seen: int = 1
+    trace: List[tuple] = field(default_factory=list)   # per two-qubit gate: (cut bond, sum_l D_l D_{l+1})
 
     @property
     def bond_dims(self) -> List[int]:
@@ -161,6 +167,7 @@ def simulate(x: np.ndarray, d: int, reps: int, chi: int, cutoff: float,
         p_next = nxt[gi]
         absorb_right = p_next is None or p_next > p
         apply_two_qubit(A, p, u4, chi, cutoff, absorb_right, res)
+        res.trace.append((A[p].shape[2], sum(t.shape[0] * t.shape[2] for t in A)))
         center = p + 1 if absorb_right else p
     move_center(A, center, m - 1)
     A[m - 1] = A[m - 1] / np.linalg.norm(A[m - 1])

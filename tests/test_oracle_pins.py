@@ -156,6 +156,40 @@ def test_rxx_only_gives_all_ones():
     assert np.allclose(K, 1.0, atol=1e-12)
 
 
+# ---------------------------------------------------------------- memory trace (Fig. 6)
+@pytest.mark.parametrize("m,d,reps,routing", [(7, 2, 2, 0), (8, 3, 1, 1), (6, 5, 2, 0), (8, 2, 2, 1)])
+def test_trace_cut_bond_is_schmidt_rank(m, d, reps, routing):
+    """After every two-qubit gate, the recorded bond at the gate's cut is the
+    Schmidt rank (discarded tail weight <= cutoff, Eq. (8)) of the state
+    vector obtained by applying the same gate prefix, SWAPs included, across
+    that cut; the memory sum of the last gate is that of the final tensors."""
+    rng = np.random.default_rng(7 * m + d + routing)
+    x = rng.random(m)
+    cutoff = 1e-12
+    glist = circuit.build_gate_list(m, d, reps, routing)
+    r = mps.simulate(x, d, reps, 64, cutoff, routing=routing, glist=glist)
+    two_q = [i for i, rec in enumerate(glist) if int(rec[0]) != circuit.OP_RZ]
+    assert len(r.trace) == len(two_q)
+    for g, gi in enumerate(two_q):
+        p = int(glist[gi][1])
+        psi = sv.state_from_gate_list(x, glist[:gi + 1], 2.0, 2.0)
+        s = np.linalg.svd(psi.reshape(2 ** (p + 1), -1), compute_uv=False)
+        w = s ** 2
+        tail = np.concatenate([np.cumsum(w[::-1])[::-1], [0.0]])
+        rank = next(k for k in range(len(w) + 1) if tail[k] <= cutoff * w.sum())
+        assert r.trace[g][0] == max(1, rank), (g, p)
+    assert r.trace[-1][1] == sum(t.shape[0] * t.shape[2] for t in r.tensors)
+
+
+def test_trace_of_product_states():
+    """coef_xx = 0: every bond stays 1, so each entry is (1, m)."""
+    x = sd.make_uniform(1, 40, seed=9)[0]
+    r = mps.simulate(x, 4, 2, 64, 1e-12, coef_z=2.0, coef_xx=0.0, routing=1)
+    _, n_rxx, n_swap = circuit.gate_counts_closed_form(40, 4, 2, 1)
+    assert len(r.trace) == n_rxx + n_swap
+    assert set(r.trace) == {(1, 40)}
+
+
 # ---------------------------------------------------------------- Eq. (8)
 def test_single_truncation_fidelity_eq8():
     """Truncating one bond of a normalised canonical state: |<psi|psi_tr>|^2 = 1 - eps."""
