@@ -204,6 +204,10 @@ def main():
                     help="only time the symmetric Gram of N random saturated 165-site chi=64 MPS in every "
                          "form (kernel microbenchmark, no simulation), then exit")
     ap.add_argument("--form", choices=sorted(FORMS), default="split_i8", help="form of the timed Gram")
+    ap.add_argument("--d-sweep", action="store_true",
+                    help="interaction-distance sweep (100 qubits, gamma 1, d = 2..12, 8 points each): "
+                         "simulation and overlap times, largest bond and memory per MPS, against the CPU "
+                         "oracle where it finishes in seconds; one JSON line, then exit")
     ap.add_argument("--counter-record", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="only write profiles/gram_<form>_counters.json from rocprofv3 counter CSVs of "
                          "'--slabs-run 1' runs (no GPU use), then exit")
@@ -233,7 +237,25 @@ def main():
     if args.kernel_probe > 0:
         kernel_probe(args.kernel_probe)
         return
+    if args.d_sweep:
+        d_sweep(args.routing, args.no_cpu)
+        return
     run(args)
+
+
+# decade bins of K: [0, 1e-16), [1e-16, 1e-15), ..., [0.1, 1]
+K_HIST_EDGES = tuple(range(-16, 1))
+
+
+def k_histogram(values):
+    """Counts of K values per decade bin (K_HIST_EDGES; values below 1e-16,
+    zero included, in the first bin, K = 1 in the last)."""
+    import numpy as np
+    v = np.asarray(values, dtype=np.float64).ravel()
+    lg = np.log10(np.maximum(v, 1e-300))
+    b = np.clip(np.floor(lg).astype(np.int64) - K_HIST_EDGES[0] + 1, 0, len(K_HIST_EDGES) - 1)
+    b[lg >= 0] = len(K_HIST_EDGES) - 1
+    return np.bincount(b, minlength=len(K_HIST_EDGES)).astype(int).tolist()
 
 
 def random_saturated_mps(m, chi, rng):
@@ -276,6 +298,66 @@ def kernel_probe(n):
             ref = K.clone()
         log(f"[bench] probe {prec}: n={n}, {pairs} entries in {dt:.3f} s -> {pairs / dt:.1f} entries/s; "
             f"max|dK| vs fp64 {(K - ref).abs().max().item():.3e}")
+
+
+def d_sweep(routing, no_cpu):
+    """Resource scaling with the interaction distance (Sec. III-A, Fig. 5, Table I): for each d, 8 synthetic
+    points on 100 qubits, reps 2, gamma 1 (coef_z 2, coef_xx pi), truncation at discarded weight 1e-16 and
+    the bond cap 64: simulation time of the 8 circuits (one workgroup each, run side by side), time per
+    inner product of their 8 x 8 Gram (28 off-diagonal entries, FP64 and split-int8), average largest final
+    bond and memory per MPS; the CPU oracle simulates the same circuits where it takes seconds (d <= 4) and
+    gives the same bond profiles and K."""
+    import numpy as np
+    import torch
+
+    import paper_2411_09336_amd as q
+    import synthdata as sd
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    base = sd.Workload("d_sweep", 8, 100, 2, 2, 64, 1e-16, coef_z=2.0, coef_xx=np.pi, n_dirs=10, mean_scale=0.3)
+    X = sd.workload_features(base)
+    rows = []
+    for d in (2, 4, 6, 8, 10, 12):
+        spec = q.CircuitSpec(100, d, 2, base.coef_z, base.coef_xx, routing)
+        xt = torch.tensor(X, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b = q.simulate(xt, spec, base.chi, base.cutoff, stream=stream)
+        stream.synchronize()
+        t_sim = time.perf_counter() - t0
+        dims = b.bond_dims()
+        row = {"d": d, "two_qubit_gates": b.info()["n_two_qubit_gates"], "sim_s_8_circuits": round(t_sim, 3),
+               "avg_largest_bond": float(dims.max(1).mean()),
+               "mib_per_mps": round(float(np.mean(np.sum(dims[:, :-1] * dims[:, 1:], 1))) * 32 / 2 ** 20, 4)}
+        for prec in ("fp64", "split_i8"):
+            q.gram(b, precision=prec, stream=stream)
+            stream.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            K = q.gram(b, precision=prec, stream=stream)
+            e1.record(stream)
+            e1.synchronize()
+            row[f"gram_{prec}_ms_36_entries"] = round(e0.elapsed_time(e1), 3)
+            if prec == "fp64":
+                Kd = K.cpu().numpy()
+            else:
+                row["split_i8_vs_fp64_max_dK"] = float(np.abs(K.cpu().numpy() - Kd).max())
+        if not no_cpu and d <= 4:
+            from oracle import gram as ogram
+            from oracle import mps as omps
+            t0 = time.perf_counter()
+            res = [omps.simulate(x, d, 2, base.chi, base.cutoff, base.coef_z, base.coef_xx, routing=routing)
+                   for x in X]
+            row["oracle_sim_s_8_circuits"] = round(time.perf_counter() - t0, 2)
+            row["oracle_avg_largest_bond"] = float(np.mean([max(r.bond_dims) for r in res]))
+            row["oracle_bond_profiles_equal"] = int(sum(list(dims[i]) == r.bond_dims for i, r in enumerate(res)))
+            row["oracle_max_dK_fp64"] = float(np.abs(ogram.gram([r.tensors for r in res]) - Kd).max())
+        log(f"[bench] d-sweep {row}")
+        rows.append(row)
+        del b
+    print(json.dumps({"d_sweep": rows, "workload": "100 qubits, reps 2, gamma 1 (coef_z 2, coef_xx pi), "
+                      "cutoff 1e-16, bond cap 64, 8 synthetic points per d", "routing": routing}), flush=True)
 
 
 def calibrate_copy(nbytes):
@@ -502,6 +584,32 @@ def run(args):
     t_point = time.time() - t0
     log(f"[bench] new point end to end: simulation {t_sim1:.2f} s, with its 1 x {N} row {t_point:.2f} s")
 
+    # (v) memory evolution during simulation (Fig. 6's circuits: 100 qubits, d = 6 and 12, gamma = 1,
+    # 8 samples each): MPS memory after every two-qubit gate from the library's trace
+    memtrace = {}
+    for name in ("fig6_d6", "fig6_d12"):
+        wf = sd.WORKLOADS[name]
+        xf = torch.tensor(sd.workload_features(wf), dtype=torch.float64, device="cuda")
+        specf = q.CircuitSpec(wf.n_qubits, wf.distance, wf.reps, wf.coef_z, wf.coef_xx, args.routing)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        bf, trf = q.simulate_trace(xf, specf, wf.chi, wf.cutoff, stream=stream)
+        stream.synchronize()
+        t_f = time.perf_counter() - t0
+        mib = trf[:, :, 1].double().cpu().numpy() * 32 / 2 ** 20      # FP64 tensors, MiB
+        g2 = mib.shape[1]
+        at = [min(g2 - 1, max(0, int(round(f * g2)) - 1)) for f in np.linspace(0.1, 1.0, 10)]
+        memtrace[name] = {"circuits": int(mib.shape[0]), "two_qubit_gates": g2, "seconds": round(t_f, 2),
+                          "max_bond": bf.info()["max_bond"],
+                          "mib_at_10pct_steps_mean": [round(float(v), 3) for v in mib[:, at].mean(0)],
+                          "mib_at_10pct_steps_min": [round(float(v), 3) for v in mib[:, at].min(0)],
+                          "mib_at_10pct_steps_max": [round(float(v), 3) for v in mib[:, at].max(0)],
+                          "peak_mib_mean": round(float(mib.max(1).mean()), 3),
+                          "final_mib_mean": round(float(mib[:, -1].mean()), 3)}
+        log(f"[bench] memory trace {name}: {g2} gates in {t_f:.1f} s, max bond {memtrace[name]['max_bond']}, "
+            f"mean MiB at 10 % steps {memtrace[name]['mib_at_10pct_steps_mean']}")
+        del bf, trf
+
     # ---------------------------------------------------------------- 5. CPU oracle
     cpu = None
     dk_oracle = None
@@ -569,7 +677,12 @@ def run(args):
         "inference": {"row_entries": N, "ms": round(t_row * 1e3, 3), "entries_per_s": round(N / t_row, 1),
                       "new_point_simulation_s": round(t_sim1, 3), "new_point_end_to_end_s": round(t_point, 3)},
         "K_distribution": {"offdiag_median": float(np.median(offd)), "offdiag_max": float(offd.max()),
-                           "offdiag_frac_above_1e-6": float((offd > 1e-6).mean())},
+                           "offdiag_frac_above_1e-6": float((offd > 1e-6).mean()),
+                           "hist_edges_log10": list(K_HIST_EDGES),
+                           "hist_offdiag": k_histogram(offd),
+                           "hist_near_duplicates": k_histogram(nd_diag.cpu().numpy()),
+                           "hist_paper_bandwidth": k_histogram(offp)},
+        "memory_trace": memtrace,
         "simulation": {"circuits": n_sim, "seconds": round(t_sim, 2), "circuits_per_s": round(n_sim / t_sim, 3),
                        "two_qubit_gates_per_circuit": info["n_two_qubit_gates"],
                        "two_qubit_gates_per_s": round(n_sim * info["n_two_qubit_gates"] / t_sim, 1),

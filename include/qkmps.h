@@ -155,6 +155,24 @@ qk_status mps_simulate_progress(const double *features_dev, int64_t n_points,
                                 qk_progress_fn fn, void *user, int64_t every,
                                 qk_mps_batch **out);
 
+/* mps_simulate that also records how the MPS grows during the simulation
+ * (the memory evolution of Sec. III-A, Fig. 6).  After the g-th two-qubit
+ * gate of circuit i (g counted from 0 in circuit order, SWAPs included, as
+ * in qk_circuit_compile without its Rz records), two int32 values are
+ * written to trace_dev[(i * n2q + g) * 2 + {0, 1}]:
+ *   [0] the bond dimension at the gate's cut (between its sites p, p+1);
+ *   [1] sum_l D_l D_{l+1} over the MPS, i.e. its FP64 tensors take
+ *       32 bytes times this value (2 physical values, 16-byte complex).
+ * Both reflect every truncation and centre move up to that gate.
+ * trace_dev is caller-owned device memory of n_points * n2q * 2 int32,
+ * where n2q is the number of two-qubit gates of `spec`; it may be NULL only
+ * if that product is 0 (QK_EINVAL otherwise).  The batch is bit-identical to
+ * mps_simulate's. */
+qk_status mps_simulate_trace(const double *features_dev, int64_t n_points,
+                             const qk_circuit_spec *spec, int32_t chi_max,
+                             double cutoff, int32_t *trace_dev,
+                             void *hip_stream, qk_mps_batch **out);
+
 /* mps_simulate with the kernel launches recorded as HIP graphs: the launches
  * of every `gates_per_graph` two-qubit gates (0: the whole circuit) are
  * captured on a private stream, instantiated and launched as one graph,

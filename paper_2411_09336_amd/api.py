@@ -95,6 +95,7 @@ def _load():
         "mps_simulate": (S, [P, I64, C.POINTER(_Spec), I32, D, P, C.POINTER(P)]),
         "mps_simulate_progress": (S, [P, I64, C.POINTER(_Spec), I32, D, P, _PROGRESS, P, I64, C.POINTER(P)]),
         "mps_simulate_graph": (S, [P, I64, C.POINTER(_Spec), I32, D, I64, P, C.POINTER(P)]),
+        "mps_simulate_trace": (S, [P, I64, C.POINTER(_Spec), I32, D, P, P, C.POINTER(P)]),
         "mps_gram": (S, [P, P, C.c_int, P, I64, P]),
         "mps_gram_block": (S, [P, I64, I64, P, I64, I64, I32, C.c_int, P, I64, P]),
         "mps_gram_multi": (S, [C.POINTER(_Job), I32, C.c_int, P]),
@@ -299,6 +300,26 @@ def simulate(features, spec: CircuitSpec, chi: int, cutoff: float, stream=None, 
                                              float(cutoff), _stream_ptr(stream), cb, None, int(every),
                                              C.byref(h)))
     return MPSBatch(h.value)
+
+
+def simulate_trace(features, spec: CircuitSpec, chi: int, cutoff: float, stream=None):
+    """``simulate`` that also returns the memory trace: an int32 CUDA tensor
+    (n, n_two_qubit_gates, 2) holding, after each two-qubit gate, the bond
+    dimension at its cut and sum_l D_l D_{l+1} over the MPS (its FP64 tensors
+    take 32 bytes times that value)."""
+    import torch
+    if not isinstance(features, torch.Tensor) or features.device.type != "cuda":
+        raise TypeError("features must be a CUDA tensor")
+    x = features.to(torch.float64).contiguous()
+    if x.dim() != 2 or x.shape[1] != spec.n_qubits:
+        raise ValueError("features must be n x n_qubits")
+    n2q = int((circuit_compile(spec)[:, 0] != 0).sum())
+    trace = torch.zeros((x.shape[0], n2q, 2), dtype=torch.int32, device=x.device)
+    cs = spec._c()
+    h = C.c_void_p(0)
+    _check(_load().mps_simulate_trace(C.c_void_p(x.data_ptr()), x.shape[0], C.byref(cs), int(chi), float(cutoff),
+                                      C.c_void_p(trace.data_ptr()), _stream_ptr(stream), C.byref(h)))
+    return MPSBatch(h.value), trace
 
 
 def autotune(batch: MPSBatch, precision="fp64", sample: int = 64, stream=None) -> dict:

@@ -228,12 +228,26 @@ qk_status mps_simulate(const double *features_dev, int64_t n_points, const qk_ci
 
 static qk_status simulate_impl(const double *features_dev, int64_t n_points, const qk_circuit_spec *spec,
                                int32_t chi_max, double cutoff, void *hip_stream, qk_progress_fn fn, void *user,
-                               int64_t every, int64_t graph_gates, qk_mps_batch **out);
+                               int64_t every, int64_t graph_gates, int32_t *trace_dev, qk_mps_batch **out);
 
 qk_status mps_simulate_progress(const double *features_dev, int64_t n_points, const qk_circuit_spec *spec,
                                 int32_t chi_max, double cutoff, void *hip_stream, qk_progress_fn fn, void *user,
                                 int64_t every, qk_mps_batch **out) {
-  return simulate_impl(features_dev, n_points, spec, chi_max, cutoff, hip_stream, fn, user, every, 0, out);
+  return simulate_impl(features_dev, n_points, spec, chi_max, cutoff, hip_stream, fn, user, every, 0, nullptr, out);
+}
+
+qk_status mps_simulate_trace(const double *features_dev, int64_t n_points, const qk_circuit_spec *spec,
+                             int32_t chi_max, double cutoff, int32_t *trace_dev, void *hip_stream,
+                             qk_mps_batch **out) {
+  if (!out) return fail(QK_EINVAL, "out is NULL");
+  *out = nullptr;
+  const qk_status st = validate_spec(spec);
+  if (st != QK_OK) return st;
+  int64_t n2q = 0;
+  for (const auto &g : compile_circuit(*spec)) n2q += g.op != 0 ? 1 : 0;   // op 0: Rz
+  if (n_points > 0 && n2q > 0 && !trace_dev) return fail(QK_EINVAL, "trace_dev is NULL");
+  return simulate_impl(features_dev, n_points, spec, chi_max, cutoff, hip_stream, nullptr, nullptr, 0, 0,
+                       trace_dev, out);
 }
 
 qk_status mps_simulate_graph(const double *features_dev, int64_t n_points, const qk_circuit_spec *spec,
@@ -241,12 +255,12 @@ qk_status mps_simulate_graph(const double *features_dev, int64_t n_points, const
                              qk_mps_batch **out) {
   if (gates_per_graph < 0) return fail(QK_EINVAL, "gates_per_graph < 0");
   return simulate_impl(features_dev, n_points, spec, chi_max, cutoff, hip_stream, nullptr, nullptr, 0,
-                       gates_per_graph == 0 ? INT64_MAX : gates_per_graph, out);
+                       gates_per_graph == 0 ? INT64_MAX : gates_per_graph, nullptr, out);
 }
 
 static qk_status simulate_impl(const double *features_dev, int64_t n_points, const qk_circuit_spec *spec,
                                int32_t chi_max, double cutoff, void *hip_stream, qk_progress_fn fn, void *user,
-                               int64_t every, int64_t graph_gates, qk_mps_batch **out) {
+                               int64_t every, int64_t graph_gates, int32_t *trace_dev, qk_mps_batch **out) {
   if (!out) return fail(QK_EINVAL, "out is NULL");
   *out = nullptr;
   qk_status st = validate_spec(spec);
@@ -269,7 +283,8 @@ static qk_status simulate_impl(const double *features_dev, int64_t n_points, con
   st = batch_create(n_points, m, pad, stream, &b);
   if (st != QK_OK) return st;
   auto gates = compile_circuit(*spec);
-  st = run_simulation(b, features_dev, gates, *spec, chi_max, cutoff, stream, fn, user, every, graph_gates);
+  st = run_simulation(b, features_dev, gates, *spec, chi_max, cutoff, stream, fn, user, every, graph_gates,
+                      trace_dev);
   if (st != QK_OK) {
     batch_release(b);
     return st;

@@ -77,6 +77,8 @@ struct SvParams {
   int32_t *degen;
   int32_t *unconv;
   int64_t n;
+  int32_t *trace;     // optional: per circuit and two-qubit gate (cut bond, sum_l D_l D_{l+1})
+  int32_t trace_n2q;  // two-qubit gates per circuit (row length of the trace / 2)
 };
 
 // DPP lane moves of a double.  Lanes without a source lane receive zero
@@ -372,7 +374,8 @@ enum StepKind { STEP_RZ = 0, STEP_TWO_SITE = 1 };
 struct SimStep {
   int32_t kind;
   int32_t p, mode, op, fi, fj;  // two-site step: sites (p, p+1), SvMode, GateOp, features of Rxx
-  int32_t r0, nr;               // Rz run: gate records [r0, r0 + nr)
+  int32_t r0, nr;               // Rz run: gate records [r0, r0 + nr); two-site step: r0 = index of
+                                // the two-qubit gate among the circuit's (-1 for a centre move)
 };
 
 // Two-site step of circuit ci (one 1024-thread workgroup).
@@ -800,6 +803,21 @@ __global__ __launch_bounds__(kSvThreads) void sim_steps_kernel(SvParams P, const
     if (st.kind == STEP_RZ) rz_run(P, ci, recs + st.r0, st.nr, coef_z);
     else svd_step(P, ci, st);
     __syncthreads();  // the next step reads the tensors and bond dims this one wrote
+    if (P.trace && st.kind == STEP_TWO_SITE && st.r0 >= 0 && threadIdx.x < 64) {
+      // memory trace after a two-qubit gate: the bond at its cut and
+      // sum_l D_l D_{l+1} (complex entries per physical index) over the MPS.
+      // Only reads of the bond dims, which the next step's first thread
+      // rewrites after this wave has passed here.
+      const int32_t *dims = P.dims + ci * (P.m + 1);
+      int acc = 0;
+      for (int l = threadIdx.x; l < P.m; l += 64) acc += dims[l] * dims[l + 1];
+      for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+      if (threadIdx.x == 0) {
+        int32_t *t = P.trace + (ci * P.trace_n2q + st.r0) * 2;
+        t[0] = dims[st.p + 1];
+        t[1] = acc;
+      }
+    }
   }
 }
 
@@ -843,7 +861,7 @@ __global__ void normalize_last_kernel(double2 *f64, int64_t mps_stride, const in
 
 qk_status run_simulation(qk_mps_batch *b, const double *features_dev, const std::vector<qk_gate> &gates,
                          const qk_circuit_spec &spec, int chi, double cutoff, hipStream_t stream_in, qk_progress_fn fn,
-                         void *user, int64_t every, int64_t graph_gates) {
+                         void *user, int64_t every, int64_t graph_gates, int32_t *trace) {
   const int64_t n = b->n;
   const int m = b->m;
   int n2q = 0;
@@ -897,6 +915,8 @@ qk_status run_simulation(qk_mps_batch *b, const double *features_dev, const std:
   P.degen = b->degen_dev;
   P.unconv = b->unconv_dev;
   P.n = n;
+  P.trace = trace;
+  P.trace_n2q = n2q;
 
 
   // HIP-graph mode: the launches of every `graph_gates` two-qubit gates are
@@ -968,16 +988,17 @@ qk_status run_simulation(qk_mps_batch *b, const double *features_dev, const std:
         continue;
       }
       const int p = gates[gi].site;
-      for (; center < p; ++center) push({STEP_TWO_SITE, center, MOVE_RIGHT, OP_ID, -1, -1, 0, 0}, 0);
-      for (; center > p + 1; --center) push({STEP_TWO_SITE, center - 1, MOVE_LEFT, OP_ID, -1, -1, 0, 0}, 0);
+      for (; center < p; ++center) push({STEP_TWO_SITE, center, MOVE_RIGHT, OP_ID, -1, -1, -1, 0}, 0);
+      for (; center > p + 1; --center) push({STEP_TWO_SITE, center - 1, MOVE_LEFT, OP_ID, -1, -1, -1, 0}, 0);
       const bool absorb_right = next2q[gi] < 0 || next2q[gi] > p;
       push({STEP_TWO_SITE, p, absorb_right ? GATE_RIGHT : GATE_LEFT, gates[gi].op == 1 ? OP_RXX : OP_SWAP,
-            gates[gi].feat_i, gates[gi].feat_j, 0, 0},
-           ++d2q);
+            gates[gi].feat_i, gates[gi].feat_j, int32_t(d2q), 0},
+           d2q + 1);
+      ++d2q;
       center = absorb_right ? p + 1 : p;
       ++gi;
     }
-    for (; center < m - 1; ++center) push({STEP_TWO_SITE, center, MOVE_RIGHT, OP_ID, -1, -1, 0, 0}, 0);
+    for (; center < m - 1; ++center) push({STEP_TWO_SITE, center, MOVE_RIGHT, OP_ID, -1, -1, -1, 0}, 0);
   }
   SimStep *steps_dev = nullptr;
   qk_status st = QK_OK;

@@ -53,6 +53,13 @@ WORKLOADS = {
     # coef_xx = gamma^2 pi), d = 1, two repetitions.
     "paper_d1": Workload("paper_d1", 6400, 165, 1, 2, 64, 1e-8,
                          coef_z=0.2, coef_xx=0.01 * np.pi, n_dirs=10, mean_scale=0.3),
+    # memory evolution during simulation (the setting of Fig. 6): 100 qubits,
+    # d = 6 and d = 12, two repetitions, gamma = 1 (coef_z = 2, coef_xx = pi),
+    # truncation at discarded weight 1e-16; 8 samples each, bond cap 64.
+    "fig6_d6": Workload("fig6_d6", 8, 100, 6, 2, 64, 1e-16,
+                        coef_z=2.0, coef_xx=np.pi, n_dirs=10, mean_scale=0.3),
+    "fig6_d12": Workload("fig6_d12", 8, 100, 12, 2, 64, 1e-16,
+                         coef_z=2.0, coef_xx=np.pi, n_dirs=10, mean_scale=0.3),
 }
 
 

@@ -244,3 +244,36 @@ def test_graph_captured_simulation_bit_identical():
         K1 = q.gram(g, precision="fp64")
         K0 = q.gram(ref, precision="fp64")
         assert torch.equal(K1, K0)
+
+
+@pytest.mark.parametrize("routing", [0, 1])
+def test_memory_trace_vs_oracle(routing):
+    """mps_simulate_trace: after every two-qubit gate, the bond at the gate's
+    cut and sum_l D_l D_{l+1} (Fig. 6's memory, in units of 32 bytes) equal
+    the oracle's for circuits without a near-degenerate cut; the batch is the
+    one mps_simulate gives, bit for bit; the last entry matches the final
+    bond profile."""
+    import paper_2411_09336_amd as q
+    torch = require_gpu()
+    w = sd.WORKLOADS["fp32"]
+    X = sd.workload_features(w, 4)
+    xt = torch.tensor(X, dtype=torch.float64, device="cuda")
+    spec = q.CircuitSpec(w.n_qubits, w.distance, w.reps, w.coef_z, w.coef_xx, routing)
+    b, trace = q.simulate_trace(xt, spec, w.chi, w.cutoff)
+    ref = q.simulate(xt, spec, w.chi, w.cutoff)
+    tr = trace.cpu().numpy()
+    n2q = int((q.circuit_compile(spec)[:, 0] != 0).sum())
+    assert tr.shape == (4, n2q, 2)
+    assert np.array_equal(b.bond_dims(), ref.bond_dims())
+    _, deg = b.trunc_stats()
+    for i in range(len(X)):
+        assert all(np.array_equal(s, t) for s, t in zip(b.export(i), ref.export(i)))
+        dims = b.bond_dims()[i]
+        assert tr[i, -1, 1] == int(np.sum(dims[:-1] * dims[1:]))
+        r = omps.simulate(X[i], w.distance, w.reps, w.chi, w.cutoff, w.coef_z, w.coef_xx, routing=routing)
+        mine = [tuple(int(v) for v in e) for e in tr[i]]
+        same = sum(a == c for a, c in zip(mine, r.trace))
+        print("routing", routing, "circuit", i, "entries equal", same, "/", n2q, "degenerate", deg[i],
+              r.degenerate_cuts, "peak memory MiB", 32 * tr[i, :, 1].max() / 2 ** 20)
+        if deg[i] == 0 and r.degenerate_cuts == 0:
+            assert mine == r.trace
