@@ -662,9 +662,15 @@ __device__ void overlap_split(const GramJobDev &J, int64_t ia, int64_t ib, uint8
 // four-value slice word.
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 
-// The sign-definite (2, 2) digit pair costs 9 % of the MFMAs; without it the
-// kernel is 9 % faster but max |dK| on 165-site chi = 64 states grows from
-// 2.7e-9 to 4.0e-7 (a one-signed bias on self-overlaps), so it is kept.
+// The (2, 2) digit pair (weight 2^-32, like the omitted (1, 3) and (3, 1))
+// is kept in GEMM2 only.  There, for a bra equal (or close) to the ket, T is
+// the site tensor itself (E = I for left-canonical states) and the pair's
+// products are sums of squares: dropping it biases every self-overlap one
+// way (max |dK| on 165-site chi = 64 states 2.7e-9 -> 4.0e-7).  In GEMM1 the
+// LDS operand is E, whose digit 2 vanishes for E = I and whose products with
+// the site digits carry no common sign, so the pair is omitted there (CPU
+// emulation on 100-site chi = 64 states: max |dK| 1.8e-8 -> 2.3e-8, the
+// diagonal unchanged at 1.8e-8; dropping it in GEMM2: 2.6e-6).
 #ifndef QK_I8_PAIR22
 #define QK_I8_PAIR22 1
 #endif
@@ -749,8 +755,9 @@ struct I8Acc {
 // fragments (digit a, plane 0 / 1) at (2 a + q) KiB).  CPL1: complement plane 1
 // in the real part (GEMM1: re += X0 Y0 + (~X1) Y1, im += X0 Y1 + X1 Y0);
 // otherwise complement plane 0 in the imaginary part (GEMM2: re += X0 Y0 +
-// X1 Y1, im += (~X0) Y1 + X1 Y0).  Only one digit's operands are live.
-template <bool CPL1>
+// X1 Y1, im += (~X0) Y1 + X1 Y0).  P22: include the (2, 2) pair (class 4).
+// Only one digit's operands are live.
+template <bool CPL1, bool P22>
 __device__ inline void i8_block_lds(const uint8_t *tg, const uint4 (&Y0)[4], const uint4 (&Y1)[4], I8Acc &acc) {
 #pragma unroll
   for (int c = 0; c < 5; ++c) {
@@ -762,8 +769,8 @@ __device__ inline void i8_block_lds(const uint8_t *tg, const uint4 (&Y0)[4], con
     const uint4 x0 = *reinterpret_cast<const uint4 *>(tg + (a * 2 + 0) * kI8FragBytes);
     const uint4 x1 = *reinterpret_cast<const uint4 *>(tg + (a * 2 + 1) * kI8FragBytes);
     const uint4 P = x0, Q = CPL1 ? not4(x1) : x1, R = CPL1 ? x0 : not4(x0), S = x1;
-    // digit pairs (a, b) with a + b <= 3, plus (2, 2) in class 4
-    const int nb = a == 0 ? 4 : a == 1 ? 3 : a == 2 ? (QK_I8_PAIR22 ? 3 : 2) : 1;
+    // digit pairs (a, b) with a + b <= 3, plus (2, 2) in class 4 if P22
+    const int nb = a == 0 ? 4 : a == 1 ? 3 : a == 2 ? (P22 ? 3 : 2) : 1;
 #pragma unroll
     for (int b = 0; b < nb; ++b) {
       const int c = (a == 2 && b == 2) ? 4 : a + b;
@@ -776,17 +783,18 @@ __device__ inline void i8_block_lds(const uint8_t *tg, const uint4 (&Y0)[4], con
 }
 
 // Exact digit sum of element e of a class accumulator set, plus correction
-// words, as a double times 2^-32 of the code product scale.
+// words, as a double in units of 2^-32 of the code product scale (P22) or,
+// without class 4, in units of 2^-24 (the caller adds 8 to the exponent).
+template <bool P22>
 __device__ inline double i8_value(const i32x4 (&a)[5], int e, uint32_t chi, uint32_t clo, uint32_t c4) {
   const int hiw = int((uint32_t(a[0][e]) << 8) + uint32_t(a[1][e]) + chi);
   const int low = int((uint32_t(a[2][e]) << 8) + uint32_t(a[3][e]) + clo);
-#if QK_I8_PAIR22
-  const int w4 = int(uint32_t(a[4][e]) + c4);
-  return fma(fma(double(hiw), 65536.0, double(low)), 256.0, double(w4));
-#else
+  if (P22) {
+    const int w4 = int(uint32_t(a[4][e]) + c4);
+    return fma(fma(double(hiw), 65536.0, double(low)), 256.0, double(w4));
+  }
   (void)c4;
-  return fma(double(hiw), 16777216.0, double(low) * 256.0);
-#endif
+  return fma(double(hiw), 65536.0, double(low));
 }
 
 // Class corrections from the column digit sums cs0..cs3 of the operand that
@@ -860,13 +868,14 @@ __device__ inline void i8_gemm1(const I8Ctx &C, const I8Operand &Bs, const uint8
     // re = Er Br - Ei Bi = Er Br + (~Ei) Bi + colsum(Bi) ; im = Er Bi + Ei Br
     I8Acc acc;
     __builtin_amdgcn_s_setprio(1);
-    i8_block_lds<true>(Ebuf + size_t(rt * 8) * kI8FragBytes + C.lane * 16, Br, Bi, acc);
+    i8_block_lds<true, false>(Ebuf + size_t(rt * 8) * kI8FragBytes + C.lane * 16, Br, Bi, acc);
     __builtin_amdgcn_s_setprio(0);
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const int ex = s_ea[16 * rt + 4 * C.g + e] + ebc - 46;
-      const double vr = ldexp(i8_value(acc.re, e, chi, clo, c4), ex);
-      const double vi = ldexp(i8_value(acc.im, e, 0u, 0u, 0u), ex);
+      // a code product is x_E x_B 2^(62 - ea - eb); i8_value<false> counts units of 2^24 of it
+      const int ex = s_ea[16 * rt + 4 * C.g + e] + ebc - 38;
+      const double vr = ldexp(i8_value<false>(acc.re, e, chi, clo, c4), ex);
+      const double vi = ldexp(i8_value<false>(acc.im, e, 0u, 0u, 0u), ex);
       Td[rt][0][e] = vr;
       Td[rt][1][e] = vi;
       tmax = fmax(tmax, fmax(fabs(vr), fabs(vi)));
@@ -911,13 +920,13 @@ __device__ inline void i8_gemm2(const I8Ctx &C, const I8Operand &As, const uint8
     // re = Tr Ar + Ti Ai ; im = Ti Ar - Tr Ai = Ti Ar + (~Tr) Ai + colsum(Ai)
     I8Acc acc;
     __builtin_amdgcn_s_setprio(1);
-    i8_block_lds<false>(Tbuf + size_t(bt * 8) * kI8FragBytes + C.lane * 16, Ar, Ai, acc);
+    i8_block_lds<false, QK_I8_PAIR22>(Tbuf + size_t(bt * 8) * kI8FragBytes + C.lane * 16, Ar, Ai, acc);
     __builtin_amdgcn_s_setprio(0);
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const int ex = s_eTs[16 * bt + 4 * C.g + e] + eac - 46;
-      Ep[bt][0][e] += ldexp(i8_value(acc.re, e, 0u, 0u, 0u), ex);
-      Ep[bt][1][e] += ldexp(i8_value(acc.im, e, chi, clo, c4), ex);
+      const int ex = s_eTs[16 * bt + 4 * C.g + e] + eac - (QK_I8_PAIR22 ? 46 : 38);
+      Ep[bt][0][e] += ldexp(i8_value<QK_I8_PAIR22>(acc.re, e, 0u, 0u, 0u), ex);
+      Ep[bt][1][e] += ldexp(i8_value<QK_I8_PAIR22>(acc.im, e, chi, clo, c4), ex);
     }
     tile_fence(Ep[bt]);
   }
