@@ -41,13 +41,13 @@ PEAK_TFLOPS = {"bf16": 2500.0, "int8": 5000.0, "fp64": 78.6, "fp32": 157.3}
 FORMS = {
     "split_i8": ("int8", "gram_kernel<split_i8,64>",
                  "split-int8: 31-bit fixed-point codes with row/column exponents, four int8 digits, "
-                 "10 (E B) and 11 (T^T conj A) digit products on int8 MFMA, exact int32 accumulation, "
-                 "fp64 combine"),
+                 "10 digit products (11 in the real part of T^T conj A) on int8 MFMA, exact int32 "
+                 "accumulation, fp64 combine"),
     "split_bf16": ("bf16", "gram_kernel<split_bf16,64>",
                    "split-bf16: the same four digits carried as bf16, 11 digit products on bf16 MFMA, "
                    "exact fp32 leading accumulator + fp32 accumulator for the rest, fp64 combine"),
 }
-ISSUED_PER_ALGORITHMIC = {"split_i8": 10.5, "split_bf16": 11.0}
+ISSUED_PER_ALGORITHMIC = {"split_i8": 10.25, "split_bf16": 11.0}
 HBM_PEAK_GBS = 8000.0
 
 
@@ -522,8 +522,9 @@ def run(args):
     achieved_tf = flops_launch / t_split / 1e12
     # a complex MAC is 8 algorithmic flops; the split forms issue 4 real
     # products per digit product: 11 digit products in both GEMMs of a site
-    # (split-BF16), 10 in E B and 11 in T^T conj A (split-int8; the two GEMMs
-    # do equal work), i.e. 11 or 10.5 x the algorithmic ops
+    # (split-BF16, 44 real MACs); split-int8 issues 40 real MACs in E B and
+    # 42 in T^T conj A (the (2, 2) pair in its real part only), and the two
+    # GEMMs do equal work: 11 or 10.25 x the algorithmic ops
     mdt, kname, fdesc = FORMS[form]
     issued_tf = achieved_tf * ISSUED_PER_ALGORITHMIC[form]
     traffic, crec = counter_traffic(form, tune)

@@ -648,8 +648,9 @@ __device__ void overlap_split(const GramJobDev &J, int64_t ia, int64_t ib, uint8
 // row (E, T^T) or column (site tensors), cut into four balanced base-256
 // digits that are int8 MFMA operands (v_mfma_i32_16x16x64_i8, twice the
 // bf16 rate).  Digit products accumulate EXACTLY in int32, grouped by weight
-// 2^(-8 c), c = a + b for digit pair (a, b): c = 0..3 (ten pairs) and the
-// (2, 2) pair.  A product with a negated operand uses ~x = -x - 1: the
+// 2^(-8 c), c = a + b for digit pair (a, b): c = 0..3 (ten pairs) and, in
+// the real part of GEMM2, the (2, 2) pair.  A product with a negated operand
+// uses ~x = -x - 1: the
 // accumulator then lacks a column digit sum of the other operand, which the
 // packed site block carries and the combination adds back.
 //
@@ -663,14 +664,16 @@ __device__ void overlap_split(const GramJobDev &J, int64_t ia, int64_t ib, uint8
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 
 // The (2, 2) digit pair (weight 2^-32, like the omitted (1, 3) and (3, 1))
-// is kept in GEMM2 only.  There, for a bra equal (or close) to the ket, T is
-// the site tensor itself (E = I for left-canonical states) and the pair's
-// products are sums of squares: dropping it biases every self-overlap one
-// way (max |dK| on 165-site chi = 64 states 2.7e-9 -> 4.0e-7).  In GEMM1 the
-// LDS operand is E, whose digit 2 vanishes for E = I and whose products with
-// the site digits carry no common sign, so the pair is omitted there (CPU
-// emulation on 100-site chi = 64 states: max |dK| 1.8e-8 -> 2.3e-8, the
-// diagonal unchanged at 1.8e-8; dropping it in GEMM2: 2.6e-6).
+// is kept only in the real part of GEMM2.  There, for a bra equal (or close)
+// to the ket, T is the site tensor itself (E = I for left-canonical states)
+// and the pair's products Tr Ar + Ti Ai are sums of squares: dropping them
+// biases every self-overlap one way (max |dK| on 165-site chi = 64 states
+// 2.7e-9 -> 4.0e-7).  In the imaginary part Ti Ar - Tr Ai they cancel for
+// T = A, and in GEMM1 the LDS operand is E, whose digit 2 vanishes for E = I
+// and whose products with the site digits carry no common sign, so the pair
+// is omitted there (CPU emulation on 100-site chi = 64 states: max |dK|
+// 1.8e-8 with the pair everywhere, 2.5e-8 with it in GEMM2's real part only,
+// the diagonal 1.6e-8; without it in GEMM2's real part: 2.6e-6).
 #ifndef QK_I8_PAIR22
 #define QK_I8_PAIR22 1
 #endif
@@ -746,7 +749,8 @@ __device__ inline uint4 i8_frag(SiteRsrc site, int s, int k, int q, int ct, int 
 }
 
 // Class accumulators of one complex 16 x 16 tile: class c holds the digit
-// products of weight 2^(-8 c) (c = 0..3) and class 4 the (2, 2) product.
+// products of weight 2^(-8 c) (c = 0..3) and class 4 the (2, 2) product
+// (real part of GEMM2 only; unused accumulators are never formed).
 struct I8Acc {
   i32x4 re[5], im[5];
 };
@@ -755,9 +759,9 @@ struct I8Acc {
 // fragments (digit a, plane 0 / 1) at (2 a + q) KiB).  CPL1: complement plane 1
 // in the real part (GEMM1: re += X0 Y0 + (~X1) Y1, im += X0 Y1 + X1 Y0);
 // otherwise complement plane 0 in the imaginary part (GEMM2: re += X0 Y0 +
-// X1 Y1, im += (~X0) Y1 + X1 Y0).  P22: include the (2, 2) pair (class 4).
-// Only one digit's operands are live.
-template <bool CPL1, bool P22>
+// X1 Y1, im += (~X0) Y1 + X1 Y0).  P22_RE: include the (2, 2) pair (class 4)
+// in the real part.  Only one digit's operands are live.
+template <bool CPL1, bool P22_RE>
 __device__ inline void i8_block_lds(const uint8_t *tg, const uint4 (&Y0)[4], const uint4 (&Y1)[4], I8Acc &acc) {
 #pragma unroll
   for (int c = 0; c < 5; ++c) {
@@ -769,43 +773,44 @@ __device__ inline void i8_block_lds(const uint8_t *tg, const uint4 (&Y0)[4], con
     const uint4 x0 = *reinterpret_cast<const uint4 *>(tg + (a * 2 + 0) * kI8FragBytes);
     const uint4 x1 = *reinterpret_cast<const uint4 *>(tg + (a * 2 + 1) * kI8FragBytes);
     const uint4 P = x0, Q = CPL1 ? not4(x1) : x1, R = CPL1 ? x0 : not4(x0), S = x1;
-    // digit pairs (a, b) with a + b <= 3, plus (2, 2) in class 4 if P22
-    const int nb = a == 0 ? 4 : a == 1 ? 3 : a == 2 ? (P22 ? 3 : 2) : 1;
+    // digit pairs (a, b) with a + b <= 3
+    const int nb = a == 0 ? 4 : a == 1 ? 3 : a == 2 ? 2 : 1;
 #pragma unroll
     for (int b = 0; b < nb; ++b) {
-      const int c = (a == 2 && b == 2) ? 4 : a + b;
+      const int c = a + b;
       acc.re[c] = mma_i8(P, Y0[b], acc.re[c]);
       acc.im[c] = mma_i8(R, Y1[b], acc.im[c]);
       acc.re[c] = mma_i8(Q, Y1[b], acc.re[c]);
       acc.im[c] = mma_i8(S, Y0[b], acc.im[c]);
     }
+    if (P22_RE && a == 2) {   // (2, 2) into class 4 of the real part
+      acc.re[4] = mma_i8(P, Y0[2], acc.re[4]);
+      acc.re[4] = mma_i8(Q, Y1[2], acc.re[4]);
+    }
   }
 }
 
 // Exact digit sum of element e of a class accumulator set, plus correction
-// words, as a double in units of 2^-32 of the code product scale (P22) or,
-// without class 4, in units of 2^-24 (the caller adds 8 to the exponent).
+// words (classes 0..3), as a double in units of 2^24 of the code product
+// (class c weighs 2^(24 - 8 c); class 4, if P22, 2^-8: one rounding).
 template <bool P22>
-__device__ inline double i8_value(const i32x4 (&a)[5], int e, uint32_t chi, uint32_t clo, uint32_t c4) {
+__device__ inline double i8_value(const i32x4 (&a)[5], int e, uint32_t chi, uint32_t clo) {
   const int hiw = int((uint32_t(a[0][e]) << 8) + uint32_t(a[1][e]) + chi);
   const int low = int((uint32_t(a[2][e]) << 8) + uint32_t(a[3][e]) + clo);
-  if (P22) {
-    const int w4 = int(uint32_t(a[4][e]) + c4);
-    return fma(fma(double(hiw), 65536.0, double(low)), 256.0, double(w4));
-  }
-  (void)c4;
+  if (P22) return fma(double(a[4][e]), 0x1p-8, fma(double(hiw), 65536.0, double(low)));
   return fma(double(hiw), 65536.0, double(low));
 }
 
 // Class corrections from the column digit sums cs0..cs3 of the operand that
 // was multiplied by a complemented one: class c gets the sum over its pairs
-// (a, b) of cs_b, packed like the accumulator words of i8_value.
-__device__ inline void i8_corrections(const int (&cs)[4], uint32_t &chi, uint32_t &clo, uint32_t &c4) {
+// (a, b) of cs_b, packed like the accumulator words of i8_value.  Class 4 is
+// only formed where no operand is complemented (the real part of GEMM2), so
+// it needs none.
+__device__ inline void i8_corrections(const int (&cs)[4], uint32_t &chi, uint32_t &clo) {
   const int c0 = cs[0], c1 = cs[1], c2 = cs[2], c3 = cs[3];
   const int k0 = c0, k1 = c0 + c1, k2 = c0 + c1 + c2, k3 = k2 + c3;
   chi = (uint32_t(k0) << 8) + uint32_t(k1);
   clo = (uint32_t(k2) << 8) + uint32_t(k3);
-  c4 = uint32_t(c2);
 }
 
 // Work split of the int8 kernel: workgroups of four waves, two per CU, each
@@ -860,8 +865,8 @@ __device__ inline void i8_gemm1(const I8Ctx &C, const I8Operand &Bs, const uint8
   const uint4(&Bi)[4] = *reinterpret_cast<const uint4(*)[4]>(&Bs.f[4]);
   int ebc, cs[4];
   i8_column_meta(C, Bs, ebc, cs);
-  uint32_t chi, clo, c4;
-  i8_corrections(cs, chi, clo, c4);
+  uint32_t chi, clo;
+  i8_corrections(cs, chi, clo);
   tmax = 0.0;
 #pragma unroll
   for (int rt = 0; rt < 4; ++rt) {
@@ -872,10 +877,10 @@ __device__ inline void i8_gemm1(const I8Ctx &C, const I8Operand &Bs, const uint8
     __builtin_amdgcn_s_setprio(0);
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      // a code product is x_E x_B 2^(62 - ea - eb); i8_value<false> counts units of 2^24 of it
+      // a code product is x_E x_B 2^(62 - ea - eb); i8_value counts units of 2^24 of it
       const int ex = s_ea[16 * rt + 4 * C.g + e] + ebc - 38;
-      const double vr = ldexp(i8_value<false>(acc.re, e, chi, clo, c4), ex);
-      const double vi = ldexp(i8_value<false>(acc.im, e, 0u, 0u, 0u), ex);
+      const double vr = ldexp(i8_value<false>(acc.re, e, chi, clo), ex);
+      const double vi = ldexp(i8_value<false>(acc.im, e, 0u, 0u), ex);
       Td[rt][0][e] = vr;
       Td[rt][1][e] = vi;
       tmax = fmax(tmax, fmax(fabs(vr), fabs(vi)));
@@ -913,8 +918,8 @@ __device__ inline void i8_gemm2(const I8Ctx &C, const I8Operand &As, const uint8
   const uint4(&Ai)[4] = *reinterpret_cast<const uint4(*)[4]>(&As.f[4]);
   int eac, cs[4];
   i8_column_meta(C, As, eac, cs);
-  uint32_t chi, clo, c4;
-  i8_corrections(cs, chi, clo, c4);
+  uint32_t chi, clo;
+  i8_corrections(cs, chi, clo);
 #pragma unroll
   for (int bt = 0; bt < 4; ++bt) {
     // re = Tr Ar + Ti Ai ; im = Ti Ar - Tr Ai = Ti Ar + (~Tr) Ai + colsum(Ai)
@@ -924,9 +929,9 @@ __device__ inline void i8_gemm2(const I8Ctx &C, const I8Operand &As, const uint8
     __builtin_amdgcn_s_setprio(0);
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const int ex = s_eTs[16 * bt + 4 * C.g + e] + eac - (QK_I8_PAIR22 ? 46 : 38);
-      Ep[bt][0][e] += ldexp(i8_value<QK_I8_PAIR22>(acc.re, e, 0u, 0u, 0u), ex);
-      Ep[bt][1][e] += ldexp(i8_value<QK_I8_PAIR22>(acc.im, e, chi, clo, c4), ex);
+      const int ex = s_eTs[16 * bt + 4 * C.g + e] + eac - 38;
+      Ep[bt][0][e] += ldexp(i8_value<QK_I8_PAIR22>(acc.re, e, 0u, 0u), ex);
+      Ep[bt][1][e] += ldexp(i8_value<false>(acc.im, e, chi, clo), ex);
     }
     tile_fence(Ep[bt]);
   }
