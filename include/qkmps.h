@@ -61,9 +61,11 @@ typedef enum {
                       /* digits carried as bf16; the leading digit product     */
                       /* accumulates exactly in one FP32 MFMA accumulator, ten */
                       /* smaller digit products in a second; FP64 combine      */
-  QK_SPLIT_I8 = 3     /* the same four digits as int8 MFMA operands; the      */
-                      /* eleven digit products accumulate exactly in int32,   */
-                      /* grouped by weight; FP64 combine                       */
+  QK_SPLIT_I8 = 3     /* the same four digits as int8 MFMA operands; the ten  */
+                      /* digit products of weight >= 2^-24 (and the (2,2)     */
+                      /* product where bra ~ ket makes it one-signed)         */
+                      /* accumulate exactly in int32, grouped by weight; FP64 */
+                      /* combine                                              */
 } qk_precision;
 
 /* Circuit of Sec. II-C.  Rotation angles: Rz on qubit i uses coef_z * x_i;
