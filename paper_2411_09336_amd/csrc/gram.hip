@@ -759,14 +759,17 @@ struct I8Acc {
 // fragments (digit a, plane 0 / 1) at (2 a + q) KiB).  CPL1: complement plane 1
 // in the real part (GEMM1: re += X0 Y0 + (~X1) Y1, im += X0 Y1 + X1 Y0);
 // otherwise complement plane 0 in the imaginary part (GEMM2: re += X0 Y0 +
-// X1 Y1, im += (~X0) Y1 + X1 Y0).  P22_RE: include the (2, 2) pair (class 4)
-// in the real part.  Only one digit's operands are live.
+// X1 Y1, im += (~X0) Y1 + X1 Y0).  The part with the complemented operand
+// starts from the class corrections `corr` (so its sums come out exact), the
+// other from zero.  P22_RE: include the (2, 2) pair (class 4) in the real
+// part.  Only one digit's operands are live.
 template <bool CPL1, bool P22_RE>
-__device__ inline void i8_block_lds(const uint8_t *tg, const uint4 (&Y0)[4], const uint4 (&Y1)[4], I8Acc &acc) {
+__device__ inline void i8_block_lds(const uint8_t *tg, const uint4 (&Y0)[4], const uint4 (&Y1)[4],
+                                    const i32x4 (&corr)[4], I8Acc &acc) {
 #pragma unroll
   for (int c = 0; c < 5; ++c) {
-    acc.re[c] = i32x4{0, 0, 0, 0};
-    acc.im[c] = i32x4{0, 0, 0, 0};
+    acc.re[c] = (CPL1 && c < 4) ? corr[c] : i32x4{0, 0, 0, 0};
+    acc.im[c] = (!CPL1 && c < 4) ? corr[c] : i32x4{0, 0, 0, 0};
   }
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
@@ -790,27 +793,28 @@ __device__ inline void i8_block_lds(const uint8_t *tg, const uint4 (&Y0)[4], con
   }
 }
 
-// Exact digit sum of element e of a class accumulator set, plus correction
-// words (classes 0..3), as a double in units of 2^24 of the code product
-// (class c weighs 2^(24 - 8 c); class 4, if P22, 2^-8: one rounding).
+// Exact digit sum of element e of a class accumulator set (corrections
+// already in the accumulators), as a double in units of 2^24 of the code
+// product (class c weighs 2^(24 - 8 c); class 4, if P22, 2^-8: one rounding).
 template <bool P22>
-__device__ inline double i8_value(const i32x4 (&a)[5], int e, uint32_t chi, uint32_t clo) {
-  const int hiw = int((uint32_t(a[0][e]) << 8) + uint32_t(a[1][e]) + chi);
-  const int low = int((uint32_t(a[2][e]) << 8) + uint32_t(a[3][e]) + clo);
+__device__ inline double i8_value(const i32x4 (&a)[5], int e) {
+  const int hiw = int((uint32_t(a[0][e]) << 8) + uint32_t(a[1][e]));
+  const int low = int((uint32_t(a[2][e]) << 8) + uint32_t(a[3][e]));
   if (P22) return fma(double(a[4][e]), 0x1p-8, fma(double(hiw), 65536.0, double(low)));
   return fma(double(hiw), 65536.0, double(low));
 }
 
 // Class corrections from the column digit sums cs0..cs3 of the operand that
 // was multiplied by a complemented one: class c gets the sum over its pairs
-// (a, b) of cs_b, packed like the accumulator words of i8_value.  Class 4 is
-// only formed where no operand is complemented (the real part of GEMM2), so
-// it needs none.
-__device__ inline void i8_corrections(const int (&cs)[4], uint32_t &chi, uint32_t &clo) {
-  const int c0 = cs[0], c1 = cs[1], c2 = cs[2], c3 = cs[3];
-  const int k0 = c0, k1 = c0 + c1, k2 = c0 + c1 + c2, k3 = k2 + c3;
-  chi = (uint32_t(k0) << 8) + uint32_t(k1);
-  clo = (uint32_t(k2) << 8) + uint32_t(k3);
+// (a, b) of cs_b, the same for the four accumulator rows of a lane (its
+// column).  Class 4 is only formed where no operand is complemented (the
+// real part of GEMM2), so it needs none.
+__device__ inline void i8_corrections(const int (&cs)[4], i32x4 (&corr)[4]) {
+  const int k0 = cs[0], k1 = k0 + cs[1], k2 = k1 + cs[2], k3 = k2 + cs[3];
+  corr[0] = i32x4{k0, k0, k0, k0};
+  corr[1] = i32x4{k1, k1, k1, k1};
+  corr[2] = i32x4{k2, k2, k2, k2};
+  corr[3] = i32x4{k3, k3, k3, k3};
 }
 
 // Work split of the int8 kernel: workgroups of four waves, two per CU, each
@@ -865,22 +869,22 @@ __device__ inline void i8_gemm1(const I8Ctx &C, const I8Operand &Bs, const uint8
   const uint4(&Bi)[4] = *reinterpret_cast<const uint4(*)[4]>(&Bs.f[4]);
   int ebc, cs[4];
   i8_column_meta(C, Bs, ebc, cs);
-  uint32_t chi, clo;
-  i8_corrections(cs, chi, clo);
+  i32x4 corr[4];
+  i8_corrections(cs, corr);
   tmax = 0.0;
 #pragma unroll
   for (int rt = 0; rt < 4; ++rt) {
     // re = Er Br - Ei Bi = Er Br + (~Ei) Bi + colsum(Bi) ; im = Er Bi + Ei Br
     I8Acc acc;
     __builtin_amdgcn_s_setprio(1);
-    i8_block_lds<true, false>(Ebuf + size_t(rt * 8) * kI8FragBytes + C.lane * 16, Br, Bi, acc);
+    i8_block_lds<true, false>(Ebuf + size_t(rt * 8) * kI8FragBytes + C.lane * 16, Br, Bi, corr, acc);
     __builtin_amdgcn_s_setprio(0);
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       // a code product is x_E x_B 2^(62 - ea - eb); i8_value counts units of 2^24 of it
       const int ex = s_ea[16 * rt + 4 * C.g + e] + ebc - 38;
-      const double vr = ldexp(i8_value<false>(acc.re, e, chi, clo), ex);
-      const double vi = ldexp(i8_value<false>(acc.im, e, 0u, 0u), ex);
+      const double vr = ldexp(i8_value<false>(acc.re, e), ex);
+      const double vi = ldexp(i8_value<false>(acc.im, e), ex);
       Td[rt][0][e] = vr;
       Td[rt][1][e] = vi;
       tmax = fmax(tmax, fmax(fabs(vr), fabs(vi)));
@@ -918,20 +922,20 @@ __device__ inline void i8_gemm2(const I8Ctx &C, const I8Operand &As, const uint8
   const uint4(&Ai)[4] = *reinterpret_cast<const uint4(*)[4]>(&As.f[4]);
   int eac, cs[4];
   i8_column_meta(C, As, eac, cs);
-  uint32_t chi, clo;
-  i8_corrections(cs, chi, clo);
+  i32x4 corr[4];
+  i8_corrections(cs, corr);
 #pragma unroll
   for (int bt = 0; bt < 4; ++bt) {
     // re = Tr Ar + Ti Ai ; im = Ti Ar - Tr Ai = Ti Ar + (~Tr) Ai + colsum(Ai)
     I8Acc acc;
     __builtin_amdgcn_s_setprio(1);
-    i8_block_lds<false, QK_I8_PAIR22>(Tbuf + size_t(bt * 8) * kI8FragBytes + C.lane * 16, Ar, Ai, acc);
+    i8_block_lds<false, QK_I8_PAIR22>(Tbuf + size_t(bt * 8) * kI8FragBytes + C.lane * 16, Ar, Ai, corr, acc);
     __builtin_amdgcn_s_setprio(0);
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int ex = s_eTs[16 * bt + 4 * C.g + e] + eac - 38;
-      Ep[bt][0][e] += ldexp(i8_value<QK_I8_PAIR22>(acc.re, e, 0u, 0u), ex);
-      Ep[bt][1][e] += ldexp(i8_value<false>(acc.im, e, chi, clo), ex);
+      Ep[bt][0][e] += ldexp(i8_value<QK_I8_PAIR22>(acc.re, e), ex);
+      Ep[bt][1][e] += ldexp(i8_value<false>(acc.im, e), ex);
     }
     tile_fence(Ep[bt]);
   }
