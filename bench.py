@@ -206,6 +206,10 @@ def main():
                     help="only time the symmetric Gram of N random saturated 165-site chi=64 MPS in every "
                          "form (kernel microbenchmark, no simulation), then exit")
     ap.add_argument("--form", choices=sorted(FORMS), default="split_i8", help="form of the timed Gram")
+    ap.add_argument("--svm", action="store_true",
+                    help="downstream use of K: SVM with the precomputed quantum kernel on synthetic two-class "
+                         "data (165 features, d = 1, gamma 0.1; 300 / 1500 / 6400 points, 80/20 split), test "
+                         "AUC beside an RBF-kernel SVM; one JSON line, then exit")
     ap.add_argument("--d-sweep", action="store_true",
                     help="interaction-distance sweep (100 qubits, gamma 1, d = 2..12, 8 points each): "
                          "simulation and overlap times, largest bond and memory per MPS, against the CPU "
@@ -241,6 +245,9 @@ def main():
         return
     if args.d_sweep:
         d_sweep(args.routing, args.no_cpu)
+        return
+    if args.svm:
+        svm_auc(args.routing)
         return
     run(args)
 
@@ -360,6 +367,87 @@ def d_sweep(routing, no_cpu):
         del b
     print(json.dumps({"d_sweep": rows, "workload": "100 qubits, reps 2, gamma 1 (coef_z 2, coef_xx pi), "
                       "cutoff 1e-16, bond cap 64, 8 synthetic points per d", "routing": routing}), flush=True)
+
+
+def svm_auc(routing):
+    """Downstream use of the Gram matrices (Sec. III-B): the paper's classification circuit (165 features,
+    d = 1, reps 2, gamma 0.1: coef_z 0.2, coef_xx 0.01 pi; bond cap 64, cutoff 1e-8) on a synthetic balanced
+    two-class mixture (the Elliptic stand-in of the full workload, with labels), for 300, 1500 and 6400
+    points split 80/20: every Gram form is timed on 128 test rows x the training set, the fastest computes
+    K_train (symmetric, in row slabs) and K_test (test x train), an SVM is fitted with the precomputed
+    kernel, and its test AUC is reported beside that of an RBF-kernel SVM on the raw features."""
+    import numpy as np
+    import torch
+    from sklearn.metrics import roc_auc_score
+    from sklearn.svm import SVC
+
+    import paper_2411_09336_amd as q
+    import synthdata as sd
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    wp = sd.WORKLOADS["paper_d1"]
+    X, y = sd.make_mixture(wp.n_points, wp.n_qubits, n_dirs=wp.n_dirs, mean_scale=wp.mean_scale, seed=wp.seed,
+                           dir_seed=wp.dir_seed, return_labels=True)
+    spec = q.CircuitSpec(wp.n_qubits, wp.distance, wp.reps, wp.coef_z, wp.coef_xx, routing)
+    rows = []
+    for n in (300, 1500, 6400):
+        ntr = int(0.8 * n)
+        xt = torch.tensor(X[:n], dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b = q.simulate(xt, spec, wp.chi, wp.cutoff, stream=stream)
+        stream.synchronize()
+        t_sim = time.perf_counter() - t0
+        log(f"[bench] svm n={n}: simulated in {t_sim:.2f} s, max bond {b.info()['max_bond']}")
+        # every form on the same block (the plain forms work on the batch's bond pads, the split forms on
+        # 64 x 64 blocks), fastest first
+        nb = min(128, n - ntr)
+        Kd = q.gram_block(b, ntr, nb, b, 0, ntr, precision="fp64", stream=stream)
+        forms = {}
+        for f in ("fp64", "fp32", "split_bf16", "split_i8"):
+            q.gram_block(b, ntr, 8, b, 0, ntr, precision=f, stream=stream)
+            stream.synchronize()
+            t0 = time.perf_counter()
+            Kf = q.gram_block(b, ntr, nb, b, 0, ntr, precision=f, stream=stream)
+            stream.synchronize()
+            forms[f] = {"entries_per_s": round(nb * ntr / (time.perf_counter() - t0), 1),
+                        "max_dK_vs_fp64": float((Kf - Kd).abs().max().item())}
+        best = max(("fp64", "split_i8"), key=lambda f: forms[f]["entries_per_s"])
+        log(f"[bench] svm n={n}: forms on {nb} x {ntr}: {forms}; using {best}")
+        t0 = time.perf_counter()
+        Ktr = torch.zeros((ntr, ntr), dtype=torch.float64, device="cuda")
+        bounds = slab_bounds(ntr, 8)
+        for k in range(len(bounds) - 1):
+            r0, r1 = bounds[k], bounds[k + 1]
+            q.gram_block(b, r0, r1 - r0, b, r0, ntr - r0, precision=best, upper_only=True, out=Ktr[r0:, r0:],
+                         stream=stream)
+            stream.synchronize()
+            log(f"[bench] svm n={n}: K_train rows {r0}:{r1} done")
+        Ktr = torch.triu(Ktr) + torch.triu(Ktr, 1).T
+        Kte = q.gram_block(b, ntr, n - ntr, b, 0, ntr, precision=best, stream=stream)
+        stream.synchronize()
+        t_gram = time.perf_counter() - t0
+        Ktr, Kte = Ktr.cpu().numpy(), Kte.cpu().numpy()
+        t0 = time.perf_counter()
+        svm = SVC(kernel="precomputed", C=1.0).fit(Ktr, y[:ntr])
+        auc_q = roc_auc_score(y[ntr:n], svm.decision_function(Kte))
+        auc_q_train = roc_auc_score(y[:ntr], svm.decision_function(Ktr))
+        t_fit = time.perf_counter() - t0
+        rbf = SVC(kernel="rbf", C=1.0, gamma="scale").fit(X[:ntr], y[:ntr])
+        auc_rbf = roc_auc_score(y[ntr:n], rbf.decision_function(X[ntr:n]))
+        off = Ktr[~np.eye(ntr, dtype=bool)]
+        row = {"points": n, "train": ntr, "test": n - ntr, "max_bond": b.info()["max_bond"],
+               "sim_s": round(t_sim, 3), "gram_form": best, "gram_s": round(t_gram, 3),
+               "gram_entries": ntr * (ntr + 1) // 2 + (n - ntr) * ntr, "svm_fit_s": round(t_fit, 2),
+               "K_offdiag_median": float(np.median(off)), "K_offdiag_min": float(off.min()),
+               "auc_test_quantum": round(float(auc_q), 4), "auc_train_quantum": round(float(auc_q_train), 4),
+               "auc_test_rbf": round(float(auc_rbf), 4), "forms_on_test_rows": forms}
+        log(f"[bench] svm {row}")
+        rows.append(row)
+        del b
+    print(json.dumps({"svm": rows, "workload": "165 features, d=1, reps=2, gamma 0.1 (coef_z 0.2, coef_xx 0.01 pi), "
+                      "chi 64, cutoff 1e-8; synthetic two-class mixture, 80/20 split", "routing": routing}),
+          flush=True)
 
 
 def calibrate_copy(nbytes):

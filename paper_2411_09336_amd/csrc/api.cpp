@@ -258,6 +258,50 @@ qk_status mps_simulate_graph(const double *features_dev, int64_t n_points, const
                        gates_per_graph == 0 ? INT64_MAX : gates_per_graph, nullptr, out);
 }
 
+// The simulation allocates for the largest bonds its chi cap allows; once
+// the states are known, the batch is re-laid with the pads of the bonds they
+// reached (pad of the largest bond at each site), so Gram kernels of the
+// plain forms work on blocks that size (bond-2 states: 32-wide pads instead
+// of 64).  Tensors, bond dimensions and statistics are copied unchanged.
+static qk_status shrink_to_bonds(qk_mps_batch **pb, hipStream_t stream) {
+  qk_mps_batch *b = *pb;
+  const int m = b->m;
+  if (b->n == 0) return QK_OK;
+  std::vector<int32_t> dims(size_t(b->n) * (m + 1));
+  QK_HIP_CHECK(hipMemcpyAsync(dims.data(), b->dims_dev, sizeof(int32_t) * dims.size(), hipMemcpyDeviceToHost, stream));
+  QK_HIP_CHECK(hipStreamSynchronize(stream));
+  std::vector<int32_t> pad(m + 1, 1);
+  for (int64_t i = 0; i < b->n; ++i)
+    for (int l = 0; l <= m; ++l) pad[l] = std::max(pad[l], dims[size_t(i) * (m + 1) + l]);
+  for (int l = 0; l <= m; ++l) pad[l] = std::min(pad_of(pad[l]), b->pad[l]);
+  if (pad == b->pad) return QK_OK;
+  qk_mps_batch *c = nullptr;
+  qk_status st = batch_create(b->n, m, pad, stream, &c);
+  if (st != QK_OK) return st;
+  st = launch_repad_f64(b, c, stream);
+  const size_t n = size_t(b->n);
+  if (st == QK_OK &&
+      (hipMemcpyAsync(c->dims_dev, b->dims_dev, sizeof(int32_t) * n * (m + 1), hipMemcpyDeviceToDevice, stream) !=
+           hipSuccess ||
+       hipMemcpyAsync(c->disc_dev, b->disc_dev, sizeof(double) * n, hipMemcpyDeviceToDevice, stream) != hipSuccess ||
+       hipMemcpyAsync(c->maxdisc_dev, b->maxdisc_dev, sizeof(double) * n, hipMemcpyDeviceToDevice, stream) !=
+           hipSuccess ||
+       hipMemcpyAsync(c->degen_dev, b->degen_dev, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, stream) !=
+           hipSuccess ||
+       hipMemcpyAsync(c->unconv_dev, b->unconv_dev, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, stream) !=
+           hipSuccess ||
+       hipStreamSynchronize(stream) != hipSuccess))
+    st = fail(QK_EDEVICE, "copy into the re-laid batch failed");
+  if (st != QK_OK) {
+    batch_release(c);
+    return st;
+  }
+  c->n_two_qubit_gates = b->n_two_qubit_gates;
+  batch_release(b);
+  *pb = c;
+  return QK_OK;
+}
+
 static qk_status simulate_impl(const double *features_dev, int64_t n_points, const qk_circuit_spec *spec,
                                int32_t chi_max, double cutoff, void *hip_stream, qk_progress_fn fn, void *user,
                                int64_t every, int64_t graph_gates, int32_t *trace_dev, qk_mps_batch **out) {
@@ -285,6 +329,7 @@ static qk_status simulate_impl(const double *features_dev, int64_t n_points, con
   auto gates = compile_circuit(*spec);
   st = run_simulation(b, features_dev, gates, *spec, chi_max, cutoff, stream, fn, user, every, graph_gates,
                       trace_dev);
+  if (st == QK_OK) st = shrink_to_bonds(&b, stream);
   if (st != QK_OK) {
     batch_release(b);
     return st;

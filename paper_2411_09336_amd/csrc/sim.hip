@@ -859,6 +859,43 @@ __global__ void normalize_last_kernel(double2 *f64, int64_t mps_stride, const in
 
 }  // namespace
 
+// FP64 tensors of src copied into dst, whose pads are no larger (and no
+// smaller than every bond dimension of src): block (mps i, site l) of dst is
+// [s][r][c] with r < dst pad[l], c < dst pad[l+1].  Grid (m, MPS chunk).
+__global__ __launch_bounds__(256) void repad_f64_kernel(const double2 *__restrict__ src, double2 *__restrict__ dst,
+                                                        const int32_t *__restrict__ spad,
+                                                        const int32_t *__restrict__ dpad,
+                                                        const int64_t *__restrict__ soff,
+                                                        const int64_t *__restrict__ doff, int64_t sstride,
+                                                        int64_t dstride, int32_t m, int64_t n) {
+  const int l = blockIdx.x;
+  const int64_t i = blockIdx.y;
+  if (l >= m || i >= n) return;
+  const int sl = spad[l], sr = spad[l + 1], dl = dpad[l], dr = dpad[l + 1];
+  const double2 *a = src + i * sstride + soff[l];
+  double2 *b = dst + i * dstride + doff[l];
+  for (int e = threadIdx.x; e < 2 * dl * dr; e += blockDim.x) {
+    const int s = e / (dl * dr), r = (e / dr) % dl, c = e % dr;
+    b[e] = a[(size_t(s) * sl + r) * sr + c];
+  }
+}
+
+qk_status launch_repad_f64(const qk_mps_batch *src, qk_mps_batch *dst, hipStream_t stream) {
+  if (src->n == 0) return QK_OK;
+  for (int l = 0; l <= src->m; ++l)
+    if (dst->pad[l] > src->pad[l]) return fail(QK_EINVAL, "repad to a larger pad");
+  const int64_t chunk = 65535;
+  for (int64_t i0 = 0; i0 < src->n; i0 += chunk) {
+    const int64_t cnt = std::min(chunk, src->n - i0);
+    hipLaunchKernelGGL(repad_f64_kernel, dim3(unsigned(src->m), unsigned(cnt)), dim3(256), 0, stream,
+                       src->f64 + i0 * src->mps_stride, dst->f64 + i0 * dst->mps_stride, src->pad_dev,
+                       dst->pad_dev, src->site_off_dev, dst->site_off_dev, src->mps_stride, dst->mps_stride,
+                       src->m, cnt);
+    QK_HIP_CHECK(hipGetLastError());
+  }
+  return QK_OK;
+}
+
 qk_status run_simulation(qk_mps_batch *b, const double *features_dev, const std::vector<qk_gate> &gates,
                          const qk_circuit_spec &spec, int chi, double cutoff, hipStream_t stream_in, qk_progress_fn fn,
                          void *user, int64_t every, int64_t graph_gates, int32_t *trace) {

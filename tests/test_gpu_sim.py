@@ -277,3 +277,29 @@ def test_memory_trace_vs_oracle(routing):
               r.degenerate_cuts, "peak memory MiB", 32 * tr[i, :, 1].max() / 2 ** 20)
         if deg[i] == 0 and r.degenerate_cuts == 0:
             assert mine == r.trace
+
+
+def test_batch_relaid_to_reached_bonds():
+    """A simulated batch is laid out for the bonds its states reach, not for
+    the chi cap: the paper's d = 1 bandwidth circuit (bonds <= 2) under chi 64
+    stores 32-wide pads (2 x 32 x 32 complex128 per site), and its states and
+    Gram still match the oracle."""
+    import paper_2411_09336_amd as q
+    torch = require_gpu()
+    wp = sd.WORKLOADS["paper_d1"]
+    X = sd.workload_features(wp, 6)
+    xt = torch.tensor(X, dtype=torch.float64, device="cuda")
+    spec = q.CircuitSpec(wp.n_qubits, wp.distance, wp.reps, wp.coef_z, wp.coef_xx, 1)
+    b = q.simulate(xt, spec, 64, wp.cutoff)
+    inf = b.info()
+    assert inf["max_bond"] <= 2
+    assert inf["bytes_f64"] == 6 * wp.n_qubits * 2 * 32 * 32 * 16
+    ref = [omps.simulate(x, wp.distance, wp.reps, 64, wp.cutoff, wp.coef_z, wp.coef_xx, routing=1) for x in X]
+    for i in range(len(X)):
+        assert list(b.bond_dims()[i]) == ref[i].bond_dims
+        assert fidelity(b.export(i), ref[i].tensors) > 1 - 1e-12
+    Ko = ogram.gram([r.tensors for r in ref])
+    for prec, tol in (("fp64", 1e-12), ("split_i8", 1e-7)):
+        K = q.gram(b, precision=prec).cpu().numpy()
+        print(prec, "max|dK| vs oracle", np.abs(K - Ko).max())
+        assert np.abs(K - Ko).max() < tol
