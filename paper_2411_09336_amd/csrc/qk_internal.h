@@ -132,7 +132,6 @@ qk_status launch_gather_meta(const qk_mps_batch_meta &src, const qk_mps_batch_me
 qk_status launch_pack_f32(const qk_mps_batch *b, hipStream_t stream);
 qk_status launch_pack_split(const qk_mps_batch *b, hipStream_t stream);
 qk_status launch_pack_i8(const qk_mps_batch *b, hipStream_t stream);
-qk_status launch_repad_f64(const qk_mps_batch *src, qk_mps_batch *dst, hipStream_t stream);
 
 struct GramJobDev {
   const void *a_base;              // form-specific base pointer of batch a
