@@ -258,10 +258,12 @@ qk_status mps_simulate_graph(const double *features_dev, int64_t n_points, const
                        gates_per_graph == 0 ? INT64_MAX : gates_per_graph, nullptr, out);
 }
 
+extern "C++" {
 namespace qk {
 // Copy of a batch's FP64 tensors into a batch with smaller pads (sim.hip).
 qk_status launch_repad_f64(const qk_mps_batch *src, qk_mps_batch *dst, hipStream_t stream);
 }  // namespace qk
+}
 
 // The simulation allocates for the largest bonds its chi cap allows; once
 // the states are known, the batch is re-laid with the pads of the bonds they
