@@ -44,10 +44,11 @@ FORMS = {
                  "10 digit products (11 in the real part of T^T conj A) on int8 MFMA, exact int32 "
                  "accumulation, fp64 combine"),
     "split_bf16": ("bf16", "gram_kernel<split_bf16,64>",
-                   "split-bf16: the same four digits carried as bf16, 11 digit products on bf16 MFMA, "
-                   "exact fp32 leading accumulator + fp32 accumulator for the rest, fp64 combine"),
+                   "split-bf16: the same four digits carried as bf16, 10 digit products (11 in the real part "
+                   "of T^T conj A) on bf16 MFMA, exact fp32 leading accumulator + fp32 accumulator for the "
+                   "rest, fp64 combine"),
 }
-ISSUED_PER_ALGORITHMIC = {"split_i8": 10.25, "split_bf16": 11.0}
+ISSUED_PER_ALGORITHMIC = {"split_i8": 10.25, "split_bf16": 10.25}
 HBM_PEAK_GBS = 8000.0
 
 
@@ -609,10 +610,9 @@ def run(args):
     flops_launch = fpe * n_comp
     achieved_tf = flops_launch / t_split / 1e12
     # a complex MAC is 8 algorithmic flops; the split forms issue 4 real
-    # products per digit product: 11 digit products in both GEMMs of a site
-    # (split-BF16, 44 real MACs); split-int8 issues 40 real MACs in E B and
+    # products per digit product: 40 real MACs in E B (ten digit pairs) and
     # 42 in T^T conj A (the (2, 2) pair in its real part only), and the two
-    # GEMMs do equal work: 11 or 10.25 x the algorithmic ops
+    # GEMMs do equal work: 10.25 x the algorithmic ops
     mdt, kname, fdesc = FORMS[form]
     issued_tf = achieved_tf * ISSUED_PER_ALGORITHMIC[form]
     traffic, crec = counter_traffic(form, tune)

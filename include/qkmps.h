@@ -59,8 +59,10 @@ typedef enum {
   QK_SPLIT_BF16 = 2,  /* each real operand as a 31-bit fixed-point code with   */
                       /* one exponent per row / column, cut into four 8-bit    */
                       /* digits carried as bf16; the leading digit product     */
-                      /* accumulates exactly in one FP32 MFMA accumulator, ten */
-                      /* smaller digit products in a second; FP64 combine      */
+                      /* accumulates exactly in one FP32 MFMA accumulator, the */
+                      /* smaller digit products of weight >= 2^-24 (and the   */
+                      /* (2,2) product where bra ~ ket makes it one-signed)   */
+                      /* in a second; FP64 combine                             */
   QK_SPLIT_I8 = 3     /* the same four digits as int8 MFMA operands; the ten  */
                       /* digit products of weight >= 2^-24 (and the (2,2)     */
                       /* product where bra ~ ket makes it one-signed)         */

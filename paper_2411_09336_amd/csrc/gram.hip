@@ -362,14 +362,18 @@ __device__ inline Sl4 neg4(const Sl4 &x) {
   return y;
 }
 
-// hi += X0 Y0 (exact); lo += the ten smaller slice products, smallest first.
+// hi += X0 Y0 (exact); lo += the smaller slice products, smallest first:
+// the nine others of weight >= 2^-24 and, if P22, the (2, 2) product, which
+// is kept only where bra ~ ket makes it one-signed (the real part of GEMM2;
+// the reasoning of the split-int8 form below applies to the same digits).
+template <bool P22>
 __device__ inline void slice_mac(const Sl4 &X, const Sl4 &Y, f32x4 &hi, f32x4 &lo) {
   hi = mma16(X.v[0], Y.v[0], hi);
   lo = mma16(X.v[3], Y.v[0], lo);
   lo = mma16(X.v[0], Y.v[3], lo);
   lo = mma16(X.v[2], Y.v[1], lo);
   lo = mma16(X.v[1], Y.v[2], lo);
-  lo = mma16(X.v[2], Y.v[2], lo);
+  if (P22) lo = mma16(X.v[2], Y.v[2], lo);
   lo = mma16(X.v[2], Y.v[0], lo);
   lo = mma16(X.v[1], Y.v[1], lo);
   lo = mma16(X.v[0], Y.v[2], lo);
@@ -449,10 +453,12 @@ __device__ inline void split_gemm1(const SplitCtx &C, const uint8_t *B, const ui
         Ei.v[k] = *reinterpret_cast<const uint4 *>(eg + (k * 2 + 1) * 1024);
       }
       // re += Er Br - Ei Bi ; im += Er Bi + Ei Br
-      slice_mac(Er, Br, h1[u][0], l1[u][0]);
-      slice_mac(Ei, Bin, h1[u][0], l1[u][0]);
-      slice_mac(Er, Bi, h1[u][1], l1[u][1]);
-      slice_mac(Ei, Br, h1[u][1], l1[u][1]);
+      __builtin_amdgcn_s_setprio(1);   // MFMA burst first when both waves of a SIMD are ready
+      slice_mac<false>(Er, Br, h1[u][0], l1[u][0]);
+      slice_mac<false>(Ei, Bin, h1[u][0], l1[u][0]);
+      slice_mac<false>(Er, Bi, h1[u][1], l1[u][1]);
+      slice_mac<false>(Ei, Br, h1[u][1], l1[u][1]);
+      __builtin_amdgcn_s_setprio(0);
     }
   }
   const int ebc = int(gview(reinterpret_cast<const int8_t *>(B))[s * 128 + 16 * C.cb + C.j]);
@@ -528,10 +534,12 @@ __device__ inline void split_gemm2(const SplitCtx &C, const uint8_t *A, const ui
       }
       const Sl4 Trn = neg4(Tr);
       // re += Tr Ar + Ti Ai ; im += Ti Ar - Tr Ai
-      slice_mac(Tr, Ar, h2[u][0], l2[u][0]);
-      slice_mac(Ti, Ai, h2[u][0], l2[u][0]);
-      slice_mac(Ti, Ar, h2[u][1], l2[u][1]);
-      slice_mac(Trn, Ai, h2[u][1], l2[u][1]);
+      __builtin_amdgcn_s_setprio(1);
+      slice_mac<true>(Tr, Ar, h2[u][0], l2[u][0]);
+      slice_mac<true>(Ti, Ai, h2[u][0], l2[u][0]);
+      slice_mac<false>(Ti, Ar, h2[u][1], l2[u][1]);
+      slice_mac<false>(Trn, Ai, h2[u][1], l2[u][1]);
+      __builtin_amdgcn_s_setprio(0);
     }
   }
   const int eac = int(gview(reinterpret_cast<const int8_t *>(A))[s * 128 + 16 * C.cb + C.j]);
