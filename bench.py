@@ -238,6 +238,10 @@ def main():
                              f"bench.py --form {args.form} --slabs-run 1 --no-cpu --warmup 0",
                              {k: int(v) for k, v in (kv.split("=") for kv in args.counter_config.split(","))})
         return
+    import torch
+    if not torch.cuda.is_available():
+        log("bench.py needs a GPU (the Gram and simulation kernels run only on the device)")
+        sys.exit(1)
     if args.calibrate_copy > 0:
         calibrate_copy(args.calibrate_copy)
         return
