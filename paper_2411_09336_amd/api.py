@@ -337,6 +337,29 @@ def autotune_reset() -> None:
     _check(_load().mps_gram_tune_reset())
 
 
+def _check_out(out, na: int, nb: int, what: str = "out"):
+    """A caller-supplied K block must be a CUDA float64 matrix with unit column
+    stride that holds na x nb entries: the kernels write K[i * ldk + j]
+    through its pointer with ldk = out.stride(0)."""
+    import torch
+    if not isinstance(out, torch.Tensor) or out.dim() != 2:
+        raise ValueError(f"{what} must be a 2-D torch tensor")
+    if out.dtype != torch.float64:
+        raise ValueError(f"{what} must be float64 (got {out.dtype})")
+    if out.shape[0] < na or out.shape[1] < nb:
+        raise ValueError(f"{what} of shape {tuple(out.shape)} cannot hold {na} x {nb} entries")
+    if nb > 1 and out.stride(1) != 1:
+        raise ValueError(f"{what} must have unit column stride (got strides {out.stride()})")
+    if na > 1 and out.stride(0) < nb:
+        raise ValueError(f"{what} row stride {out.stride(0)} is below the {nb} columns written")
+    if not out.is_cuda:
+        raise ValueError(f"{what} must live on the GPU")
+
+
+def _ldk(out, nb: int) -> int:
+    return max(int(out.stride(0)), nb, 1)
+
+
 def gram(a: MPSBatch, b: Optional[MPSBatch] = None, precision="fp64", out=None, stream=None):
     """K[i, j] = |<a_i|b_j>|^2 as a CUDA float64 tensor (symmetric when b is None)."""
     import torch
@@ -344,10 +367,9 @@ def gram(a: MPSBatch, b: Optional[MPSBatch] = None, precision="fp64", out=None, 
     nb = na if b is None else b.n
     if out is None:
         out = torch.empty((na, nb), dtype=torch.float64, device="cuda")
-    if out.dtype != torch.float64 or not out.is_cuda or out.stride(1) != 1:
-        raise ValueError("out must be a CUDA float64 tensor with unit column stride")
+    _check_out(out, na, nb)
     _check(_load().mps_gram(a.handle, None if b is None else b.handle, Precision.of(precision),
-                            C.c_void_p(out.data_ptr()), out.stride(0), _stream_ptr(stream)))
+                            C.c_void_p(out.data_ptr()), _ldk(out, nb), _stream_ptr(stream)))
     return out
 
 
@@ -356,8 +378,9 @@ def gram_block(a: MPSBatch, a0: int, na: int, b: MPSBatch, b0: int, nb: int, pre
     import torch
     if out is None:
         out = torch.zeros((na, nb), dtype=torch.float64, device="cuda")
+    _check_out(out, na, nb)
     _check(_load().mps_gram_block(a.handle, a0, na, b.handle, b0, nb, int(bool(upper_only)),
-                                  Precision.of(precision), C.c_void_p(out.data_ptr()), out.stride(0),
+                                  Precision.of(precision), C.c_void_p(out.data_ptr()), _ldk(out, nb),
                                   _stream_ptr(stream)))
     return out
 
@@ -366,6 +389,7 @@ def gram_multi(jobs, precision="fp64", stream=None):
     """jobs: list of dicts {a, b, a0, na, b0, nb, upper_only, out} -> one persistent launch."""
     arr = (_Job * len(jobs))()
     for k, j in enumerate(jobs):
+        _check_out(j["out"], j["na"], j["nb"], f"jobs[{k}]['out']")
         arr[k].a = j["a"].handle.value
         arr[k].b = j["b"].handle.value
         arr[k].a0, arr[k].na = j.get("a0", 0), j["na"]
@@ -373,5 +397,5 @@ def gram_multi(jobs, precision="fp64", stream=None):
         arr[k].upper_only = int(bool(j.get("upper_only", False)))
         arr[k].reserved = 0
         arr[k].K_dev = j["out"].data_ptr()
-        arr[k].ldk = j["out"].stride(0)
+        arr[k].ldk = _ldk(j["out"], j["nb"])
     _check(_load().mps_gram_multi(arr, len(jobs), Precision.of(precision), _stream_ptr(stream)))

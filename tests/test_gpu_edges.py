@@ -59,13 +59,17 @@ def test_chi_one_truncation_vs_oracle():
     dims = b.bond_dims()
     disc, deg = b.trunc_stats()
     assert b.info()["max_bond"] == 1
+    compared = 0
     for i in range(len(X)):
         r = omps.simulate(X[i], 2, 2, 1, 0.0, 2.0, 2.0)
         print("chi 1", i, "fidelity", fidelity(b.export(i), r.tensors), "degenerate", deg[i], r.degenerate_cuts)
         assert list(dims[i]) == r.bond_dims == [1] * 11
         if deg[i] == 0 and r.degenerate_cuts == 0:
+            compared += 1
             assert fidelity(b.export(i), r.tensors) > 1 - 1e-10
             assert abs(disc[i] - r.discarded) <= 1e-9 * max(1.0, r.discarded)
+    print("chi 1: circuits compared", compared, "of", len(X))
+    assert compared >= 1
 
 
 def test_identical_points():

@@ -63,15 +63,19 @@ def test_truncated_vs_oracle(name, n, chi):
     b = _sim(X, w, chi=chi)
     dims = b.bond_dims()
     disc, deg = b.trunc_stats()
+    compared = 0
     for i in range(n):
         r = omps.simulate(X[i], w.distance, w.reps, chi, w.cutoff, w.coef_z, w.coef_xx)
         g = b.export(i)
         f = fidelity(g, r.tensors)
         print(name, i, "fidelity", f, "bonds equal", list(dims[i]) == r.bond_dims, "disc", disc[i], r.discarded)
         if r.degenerate_cuts == 0 and deg[i] == 0:
+            compared += 1
             assert f > 1 - 1e-10
             assert list(dims[i]) == r.bond_dims
             assert abs(disc[i] - r.discarded) <= 1e-9 * max(1.0, r.discarded)
+    print(name, "circuits compared", compared, "of", n)
+    assert compared >= max(1, n // 2)
 
 
 def test_simulated_gram_invariants():
@@ -92,13 +96,18 @@ def test_routing1_truncated_vs_oracle():
     X = sd.workload_features(w, 3)
     b = _sim(X, w, chi=16, routing=1)
     dims = b.bond_dims()
+    _, deg = b.trunc_stats()
+    compared = 0
     for i in range(3):
         r = omps.simulate(X[i], w.distance, w.reps, 16, w.cutoff, w.coef_z, w.coef_xx, routing=1)
         f = fidelity(b.export(i), r.tensors)
         print("routing 1", i, "fidelity", f)
-        if r.degenerate_cuts == 0:
+        if r.degenerate_cuts == 0 and deg[i] == 0:
+            compared += 1
             assert f > 1 - 1e-10
             assert list(dims[i]) == r.bond_dims
+    print("routing 1: circuits compared", compared, "of 3")
+    assert compared >= 2
 
 
 def test_saturated_chi64_vs_oracle():
@@ -116,24 +125,29 @@ def test_saturated_chi64_vs_oracle():
     assert inf["unconverged_svds"] == 0
     dims = b.bond_dims()
     disc, deg = b.trunc_stats()
+    compared = 0
     for i in range(len(X)):
         r = omps.simulate(X[i], w.distance, w.reps, w.chi, w.cutoff, w.coef_z, w.coef_xx, routing=1)
         f = fidelity(b.export(i), r.tensors)
         print("saturated", i, "fidelity", f, "disc", disc[i], r.discarded, "degenerate", deg[i], r.degenerate_cuts)
         assert r.max_bond_seen == 64
         if r.degenerate_cuts == 0 and deg[i] == 0:
+            compared += 1
             assert f > 1 - 1e-10
             assert list(dims[i]) == r.bond_dims
             assert abs(disc[i] - r.discarded) <= 1e-9 * max(1.0, r.discarded)
+    print("saturated: circuits compared", compared, "of", len(X))
+    assert compared >= 1
 
 
 def test_full_size_gram_vs_oracle():
     """The benchmark's workload at full size (165 qubits, d = 8, reps = 2,
     chi = 64, cutoff 1e-8, routing 1): 6 points and near-duplicates of two
-    of them simulated on the GPU, then the Gram in FP64 and in the timed
-    split-int8 form with the kernel configuration the autotuner picks for
-    this batch (as the benchmark does).  Every entry against the oracle's
-    overlaps of the same MPS: FP64 to 1e-12, split-int8 to the 1e-6 bound."""
+    of them simulated on the GPU, then the Gram in FP64 and in both split
+    forms with the kernel configuration the autotuner picks for this batch
+    (as the benchmark does).  Every entry against the oracle's overlaps of
+    the same MPS: FP64 to 1e-12, split-BF16 and split-int8 to the 1e-6
+    bound."""
     import paper_2411_09336_amd as q
     w = sd.WORKLOADS["full"]
     X = sd.workload_features(w, 6)
@@ -143,14 +157,19 @@ def test_full_size_gram_vs_oracle():
     assert inf["max_bond"] == 64 and inf["unconverged_svds"] == 0
     Ko = ogram.gram([b.export(i) for i in range(len(X))])
     Kd = q.gram(b, precision="fp64").cpu().numpy()
-    q.autotune(b, precision="split_i8", sample=len(X))
-    Ki = q.gram(b, precision="split_i8").cpu().numpy()
-    q.autotune_reset()
+    try:
+        q.autotune(b, precision="split_i8", sample=len(X))
+        Ki = q.gram(b, precision="split_i8").cpu().numpy()
+        q.autotune(b, precision="split_bf16", sample=len(X))
+        Kb = q.gram(b, precision="split_bf16").cpu().numpy()
+    finally:
+        q.autotune_reset()
     print("fp64 vs oracle", np.abs(Kd - Ko).max(), "split_i8 vs oracle", np.abs(Ki - Ko).max(),
-          "near-duplicate K", Ko[0, 6], Ko[1, 7])
+          "split_bf16 vs oracle", np.abs(Kb - Ko).max(), "near-duplicate K", Ko[0, 6], Ko[1, 7])
     assert Ko[0, 6] > 1e-3 and Ko[1, 7] > 1e-3   # the near-duplicate entries are not vacuous
     assert np.abs(Kd - Ko).max() < 1e-12
     assert np.abs(Ki - Ko).max() < 1e-6
+    assert np.abs(Kb - Ko).max() < 1e-6
 
 
 def test_precision_workload_split_vs_fp64():
@@ -172,6 +191,10 @@ def test_precision_workload_split_vs_fp64():
     assert np.abs(Kd - Ko).max() < 1e-12
     assert np.abs(Ks - Kd).max() < 1e-7
     assert np.abs(Ki - Ko).max() < 1e-7
+    # plain FP32 operands and accumulators: the rounding of E (2^-24 relative)
+    # at every one of the 100 sites adds up along the chain (about 2e-5 on
+    # these states); 1e-4 bounds it with margin, far above the split forms
+    assert np.abs(Kf - Ko).max() < 1e-4
     assert Kd[0, 3] > 0.05 and Kd[1, 4] > 0.05
 
 
@@ -266,6 +289,7 @@ def test_memory_trace_vs_oracle(routing):
     assert tr.shape == (4, n2q, 2)
     assert np.array_equal(b.bond_dims(), ref.bond_dims())
     _, deg = b.trunc_stats()
+    compared = 0
     for i in range(len(X)):
         assert all(np.array_equal(s, t) for s, t in zip(b.export(i), ref.export(i)))
         dims = b.bond_dims()[i]
@@ -276,7 +300,10 @@ def test_memory_trace_vs_oracle(routing):
         print("routing", routing, "circuit", i, "entries equal", same, "/", n2q, "degenerate", deg[i],
               r.degenerate_cuts, "peak memory MiB", 32 * tr[i, :, 1].max() / 2 ** 20)
         if deg[i] == 0 and r.degenerate_cuts == 0:
+            compared += 1
             assert mine == r.trace
+    print("routing", routing, "traces compared", compared, "of", len(X))
+    assert compared >= len(X) // 2
 
 
 def test_batch_relaid_to_reached_bonds():

@@ -257,3 +257,62 @@ def test_tiny_workload_matches_golden_statevector_gram():
     K = gram.gram([r.tensors for r in res])
     assert np.abs(K - K_gold[:16, :16]).max() < 1e-12
     assert np.allclose(np.diag(K_gold), 1.0, atol=1e-12)
+
+
+# ---------------------------------------------------------------- near-degenerate cuts (Eq. (8) ties)
+def _two_site_with_spectrum(s, seed=0):
+    """Sites (0, 1) of a 2-site chain with bond dimensions 1 | 2 | ... whose
+    two-site matrix theta = U diag(s) V^H has the given singular values
+    (random unitaries U, V; len(s) = 4 gives outer bonds 2 and 2)."""
+    rng = np.random.default_rng(seed)
+    n = len(s)
+    dl = n // 2
+
+    def unitary(k):
+        z = rng.standard_normal((k, k)) + 1j * rng.standard_normal((k, k))
+        return np.linalg.qr(z)[0]
+
+    U, V = unitary(n), unitary(n)
+    left = U.reshape(dl, 2, n)
+    right = (np.diag(np.asarray(s, dtype=float)) @ V.conj().T).reshape(n, 2, dl)
+    return [left, right]
+
+
+@pytest.mark.parametrize("s,chi,flag", [
+    ([2 ** -0.5, 2 ** -0.5], 1, True),        # kept and discarded value exactly equal
+    ([0.8, 0.6], 1, False),                   # clearly gapped
+    ([0.6, 0.6, np.sqrt(0.14), np.sqrt(0.14)], 1, True),
+    ([0.6, 0.6, np.sqrt(0.14), np.sqrt(0.14)], 2, False),   # the cut falls between the two pairs
+    ([0.6, 0.6, np.sqrt(0.14), np.sqrt(0.14)], 3, True),
+    ([0.6, 0.6, np.sqrt(0.14), np.sqrt(0.14)], 4, False),   # nothing discarded
+])
+def test_degenerate_cut_flag(s, chi, flag):
+    """The oracle flags a truncation whose last kept and first discarded
+    singular values coincide (several truncated states are then equally
+    optimal, Eq. (8)), and only then."""
+    s = np.asarray(s, dtype=float)
+    assert abs(np.sum(s ** 2) - 1) < 1e-15
+    A = _two_site_with_spectrum(s)
+    res = mps.MPSResult(tensors=A)
+    mps.apply_two_qubit(A, 0, np.eye(4, dtype=complex), chi, 0.0, True, res)
+    assert res.degenerate_cuts == int(flag)
+    k = min(chi, len(s))
+    assert A[0].shape[2] == k
+    assert abs(res.discarded - float(np.sum(s[k:] ** 2))) < 1e-14
+
+
+@pytest.mark.parametrize("gap,flag", [(1e-13, True), (1e-11, True), (1e-8, False), (1e-3, False)])
+def test_degenerate_cut_threshold(gap, flag):
+    """The relative gap (s_k - s_{k+1}) / s_1 at the cut is compared with the
+    stated threshold 1e-10: well below it flags, well above it does not."""
+    a = 0.7
+    b = a - gap * a
+    c = np.sqrt(1 - a * a - b * b)
+    s = np.array([a, b, c, 0.0])
+    s = s[np.argsort(-s)]
+    top = s[0]
+    A = _two_site_with_spectrum(s, seed=5)
+    res = mps.MPSResult(tensors=A)
+    mps.apply_two_qubit(A, 0, np.eye(4, dtype=complex), 1, 0.0, True, res)
+    assert (a - b) / top == pytest.approx(gap, rel=1e-3)
+    assert res.degenerate_cuts == int(flag)
