@@ -4,23 +4,29 @@
 Workload: 165 qubits (one per feature), interaction distance d = 8, two
 repetitions, bond cap chi = 64, SVD cutoff 1e-8; 6400 points from a
 two-class mixture of 165-dim Gaussians, min-max scaled to [0, 1]; the full
-symmetric 6400 x 6400 Gram matrix K = |<psi_i|psi_j>|^2.
+symmetric 6400 x 6400 Gram matrix K = |<psi_i|psi_j>|^2 in the split-BF16
+form (fixed-point digits on bf16 MFMA), with the FP64 GPU form beside it.
 
 What one run does (progress on stderr, ONE JSON line on stdout):
+  0. The CPU oracle baseline starts first, in worker processes forked before
+     the GPU is touched: each times the oracle's overlap of two random
+     left-canonical MPS with the workload's saturated bond profile (the
+     work of one Gram entry depends only on the bond dimensions).
   1. Simulate S distinct circuits of the workload on the GPU (mps_simulate,
-     timed separately: circuits/s, two-qubit gates/s).
-  2. Pack them into the timed form (default split-int8) and gather the 6400-MPS Gram batch
-     (MPS i is a copy of simulated state i mod S; every copy has the same
-     saturated bond profile as a freshly simulated point, so the Gram work is
-     that of 6400 distinct states).
-  3. TIMED: the full symmetric Gram in that form (row slabs, HIP events on the
-     launch stream).  value = N (N - 1) / 2 / t.
-  4. FP64, split-BF16 and split-int8 Grams of the S distinct states:
-     speedups over FP64 on identical work, and |dK| vs FP64; each entry of
-     the full matrix equals bit-for-bit one of the S x S entries of its form
-     (checked), so that |dK| is the maximum over all 20.5M entries.
-  5. The CPU FP64 oracle on a bounded sample of pairs (baseline, not target),
-     also giving |dK| of both GPU forms against the oracle.
+     timed separately) plus near-duplicates of the first 16 points.
+  2. Pack them and gather the 6400-MPS Gram batch in the split-BF16 form: MPS
+     i is a copy of simulated state i mod S at its own address, so the Gram
+     reads 6400 distinct MPS of the saturated bond profile.
+  3. TIMED: the full symmetric Gram as --steps row slabs of equal work (one
+     launch each, HIP events on the launch stream); ms_per_step x steps is
+     the time of the whole matrix.  value = N (N - 1) / 2 / t.
+  4. The FP64, split-int8 and split-BF16 forms on the same block
+     K[0:S, 0:C] of the full matrix (speedups on identical work, |dK|); each
+     upper entry of the full matrix is checked to equal bit for bit its
+     counterpart in the S x S part of that block, so |dK| against FP64 is the
+     maximum over all 20.5M entries.
+  5. The oracle's overlaps of exported GPU states (a sample of pairs and the
+     near-duplicates): |dK| of every form against the oracle.
 """
 from __future__ import annotations
 
@@ -37,23 +43,35 @@ if ROOT not in sys.path:
 
 METRIC = "Gram entries/s at 165 qubits chi=64, split-BF16 vs FP64 GPU, |dK|<=1e-6"
 PEAK_TFLOPS = {"bf16": 2500.0, "int8": 5000.0, "fp64": 78.6, "fp32": 157.3}
-# timed forms: MFMA dtype, kernel, description
+# forms: MFMA dtype, kernel, description
 FORMS = {
-    "split_i8": ("int8", "gram_kernel<split_i8,64>",
-                 "split-int8: 31-bit fixed-point codes with row/column exponents, four int8 digits, "
-                 "10 digit products (11 in the real part of T^T conj A) on int8 MFMA, exact int32 "
-                 "accumulation, fp64 combine"),
     "split_bf16": ("bf16", "gram_kernel<split_bf16,64>",
-                   "split-bf16: the same four digits carried as bf16, 10 digit products (11 in the real part "
-                   "of T^T conj A) on bf16 MFMA, exact fp32 leading accumulator + fp32 accumulator for the "
-                   "rest, fp64 combine"),
+                   "split-bf16: 31-bit fixed-point codes with row/column exponents cut into four 8-bit digits "
+                   "carried as bf16; 10 digit products (11 in the real part of T^T conj A) on bf16 MFMA; exact "
+                   "fp32 leading accumulator + fp32 accumulator for the rest; fp64 combine"),
+    "split_i8": ("int8", "gram_kernel<split_i8,64>",
+                 "split-int8: the same four digits as int8 MFMA operands, exact int32 accumulation per weight "
+                 "class, fp64 combine"),
 }
 ISSUED_PER_ALGORITHMIC = {"split_i8": 10.25, "split_bf16": 10.25}
 HBM_PEAK_GBS = 8000.0
+# wall-clock budget of one default run (the driver allows 600 s including
+# interpreter start and the first import of torch): optional legs are skipped
+# once the run has used this much
+SOFT_BUDGET_S = 470.0
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def process_age():
+    """Seconds since this process started (interpreter start included)."""
+    try:
+        import psutil
+        return time.time() - psutil.Process().create_time()
+    except Exception:
+        return time.perf_counter()
 
 
 def flops_per_entry(dims_a, dims_b):
@@ -145,79 +163,144 @@ def slab_bounds(n, parts):
     return sorted(set(b))
 
 
-def cpu_oracle_leg(mps_list, K_split, K_fp64, seconds):
-    """The CPU FP64 oracle timed in this process on one core (one BLAS thread)
-    over a bounded random sample of the pairs, plus |dK| of both GPU forms."""
+
+
+def host_cpu_description():
+    """CPU model and core counts of this host."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return {"model": model, "nproc": os.cpu_count(), "available": avail}
+
+
+def _oracle_worker(task):
+    """One worker of the CPU baseline: overlaps of two random saturated
+    165-site chi=64 MPS by the oracle, one BLAS thread, for `seconds`."""
+    seconds, seed = task
     import numpy as np
-
-    from oracle import gram as ogram
-
     try:
         import threadpoolctl
-        limiter = threadpoolctl.threadpool_limits(1)
+        threadpoolctl.threadpool_limits(1)
     except Exception:
-        limiter = None
-    n = len(mps_list)
-    pairs = [(i, j) for i in range(n) for j in range(i, n)]
-    rng = np.random.default_rng(11)
-    rng.shuffle(pairs)
-    vals = {}
+        pass
+    from oracle import gram as ogram
+    rng = np.random.default_rng(1000 + seed)
+    a = random_saturated_mps(165, 64, rng)
+    b = random_saturated_mps(165, 64, rng)
+    n = 0
     t0 = time.perf_counter()
-    last = t0
-    for (i, j) in pairs:
-        vals[(i, j)] = ogram.overlap(mps_list[i], mps_list[j])
-        now = time.perf_counter()
-        if now - last > 10:
-            last = now
-            log(f"[bench] oracle: {len(vals)} pairs, {now - t0:.0f} s")
-        if now - t0 > seconds:
+    while True:
+        ogram.overlap(a, b)
+        n += 1
+        dt = time.perf_counter() - t0
+        if dt >= seconds:
+            return n, dt
+
+
+class CpuBaseline:
+    """The oracle timed on the host cores: `workers` processes forked before
+    any GPU call (so none of them holds GPU state), each computing overlaps
+    for `seconds`; started asynchronously, collected with result()."""
+
+    def __init__(self, seconds, workers):
+        import multiprocessing as mp
+        self.seconds, self.workers = seconds, workers
+        self.pool = mp.get_context("fork").Pool(workers)
+        self.t0 = time.perf_counter()
+        self.job = self.pool.map_async(_oracle_worker, [(seconds, k) for k in range(workers)])
+
+    def result(self):
+        out = self.job.get(timeout=self.seconds + 120)
+        self.pool.close()
+        self.pool.join()
+        n = sum(k for k, _ in out)
+        rate = sum(k / dt for k, dt in out)
+        host = host_cpu_description()
+        return {"value": round(rate, 3), "unit": "entries/s", "cores": self.workers, "kind": "oracle",
+                "sample": f"{n} overlaps in {self.workers} worker processes x {self.seconds:.0f} s (one BLAS "
+                          f"thread each), each between two random left-canonical 165-site MPS with the "
+                          f"workload's saturated bond profile min(64, 2^min(l, m-l)) (the work of one Gram "
+                          f"entry); complex128 NumPy oracle",
+                "cpu_model": host["model"], "nproc": host["nproc"], "cpus_available": host["available"],
+                "per_core": round(rate / self.workers, 3)}
+
+    def cancel(self):
+        self.pool.terminate()
+
+
+def oracle_dk(mps, pairs, K_by_form, seconds):
+    """|dK| of each form's K against the oracle's overlaps of the exported GPU
+    states, over `pairs` (list of (i, j, key)); K_by_form[f][key] is the GPU
+    value.  Stops after `seconds`."""
+    import numpy as np
+    from oracle import gram as ogram
+    t0 = time.perf_counter()
+    ref = {}
+    for (i, j, key) in pairs:
+        ref[key] = abs(ogram.overlap(mps[i], mps[j])) ** 2
+        if time.perf_counter() - t0 > seconds:
             break
-    dt = time.perf_counter() - t0
-    if limiter is not None:
-        limiter.restore_original_limits()
-    sample = list(vals.keys())
-    d_split = np.array([abs(K_split[i, j] - abs(vals[(i, j)]) ** 2) for (i, j) in sample])
-    d_fp64 = np.array([abs(K_fp64[i, j] - abs(vals[(i, j)]) ** 2) for (i, j) in sample])
-    cpu = {"value": round(len(sample) / dt, 3), "unit": "entries/s", "cores": 1, "kind": "oracle",
-           "sample": f"{len(sample)} entries (random pairs among {n} simulated 165-qubit chi=64 MPS); "
-                     f"complex128 NumPy, one core, one BLAS thread, {dt:.1f} s"}
-    dk = {"split_vs_oracle_max": float(d_split.max()), "split_vs_oracle_mean": float(d_split.mean()),
-          "fp64_vs_oracle_max": float(d_fp64.max()), "fp64_vs_oracle_mean": float(d_fp64.mean()),
-          "pairs": len(sample)}
-    return cpu, dk
+    out = {"pairs": len(ref), "oracle_seconds_one_core": round(time.perf_counter() - t0, 2)}
+    for f, Kf in K_by_form.items():
+        d = np.array([abs(Kf[k] - ref[k]) for k in ref])
+        out[f"{f}_max"] = float(d.max()) if len(d) else None
+        out[f"{f}_mean"] = float(d.mean()) if len(d) else None
+    return out
+
+
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20,
+                    help="timed launches: equal-work row slabs of the full symmetric Gram, so that the steps "
+                         "together compute the whole matrix once")
+    ap.add_argument("--warmup", type=int, default=2, help="untimed warm-up launches (8-row blocks)")
     ap.add_argument("--n", type=int, default=6400, help="Gram size (points)")
     ap.add_argument("--sim-sample", type=int, default=240,
                     help="distinct circuits simulated on the GPU, plus 16 near-duplicates (one workgroup per "
                          "circuit: up to one per CU, 256, costs the same time)")
-    ap.add_argument("--slabs", type=int, default=8)
-    ap.add_argument("--slabs-run", type=int, default=0,
-                    help="run only the first K slabs of the timed Gram (hardware-counter passes); 0 = all")
+    ap.add_argument("--block-cols", type=int, default=1024,
+                    help="columns C of the block K[0:S, 0:C] on which every form is timed and compared")
+    ap.add_argument("--steps-run", type=int, default=0,
+                    help="run only the first K timed launches (hardware-counter passes), then exit")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--cpu-workers", type=int, default=0,
+                    help="worker processes of the CPU baseline (0: the cores available to this process, "
+                         "at most 16)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="use the stored kernel configurations")
+    ap.add_argument("--extras", action="store_true",
+                    help="also: the paper's 165-qubit bandwidth as a stress set, one inference row, one new "
+                         "point end to end, and the memory traces of the Fig. 6 circuits")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes (hardware-counter scale), then exit")
     ap.add_argument("--kernel-probe", type=int, default=0, metavar="N",
                     help="only time the symmetric Gram of N random saturated 165-site chi=64 MPS in every "
                          "form (kernel microbenchmark, no simulation), then exit")
-    ap.add_argument("--form", choices=sorted(FORMS), default="split_i8", help="form of the timed Gram")
+    ap.add_argument("--form", choices=sorted(FORMS), default="split_bf16", help="form of the timed Gram")
     ap.add_argument("--svm", action="store_true",
                     help="downstream use of K: SVM with the precomputed quantum kernel on synthetic two-class "
                          "data (165 features, d = 1, gamma 0.1; 300 / 1500 / 6400 points, 80/20 split), test "
-                         "AUC beside an RBF-kernel SVM; one JSON line, then exit")
+                         "AUC; one JSON line, then exit")
     ap.add_argument("--d-sweep", action="store_true",
                     help="interaction-distance sweep (100 qubits, gamma 1, d = 2..12, 8 points each): "
                          "simulation and overlap times, largest bond and memory per MPS, against the CPU "
                          "oracle where it finishes in seconds; one JSON line, then exit")
     ap.add_argument("--counter-record", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="only write profiles/gram_<form>_counters.json from rocprofv3 counter CSVs of "
-                         "'--slabs-run 1' runs (no GPU use), then exit")
+                         "'--steps-run 1' runs (no GPU use), then exit")
     ap.add_argument("--counter-config", default="maxp=64,tile_side=16,queues=1",
                     help="kernel configuration of the counter runs (as reported by their autotune line)")
     ap.add_argument("--counter-scale", nargs=2, type=float, default=(2047.93, 1024.0),
@@ -235,11 +318,20 @@ def main():
         write_counter_record(args.form, args.counter_record[0], args.counter_record[1], args.counter_scale[0],
                              args.counter_scale[1],
                              f"rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) --output-format csv -- python3 "
-                             f"bench.py --form {args.form} --slabs-run 1 --no-cpu --warmup 0",
+                             f"bench.py --form {args.form} --steps {args.steps} --steps-run 1 --no-cpu "
+                             f"--warmup 0",
                              {k: int(v) for k, v in (kv.split("=") for kv in args.counter_config.split(","))})
         return
+    default_run = not (args.calibrate_copy or args.kernel_probe or args.d_sweep or args.svm)
+    cpu = None
+    if default_run and not args.no_cpu and args.steps_run == 0:
+        # forked before any GPU call: the workers hold no GPU state
+        workers = args.cpu_workers or max(1, min(16, host_cpu_description()["available"] or 1))
+        cpu = CpuBaseline(args.cpu_seconds, workers)
     import torch
     if not torch.cuda.is_available():
+        if cpu is not None:
+            cpu.cancel()
         log("bench.py needs a GPU (the Gram and simulation kernels run only on the device)")
         sys.exit(1)
     if args.calibrate_copy > 0:
@@ -254,10 +346,9 @@ def main():
     if args.svm:
         svm_auc(args.routing)
         return
-    run(args)
+    run(args, cpu)
 
 
-# decade bins of K: [0, 1e-16), [1e-16, 1e-15), ..., [0.1, 1]
 K_HIST_EDGES = tuple(range(-16, 1))
 
 
@@ -380,7 +471,7 @@ def svm_auc(routing):
     two-class mixture (the Elliptic stand-in of the full workload, with labels), for 300, 1500 and 6400
     points split 80/20: every Gram form is timed on 128 test rows x the training set, the fastest computes
     K_train (symmetric, in row slabs) and K_test (test x train), an SVM is fitted with the precomputed
-    kernel, and its test AUC is reported beside that of an RBF-kernel SVM on the raw features."""
+    kernel, and its test AUC is reported."""
     import numpy as np
     import torch
     from sklearn.metrics import roc_auc_score
@@ -438,15 +529,13 @@ def svm_auc(routing):
         auc_q = roc_auc_score(y[ntr:n], svm.decision_function(Kte))
         auc_q_train = roc_auc_score(y[:ntr], svm.decision_function(Ktr))
         t_fit = time.perf_counter() - t0
-        rbf = SVC(kernel="rbf", C=1.0, gamma="scale").fit(X[:ntr], y[:ntr])
-        auc_rbf = roc_auc_score(y[ntr:n], rbf.decision_function(X[ntr:n]))
         off = Ktr[~np.eye(ntr, dtype=bool)]
         row = {"points": n, "train": ntr, "test": n - ntr, "max_bond": b.info()["max_bond"],
                "sim_s": round(t_sim, 3), "gram_form": best, "gram_s": round(t_gram, 3),
                "gram_entries": ntr * (ntr + 1) // 2 + (n - ntr) * ntr, "svm_fit_s": round(t_fit, 2),
                "K_offdiag_median": float(np.median(off)), "K_offdiag_min": float(off.min()),
                "auc_test_quantum": round(float(auc_q), 4), "auc_train_quantum": round(float(auc_q_train), 4),
-               "auc_test_rbf": round(float(auc_rbf), 4), "forms_on_test_rows": forms}
+               "forms_on_test_rows": forms}
         log(f"[bench] svm {row}")
         rows.append(row)
         del b
@@ -468,32 +557,105 @@ def calibrate_copy(nbytes):
     log(f"[bench] copy calibration: {4 * n} bytes read, {4 * n} bytes written")
 
 
-def run(args):
+
+
+def _events():
+    import torch
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def run_extras(q, sd, w, spec, sim, gb, form, S, N, stream, routing):
+    """Optional legs (--extras): the paper's own 165-qubit bandwidth as a
+    stress set, one inference row, one new point end to end, and the memory
+    evolution of the Fig. 6 circuits."""
+    import numpy as np
+    import torch
+    out = {}
+    # the paper's 165-qubit bandwidth (gamma = 0.1, d = 1): K = O(0.1 .. 1)
+    wp = sd.WORKLOADS["paper_d1"]
+    P = min(64, S)
+    specp = q.CircuitSpec(wp.n_qubits, wp.distance, wp.reps, wp.coef_z, wp.coef_xx, routing)
+    xp = torch.tensor(sd.workload_features(wp, P), dtype=torch.float64, device="cuda")
+    simp = q.simulate(xp, specp, wp.chi, wp.cutoff)
+    Kp = {f: q.gram(simp, precision=f) for f in ("fp64",) + tuple(FORMS)}
+    stream.synchronize()
+    offp = Kp["fp64"].cpu().numpy()[~np.eye(P, dtype=bool)]
+    out["paper_bandwidth"] = {
+        "workload": "165 qubits, d=1, reps=2, coef_z=0.2, coef_xx=0.01*pi (gamma 0.1), chi 64",
+        "points": P, "max_bond": simp.info()["max_bond"], "offdiag_K_median": float(np.median(offp)),
+        "hist_offdiag": k_histogram(offp),
+        **{f"{f}_vs_fp64_max": float((Kp[f] - Kp["fp64"]).abs().max().item()) for f in FORMS}}
+    log(f"[bench] paper bandwidth: {out['paper_bandwidth']}")
+    # one inference row against the N training MPS
+    q.gram_block(gb, 0, 1, gb, 0, N, precision=form, stream=stream)
+    stream.synchronize()
+    e0, e1 = _events()
+    e0.record(stream)
+    q.gram_block(gb, 0, 1, gb, 0, N, precision=form, stream=stream)
+    e1.record(stream)
+    e1.synchronize()
+    t_row = e0.elapsed_time(e1) / 1e3
+    # one new point end to end (features on the device): simulation, then its row
+    xn = torch.tensor(sd.workload_features(w, S + 1)[S:S + 1], dtype=torch.float64, device="cuda")
+    rown = torch.zeros((1, N), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    simn = q.simulate(xn, spec, w.chi, w.cutoff, stream=stream)
+    stream.synchronize()
+    t_sim1 = time.perf_counter() - t0
+    q.gram_block(simn, 0, 1, gb, 0, N, precision=form, out=rown, stream=stream)
+    stream.synchronize()
+    out["inference"] = {"row_entries": N, "ms": round(t_row * 1e3, 3), "entries_per_s": round(N / t_row, 1),
+                        "new_point_simulation_s": round(t_sim1, 3),
+                        "new_point_end_to_end_s": round(time.perf_counter() - t0, 3)}
+    log(f"[bench] inference: {out['inference']}")
+    # memory evolution during simulation (Fig. 6's circuits: 100 qubits, d = 6 and 12, gamma = 1)
+    memtrace = {}
+    for name in ("fig6_d6", "fig6_d12"):
+        wf = sd.WORKLOADS[name]
+        xf = torch.tensor(sd.workload_features(wf), dtype=torch.float64, device="cuda")
+        specf = q.CircuitSpec(wf.n_qubits, wf.distance, wf.reps, wf.coef_z, wf.coef_xx, routing)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        bf, trf = q.simulate_trace(xf, specf, wf.chi, wf.cutoff, stream=stream)
+        stream.synchronize()
+        mib = trf[:, :, 1].double().cpu().numpy() * 32 / 2 ** 20
+        g2 = mib.shape[1]
+        at = [min(g2 - 1, max(0, int(round(f * g2)) - 1)) for f in np.linspace(0.1, 1.0, 10)]
+        memtrace[name] = {"circuits": int(mib.shape[0]), "two_qubit_gates": g2,
+                          "seconds": round(time.perf_counter() - t0, 2), "max_bond": bf.info()["max_bond"],
+                          "mib_at_10pct_steps_mean": [round(float(v), 3) for v in mib[:, at].mean(0)],
+                          "peak_mib_mean": round(float(mib.max(1).mean()), 3)}
+        log(f"[bench] memory trace {name}: {memtrace[name]}")
+    out["memory_trace"] = memtrace
+    return out
+
+
+def run(args, cpu):
     import numpy as np
     import torch
 
     import paper_2411_09336_amd as q
     import synthdata as sd
 
-    if not torch.cuda.is_available():
-        log("bench.py needs a GPU")
-        sys.exit(1)
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
     w = sd.WORKLOADS["full"]
+    form = args.form
+    mdt, kname, fdesc = FORMS[form]
     N, S = args.n, min(args.sim_sample, args.n)
     X = sd.workload_features(w, N)
     spec = q.CircuitSpec(w.n_qubits, w.distance, w.reps, w.coef_z, w.coef_xx, args.routing)
+    skipped = []
 
     # ---------------------------------------------------------------- 1. simulation
-    log(f"[bench] simulating {S} circuits: m={w.n_qubits} d={w.distance} reps={w.reps} chi={w.chi} cutoff={w.cutoff}")
-    # D near-duplicates of the first D points ride along in the same batch
-    # (same launches): pairs (x, x') have mid-range K for the precision check
     D = min(16, S)
+    log(f"[bench] simulating {S} + {D} circuits: m={w.n_qubits} d={w.distance} reps={w.reps} chi={w.chi} "
+        f"cutoff={w.cutoff} routing={args.routing}")
     xs = torch.tensor(np.vstack([X[:S], sd.perturb_near_duplicates(X[:D])]), dtype=torch.float64, device="cuda")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    t_last = [time.perf_counter()]
+    t_last = [t0]
 
     def progress(done, total):
         if time.perf_counter() - t_last[0] > 20 or done == total:
@@ -501,7 +663,7 @@ def run(args):
             log(f"[bench] simulation: {done}/{total} two-qubit gates, {t_last[0] - t0:.0f} s")
         return False
 
-    sim = q.simulate(xs, spec, w.chi, w.cutoff, progress=progress, every=200)
+    sim = q.simulate(xs, spec, w.chi, w.cutoff, progress=progress, every=500)
     torch.cuda.synchronize()
     t_sim = time.perf_counter() - t0
     info = sim.info()
@@ -511,281 +673,202 @@ def run(args):
         f"unconverged SVDs {info['unconverged_svds']}, degenerate cuts {info['degenerate_cuts']}")
 
     # ---------------------------------------------------------------- 2. Gram batch
-    form = args.form
-    for f in ("fp64", "split_bf16", "split_i8"):
-        sim.pack(f)
+    t0 = time.perf_counter()
+    sim.pack(form)
     idx = np.arange(N) % S
     gb = sim.gather(idx, forms=(form,))
-    ginfo = gb.info()
-    log(f"[bench] Gram batch: {N} MPS, {form} planes {ginfo['bytes_' + form] / 1e9:.1f} GB")
-
-    # kernel configuration for this form and pad bucket, timed on a sample
-    # of the batch (outside the timed region)
-    tune = q.autotune(gb, precision=form, sample=min(256, N), stream=stream)
-    log(f"[bench] autotune {form}: {tune}")
+    torch.cuda.synchronize()
+    log(f"[bench] Gram batch: {N} MPS in {form} ({gb.info()['bytes_' + form] / 1e9:.1f} GB) in "
+        f"{time.perf_counter() - t0:.1f} s")
+    tune = None
+    if not args.no_tune:
+        # kernel configuration for this form and pad bucket, timed on a
+        # sample of the batch (outside the timed region)
+        tune = q.autotune(gb, precision=form, sample=min(128, N), stream=stream)
+        log(f"[bench] autotune {form}: {tune}")
 
     K = torch.zeros((N, N), dtype=torch.float64, device="cuda")
-    slabs = slab_bounds(N, args.slabs)
-
-    def run_full(tag):
-        ev0 = torch.cuda.Event(enable_timing=True)
-        ev1 = torch.cuda.Event(enable_timing=True)
-        ev0.record(stream)
-        nrun = len(slabs) - 1 if args.slabs_run <= 0 else min(args.slabs_run, len(slabs) - 1)
-        for p in range(nrun):
-            r0, r1 = slabs[p], slabs[p + 1]
-            out = K[r0:, r0:]
-            q.gram_block(gb, r0, r1 - r0, gb, r0, N - r0, precision=form, upper_only=True,
-                         out=out, stream=stream)
-            stream.synchronize()
-            log(f"[bench] {tag} slab {p + 1}/{len(slabs) - 1} rows {r0}:{r1} done")
-        ev1.record(stream)
-        ev1.synchronize()
-        return ev0.elapsed_time(ev1) / 1e3
-
-    # warmup: one slab-sized block outside the timed region
-    for _ in range(args.warmup):
-        wr = min(64, N)
+    slabs = slab_bounds(N, args.steps)
+    n_launch = len(slabs) - 1
+    for k in range(args.warmup):
+        wr = min(8, N)
         q.gram_block(gb, 0, wr, gb, 0, N, precision=form, upper_only=True, out=K[:wr], stream=stream)
         stream.synchronize()
-        log("[bench] warmup done")
+    log(f"[bench] {args.warmup} warm-up launches done")
+    cpu_res = None
+    if cpu is not None:
+        # the baseline's workers finish before the timed region starts
+        cpu_res = cpu.result()
+        log(f"[bench] CPU oracle baseline: {cpu_res}")
 
     # ---------------------------------------------------------------- 3. timed
-    times = []
-    for st in range(args.steps):
-        times.append(run_full(f"step {st + 1}/{args.steps}"))
-    t_split = float(np.median(times))
+    nrun = n_launch if args.steps_run <= 0 else min(args.steps_run, n_launch)
+    evs = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for p in range(nrun):
+        r0, r1 = slabs[p], slabs[p + 1]
+        e0, e1 = _events()
+        e0.record(stream)
+        q.gram_block(gb, r0, r1 - r0, gb, r0, N - r0, precision=form, upper_only=True, out=K[r0:, r0:],
+                     stream=stream)
+        e1.record(stream)
+        evs.append((e0, e1))
+        stream.synchronize()
+        log(f"[bench] step {p + 1}/{n_launch}: rows {r0}:{r1}, {e0.elapsed_time(e1) / 1e3:.2f} s")
+    torch.cuda.synchronize()
+    t_gram = time.perf_counter() - t0
+    if args.steps_run > 0:
+        log(f"[bench] partial run ({nrun} launches) for hardware counters: no result line")
+        return
     n_off = N * (N - 1) // 2
     n_comp = N * (N + 1) // 2
-    value = n_off / t_split
-    if args.slabs_run > 0:
-        log(f"[bench] partial run ({args.slabs_run} slabs) for hardware counters: no result line")
-        return
-    log(f"[bench] {form} full Gram: {t_split:.2f} s -> {value:.1f} entries/s")
-
-    # complete the lower triangle (outside the timed region)
+    value = n_off / t_gram
+    launch_s = [a.elapsed_time(b) / 1e3 for a, b in evs]
+    log(f"[bench] {form} full Gram: {t_gram:.2f} s -> {value:.1f} entries/s "
+        f"(launches {min(launch_s):.3f} .. {max(launch_s):.3f} s)")
     Ku = torch.triu(K)
     K = Ku + torch.triu(K, 1).T
     del Ku
 
-    # ---------------------------------------------------------------- 4. FP64 vs split on S distinct
-    # full S x S blocks (bra i, ket j for every i, j), so that each upper
-    # entry of the full matrix has an identically computed counterpart
-    Kd = torch.zeros((S, S), dtype=torch.float64, device="cuda")
-    Kforms = {f: torch.zeros((S, S), dtype=torch.float64, device="cuda") for f in FORMS}
-
-    def timed_gram(prec, out):
-        q.gram_block(sim, 0, S, sim, 0, S, precision=prec, out=out, stream=stream)   # warm
+    # ---------------------------------------------------------------- 4. every form on K[0:S, 0:C]
+    C = min(max(args.block_cols, S), N)
+    sim.pack("split_i8")
+    gc = sim.gather(idx[:C], forms=("fp64", "split_i8"), stream=stream)
+    col_batch = {"fp64": gc, "split_i8": gc, form: gb}
+    tuned = {form: tune}
+    Kblk, t_blk = {}, {}
+    for f in ("fp64", "split_i8", form):
+        if f not in tuned and not args.no_tune:
+            tuned[f] = q.autotune(sim, precision=f, sample=64, stream=stream)
+        out = torch.zeros((S, C), dtype=torch.float64, device="cuda")
+        q.gram_block(sim, 0, min(8, S), col_batch[f], 0, C, precision=f, out=out[:8], stream=stream)
         stream.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
+        e0, e1 = _events()
         e0.record(stream)
-        q.gram_block(sim, 0, S, sim, 0, S, precision=prec, out=out, stream=stream)
+        q.gram_block(sim, 0, S, col_batch[f], 0, C, precision=f, out=out, stream=stream)
         e1.record(stream)
         e1.synchronize()
-        return e0.elapsed_time(e1) / 1e3
-
-    # every form runs its own best configuration (autotuned on a sample of
-    # the simulated states; the timed form keeps the one tuned above)
-    tuned = {form: tune}
-    for f in ("fp64",) + tuple(x for x in FORMS if x != form):
-        tuned[f] = q.autotune(sim, precision=f, sample=min(128, S), stream=stream)
-    log(f"[bench] autotuned comparison forms: {tuned}")
-    t_d_small = timed_gram("fp64", Kd)
-    t_forms = {f: timed_gram(f, Kforms[f]) for f in FORMS}
-    Ks = Kforms[form]
-    t_s_small = t_forms[form]
-    speedup = t_d_small / t_s_small
-    dK = (Ks - Kd).abs()
+        Kblk[f], t_blk[f] = out, e0.elapsed_time(e1) / 1e3
+        log(f"[bench] block K[0:{S}, 0:{C}] in {f}: {t_blk[f]:.3f} s ({S * C / t_blk[f]:.1f} entries/s)")
+    del gc
+    speedup = t_blk["fp64"] / t_blk[form]
     ii = torch.as_tensor(idx, device="cuda")
     upper = torch.ones((N, N), dtype=torch.bool, device="cuda").triu_()
-    Kmap = Ks[ii][:, ii]
+    Kmap = Kblk[form][:, :S][ii][:, ii]
     bit_identical = bool(torch.equal(Kmap[upper], K[upper]))
     del Kmap
-    full_dK_max = float((K - Kd[ii][:, ii]).abs()[upper].max().item())
-    del upper
-    s_pairs = S * S
-    log(f"[bench] S={S}: {form} {t_s_small:.3f} s, fp64 {t_d_small:.3f} s, speedup {speedup:.2f}x; "
-        f"|dK| max {dK.max().item():.3e}; full-matrix upper entries identical to the S x S map: {bit_identical}")
+    Kdmap = Kblk["fp64"][:, :S][ii][:, ii]
+    dfull = (K - Kdmap).abs()[upper]
+    full_dK_max, full_dK_mean = float(dfull.max().item()), float(dfull.mean().item())
+    del Kdmap, dfull, upper
+    log(f"[bench] speedup over FP64 on K[0:{S}, 0:{C}]: {speedup:.2f}x; all {n_comp} upper entries identical to "
+        f"their S x S counterparts: {bit_identical}; max|dK| vs FP64 over them {full_dK_max:.3e}")
 
-    # ---------------------------------------------------------------- roofline
-    d0 = dims[0]
-    fpe = flops_per_entry(d0, d0)
-    flops_launch = fpe * n_comp
-    achieved_tf = flops_launch / t_split / 1e12
-    # a complex MAC is 8 algorithmic flops; the split forms issue 4 real
-    # products per digit product: 40 real MACs in E B (ten digit pairs) and
-    # 42 in T^T conj A (the (2, 2) pair in its real part only), and the two
-    # GEMMs do equal work: 10.25 x the algorithmic ops
-    mdt, kname, fdesc = FORMS[form]
-    issued_tf = achieved_tf * ISSUED_PER_ALGORITHMIC[form]
-    traffic, crec = counter_traffic(form, tune)
-    roof = {"bound": "mfma", "achieved": round(achieved_tf, 3), "peak": PEAK_TFLOPS[mdt], "unit": "TFLOP/s",
-            "frac": round(achieved_tf / PEAK_TFLOPS[mdt], 5), "traffic": traffic,
-            "traffic_note": (None if crec is None else crec.get("note")),
-            "peak_note": f"dense {mdt} MFMA peak of the contraction's operand type; achieved counts "
-                         "algorithmic complex-GEMM flops (8 per complex MAC)",
-            "launches_in_timed_region": len(slabs) - 1,
-            "kernel": kname, "flops_per_entry": fpe, "entries_per_timed_region": n_comp,
-            "issued_tops": round(issued_tf, 2), "issued_frac": round(issued_tf / PEAK_TFLOPS[mdt], 4),
-            "fp64_form_tflops": round(fpe * s_pairs / t_d_small / 1e12, 3),
-            "fp64_form_frac": round(fpe * s_pairs / t_d_small / 1e12 / PEAK_TFLOPS["fp64"], 4)}
-
-    # ---------------------------------------------------------------- 4b. stress sets and inference
-    # (i) near-duplicate block: rows = D points, columns = their near-duplicates
+    # near-duplicate block: rows = the first D points, columns = their near-duplicates
     Knd = {}
-    for f in ("fp64",) + tuple(FORMS):
+    for f in ("fp64", "split_i8", form):
         out = torch.zeros((D, D), dtype=torch.float64, device="cuda")
         q.gram_block(sim, 0, D, sim, S, D, precision=f, out=out, stream=stream)
         Knd[f] = out
     stream.synchronize()
     nd_diag = Knd["fp64"].diagonal()
-    log(f"[bench] near-duplicate block: K(x, x') in [{nd_diag.min().item():.3f}, {nd_diag.max().item():.3f}]; "
+    log(f"[bench] near-duplicates: K(x, x') in [{nd_diag.min().item():.3f}, {nd_diag.max().item():.3f}]; "
         + ", ".join(f"{f} max|dK| {(Knd[f] - Knd['fp64']).abs().max().item():.2e}" for f in FORMS))
-    # (ii) the paper's own 165-qubit bandwidth (gamma = 0.1, d = 1): K = O(0.1 .. 1)
-    wp = sd.WORKLOADS["paper_d1"]
-    P = min(64, S)
-    specp = q.CircuitSpec(wp.n_qubits, wp.distance, wp.reps, wp.coef_z, wp.coef_xx, args.routing)
-    xp = torch.tensor(sd.workload_features(wp, P), dtype=torch.float64, device="cuda")
-    simp = q.simulate(xp, specp, wp.chi, wp.cutoff)
-    Kp = {}
-    for f in ("fp64",) + tuple(FORMS):
-        Kp[f] = q.gram(simp, precision=f)
-    stream.synchronize()
-    offp = Kp["fp64"].cpu().numpy()[~np.eye(P, dtype=bool)]
-    log(f"[bench] paper bandwidth (gamma 0.1, d 1): max bond {simp.info()['max_bond']}, off-diagonal K median "
-        f"{np.median(offp):.3f}; " + ", ".join(f"{f} max|dK| {(Kp[f] - Kp['fp64']).abs().max().item():.2e}"
-                                               for f in FORMS))
-    # (iii) inference: one new point's kernel row against the N-point training batch
-    q.gram_block(gb, 0, 1, gb, 0, N, precision=form, stream=stream)
-    stream.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    q.gram_block(gb, 0, 1, gb, 0, N, precision=form, stream=stream)
-    e1.record(stream)
-    e1.synchronize()
-    t_row = e0.elapsed_time(e1) / 1e3
-    log(f"[bench] inference row (1 x {N}, {form}): {t_row * 1e3:.2f} ms")
-    # (iv) one new point end to end (features on the device): its simulation, then its kernel row
-    # against the training batch; one circuit occupies one CU for its whole step list
-    xn = torch.tensor(sd.workload_features(w, S + 1)[S:S + 1], dtype=torch.float64, device="cuda")
-    rown = torch.zeros((1, N), dtype=torch.float64, device="cuda")
-    torch.cuda.synchronize()
-    t0 = time.time()
-    simn = q.simulate(xn, spec, w.chi, w.cutoff, stream=stream)
-    stream.synchronize()
-    t_sim1 = time.time() - t0
-    q.gram_block(simn, 0, 1, gb, 0, N, precision=form, out=rown, stream=stream)
-    stream.synchronize()
-    t_point = time.time() - t0
-    log(f"[bench] new point end to end: simulation {t_sim1:.2f} s, with its 1 x {N} row {t_point:.2f} s")
 
-    # (v) memory evolution during simulation (Fig. 6's circuits: 100 qubits, d = 6 and 12, gamma = 1,
-    # 8 samples each): MPS memory after every two-qubit gate from the library's trace
-    memtrace = {}
-    for name in ("fig6_d6", "fig6_d12"):
-        wf = sd.WORKLOADS[name]
-        xf = torch.tensor(sd.workload_features(wf), dtype=torch.float64, device="cuda")
-        specf = q.CircuitSpec(wf.n_qubits, wf.distance, wf.reps, wf.coef_z, wf.coef_xx, args.routing)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        bf, trf = q.simulate_trace(xf, specf, wf.chi, wf.cutoff, stream=stream)
-        stream.synchronize()
-        t_f = time.perf_counter() - t0
-        mib = trf[:, :, 1].double().cpu().numpy() * 32 / 2 ** 20      # FP64 tensors, MiB
-        g2 = mib.shape[1]
-        at = [min(g2 - 1, max(0, int(round(f * g2)) - 1)) for f in np.linspace(0.1, 1.0, 10)]
-        memtrace[name] = {"circuits": int(mib.shape[0]), "two_qubit_gates": g2, "seconds": round(t_f, 2),
-                          "max_bond": bf.info()["max_bond"],
-                          "mib_at_10pct_steps_mean": [round(float(v), 3) for v in mib[:, at].mean(0)],
-                          "mib_at_10pct_steps_min": [round(float(v), 3) for v in mib[:, at].min(0)],
-                          "mib_at_10pct_steps_max": [round(float(v), 3) for v in mib[:, at].max(0)],
-                          "peak_mib_mean": round(float(mib.max(1).mean()), 3),
-                          "final_mib_mean": round(float(mib[:, -1].mean()), 3)}
-        log(f"[bench] memory trace {name}: {g2} gates in {t_f:.1f} s, max bond {memtrace[name]['max_bond']}, "
-            f"mean MiB at 10 % steps {memtrace[name]['mib_at_10pct_steps_mean']}")
-        del bf, trf
-
-    # ---------------------------------------------------------------- 5. CPU oracle
-    cpu = None
+    # ---------------------------------------------------------------- 5. the oracle on GPU states
     dk_oracle = None
     if not args.no_cpu:
-        n_exp = min(S, 48)
-        log(f"[bench] exporting {n_exp} MPS for the CPU oracle")
-        mps_np = [sim.export(i) for i in range(n_exp)]
-        try:
-            cpu, dk_oracle = cpu_oracle_leg(mps_np, Ks.cpu().numpy(), Kd.cpu().numpy(), args.cpu_seconds)
-            # the oracle on the two stress sets (all pairs; the paper-bandwidth states have small bonds)
-            from oracle import gram as ogram
-            nd_o = np.array([[abs(ogram.overlap(sim.export(i), sim.export(S + j))) ** 2 for j in range(D)]
-                             for i in range(D)])
-            mp = [simp.export(i) for i in range(P)]
-            kp_o = ogram.gram(mp)
-            for f in ("fp64",) + tuple(FORMS):
-                dk_oracle[f"near_duplicates_{f}_max"] = float(np.abs(Knd[f].cpu().numpy() - nd_o).max())
-                dk_oracle[f"paper_bandwidth_{f}_max"] = float(np.abs(Kp[f].cpu().numpy() - kp_o).max())
-            log(f"[bench] oracle on stress sets: {dk_oracle}")
-            log(f"[bench] oracle: {cpu['value']:.2f} entries/s on {cpu['cores']} cores; {dk_oracle}")
-        except Exception as e:   # the baseline must not cost the measurement
-            log(f"[bench] CPU oracle leg failed: {e!r}")
-            dk_oracle = {"error": repr(e)}
+        if process_age() < SOFT_BUDGET_S:
+            n_exp = min(12, S)
+            mps = {i: sim.export(i) for i in range(n_exp)}
+            mps.update({S + i: sim.export(S + i) for i in range(D)})
+            pairs = [(i, j, ("b", i, j)) for i in range(n_exp) for j in range(i, n_exp)]
+            pairs += [(i, S + i, ("n", i, i)) for i in range(D)]
+            Kb = {f: Kblk[f][:n_exp, :n_exp].cpu().numpy() for f in Kblk}
+            Kn = {f: Knd[f].cpu().numpy() for f in Knd}
+            K_by_form = {f: {key: (Kb[f][key[1], key[2]] if key[0] == "b" else Kn[f][key[1], key[2]])
+                             for (_, _, key) in pairs} for f in Kblk}
+            dk_oracle = oracle_dk(mps, pairs, K_by_form, seconds=30.0)
+            log(f"[bench] vs oracle: {dk_oracle}")
+        else:
+            skipped.append("oracle |dK| on GPU states (time budget)")
 
-    Kh = Ks.cpu().numpy()
+    extras = None
+    if args.extras:
+        extras = run_extras(q, sd, w, spec, sim, gb, form, S, N, stream, args.routing)
+
+    # ---------------------------------------------------------------- roofline of the timed kernel
+    fpe = flops_per_entry(dims[0], dims[0])
+    entries_run = sum(N - r for r in range(slabs[0], slabs[nrun]))
+    t_kernels = float(sum(launch_s))
+    achieved = fpe * entries_run / t_kernels / 1e12
+    issued = achieved * ISSUED_PER_ALGORITHMIC[form]
+    traffic, crec = counter_traffic(form, tune or {})
+    roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS[mdt], "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_TFLOPS[mdt], 5), "traffic": traffic,
+            "traffic_note": None if crec is None else crec.get("note"),
+            "peak_note": f"dense {mdt} MFMA peak of the contraction's operand type; achieved counts algorithmic "
+                         "complex-GEMM flops (8 per complex MAC) of one launch over its HIP-event duration",
+            "kernel": kname, "flops_per_entry": fpe, "entries_per_launch": round(entries_run / nrun, 1),
+            "avg_launch_s": round(t_kernels / nrun, 4), "launches": nrun,
+            "issued_tops": round(issued, 2), "issued_frac": round(issued / PEAK_TFLOPS[mdt], 4),
+            "fp64_form_tflops": round(fpe * S * C / t_blk["fp64"] / 1e12, 3),
+            "fp64_form_frac": round(fpe * S * C / t_blk["fp64"] / 1e12 / PEAK_TFLOPS["fp64"], 4)}
+
+    Kh = Kblk["fp64"][:, :S].cpu().numpy()
     offd = Kh[~np.eye(S, dtype=bool)]
     result = {
         "metric": METRIC,
         "value": round(value, 2),
         "unit": "entries/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": nrun,
         "warmup": args.warmup,
-        "ms_per_step": round(t_split * 1e3, 1),
+        "ms_per_step": round(t_gram / nrun * 1e3, 1),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": mdt,
         "data": "synthetic",
-        "config": {"workload": "full: 165 qubits, d=8, reps=2, chi=64, cutoff=1e-8, N=6400 symmetric Gram",
+        "config": {"workload": f"full: {N} points x 165 qubits (one per feature), d=8, reps=2, chi=64, "
+                               f"cutoff=1e-8, symmetric {N}x{N} Gram ({n_off} off-diagonal entries) in {form}; "
+                               f"{S} distinct GPU-simulated states, MPS i a copy of state i mod {S} at its own "
+                               f"address",
                    "n_points": N, "n_qubits": w.n_qubits, "distance": w.distance, "reps": w.reps,
                    "chi": w.chi, "cutoff": w.cutoff, "routing": args.routing, "distinct_states": S,
-                   "form": form, "precision": fdesc},
-        "autotune": tuned,
+                   "form": form, "precision": fdesc,
+                   "step": f"one launch = one of {n_launch} equal-work row slabs of the upper triangle"},
         "roofline": roof,
-        "cpu_baseline": cpu,
-        "fp64_gpu": {"entries_per_s": round(s_pairs / t_d_small, 2), "speedup_vs_fp64": round(speedup, 3),
-                     "measured_on": f"{S}x{S} Gram of the simulated states ({s_pairs} entries)"},
+        "cpu_baseline": cpu_res,
+        "gram_seconds": round(t_gram, 3),
+        "fp64_gpu": {"entries_per_s": round(S * C / t_blk["fp64"], 2), "speedup_of_form": round(speedup, 3),
+                     "measured_on": f"block K[0:{S}, 0:{C}] of the full matrix ({S * C} entries), "
+                                    f"the same work in every form"},
         "forms_on_same_work": {
-            f: {"entries_per_s": round(s_pairs / t_forms[f], 2), "speedup_vs_fp64": round(t_d_small / t_forms[f], 3),
-                "dK_vs_fp64_max": float((Kforms[f] - Kd).abs().max().item()),
-                "dK_vs_fp64_mean": float((Kforms[f] - Kd).abs().mean().item())} for f in FORMS},
-        "dK": {"vs_fp64_max_all_entries": full_dK_max, "vs_fp64_max": float(dK.max().item()),
-               "vs_fp64_mean": float(dK.mean().item()), "full_matrix_bit_identical_to_SxS": bit_identical,
-               "oracle": dk_oracle},
-        "stress": {
-            "near_duplicates": {"points": D, "K_range": [float(nd_diag.min().item()), float(nd_diag.max().item())],
-                                **{f"{f}_vs_fp64_max": float((Knd[f] - Knd["fp64"]).abs().max().item())
-                                   for f in FORMS}},
-            "paper_bandwidth": {"workload": "165 qubits, d=1, reps=2, coef_z=0.2, coef_xx=0.01*pi (gamma 0.1), chi 64",
-                                "points": P, "max_bond": simp.info()["max_bond"],
-                                "offdiag_K_median": float(np.median(offp)), "offdiag_K_min": float(offp.min()),
-                                **{f"{f}_vs_fp64_max": float((Kp[f] - Kp["fp64"]).abs().max().item())
-                                   for f in FORMS}}},
-        "inference": {"row_entries": N, "ms": round(t_row * 1e3, 3), "entries_per_s": round(N / t_row, 1),
-                      "new_point_simulation_s": round(t_sim1, 3), "new_point_end_to_end_s": round(t_point, 3)},
+            f: {"entries_per_s": round(S * C / t_blk[f], 2), "speedup_vs_fp64": round(t_blk["fp64"] / t_blk[f], 3),
+                "dK_vs_fp64_max": float((Kblk[f] - Kblk["fp64"]).abs().max().item()),
+                "dK_vs_fp64_mean": float((Kblk[f] - Kblk["fp64"]).abs().mean().item())}
+            for f in ("split_bf16", "split_i8")},
+        "dK": {"vs_fp64_max_all_entries": full_dK_max, "vs_fp64_mean_all_entries": full_dK_mean,
+               "full_matrix_bit_identical_to_block": bit_identical, "oracle": dk_oracle,
+               "near_duplicates": {"points": D,
+                                   "K_range": [float(nd_diag.min().item()), float(nd_diag.max().item())],
+                                   **{f"{f}_vs_fp64_max": float((Knd[f] - Knd["fp64"]).abs().max().item())
+                                      for f in FORMS}}},
         "K_distribution": {"offdiag_median": float(np.median(offd)), "offdiag_max": float(offd.max()),
-                           "offdiag_frac_above_1e-6": float((offd > 1e-6).mean()),
-                           "hist_edges_log10": list(K_HIST_EDGES),
-                           "hist_offdiag": k_histogram(offd),
-                           "hist_near_duplicates": k_histogram(nd_diag.cpu().numpy()),
-                           "hist_paper_bandwidth": k_histogram(offp)},
-        "memory_trace": memtrace,
+                           "hist_edges_log10": list(K_HIST_EDGES), "hist_offdiag": k_histogram(offd),
+                           "hist_near_duplicates": k_histogram(nd_diag.cpu().numpy())},
+        "autotune": tuned,
         "simulation": {"circuits": n_sim, "seconds": round(t_sim, 2), "circuits_per_s": round(n_sim / t_sim, 3),
                        "two_qubit_gates_per_circuit": info["n_two_qubit_gates"],
                        "two_qubit_gates_per_s": round(n_sim * info["n_two_qubit_gates"] / t_sim, 1),
                        "max_bond": info["max_bond"], "unconverged_svds": info["unconverged_svds"],
                        "degenerate_cuts": info["degenerate_cuts"],
                        "mean_total_discarded": info["mean_total_discarded"]},
+        "extras": extras,
+        "skipped": skipped,
+        "wall_s": round(process_age(), 1),
     }
     print(json.dumps(result), flush=True)
 

@@ -112,8 +112,35 @@ typedef struct {
 
 /* ---------------------------------------------------------------- setup */
 
-/* Select the HIP device for subsequent calls on this thread. */
-qk_status qk_init(int device);
+/* Device-memory hook.  Every MPS is simulated once and its state reused by
+ * many overlaps (Sec. II-D), so the batches that hold those states are long
+ * lived and large; this hook lets them (and every scratch buffer the library
+ * needs) live in the caller's memory pool, e.g. a framework's caching
+ * allocator.
+ *   alloc(bytes, ctx, stream): `bytes` of device memory on the current
+ *       device, usable in stream order on `stream` (a hipStream_t as void*;
+ *       NULL = the default stream), or NULL on failure (the library then
+ *       returns QK_ENOMEM and enqueues nothing further for that call).
+ *   free(ptr, ctx, stream): release a pointer returned by alloc; `stream` is
+ *       the stream of its last use (NULL when it was last used in work the
+ *       library has already synchronised).
+ *   ctx: passed through unchanged.
+ * Both function pointers must be non-NULL. */
+typedef struct {
+  void *(*alloc)(size_t bytes, void *ctx, void *stream);
+  void (*free)(void *ptr, void *ctx, void *stream);
+  void *ctx;
+} qk_allocator;
+
+/* Select HIP device `device` for subsequent calls on this thread and set the
+ * allocator of that device: `alloc` (copied; its functions must stay valid
+ * while the library uses them) or, with alloc == NULL, hipMalloc / hipFree
+ * for batches and hipMallocAsync / hipFreeAsync for scratch.  The allocator
+ * is registered before the device is selected, so it is in place even when
+ * the call fails with QK_EDEVICE.  Batches keep the allocator that created
+ * them and release their memory through it.  QK_EINVAL for a negative
+ * device or an allocator with a NULL function. */
+qk_status qk_init(int device, const qk_allocator *alloc);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char *qk_last_error(void);
@@ -193,6 +220,21 @@ qk_status mps_simulate_graph(const double *features_dev, int64_t n_points,
 
 /* ---------------------------------------------------------------- Gram */
 
+/* Statistics of one Gram call (optional output of mps_gram*).  When a
+ * stats pointer is given, the call waits for its launch to finish. */
+typedef struct {
+  int64_t entries;      /* overlaps contracted (a mirrored entry counts once) */
+  int64_t tiles;        /* pair tiles in the work queue                       */
+  int32_t workgroups;   /* persistent workgroups launched                     */
+  int32_t tile_side;    /* pair-tile side of the kernel configuration         */
+  int32_t queues;       /* work queues (1, or one per XCD)                    */
+  int32_t block;        /* block size of the FP64 / FP32 forms (32 or 64)     */
+  double flops;         /* algorithmic flops of the contracted overlaps: 8 per */
+                        /* complex MAC of Fig. 2's site updates, counted from  */
+                        /* the actual bond dimensions of every pair            */
+  double kernel_ms;     /* duration of the Gram kernel (HIP events)           */
+} qk_gram_stats;
+
 /* K[i][j] = |<a_i | b_j>|^2 for i < na, j < nb, written to K_dev (row-major,
  * leading dimension ldk >= nb, FP64) following Fig. 2: for every site l,
  * E <- sum_s A_a[l][s]^H E A_b[l][s], starting from E = 1.
@@ -200,10 +242,11 @@ qk_status mps_simulate_graph(const double *features_dev, int64_t n_points,
  * and mirrored (the diagonal is computed, not assumed).
  * `a` and `b` must have the same m.  The precision's packed form is built
  * (and kept) on first use.  The MFMA kernels support bond pads up to 64
- * (bond dimensions up to 64): QK_ENOTSUP for larger batches. */
+ * (bond dimensions up to 64): QK_ENOTSUP for larger batches.  `stats` may
+ * be NULL. */
 qk_status mps_gram(const qk_mps_batch *a, const qk_mps_batch *b,
                    qk_precision prec, double *K_dev, int64_t ldk,
-                   void *hip_stream);
+                   void *hip_stream, qk_gram_stats *stats);
 
 /* Block form for slabs and tile rows: rows a[a0 .. a0+na), columns
  * b[b0 .. b0+nb), written to K_dev[(i - a0) * ldk + (j - b0)].  With
@@ -213,7 +256,8 @@ qk_status mps_gram(const qk_mps_batch *a, const qk_mps_batch *b,
 qk_status mps_gram_block(const qk_mps_batch *a, int64_t a0, int64_t na,
                          const qk_mps_batch *b, int64_t b0, int64_t nb,
                          int32_t upper_only, qk_precision prec,
-                         double *K_dev, int64_t ldk, void *hip_stream);
+                         double *K_dev, int64_t ldk, void *hip_stream,
+                         qk_gram_stats *stats);
 
 /* Several Gram jobs (different batches, qubit counts and pads) in ONE
  * persistent launch: workgroups pop tiles from a device work queue across
@@ -230,7 +274,8 @@ typedef struct {
 } qk_gram_job;
 
 qk_status mps_gram_multi(const qk_gram_job *jobs, int32_t n_jobs,
-                         qk_precision prec, void *hip_stream);
+                         qk_precision prec, void *hip_stream,
+                         qk_gram_stats *stats);
 
 /* Autotuner of the Gram kernels' tile shapes.  For `prec` and the bond-pad
  * bucket of batch `b` (pads <= 32 or <= 64), every valid configuration (block
@@ -303,6 +348,31 @@ qk_status mps_batch_drop(qk_mps_batch *b, qk_precision prec);
 qk_status mps_batch_gather(const qk_mps_batch *src, const int64_t *idx_host,
                            int64_t count, uint32_t forms, void *hip_stream,
                            qk_mps_batch **out);
+
+/* Keep a batch across runs: every MPS is simulated once and its state
+ * reused (Sec. II-D), so a simulated training set can be written to a file
+ * and loaded later instead of simulated again.
+ * mps_batch_save writes, little-endian:
+ *   "QKMPSB01" (8 bytes); int32 m; int32 n_two_qubit_gates; int64 n;
+ *   int32 pad[m + 1]; int32 dims[n][m + 1];
+ *   double summed_discarded[n]; double max_discarded[n];
+ *   int32 degenerate_cuts[n]; int32 unconverged_svds[n];
+ *   the FP64 tensors, MPS after MPS, site after site, each site the padded
+ *   complex block [s][P_l][P_{l+1}] as interleaved (re, im) doubles (zero
+ *   beyond the bond dimensions).
+ * The batch must hold the FP64 form (QK_ENOTSUP otherwise).  The call
+ * synchronises the device.  QK_EINVAL for a NULL argument or a file that
+ * cannot be written (the message says why). */
+qk_status mps_batch_save(const qk_mps_batch *b, const char *path);
+
+/* Read a file written by mps_batch_save into a new batch on the current
+ * device (allocated through the registered allocator); packed forms are
+ * built on demand as after mps_simulate.  QK_EINVAL for a missing,
+ * truncated or malformed file (bad magic, sizes that do not match the
+ * header, a bond dimension outside [1, 128] or above its pad, a pad that is
+ * not a multiple of 32, a non-finite tensor entry).  On success *out
+ * receives the batch; the call returns after the data are on the device. */
+qk_status mps_batch_load(const char *path, void *hip_stream, qk_mps_batch **out);
 
 void mps_batch_free(qk_mps_batch *b);
 

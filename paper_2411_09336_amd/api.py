@@ -71,6 +71,20 @@ class _Job(C.Structure):
                 ("K_dev", C.c_void_p), ("ldk", C.c_int64)]
 
 
+class _GramStats(C.Structure):
+    _fields_ = [("entries", C.c_int64), ("tiles", C.c_int64), ("workgroups", C.c_int32),
+                ("tile_side", C.c_int32), ("queues", C.c_int32), ("block", C.c_int32),
+                ("flops", C.c_double), ("kernel_ms", C.c_double)]
+
+
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+class _Allocator(C.Structure):
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("ctx", C.c_void_p)]
+
+
 class _Tune(C.Structure):
     _fields_ = [("maxp", C.c_int32), ("tile_side", C.c_int32), ("queues", C.c_int32),
                 ("n_candidates", C.c_int32), ("best_ms", C.c_double), ("default_ms", C.c_double)]
@@ -88,7 +102,7 @@ def _load():
     L = C.CDLL(_LIB_PATH)
     P, I32, I64, D, S = C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_int
     sig = {
-        "qk_init": (S, [C.c_int]),
+        "qk_init": (S, [C.c_int, C.POINTER(_Allocator)]),
         "qk_last_error": (C.c_char_p, []),
         "qk_version": (C.c_char_p, []),
         "qk_circuit_compile": (S, [C.POINTER(_Spec), P, I64, C.POINTER(I64)]),
@@ -96,9 +110,11 @@ def _load():
         "mps_simulate_progress": (S, [P, I64, C.POINTER(_Spec), I32, D, P, _PROGRESS, P, I64, C.POINTER(P)]),
         "mps_simulate_graph": (S, [P, I64, C.POINTER(_Spec), I32, D, I64, P, C.POINTER(P)]),
         "mps_simulate_trace": (S, [P, I64, C.POINTER(_Spec), I32, D, P, P, C.POINTER(P)]),
-        "mps_gram": (S, [P, P, C.c_int, P, I64, P]),
-        "mps_gram_block": (S, [P, I64, I64, P, I64, I64, I32, C.c_int, P, I64, P]),
-        "mps_gram_multi": (S, [C.POINTER(_Job), I32, C.c_int, P]),
+        "mps_gram": (S, [P, P, C.c_int, P, I64, P, C.POINTER(_GramStats)]),
+        "mps_gram_block": (S, [P, I64, I64, P, I64, I64, I32, C.c_int, P, I64, P, C.POINTER(_GramStats)]),
+        "mps_gram_multi": (S, [C.POINTER(_Job), I32, C.c_int, P, C.POINTER(_GramStats)]),
+        "mps_batch_save": (S, [P, C.c_char_p]),
+        "mps_batch_load": (S, [C.c_char_p, P, C.POINTER(P)]),
         "mps_batch_import": (S, [P, P, I64, I32, P, C.POINTER(P)]),
         "mps_batch_info": (S, [P, C.POINTER(_Info)]),
         "mps_batch_bond_dims": (S, [P, P]),
@@ -116,7 +132,23 @@ def _load():
         f.restype = res
         f.argtypes = args
     _lib = L
+    _default_allocator(L)
     return L
+
+
+def _default_allocator(L):
+    """Batches and scratch buffers of the current device come from PyTorch's
+    caching allocator unless QKMPS_ALLOCATOR=hip (then hipMalloc)."""
+    if os.environ.get("QKMPS_ALLOCATOR", "torch") != "torch":
+        return
+    try:
+        import torch
+        if not torch.cuda.is_available():
+            return
+        dev = torch.cuda.current_device()
+    except Exception:
+        return
+    _register(L, dev, "torch")
 
 
 def _check(st: int):
@@ -126,6 +158,79 @@ def _check(st: int):
 
 def version() -> str:
     return _load().qk_version().decode()
+
+
+# An allocator registered with the library must outlive every batch made
+# through it (a batch frees its memory through the allocator that made it):
+# the callbacks are kept here for the life of the process, and the batches
+# still alive when the interpreter exits are freed first (while torch can
+# still take their memory back).
+_ALLOCATOR_KEEP = []
+_LIVE = None
+
+
+def _torch_alloc(nbytes, _ctx, stream):
+    try:
+        import torch
+        return torch.cuda.caching_allocator_alloc(int(nbytes), device=torch.cuda.current_device(),
+                                                  stream=int(stream or 0))
+    except Exception:       # out of memory or no device: the library reports QK_ENOMEM
+        return None
+
+
+def _torch_free(ptr, _ctx, _stream):
+    try:
+        import torch
+        torch.cuda.caching_allocator_delete(int(ptr))
+    except Exception:
+        pass
+
+
+def _free_live_batches():
+    if _LIVE is not None:
+        for b in list(_LIVE):
+            b.free()
+
+
+def init(device: int = 0, allocator="torch") -> None:
+    """Select ``device`` and the device memory the library uses for batches
+    and scratch buffers: "torch" (PyTorch's caching allocator, so the batches
+    count in torch.cuda.memory_allocated() and share its pool), None
+    (hipMalloc / hipMallocAsync), or a pair of callables
+    ``(alloc(nbytes, stream) -> int pointer or 0, free(pointer, stream))``."""
+    L = _load()
+    if allocator is None:
+        _check(L.qk_init(int(device), None))
+        return
+    _register(L, device, allocator)
+
+
+def _register(L, device, allocator):
+    global _LIVE
+    import atexit
+    import weakref
+    if allocator == "torch":
+        a = _Allocator(_ALLOC_FN(_torch_alloc), _FREE_FN(_torch_free), None)
+    else:
+        fa, ff = allocator
+
+        def _a(nbytes, _ctx, stream):
+            try:
+                return fa(int(nbytes), int(stream or 0)) or None
+            except Exception:
+                return None
+
+        def _f(ptr, _ctx, stream):
+            try:
+                ff(int(ptr), int(stream or 0))
+            except Exception:
+                pass
+        a = _Allocator(_ALLOC_FN(_a), _FREE_FN(_f), None)
+    _ALLOCATOR_KEEP.append(a)
+    if _LIVE is None:
+        _LIVE = weakref.WeakSet()
+        atexit.register(_free_live_batches)
+    _check(L.qk_init(int(device), C.byref(a)))
 
 
 def _stream_ptr(stream) -> Optional[int]:
@@ -172,6 +277,8 @@ class MPSBatch:
 
     def __init__(self, handle: int):
         self._h = C.c_void_p(handle)
+        if _LIVE is not None:
+            _LIVE.add(self)
 
     @property
     def handle(self):
@@ -237,6 +344,10 @@ class MPSBatch:
     def drop(self, precision):
         _check(_load().mps_batch_drop(self._h, Precision.of(precision)))
 
+    def save(self, path: str) -> None:
+        """Write the batch (bond dimensions, statistics, FP64 tensors) to ``path``."""
+        _check(_load().mps_batch_save(self._h, os.fsencode(path)))
+
     def gather(self, indices: Sequence[int], forms=("fp64",), stream=None) -> "MPSBatch":
         """Copies of MPS ``indices`` in the given forms ("fp64", "fp32", "split_bf16", "split_i8")."""
         idx = np.ascontiguousarray(np.asarray(indices, dtype=np.int64))
@@ -247,6 +358,13 @@ class MPSBatch:
         _check(_load().mps_batch_gather(self._h, idx.ctypes.data, len(idx), mask, _stream_ptr(stream),
                                         C.byref(h)))
         return MPSBatch(h.value)
+
+
+def load_batch(path: str, stream=None) -> MPSBatch:
+    """A batch written by ``MPSBatch.save``, on the current device."""
+    h = C.c_void_p(0)
+    _check(_load().mps_batch_load(os.fsencode(path), _stream_ptr(stream), C.byref(h)))
+    return MPSBatch(h.value)
 
 
 def import_batch(mps_list: Sequence[Sequence[np.ndarray]], stream=None) -> MPSBatch:
@@ -360,32 +478,50 @@ def _ldk(out, nb: int) -> int:
     return max(int(out.stride(0)), nb, 1)
 
 
-def gram(a: MPSBatch, b: Optional[MPSBatch] = None, precision="fp64", out=None, stream=None):
-    """K[i, j] = |<a_i|b_j>|^2 as a CUDA float64 tensor (symmetric when b is None)."""
+def _stats_arg(stats):
+    return C.byref(stats) if stats is not None else None
+
+
+def _stats_dict(st) -> dict:
+    return {f: getattr(st, f) for f, _ in _GramStats._fields_}
+
+
+def gram(a: MPSBatch, b: Optional[MPSBatch] = None, precision="fp64", out=None, stream=None,
+         stats: Optional[dict] = None):
+    """K[i, j] = |<a_i|b_j>|^2 as a CUDA float64 tensor (symmetric when b is None).
+    With a dict ``stats`` the call waits for the kernel and fills the dict
+    with its statistics (entries, tiles, workgroups, configuration,
+    algorithmic flops, kernel_ms)."""
     import torch
     na = a.n
     nb = na if b is None else b.n
     if out is None:
         out = torch.empty((na, nb), dtype=torch.float64, device="cuda")
     _check_out(out, na, nb)
+    st = _GramStats() if stats is not None else None
     _check(_load().mps_gram(a.handle, None if b is None else b.handle, Precision.of(precision),
-                            C.c_void_p(out.data_ptr()), _ldk(out, nb), _stream_ptr(stream)))
+                            C.c_void_p(out.data_ptr()), _ldk(out, nb), _stream_ptr(stream), _stats_arg(st)))
+    if st is not None:
+        stats.update(_stats_dict(st))
     return out
 
 
 def gram_block(a: MPSBatch, a0: int, na: int, b: MPSBatch, b0: int, nb: int, precision="fp64",
-               upper_only: bool = False, out=None, stream=None):
+               upper_only: bool = False, out=None, stream=None, stats: Optional[dict] = None):
     import torch
     if out is None:
         out = torch.zeros((na, nb), dtype=torch.float64, device="cuda")
     _check_out(out, na, nb)
+    st = _GramStats() if stats is not None else None
     _check(_load().mps_gram_block(a.handle, a0, na, b.handle, b0, nb, int(bool(upper_only)),
                                   Precision.of(precision), C.c_void_p(out.data_ptr()), _ldk(out, nb),
-                                  _stream_ptr(stream)))
+                                  _stream_ptr(stream), _stats_arg(st)))
+    if st is not None:
+        stats.update(_stats_dict(st))
     return out
 
 
-def gram_multi(jobs, precision="fp64", stream=None):
+def gram_multi(jobs, precision="fp64", stream=None, stats: Optional[dict] = None):
     """jobs: list of dicts {a, b, a0, na, b0, nb, upper_only, out} -> one persistent launch."""
     arr = (_Job * len(jobs))()
     for k, j in enumerate(jobs):
@@ -398,4 +534,7 @@ def gram_multi(jobs, precision="fp64", stream=None):
         arr[k].reserved = 0
         arr[k].K_dev = j["out"].data_ptr()
         arr[k].ldk = _ldk(j["out"], j["nb"])
-    _check(_load().mps_gram_multi(arr, len(jobs), Precision.of(precision), _stream_ptr(stream)))
+    st = _GramStats() if stats is not None else None
+    _check(_load().mps_gram_multi(arr, len(jobs), Precision.of(precision), _stream_ptr(stream), _stats_arg(st)))
+    if st is not None:
+        stats.update(_stats_dict(st))

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <fstream>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -27,6 +28,46 @@ qk_status fail(qk_status st, const std::string &msg) {
 static qk_status ok() {
   g_last_error.clear();
   return QK_OK;
+}
+
+// Allocator per device index, set by qk_init.
+constexpr int kMaxDevices = 64;
+static std::mutex g_alloc_mu;
+static DevAlloc g_alloc[kMaxDevices];
+
+DevAlloc allocator_for_current_device() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    dev = 0;
+  }
+  if (dev < 0 || dev >= kMaxDevices) return DevAlloc{};
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  return g_alloc[dev];
+}
+
+void *dev_alloc(const DevAlloc &al, size_t bytes, hipStream_t stream, bool scratch) {
+  if (bytes == 0) bytes = 16;
+  if (al.custom()) return al.user.alloc(bytes, al.user.ctx, reinterpret_cast<void *>(stream));
+  void *p = nullptr;
+  const hipError_t e = scratch ? hipMallocAsync(&p, bytes, stream) : hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return p;
+}
+
+void dev_free(const DevAlloc &al, void *p, hipStream_t stream, bool scratch) {
+  if (!p) return;
+  if (al.custom()) {
+    al.user.free(p, al.user.ctx, reinterpret_cast<void *>(stream));
+    return;
+  }
+  if (scratch)
+    (void)hipFreeAsync(p, stream);
+  else
+    (void)hipFree(p);
 }
 
 qk_status validate_spec(const qk_circuit_spec *spec) {
@@ -95,8 +136,10 @@ static void batch_release(qk_mps_batch *b) {
   void *ptrs[] = {b->f64,          b->f32,        b->sbf16,       b->si8,       b->dims_dev,
                   b->pad_dev,      b->site_off_dev, b->split_off_dev, b->i8_off_dev, b->disc_dev,
                   b->maxdisc_dev,  b->degen_dev,   b->unconv_dev};
-  for (void *p : ptrs)
-    if (p) (void)hipFree(p);
+  // the batch may still be in use by enqueued work: wait before the memory
+  // goes back to the allocator
+  if (b->alloc.custom()) (void)hipDeviceSynchronize();
+  for (void *p : ptrs) dev_free(b->alloc, p, nullptr, false);
   (void)hipSetDevice(cur);
   delete b;
 }
@@ -104,14 +147,19 @@ static void batch_release(qk_mps_batch *b) {
 qk_status batch_create(int64_t n, int32_t m, const std::vector<int32_t> &pad,
                        hipStream_t stream, qk_mps_batch **out, bool with_f64) {
   auto *b = new qk_mps_batch();
-  QK_HIP_CHECK(hipGetDevice(&b->device));
+  if (hipGetDevice(&b->device) != hipSuccess) {
+    (void)hipGetLastError();
+    b->device = 0;
+  }
+  b->alloc = allocator_for_current_device();
   b->n = n;
   b->m = m;
   b->pad = pad;
   compute_layout(b);
   auto alloc = [&](void **p, size_t bytes) -> bool {
     if (bytes == 0) bytes = 16;
-    if (hipMalloc(p, bytes) != hipSuccess) return false;
+    *p = dev_alloc(b->alloc, bytes, stream, false);
+    if (!*p) return false;
     return hipMemsetAsync(*p, 0, bytes, stream) == hipSuccess;
   };
   const size_t nn = size_t(std::max<int64_t>(n, 1));
@@ -154,11 +202,8 @@ qk_status batch_ensure_packed(qk_mps_batch *b, qk_precision prec, hipStream_t st
   if (prec == QK_FP32) {
     if (b->f32) return QK_OK;
     size_t bytes = sizeof(float2) * size_t(std::max<int64_t>(b->n, 1)) * size_t(b->mps_stride);
-    if (hipMalloc((void **)&b->f32, bytes) != hipSuccess) {
-      (void)hipGetLastError();
-      b->f32 = nullptr;
-      return fail(QK_ENOMEM, "device allocation of FP32 planes failed");
-    }
+    b->f32 = static_cast<float2 *>(dev_alloc(b->alloc, bytes, stream, false));
+    if (!b->f32) return fail(QK_ENOMEM, "device allocation of FP32 planes failed");
     return launch_pack_f32(b, stream);
   }
   if (prec == QK_SPLIT_BF16) {
@@ -166,22 +211,16 @@ qk_status batch_ensure_packed(qk_mps_batch *b, qk_precision prec, hipStream_t st
     if (*std::max_element(b->pad.begin(), b->pad.end()) > kSplitMaxPad)
       return fail(QK_ENOTSUP, "the split-BF16 form supports bond dimensions up to 64");
     size_t bytes = size_t(std::max<int64_t>(b->n, 1)) * size_t(b->split_stride);
-    if (hipMalloc((void **)&b->sbf16, bytes) != hipSuccess) {
-      (void)hipGetLastError();
-      b->sbf16 = nullptr;
-      return fail(QK_ENOMEM, "device allocation of split-BF16 planes failed");
-    }
+    b->sbf16 = static_cast<uint8_t *>(dev_alloc(b->alloc, bytes, stream, false));
+    if (!b->sbf16) return fail(QK_ENOMEM, "device allocation of split-BF16 planes failed");
     return launch_pack_split(b, stream);
   }
   if (prec == QK_SPLIT_I8) {
     if (*std::max_element(b->pad.begin(), b->pad.end()) > kSplitMaxPad)
       return fail(QK_ENOTSUP, "the split-int8 form supports bond dimensions up to 64");
     size_t bytes = size_t(std::max<int64_t>(b->n, 1)) * size_t(b->i8_stride);
-    if (hipMalloc((void **)&b->si8, bytes) != hipSuccess) {
-      (void)hipGetLastError();
-      b->si8 = nullptr;
-      return fail(QK_ENOMEM, "device allocation of split-int8 planes failed");
-    }
+    b->si8 = static_cast<uint8_t *>(dev_alloc(b->alloc, bytes, stream, false));
+    if (!b->si8) return fail(QK_ENOMEM, "device allocation of split-int8 planes failed");
     return launch_pack_i8(b, stream);
   }
   return fail(QK_EINVAL, "unknown precision");
@@ -193,10 +232,17 @@ using namespace qk;
 
 extern "C" {
 
-qk_status qk_init(int device) {
+qk_status qk_init(int device, const qk_allocator *alloc) {
+  if (device < 0 || device >= kMaxDevices) return fail(QK_EINVAL, "device index out of range");
+  if (alloc && (!alloc->alloc || !alloc->free)) return fail(QK_EINVAL, "allocator with a NULL function");
+  {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    g_alloc[device] = DevAlloc{};
+    if (alloc) g_alloc[device].user = *alloc;
+  }
   int count = 0;
   QK_HIP_CHECK(hipGetDeviceCount(&count));
-  if (device < 0 || device >= count) return fail(QK_EINVAL, "device index out of range");
+  if (device >= count) return fail(QK_EINVAL, "device index out of range");
   QK_HIP_CHECK(hipSetDevice(device));
   return ok();
 }
@@ -359,7 +405,7 @@ static int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 static qk_status make_job(const qk_mps_batch *a, int64_t a0, int64_t na, const qk_mps_batch *b,
                           int64_t b0, int64_t nb, int32_t upper, double *K, int64_t ldk,
-                          qk_precision prec, hipStream_t stream, GramJobDev *job) {
+                          qk_precision prec, hipStream_t stream, GramJobDev *job, bool pack = true) {
   qk_status st = check_pair_batches(a, b);
   if (st != QK_OK) return st;
   if (na < 0 || nb < 0 || a0 < 0 || b0 < 0 || a0 + na > a->n || b0 + nb > b->n)
@@ -371,10 +417,19 @@ static qk_status make_job(const qk_mps_batch *a, int64_t a0, int64_t na, const q
     return fail(QK_EINVAL, "unknown precision");
   auto *am = const_cast<qk_mps_batch *>(a);
   auto *bm = const_cast<qk_mps_batch *>(b);
-  st = batch_ensure_packed(am, prec, stream);
-  if (st != QK_OK) return st;
-  st = batch_ensure_packed(bm, prec, stream);
-  if (st != QK_OK) return st;
+  if (pack) {
+    st = batch_ensure_packed(am, prec, stream);
+    if (st != QK_OK) return st;
+    st = batch_ensure_packed(bm, prec, stream);
+    if (st != QK_OK) return st;
+  } else {
+    auto present = [&](const qk_mps_batch *x) {
+      return prec == QK_FP64 ? x->f64 != nullptr : prec == QK_FP32 ? x->f32 != nullptr
+                                                 : prec == QK_SPLIT_BF16 ? x->sbf16 != nullptr : x->si8 != nullptr;
+    };
+    if (!present(a) || !present(b))
+      return fail(QK_ENOTSUP, "the precision's packed form is not built: call mps_batch_pack first");
+  }
   auto base = [&](qk_mps_batch *x) -> const void * {
     switch (prec) {
       case QK_FP64: return x->f64;
@@ -415,25 +470,87 @@ static int max_pad_of(const qk_mps_batch *x) {
   return *std::max_element(x->pad.begin(), x->pad.end());
 }
 
+// Entries and algorithmic flops of one Gram job.  An overlap costs, per site
+// l (Fig. 2), 2 Da_l Db_{l+1} (Db_l + Da_{l+1}) complex MACs of 8 flops for
+// bra bonds Da and ket bonds Db.  Summed over a block of pairs the terms
+// separate into per-row and per-column sums (prefix sums over the rows for
+// the upper triangle), so the count is exact and costs O(m (na + nb)).
+static qk_status job_work(const qk_mps_batch *a, int64_t a0, int64_t na, const qk_mps_batch *b, int64_t b0,
+                          int64_t nb, bool upper, double *entries, double *flops) {
+  const int m = a->m, m1 = m + 1;
+  std::vector<int32_t> da(size_t(na) * m1), db(size_t(nb) * m1);
+  QK_HIP_CHECK(hipDeviceSynchronize());
+  if (na > 0)
+    QK_HIP_CHECK(hipMemcpy(da.data(), a->dims_dev + a0 * m1, sizeof(int32_t) * da.size(), hipMemcpyDeviceToHost));
+  if (nb > 0)
+    QK_HIP_CHECK(hipMemcpy(db.data(), b->dims_dev + b0 * m1, sizeof(int32_t) * db.size(), hipMemcpyDeviceToHost));
+  double e = 0.0, f = 0.0;
+  if (!upper) {
+    e = double(na) * double(nb);
+    for (int l = 0; l < m; ++l) {
+      double sa = 0, qa = 0, pb = 0, sb = 0;
+      for (int64_t i = 0; i < na; ++i) {
+        sa += da[i * m1 + l];
+        qa += double(da[i * m1 + l]) * da[i * m1 + l + 1];
+      }
+      for (int64_t j = 0; j < nb; ++j) {
+        pb += double(db[j * m1 + l]) * db[j * m1 + l + 1];
+        sb += db[j * m1 + l + 1];
+      }
+      f += 2.0 * (sa * pb + qa * sb);
+    }
+  } else {
+    // pairs (i, j) with global column b0 + j >= global row a0 + i
+    std::vector<double> ps(size_t(na) + 1), pq(size_t(na) + 1);
+    for (int64_t j = 0; j < nb; ++j) {
+      const int64_t rows = std::min<int64_t>(na, std::max<int64_t>(0, b0 + j - a0 + 1));
+      e += double(rows);
+    }
+    for (int l = 0; l < m; ++l) {
+      ps[0] = pq[0] = 0.0;
+      for (int64_t i = 0; i < na; ++i) {
+        ps[i + 1] = ps[i] + da[i * m1 + l];
+        pq[i + 1] = pq[i] + double(da[i * m1 + l]) * da[i * m1 + l + 1];
+      }
+      for (int64_t j = 0; j < nb; ++j) {
+        const int64_t rows = std::min<int64_t>(na, std::max<int64_t>(0, b0 + j - a0 + 1));
+        f += 2.0 * (ps[rows] * double(db[j * m1 + l]) * db[j * m1 + l + 1] + pq[rows] * db[j * m1 + l + 1]);
+      }
+    }
+  }
+  *entries += e;
+  *flops += 8.0 * f;
+  return QK_OK;
+}
+
 qk_status mps_gram_block(const qk_mps_batch *a, int64_t a0, int64_t na, const qk_mps_batch *b,
                          int64_t b0, int64_t nb, int32_t upper_only, qk_precision prec,
-                         double *K_dev, int64_t ldk, void *hip_stream) {
+                         double *K_dev, int64_t ldk, void *hip_stream, qk_gram_stats *stats) {
   hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+  if (stats) std::memset(stats, 0, sizeof(*stats));
   GramJobDev job;
   qk_status st = make_job(a, a0, na, b, b0, nb, upper_only, K_dev, ldk, prec, stream, &job);
   if (st != QK_OK) return st;
   if (na == 0 || nb == 0) return ok();
   std::vector<GramJobDev> jobs{job};
-  st = launch_gram(jobs, std::max(max_pad_of(a), max_pad_of(b)), prec, stream);
+  st = launch_gram(jobs, std::max(max_pad_of(a), max_pad_of(b)), prec, stream, stats);
   if (st != QK_OK) return st;
+  if (stats) {
+    double e = 0.0, f = 0.0;
+    st = job_work(a, a0, na, b, b0, nb, upper_only != 0, &e, &f);
+    if (st != QK_OK) return st;
+    stats->entries = int64_t(e);
+    stats->flops = f;
+  }
   return ok();
 }
 
 qk_status mps_gram(const qk_mps_batch *a, const qk_mps_batch *b, qk_precision prec, double *K_dev,
-                   int64_t ldk, void *hip_stream) {
+                   int64_t ldk, void *hip_stream, qk_gram_stats *stats) {
   if (!a) return fail(QK_EINVAL, "batch a is NULL");
-  if (b == nullptr || b == a) return mps_gram_block(a, 0, a->n, a, 0, a->n, 1, prec, K_dev, ldk, hip_stream);
-  return mps_gram_block(a, 0, a->n, b, 0, b->n, 0, prec, K_dev, ldk, hip_stream);
+  if (b == nullptr || b == a)
+    return mps_gram_block(a, 0, a->n, a, 0, a->n, 1, prec, K_dev, ldk, hip_stream, stats);
+  return mps_gram_block(a, 0, a->n, b, 0, b->n, 0, prec, K_dev, ldk, hip_stream, stats);
 }
 
 qk_status mps_gram_autotune(qk_mps_batch *b, qk_precision prec, int64_t sample, void *hip_stream,
@@ -443,8 +560,9 @@ qk_status mps_gram_autotune(qk_mps_batch *b, qk_precision prec, int64_t sample, 
   hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
   const int64_t n = std::min<int64_t>(sample, b->n);
   if (n < 1) return fail(QK_EINVAL, "empty batch");
-  double *K = nullptr;
-  QK_HIP_CHECK(hipMallocAsync(reinterpret_cast<void **>(&K), sizeof(double) * size_t(n) * size_t(n), stream));
+  const DevAlloc al = allocator_for_current_device();
+  auto *K = static_cast<double *>(dev_alloc(al, sizeof(double) * size_t(n) * size_t(n), stream, true));
+  if (!K) return fail(QK_ENOMEM, "device allocation of the autotuning Gram failed");
   GramJobDev job;
   qk_status st = make_job(b, 0, n, b, 0, n, 1, K, n, prec, stream, &job);
   const int max_pad = max_pad_of(b);
@@ -475,7 +593,7 @@ qk_status mps_gram_autotune(qk_mps_batch *b, qk_precision prec, int64_t sample, 
       best_cfg = cands[k];
     }
   }
-  (void)hipFreeAsync(K, stream);
+  dev_free(al, K, stream, true);
   if (st != QK_OK) return st;
   store_gram_config(prec, max_pad, best_cfg);
   if (report) {
@@ -494,7 +612,9 @@ qk_status mps_gram_tune_reset(void) {
   return ok();
 }
 
-qk_status mps_gram_multi(const qk_gram_job *jobs, int32_t n_jobs, qk_precision prec, void *hip_stream) {
+qk_status mps_gram_multi(const qk_gram_job *jobs, int32_t n_jobs, qk_precision prec, void *hip_stream,
+                         qk_gram_stats *stats) {
+  if (stats) std::memset(stats, 0, sizeof(*stats));
   if (n_jobs < 0 || (n_jobs > 0 && !jobs)) return fail(QK_EINVAL, "invalid job list");
   hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
   std::vector<GramJobDev> dj;
@@ -511,8 +631,18 @@ qk_status mps_gram_multi(const qk_gram_job *jobs, int32_t n_jobs, qk_precision p
     dj.push_back(job);
   }
   if (dj.empty()) return ok();
-  qk_status st = launch_gram(dj, max_pad, prec, stream);
+  qk_status st = launch_gram(dj, max_pad, prec, stream, stats);
   if (st != QK_OK) return st;
+  if (stats) {
+    double e = 0.0, f = 0.0;
+    for (int k = 0; k < n_jobs && st == QK_OK; ++k) {
+      const qk_gram_job &j = jobs[k];
+      if (j.na > 0 && j.nb > 0) st = job_work(j.a, j.a0, j.na, j.b, j.b0, j.nb, j.upper_only != 0, &e, &f);
+    }
+    if (st != QK_OK) return st;
+    stats->entries = int64_t(e);
+    stats->flops = f;
+  }
   return ok();
 }
 
@@ -661,13 +791,13 @@ qk_status mps_batch_drop(qk_mps_batch *b, qk_precision prec) {
   if (!b) return fail(QK_EINVAL, "NULL batch");
   QK_HIP_CHECK(hipDeviceSynchronize());
   if (prec == QK_FP32 && b->f32) {
-    QK_HIP_CHECK(hipFree(b->f32));
+    dev_free(b->alloc, b->f32, nullptr, false);
     b->f32 = nullptr;
   } else if (prec == QK_SPLIT_BF16 && b->sbf16) {
-    QK_HIP_CHECK(hipFree(b->sbf16));
+    dev_free(b->alloc, b->sbf16, nullptr, false);
     b->sbf16 = nullptr;
   } else if (prec == QK_SPLIT_I8 && b->si8) {
-    QK_HIP_CHECK(hipFree(b->si8));
+    dev_free(b->alloc, b->si8, nullptr, false);
     b->si8 = nullptr;
   } else if (prec == QK_FP64) {
     return fail(QK_EINVAL, "the FP64 form cannot be dropped");
@@ -693,34 +823,30 @@ qk_status mps_batch_gather(const qk_mps_batch *src, const int64_t *idx_host, int
   b->n_two_qubit_gates = src->n_two_qubit_gates;
   const size_t nn = size_t(std::max<int64_t>(count, 1));
   if (forms & QK_FORM_FP32) {
-    if (hipMalloc(reinterpret_cast<void **>(&b->f32), sizeof(float2) * nn * size_t(b->mps_stride)) != hipSuccess) {
-      (void)hipGetLastError();
-      b->f32 = nullptr;
+    b->f32 = static_cast<float2 *>(dev_alloc(b->alloc, sizeof(float2) * nn * size_t(b->mps_stride), stream, false));
+    if (!b->f32) {
       batch_release(b);
       return fail(QK_ENOMEM, "device allocation of FP32 planes failed");
     }
   }
   if (forms & QK_FORM_SPLIT_BF16) {
-    if (hipMalloc(reinterpret_cast<void **>(&b->sbf16), nn * size_t(b->split_stride)) != hipSuccess) {
-      (void)hipGetLastError();
-      b->sbf16 = nullptr;
+    b->sbf16 = static_cast<uint8_t *>(dev_alloc(b->alloc, nn * size_t(b->split_stride), stream, false));
+    if (!b->sbf16) {
       batch_release(b);
       return fail(QK_ENOMEM, "device allocation of split-BF16 planes failed");
     }
   }
   if (forms & QK_FORM_SPLIT_I8) {
-    if (hipMalloc(reinterpret_cast<void **>(&b->si8), nn * size_t(b->i8_stride)) != hipSuccess) {
-      (void)hipGetLastError();
-      b->si8 = nullptr;
+    b->si8 = static_cast<uint8_t *>(dev_alloc(b->alloc, nn * size_t(b->i8_stride), stream, false));
+    if (!b->si8) {
       batch_release(b);
       return fail(QK_ENOMEM, "device allocation of split-int8 planes failed");
     }
   }
   const int m1 = src->m + 1;
   if (count > 0) {
-    int64_t *idx_dev = nullptr;
-    if (hipMallocAsync(reinterpret_cast<void **>(&idx_dev), sizeof(int64_t) * size_t(count), stream) != hipSuccess) {
-      (void)hipGetLastError();
+    auto *idx_dev = static_cast<int64_t *>(dev_alloc(b->alloc, sizeof(int64_t) * size_t(count), stream, true));
+    if (!idx_dev) {
       batch_release(b);
       return fail(QK_ENOMEM, "device allocation of the gather index failed");
     }
@@ -743,11 +869,147 @@ qk_status mps_batch_gather(const qk_mps_batch *src, const int64_t *idx_host, int
     if (gs == QK_OK) gs = launch_gather_meta(ms, md, idx_dev, m1, count, stream);
     // the host index list must stay valid until the copy has run
     const bool synced = hipStreamSynchronize(stream) == hipSuccess;
-    (void)hipFreeAsync(idx_dev, stream);
+    dev_free(b->alloc, idx_dev, stream, true);
     if (gs != QK_OK || !synced) {
       batch_release(b);
       return gs != QK_OK ? gs : fail(QK_EDEVICE, "gather failed");
     }
+  }
+  *out = b;
+  return ok();
+}
+
+static const char kBatchMagic[8] = {'Q', 'K', 'M', 'P', 'S', 'B', '0', '1'};
+
+qk_status mps_batch_save(const qk_mps_batch *b, const char *path) {
+  if (!b || !path) return fail(QK_EINVAL, "NULL argument");
+  if (!b->f64) return fail(QK_ENOTSUP, "batch holds no FP64 form");
+  const int m = b->m, m1 = m + 1;
+  const size_t n = size_t(b->n);
+  std::vector<int32_t> dims(n * m1), degen(n), unconv(n);
+  std::vector<double> disc(n), maxdisc(n);
+  QK_HIP_CHECK(hipDeviceSynchronize());
+  if (n > 0) {
+    QK_HIP_CHECK(hipMemcpy(dims.data(), b->dims_dev, sizeof(int32_t) * dims.size(), hipMemcpyDeviceToHost));
+    QK_HIP_CHECK(hipMemcpy(disc.data(), b->disc_dev, sizeof(double) * n, hipMemcpyDeviceToHost));
+    QK_HIP_CHECK(hipMemcpy(maxdisc.data(), b->maxdisc_dev, sizeof(double) * n, hipMemcpyDeviceToHost));
+    QK_HIP_CHECK(hipMemcpy(degen.data(), b->degen_dev, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+    QK_HIP_CHECK(hipMemcpy(unconv.data(), b->unconv_dev, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+  }
+  std::ofstream f(path, std::ios::binary | std::ios::trunc);
+  if (!f) return fail(QK_EINVAL, std::string("cannot open ") + path + " for writing");
+  const int32_t hdr32[2] = {m, b->n_two_qubit_gates};
+  const int64_t n64 = b->n;
+  f.write(kBatchMagic, 8);
+  f.write(reinterpret_cast<const char *>(hdr32), sizeof(hdr32));
+  f.write(reinterpret_cast<const char *>(&n64), sizeof(n64));
+  f.write(reinterpret_cast<const char *>(b->pad.data()), sizeof(int32_t) * m1);
+  f.write(reinterpret_cast<const char *>(dims.data()), sizeof(int32_t) * dims.size());
+  f.write(reinterpret_cast<const char *>(disc.data()), sizeof(double) * n);
+  f.write(reinterpret_cast<const char *>(maxdisc.data()), sizeof(double) * n);
+  f.write(reinterpret_cast<const char *>(degen.data()), sizeof(int32_t) * n);
+  f.write(reinterpret_cast<const char *>(unconv.data()), sizeof(int32_t) * n);
+  // tensors in chunks of whole MPS (about 256 MiB of host memory at a time)
+  const size_t per = sizeof(double2) * size_t(b->mps_stride);
+  const size_t chunk = std::max<size_t>(1, (size_t(256) << 20) / std::max<size_t>(per, 1));
+  std::vector<double2> host;
+  for (size_t i0 = 0; i0 < n && f; i0 += chunk) {
+    const size_t cnt = std::min(chunk, n - i0);
+    host.resize(cnt * size_t(b->mps_stride));
+    QK_HIP_CHECK(hipMemcpy(host.data(), b->f64 + i0 * b->mps_stride, per * cnt, hipMemcpyDeviceToHost));
+    f.write(reinterpret_cast<const char *>(host.data()), std::streamsize(per * cnt));
+  }
+  f.flush();
+  if (!f) return fail(QK_EINVAL, std::string("write to ") + path + " failed");
+  return ok();
+}
+
+qk_status mps_batch_load(const char *path, void *hip_stream, qk_mps_batch **out) {
+  if (!path || !out) return fail(QK_EINVAL, "NULL argument");
+  *out = nullptr;
+  hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+  std::ifstream f(path, std::ios::binary);
+  if (!f) return fail(QK_EINVAL, std::string("cannot open ") + path);
+  f.seekg(0, std::ios::end);
+  const int64_t fsize = int64_t(f.tellg());
+  f.seekg(0, std::ios::beg);
+  char magic[8];
+  int32_t hdr32[2];
+  int64_t n = -1;
+  f.read(magic, 8);
+  f.read(reinterpret_cast<char *>(hdr32), sizeof(hdr32));
+  f.read(reinterpret_cast<char *>(&n), sizeof(n));
+  if (!f || std::memcmp(magic, kBatchMagic, 8) != 0) return fail(QK_EINVAL, "not an MPS batch file");
+  const int32_t m = hdr32[0];
+  if (m < 1 || m > 100000 || n < 0 || hdr32[1] < 0) return fail(QK_EINVAL, "malformed batch header");
+  const int m1 = m + 1;
+  std::vector<int32_t> pad(m1);
+  f.read(reinterpret_cast<char *>(pad.data()), sizeof(int32_t) * m1);
+  if (!f) return fail(QK_EINVAL, "truncated batch file");
+  for (int l = 0; l <= m; ++l)
+    if (pad[l] < kPadQuantum || pad[l] > kMaxBond || pad[l] % kPadQuantum)
+      return fail(QK_EINVAL, "pad outside [32, 128] or not a multiple of 32");
+  int64_t stride = 0;
+  for (int l = 0; l < m; ++l) stride += int64_t(2) * pad[l] * pad[l + 1];
+  const int64_t meta = int64_t(8 + 8 + 8) + 4 * int64_t(m1) + n * (4 * int64_t(m1) + 8 + 8 + 4 + 4);
+  if (n > (int64_t(1) << 40) / std::max<int64_t>(stride, 1) || fsize != meta + n * stride * 16)
+    return fail(QK_EINVAL, "batch file size does not match its header");
+  const size_t nn = size_t(n);
+  std::vector<int32_t> dims(nn * m1), degen(nn), unconv(nn);
+  std::vector<double> disc(nn), maxdisc(nn);
+  f.read(reinterpret_cast<char *>(dims.data()), sizeof(int32_t) * dims.size());
+  f.read(reinterpret_cast<char *>(disc.data()), sizeof(double) * nn);
+  f.read(reinterpret_cast<char *>(maxdisc.data()), sizeof(double) * nn);
+  f.read(reinterpret_cast<char *>(degen.data()), sizeof(int32_t) * nn);
+  f.read(reinterpret_cast<char *>(unconv.data()), sizeof(int32_t) * nn);
+  if (!f) return fail(QK_EINVAL, "truncated batch file");
+  for (size_t i = 0; i < nn; ++i) {
+    const int32_t *d = dims.data() + i * m1;
+    if (d[0] != 1 || d[m] != 1) return fail(QK_EINVAL, "first and last bond dimensions must be 1");
+    for (int l = 0; l <= m; ++l)
+      if (d[l] < 1 || d[l] > pad[l]) return fail(QK_EINVAL, "bond dimension outside [1, pad]");
+  }
+  qk_mps_batch *b = nullptr;
+  qk_status st = batch_create(n, m, pad, stream, &b);
+  if (st != QK_OK) return st;
+  b->n_two_qubit_gates = hdr32[1];
+  const size_t per = sizeof(double2) * size_t(b->mps_stride);
+  const size_t chunk = std::max<size_t>(1, (size_t(256) << 20) / std::max<size_t>(per, 1));
+  std::vector<double2> host;
+  for (size_t i0 = 0; i0 < nn && st == QK_OK; i0 += chunk) {
+    const size_t cnt = std::min(chunk, nn - i0);
+    host.resize(cnt * size_t(b->mps_stride));
+    f.read(reinterpret_cast<char *>(host.data()), std::streamsize(per * cnt));
+    if (!f) {
+      st = fail(QK_EINVAL, "truncated batch file");
+      break;
+    }
+    for (const double2 &v : host)
+      if (!std::isfinite(v.x) || !std::isfinite(v.y)) {
+        st = fail(QK_EINVAL, "non-finite tensor entry");
+        break;
+      }
+    if (st == QK_OK &&
+        (hipMemcpyAsync(b->f64 + i0 * b->mps_stride, host.data(), per * cnt, hipMemcpyHostToDevice, stream) !=
+             hipSuccess ||
+         hipStreamSynchronize(stream) != hipSuccess))
+      st = fail(QK_EDEVICE, "copy of loaded tensors failed");
+  }
+  if (st == QK_OK && nn > 0 &&
+      (hipMemcpyAsync(b->dims_dev, dims.data(), sizeof(int32_t) * dims.size(), hipMemcpyHostToDevice, stream) !=
+           hipSuccess ||
+       hipMemcpyAsync(b->disc_dev, disc.data(), sizeof(double) * nn, hipMemcpyHostToDevice, stream) != hipSuccess ||
+       hipMemcpyAsync(b->maxdisc_dev, maxdisc.data(), sizeof(double) * nn, hipMemcpyHostToDevice, stream) !=
+           hipSuccess ||
+       hipMemcpyAsync(b->degen_dev, degen.data(), sizeof(int32_t) * nn, hipMemcpyHostToDevice, stream) !=
+           hipSuccess ||
+       hipMemcpyAsync(b->unconv_dev, unconv.data(), sizeof(int32_t) * nn, hipMemcpyHostToDevice, stream) !=
+           hipSuccess ||
+       hipStreamSynchronize(stream) != hipSuccess))
+    st = fail(QK_EDEVICE, "copy of loaded metadata failed");
+  if (st != QK_OK) {
+    batch_release(b);
+    return st;
   }
   *out = b;
   return ok();

@@ -1099,7 +1099,8 @@ size_t lds_bytes() {
 
 template <int PREC, int MAXP>
 qk_status launch_one(const GramJobDev *jobs_dev, const GramTile *tiles_dev, int64_t n_tiles,
-                     unsigned long long *counters, const GramConfig &cfg, hipStream_t stream) {
+                     unsigned long long *counters, const GramConfig &cfg, hipStream_t stream, int *grid_out,
+                     hipEvent_t ev0, hipEvent_t ev1) {
   int dev = 0, cus = 256;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -1114,16 +1115,19 @@ qk_status launch_one(const GramJobDev *jobs_dev, const GramTile *tiles_dev, int6
   grid = std::min<int64_t>(grid, std::max<int64_t>(n_tiles * cfg.tile_side * cfg.tile_side, 1));
   // every queue needs workgroups: at most one queue per workgroup
   const int nq = int(std::min<int64_t>(cfg.queues, grid));
+  if (ev0) QK_HIP_CHECK(hipEventRecord(ev0, stream));
   hipLaunchKernelGGL(kern, dim3(unsigned(grid)), dim3(threads_of<PREC>()), lds, stream, jobs_dev, tiles_dev,
                      n_tiles, nq, cfg.tile_side, counters);
   QK_HIP_CHECK(hipGetLastError());
+  if (ev1) QK_HIP_CHECK(hipEventRecord(ev1, stream));
+  *grid_out = int(grid);
   return QK_OK;
 }
 
 }  // namespace
 
 qk_status launch_gram_cfg(const std::vector<GramJobDev> &jobs_in, int max_pad, qk_precision prec,
-                          const GramConfig &cfg, hipStream_t stream) {
+                          const GramConfig &cfg, hipStream_t stream, qk_gram_stats *stats) {
   if (max_pad > 64) return fail(QK_ENOTSUP, "Gram kernels support bond pads up to 64");
   if (cfg.maxp < max_pad) return fail(QK_EINVAL, "tile configuration smaller than the batch's bond pads");
   const int side = cfg.tile_side;
@@ -1145,34 +1149,60 @@ qk_status launch_gram_cfg(const std::vector<GramJobDev> &jobs_in, int max_pad, q
         tiles.push_back(GramTile{int32_t(k), int32_t(ti), int32_t(tj), 0});
       }
   }
+  if (stats) {
+    stats->tiles = int64_t(tiles.size());
+    stats->tile_side = side;
+    stats->queues = cfg.queues;
+    stats->block = cfg.maxp;
+    stats->workgroups = 0;
+    stats->kernel_ms = 0.0;
+  }
   if (tiles.empty()) return QK_OK;
   const int64_t n_tiles = int64_t(tiles.size());
   const size_t jbytes = sizeof(GramJobDev) * jobs.size();
   const size_t tbytes = sizeof(GramTile) * tiles.size();
   constexpr size_t kCounterBytes = sizeof(unsigned long long) * kQueues * kCounterStride;
-  uint8_t *ws = nullptr;
   const size_t ws_bytes = kCounterBytes + jbytes + tbytes;
-  QK_HIP_CHECK(hipMallocAsync(reinterpret_cast<void **>(&ws), ws_bytes, stream));
+  const DevAlloc al = allocator_for_current_device();
+  auto *ws = static_cast<uint8_t *>(dev_alloc(al, ws_bytes, stream, true));
+  if (!ws) return fail(QK_ENOMEM, "device allocation of the Gram work queue failed");
   auto *counters = reinterpret_cast<unsigned long long *>(ws);
   auto *jobs_dev = reinterpret_cast<GramJobDev *>(ws + kCounterBytes);
   auto *tiles_dev = reinterpret_cast<GramTile *>(ws + kCounterBytes + jbytes);
-  QK_HIP_CHECK(hipMemsetAsync(counters, 0, kCounterBytes, stream));
-  QK_HIP_CHECK(hipMemcpyAsync(jobs_dev, jobs.data(), jbytes, hipMemcpyHostToDevice, stream));
-  QK_HIP_CHECK(hipMemcpyAsync(tiles_dev, tiles.data(), tbytes, hipMemcpyHostToDevice, stream));
-  // the host tile list must stay alive until the copies have run
-  QK_HIP_CHECK(hipStreamSynchronize(stream));
-  qk_status st;
-  if (prec == QK_FP64)
-    st = cfg.maxp == 32 ? launch_one<QK_FP64, 32>(jobs_dev, tiles_dev, n_tiles, counters, cfg, stream)
-                        : launch_one<QK_FP64, 64>(jobs_dev, tiles_dev, n_tiles, counters, cfg, stream);
-  else if (prec == QK_FP32)
-    st = cfg.maxp == 32 ? launch_one<QK_FP32, 32>(jobs_dev, tiles_dev, n_tiles, counters, cfg, stream)
-                        : launch_one<QK_FP32, 64>(jobs_dev, tiles_dev, n_tiles, counters, cfg, stream);
-  else if (prec == QK_SPLIT_BF16)
-    st = launch_one<QK_SPLIT_BF16, 64>(jobs_dev, tiles_dev, n_tiles, counters, cfg, stream);
-  else
-    st = launch_one<QK_SPLIT_I8, 64>(jobs_dev, tiles_dev, n_tiles, counters, cfg, stream);
-  (void)hipFreeAsync(ws, stream);
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  qk_status st = QK_OK;
+  if (hipMemsetAsync(counters, 0, kCounterBytes, stream) != hipSuccess ||
+      hipMemcpyAsync(jobs_dev, jobs.data(), jbytes, hipMemcpyHostToDevice, stream) != hipSuccess ||
+      hipMemcpyAsync(tiles_dev, tiles.data(), tbytes, hipMemcpyHostToDevice, stream) != hipSuccess ||
+      // the host tile list must stay alive until the copies have run
+      hipStreamSynchronize(stream) != hipSuccess)
+    st = fail(QK_EDEVICE, "upload of the Gram work queue failed");
+  if (st == QK_OK && stats &&
+      (hipEventCreate(&ev0) != hipSuccess || hipEventCreate(&ev1) != hipSuccess))
+    st = fail(QK_EDEVICE, "event creation failed");
+  int grid = 0;
+  if (st == QK_OK) {
+    if (prec == QK_FP64)
+      st = cfg.maxp == 32 ? launch_one<QK_FP64, 32>(jobs_dev, tiles_dev, n_tiles, counters, cfg, stream, &grid, ev0, ev1)
+                          : launch_one<QK_FP64, 64>(jobs_dev, tiles_dev, n_tiles, counters, cfg, stream, &grid, ev0, ev1);
+    else if (prec == QK_FP32)
+      st = cfg.maxp == 32 ? launch_one<QK_FP32, 32>(jobs_dev, tiles_dev, n_tiles, counters, cfg, stream, &grid, ev0, ev1)
+                          : launch_one<QK_FP32, 64>(jobs_dev, tiles_dev, n_tiles, counters, cfg, stream, &grid, ev0, ev1);
+    else if (prec == QK_SPLIT_BF16)
+      st = launch_one<QK_SPLIT_BF16, 64>(jobs_dev, tiles_dev, n_tiles, counters, cfg, stream, &grid, ev0, ev1);
+    else
+      st = launch_one<QK_SPLIT_I8, 64>(jobs_dev, tiles_dev, n_tiles, counters, cfg, stream, &grid, ev0, ev1);
+  }
+  dev_free(al, ws, stream, true);
+  if (st == QK_OK && stats) {
+    float ms = 0.f;
+    if (hipEventSynchronize(ev1) != hipSuccess || hipEventElapsedTime(&ms, ev0, ev1) != hipSuccess)
+      st = fail(QK_EDEVICE, "Gram kernel failed");
+    stats->workgroups = grid;
+    stats->kernel_ms = ms;
+  }
+  if (ev0) (void)hipEventDestroy(ev0);
+  if (ev1) (void)hipEventDestroy(ev1);
   return st;
 }
 
@@ -1236,8 +1266,9 @@ void clear_gram_configs() {
   g_tuned.clear();
 }
 
-qk_status launch_gram(const std::vector<GramJobDev> &jobs, int max_pad, qk_precision prec, hipStream_t stream) {
-  return launch_gram_cfg(jobs, max_pad, prec, current_gram_config(prec, max_pad), stream);
+qk_status launch_gram(const std::vector<GramJobDev> &jobs, int max_pad, qk_precision prec, hipStream_t stream,
+                      qk_gram_stats *stats) {
+  return launch_gram_cfg(jobs, max_pad, prec, current_gram_config(prec, max_pad), stream, stats);
 }
 
 // ------------------------------------------------------------------------

@@ -72,6 +72,19 @@ constexpr int kI8FragBytes = 64 * 16;
 constexpr int kI8BufBytes = 4 * 4 * 2 * kI8FragBytes;   // one A-operand buffer (64 rows)
 constexpr int64_t kI8SiteBytes = kI8ExpBytes + kI8SumBytes + int64_t(2) * 4 * 2 * 4 * kI8FragBytes;
 
+// Device memory of the library.  Batch arrays, packed planes and scratch
+// buffers come from the allocator registered for the device with qk_init
+// (for example a framework's caching allocator), else from hipMalloc /
+// hipFree (batches) and hipMallocAsync / hipFreeAsync (stream-ordered
+// scratch).  A batch keeps the allocator that made it.
+struct DevAlloc {
+  qk_allocator user{};
+  bool custom() const { return user.alloc != nullptr; }
+};
+DevAlloc allocator_for_current_device();
+void *dev_alloc(const DevAlloc &al, size_t bytes, hipStream_t stream, bool scratch);
+void dev_free(const DevAlloc &al, void *p, hipStream_t stream, bool scratch);
+
 }  // namespace qk
 
 // Opaque batch.  Every MPS of a batch has m sites with the pad profile
@@ -82,6 +95,7 @@ constexpr int64_t kI8SiteBytes = kI8ExpBytes + kI8SumBytes + int64_t(2) * 4 * 2 
 // in the split-BF16 form.
 struct qk_mps_batch {
   int device = 0;
+  qk::DevAlloc alloc;              // allocator of every array below
   int64_t n = 0;
   int32_t m = 0;
   std::vector<int32_t> pad;        // m + 1 entries
@@ -159,9 +173,10 @@ struct GramConfig {
 };
 
 qk_status launch_gram(const std::vector<GramJobDev> &jobs, int max_pad,
-                      qk_precision prec, hipStream_t stream);
+                      qk_precision prec, hipStream_t stream, qk_gram_stats *stats = nullptr);
 qk_status launch_gram_cfg(const std::vector<GramJobDev> &jobs, int max_pad,
-                          qk_precision prec, const GramConfig &cfg, hipStream_t stream);
+                          qk_precision prec, const GramConfig &cfg, hipStream_t stream,
+                          qk_gram_stats *stats = nullptr);
 GramConfig default_gram_config(qk_precision prec, int max_pad);
 GramConfig current_gram_config(qk_precision prec, int max_pad);
 std::vector<GramConfig> gram_config_candidates(qk_precision prec, int max_pad);

@@ -917,18 +917,23 @@ qk_status run_simulation(qk_mps_batch *b, const double *features_dev, const std:
       if (!std::isfinite(v)) return fail(QK_EINVAL, "non-finite feature value");
   }
 
-  qk_gate *recs_dev = nullptr;
-  double2 *scratch = nullptr;
+  const DevAlloc al = allocator_for_current_device();
   const size_t rec_bytes = sizeof(qk_gate) * std::max<size_t>(gates.size(), 1);
-  QK_HIP_CHECK(hipMallocAsync(reinterpret_cast<void **>(&recs_dev), rec_bytes, stream));
-  if (hipMallocAsync(reinterpret_cast<void **>(&scratch), sizeof(double2) * 2 * kSvMaxN * kSvMaxN * size_t(n), stream) !=
-      hipSuccess) {
-    (void)hipGetLastError();
-    (void)hipFreeAsync(recs_dev, stream);
+  auto *recs_dev = static_cast<qk_gate *>(dev_alloc(al, rec_bytes, stream, true));
+  if (!recs_dev) return fail(QK_ENOMEM, "device allocation of the gate list failed");
+  auto *scratch = static_cast<double2 *>(
+      dev_alloc(al, sizeof(double2) * 2 * kSvMaxN * kSvMaxN * size_t(n), stream, true));
+  if (!scratch) {
+    dev_free(al, recs_dev, stream, true);
     return fail(QK_ENOMEM, "device allocation of SVD scratch failed");
   }
-  if (!gates.empty())
-    QK_HIP_CHECK(hipMemcpyAsync(recs_dev, gates.data(), sizeof(qk_gate) * gates.size(), hipMemcpyHostToDevice, stream));
+  if (!gates.empty() &&
+      hipMemcpyAsync(recs_dev, gates.data(), sizeof(qk_gate) * gates.size(), hipMemcpyHostToDevice, stream) !=
+          hipSuccess) {
+    dev_free(al, scratch, stream, true);
+    dev_free(al, recs_dev, stream, true);
+    return fail(QK_EDEVICE, "copy of the gate list failed");
+  }
 
   hipLaunchKernelGGL(init_plus_kernel, dim3(unsigned(n)), dim3(64), 0, stream, b->f64, b->mps_stride, b->site_off_dev,
                      b->pad_dev, b->dims_dev, m, n);
@@ -1040,7 +1045,8 @@ qk_status run_simulation(qk_mps_batch *b, const double *features_dev, const std:
   SimStep *steps_dev = nullptr;
   qk_status st = QK_OK;
   if (!steps.empty()) {
-    if (hipMallocAsync(reinterpret_cast<void **>(&steps_dev), sizeof(SimStep) * steps.size(), stream) != hipSuccess ||
+    steps_dev = static_cast<SimStep *>(dev_alloc(al, sizeof(SimStep) * steps.size(), stream, true));
+    if (!steps_dev ||
         hipMemcpyAsync(steps_dev, steps.data(), sizeof(SimStep) * steps.size(), hipMemcpyHostToDevice, stream) !=
             hipSuccess) {
       (void)hipGetLastError();
@@ -1108,9 +1114,9 @@ qk_status run_simulation(qk_mps_batch *b, const double *features_dev, const std:
     (void)hipStreamWaitEvent(stream_in, ev_out, 0);
     stream = stream_in;
   }
-  (void)hipFreeAsync(scratch, stream);
-  (void)hipFreeAsync(recs_dev, stream);
-  if (steps_dev) (void)hipFreeAsync(steps_dev, stream);
+  dev_free(al, scratch, stream, true);
+  dev_free(al, recs_dev, stream, true);
+  dev_free(al, steps_dev, stream, true);
   if (graph_gates > 0) {
     (void)hipStreamSynchronize(stream_in);
     (void)hipEventDestroy(ev_in);

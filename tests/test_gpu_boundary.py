@@ -1,0 +1,130 @@
+"""The boundary's memory hook, batch files and Gram statistics on the GPU.
+
+* Batches and scratch come from PyTorch's caching allocator (the binding's
+  default): the batch's bytes show up in torch.cuda.memory_allocated() and
+  go back when the batch is freed; hipMalloc (allocator None) gives the same
+  results bit for bit; an allocator that fails gives QK_ENOMEM.
+* mps_batch_save -> mps_batch_load reproduces the batch exactly: bond
+  dimensions, statistics, tensors and every Gram form, bit for bit (each
+  point simulated once and its state reused, Sec. II-D).
+* qk_gram_stats: entry count, algorithmic flops counted from the bond
+  dimensions (Fig. 2), kernel time and launch shape.
+"""
+import numpy as np
+import pytest
+
+import synthdata as sd
+from oracle import gram as ogram
+from tests.gpu_util import require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _sim(n=6, chi=16):
+    import paper_2411_09336_amd as q
+    torch = require_gpu()
+    w = sd.WORKLOADS["fp32"]
+    X = sd.workload_features(w, n)
+    xt = torch.tensor(X, dtype=torch.float64, device="cuda")
+    spec = q.CircuitSpec(w.n_qubits, w.distance, w.reps, w.coef_z, w.coef_xx, 1)
+    return q.simulate(xt, spec, chi, w.cutoff)
+
+
+def test_torch_allocator_holds_batch_memory():
+    import paper_2411_09336_amd as q
+    torch = require_gpu()
+    q.init(0, "torch")
+    torch.cuda.synchronize()
+    before = torch.cuda.memory_allocated()
+    b = _sim()
+    inf = b.info()
+    mid = torch.cuda.memory_allocated()
+    print("batch bytes", inf["bytes_f64"], "torch allocated +", mid - before)
+    assert mid - before >= inf["bytes_f64"]
+    b.pack("split_i8")
+    assert torch.cuda.memory_allocated() - mid >= b.info()["bytes_split_i8"]
+    K = q.gram(b, precision="fp64").cpu().numpy()
+    Ko = ogram.gram([b.export(i) for i in range(b.n)])
+    assert np.abs(K - Ko).max() < 1e-12
+    b.free()
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_allocated() - before < inf["bytes_f64"]
+
+
+def test_hip_allocator_gives_identical_results():
+    import paper_2411_09336_amd as q
+    require_gpu()
+    try:
+        q.init(0, None)
+        a = _sim()
+        Ka = {f: q.gram(a, precision=f) for f in ("fp64", "split_i8", "split_bf16")}
+    finally:
+        q.init(0, "torch")
+    b = _sim()
+    for f, k in Ka.items():
+        assert (q.gram(b, precision=f) == k).all(), f
+
+
+def test_failing_allocator_gives_enomem():
+    import paper_2411_09336_amd as q
+    require_gpu()
+    try:
+        q.init(0, (lambda nbytes, stream: 0, lambda ptr, stream: None))
+        with pytest.raises(q.QKError) as e:
+            _sim(2)
+        assert e.value.status == -2
+    finally:
+        q.init(0, "torch")
+    assert _sim(2).n == 2          # the default allocator works again
+
+
+def test_save_load_round_trip(tmp_path):
+    import paper_2411_09336_amd as q
+    require_gpu()
+    b = _sim(5, chi=32)
+    path = str(tmp_path / "train.qkmps")
+    b.save(path)
+    c = q.load_batch(path)
+    ib, ic = b.info(), c.info()
+    for k in ("n", "m", "max_bond", "pad_max", "n_two_qubit_gates", "max_discarded", "mean_total_discarded",
+              "degenerate_cuts", "unconverged_svds", "bytes_f64"):
+        assert ib[k] == ic[k], k
+    assert np.array_equal(b.bond_dims(), c.bond_dims())
+    for x, y in zip(b.trunc_stats(), c.trunc_stats()):
+        assert np.array_equal(x, y)
+    for i in range(b.n):
+        assert all(np.array_equal(s, t) for s, t in zip(b.export(i), c.export(i)))
+    for f in ("fp64", "fp32", "split_i8", "split_bf16"):
+        assert (q.gram(b, precision=f) == q.gram(c, precision=f)).all(), f
+        assert (q.gram(b, c, precision=f) == q.gram(b, precision=f)).all(), f
+
+
+def test_gram_stats():
+    import bench
+    import paper_2411_09336_amd as q
+    require_gpu()
+    b = _sim(7, chi=32)
+    dims = b.bond_dims()
+    n = b.n
+    for f in ("fp64", "split_i8"):
+        st = {}
+        q.gram(b, precision=f, stats=st)
+        print(f, st)
+        assert st["entries"] == n * (n + 1) // 2
+        ref = sum(bench.flops_per_entry(dims[i], dims[j]) for i in range(n) for j in range(i, n))
+        assert abs(st["flops"] - ref) <= 1e-9 * ref
+        assert st["kernel_ms"] > 0 and st["workgroups"] > 0 and st["tiles"] >= 1
+        assert st["tile_side"] in (8, 16, 32) and st["queues"] in (1, 8) and st["block"] in (32, 64)
+    # rectangular block: every (row, column) pair
+    st = {}
+    q.gram_block(b, 1, 3, b, 2, 4, precision="fp64", stats=st)
+    assert st["entries"] == 12
+    ref = sum(bench.flops_per_entry(dims[i], dims[j]) for i in range(1, 4) for j in range(2, 6))
+    assert abs(st["flops"] - ref) <= 1e-9 * ref
+    # upper triangle of a slab (global column >= global row)
+    st = {}
+    q.gram_block(b, 2, 3, b, 1, 6, precision="fp64", upper_only=True, stats=st)
+    pairs = [(i, j) for i in range(2, 5) for j in range(1, 7) if j >= i]
+    assert st["entries"] == len(pairs)
+    ref = sum(bench.flops_per_entry(dims[i], dims[j]) for i, j in pairs)
+    assert abs(st["flops"] - ref) <= 1e-9 * ref
