@@ -781,7 +781,8 @@ def run(args, cpu):
     if not args.no_cpu:
         if process_age() < SOFT_BUDGET_S:
             n_exp = min(12, S)
-            mps = {i: sim.export(i) for i in range(n_exp)}
+            # bras of the sampled block pairs and of the near-duplicate pairs
+            mps = {i: sim.export(i) for i in range(max(n_exp, D))}
             mps.update({S + i: sim.export(S + i) for i in range(D)})
             pairs = [(i, j, ("b", i, j)) for i in range(n_exp) for j in range(i, n_exp)]
             pairs += [(i, S + i, ("n", i, i)) for i in range(D)]

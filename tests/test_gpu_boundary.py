@@ -80,7 +80,7 @@ def test_failing_allocator_gives_enomem():
 
 def test_save_load_round_trip(tmp_path):
     import paper_2411_09336_amd as q
-    require_gpu()
+    torch = require_gpu()
     b = _sim(5, chi=32)
     path = str(tmp_path / "train.qkmps")
     b.save(path)
@@ -95,8 +95,16 @@ def test_save_load_round_trip(tmp_path):
     for i in range(b.n):
         assert all(np.array_equal(s, t) for s, t in zip(b.export(i), c.export(i)))
     for f in ("fp64", "fp32", "split_i8", "split_bf16"):
-        assert (q.gram(b, precision=f) == q.gram(c, precision=f)).all(), f
-        assert (q.gram(b, c, precision=f) == q.gram(b, precision=f)).all(), f
+        Kb = q.gram(b, precision=f)
+        assert (Kb == q.gram(c, precision=f)).all(), f
+        # the rectangular Gram contracts <b_i|c_j> for every (i, j): on and
+        # above the diagonal the same contractions as the symmetric Gram (bit
+        # for bit); below it <b_j|c_i> with bra and ket exchanged, equal up to
+        # rounding
+        Kr = q.gram(b, c, precision=f)
+        up = torch.ones_like(Kb, dtype=torch.bool).triu_()
+        assert torch.equal(Kr[up], Kb[up]), f
+        assert (Kr - Kb).abs().max().item() <= (1e-13 if f == "fp64" else 1e-6), f
 
 
 def test_gram_stats():
