@@ -259,6 +259,26 @@ qk_status mps_gram_block(const qk_mps_batch *a, int64_t a0, int64_t na,
                          double *K_dev, int64_t ldk, void *hip_stream,
                          qk_gram_stats *stats);
 
+/* mps_gram_block for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, kernels and results as mps_gram_block (bit for bit, same
+ * kernel configuration), without `stats`.  It allocates nothing: the work
+ * queue (counters, job table and pair-tile list) lives in a static device
+ * array of QK_NOALLOC_SCRATCH_BYTES per device, held from the library's
+ * set-up on that device until the process ends, and both batches must
+ * already hold the precision's packed planes (mps_batch_pack; QK_FP64 is
+ * always present) -- QK_ENOTSUP otherwise, before any launch.  QK_EINVAL,
+ * before any launch, when the work queue does not fit the array: with the
+ * default pair tiles of side 16 that is about 520,000 tiles, e.g. a
+ * symmetric Gram of up to ~16,000 MPS.  Every call on a device uses that
+ * device's one array: calls that overlap in time on one device (other
+ * threads, other streams) race and must be serialised by the caller. */
+#define QK_NOALLOC_SCRATCH_BYTES (8u << 20)
+qk_status mps_gram_block_noalloc(const qk_mps_batch *a, int64_t a0, int64_t na,
+                                 const qk_mps_batch *b, int64_t b0, int64_t nb,
+                                 int32_t upper_only, qk_precision prec,
+                                 double *K_dev, int64_t ldk, void *hip_stream);
+
 /* Several Gram jobs (different batches, qubit counts and pads) in ONE
  * persistent launch: workgroups pop tiles from a device work queue across
  * all jobs.  Each job is as in mps_gram_block with `upper_only` meaning

@@ -10,5 +10,5 @@ raises ``RuntimeError`` if the library has not been built
 """
 from .api import (  # noqa: F401
     CircuitSpec, MPSBatch, QKError, Precision, autotune, autotune_reset, circuit_compile, gram, gram_block,
-    gram_multi, import_batch, init, library_path, load_batch, simulate, simulate_trace, version,
+    gram_block_noalloc, gram_multi, import_batch, init, library_path, load_batch, simulate, simulate_trace, version,
 )

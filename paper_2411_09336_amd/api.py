@@ -112,6 +112,7 @@ def _load():
         "mps_simulate_trace": (S, [P, I64, C.POINTER(_Spec), I32, D, P, P, C.POINTER(P)]),
         "mps_gram": (S, [P, P, C.c_int, P, I64, P, C.POINTER(_GramStats)]),
         "mps_gram_block": (S, [P, I64, I64, P, I64, I64, I32, C.c_int, P, I64, P, C.POINTER(_GramStats)]),
+        "mps_gram_block_noalloc": (S, [P, I64, I64, P, I64, I64, I32, C.c_int, P, I64, P]),
         "mps_gram_multi": (S, [C.POINTER(_Job), I32, C.c_int, P, C.POINTER(_GramStats)]),
         "mps_batch_save": (S, [P, C.c_char_p]),
         "mps_batch_load": (S, [C.c_char_p, P, C.POINTER(P)]),
@@ -518,6 +519,18 @@ def gram_block(a: MPSBatch, a0: int, na: int, b: MPSBatch, b0: int, nb: int, pre
                                   _stream_ptr(stream), _stats_arg(st)))
     if st is not None:
         stats.update(_stats_dict(st))
+    return out
+
+
+def gram_block_noalloc(a: MPSBatch, a0: int, na: int, b: MPSBatch, b0: int, nb: int, out, precision="fp64",
+                       upper_only: bool = False, stream=None):
+    """mps_gram_block_noalloc: gram_block into the caller's ``out`` with no
+    device allocation (the batches must already be packed in ``precision``;
+    the work queue lives in the library's static per-device scratch)."""
+    _check_out(out, na, nb)
+    _check(_load().mps_gram_block_noalloc(a.handle, a0, na, b.handle, b0, nb, int(bool(upper_only)),
+                                          Precision.of(precision), C.c_void_p(out.data_ptr()), _ldk(out, nb),
+                                          _stream_ptr(stream)))
     return out
 
 

@@ -244,6 +244,10 @@ qk_status qk_init(int device, const qk_allocator *alloc) {
   QK_HIP_CHECK(hipGetDeviceCount(&count));
   if (device >= count) return fail(QK_EINVAL, "device index out of range");
   QK_HIP_CHECK(hipSetDevice(device));
+  // address of this device's copy of the allocation-free Gram scratch
+  void *scratch_ptr = nullptr;
+  const qk_status st = noalloc_scratch(&scratch_ptr);
+  if (st != QK_OK) return st;
   return ok();
 }
 
@@ -542,6 +546,26 @@ qk_status mps_gram_block(const qk_mps_batch *a, int64_t a0, int64_t na, const qk
     stats->entries = int64_t(e);
     stats->flops = f;
   }
+  return ok();
+}
+
+qk_status mps_gram_block_noalloc(const qk_mps_batch *a, int64_t a0, int64_t na, const qk_mps_batch *b,
+                                 int64_t b0, int64_t nb, int32_t upper_only, qk_precision prec, double *K_dev,
+                                 int64_t ldk, void *hip_stream) {
+  hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
+  GramJobDev job;
+  // pack = false: the precision's planes must exist already (no allocation)
+  qk_status st = make_job(a, a0, na, b, b0, nb, upper_only, K_dev, ldk, prec, stream, &job, false);
+  if (st != QK_OK) return st;
+  if (na == 0 || nb == 0) return ok();
+  void *ws = nullptr;
+  st = noalloc_scratch(&ws);
+  if (st != QK_OK) return st;
+  const int max_pad = std::max(max_pad_of(a), max_pad_of(b));
+  std::vector<GramJobDev> jobs{job};
+  st = launch_gram_cfg(jobs, max_pad, prec, current_gram_config(prec, max_pad), stream, nullptr, ws,
+                       kNoAllocScratchBytes);
+  if (st != QK_OK) return st;
   return ok();
 }
 

@@ -26,6 +26,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstring>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -116,6 +117,7 @@ __device__ inline double wave_max(double v) {
 // bytes apart.
 constexpr int kQueues = 8;
 constexpr int kCounterStride = 8;   // unsigned long long elements
+constexpr size_t kGramCounterBytes = sizeof(unsigned long long) * kQueues * kCounterStride;
 
 // Decode the next pair of this workgroup's queue.  Returns false when the
 // queue is empty; *valid is false for pairs outside the job's range or below
@@ -1126,8 +1128,38 @@ qk_status launch_one(const GramJobDev *jobs_dev, const GramTile *tiles_dev, int6
 
 }  // namespace
 
+// Device scratch of the allocation-free Gram entry point: work-queue
+// counters, job table and pair-tile list of one launch.  Each device holds
+// its own copy until the process ends; host code reaches it only through the
+// address that hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxScratchDevices] = {};
+}  // namespace
+
+qk_status noalloc_scratch(void **ptr) {
+  int dev = 0;
+  QK_HIP_CHECK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxScratchDevices) return fail(QK_EINVAL, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return fail(QK_EDEVICE, std::string("hipGetSymbolAddress of the Gram scratch -> ") + hipGetErrorString(e));
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  *ptr = g_scratch_ptr[dev];
+  return QK_OK;
+}
+
 qk_status launch_gram_cfg(const std::vector<GramJobDev> &jobs_in, int max_pad, qk_precision prec,
-                          const GramConfig &cfg, hipStream_t stream, qk_gram_stats *stats) {
+                          const GramConfig &cfg, hipStream_t stream, qk_gram_stats *stats, void *ws_given,
+                          size_t ws_cap) {
   if (max_pad > 64) return fail(QK_ENOTSUP, "Gram kernels support bond pads up to 64");
   if (cfg.maxp < max_pad) return fail(QK_EINVAL, "tile configuration smaller than the batch's bond pads");
   const int side = cfg.tile_side;
@@ -1161,20 +1193,29 @@ qk_status launch_gram_cfg(const std::vector<GramJobDev> &jobs_in, int max_pad, q
   const int64_t n_tiles = int64_t(tiles.size());
   const size_t jbytes = sizeof(GramJobDev) * jobs.size();
   const size_t tbytes = sizeof(GramTile) * tiles.size();
-  constexpr size_t kCounterBytes = sizeof(unsigned long long) * kQueues * kCounterStride;
-  const size_t ws_bytes = kCounterBytes + jbytes + tbytes;
+  // workspace: [queue counters | job table | tile list], uploaded in one copy
+  // whose counter bytes are zero (no memset node in the stream)
+  const size_t ws_bytes = kGramCounterBytes + jbytes + tbytes;
+  if (ws_given && ws_bytes > ws_cap)
+    return fail(QK_EINVAL, "the Gram work queue needs " + std::to_string(ws_bytes) + " bytes (" +
+                               std::to_string(n_tiles) + " pair tiles of side " + std::to_string(side) +
+                               "), above the " + std::to_string(ws_cap) + "-byte scratch");
+  std::vector<uint8_t> host(ws_bytes, 0);
+  std::memcpy(host.data() + kGramCounterBytes, jobs.data(), jbytes);
+  std::memcpy(host.data() + kGramCounterBytes + jbytes, tiles.data(), tbytes);
   const DevAlloc al = allocator_for_current_device();
-  auto *ws = static_cast<uint8_t *>(dev_alloc(al, ws_bytes, stream, true));
-  if (!ws) return fail(QK_ENOMEM, "device allocation of the Gram work queue failed");
+  uint8_t *ws = static_cast<uint8_t *>(ws_given);
+  if (!ws) {
+    ws = static_cast<uint8_t *>(dev_alloc(al, ws_bytes, stream, true));
+    if (!ws) return fail(QK_ENOMEM, "device allocation of the Gram work queue failed");
+  }
   auto *counters = reinterpret_cast<unsigned long long *>(ws);
-  auto *jobs_dev = reinterpret_cast<GramJobDev *>(ws + kCounterBytes);
-  auto *tiles_dev = reinterpret_cast<GramTile *>(ws + kCounterBytes + jbytes);
+  auto *jobs_dev = reinterpret_cast<GramJobDev *>(ws + kGramCounterBytes);
+  auto *tiles_dev = reinterpret_cast<GramTile *>(ws + kGramCounterBytes + jbytes);
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   qk_status st = QK_OK;
-  if (hipMemsetAsync(counters, 0, kCounterBytes, stream) != hipSuccess ||
-      hipMemcpyAsync(jobs_dev, jobs.data(), jbytes, hipMemcpyHostToDevice, stream) != hipSuccess ||
-      hipMemcpyAsync(tiles_dev, tiles.data(), tbytes, hipMemcpyHostToDevice, stream) != hipSuccess ||
-      // the host tile list must stay alive until the copies have run
+  if (hipMemcpyAsync(ws, host.data(), ws_bytes, hipMemcpyHostToDevice, stream) != hipSuccess ||
+      // the host buffer must stay alive until the copy has run
       hipStreamSynchronize(stream) != hipSuccess)
     st = fail(QK_EDEVICE, "upload of the Gram work queue failed");
   if (st == QK_OK && stats &&
@@ -1193,7 +1234,7 @@ qk_status launch_gram_cfg(const std::vector<GramJobDev> &jobs_in, int max_pad, q
     else
       st = launch_one<QK_SPLIT_I8, 64>(jobs_dev, tiles_dev, n_tiles, counters, cfg, stream, &grid, ev0, ev1);
   }
-  dev_free(al, ws, stream, true);
+  if (!ws_given) dev_free(al, ws, stream, true);
   if (st == QK_OK && stats) {
     float ms = 0.f;
     if (hipEventSynchronize(ev1) != hipSuccess || hipEventElapsedTime(&ms, ev0, ev1) != hipSuccess)

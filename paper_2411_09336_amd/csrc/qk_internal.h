@@ -174,9 +174,18 @@ struct GramConfig {
 
 qk_status launch_gram(const std::vector<GramJobDev> &jobs, int max_pad,
                       qk_precision prec, hipStream_t stream, qk_gram_stats *stats = nullptr);
+// ws / ws_cap: caller-provided workspace for the work queue (nullptr: drawn
+// from the device's allocator for the launch).
 qk_status launch_gram_cfg(const std::vector<GramJobDev> &jobs, int max_pad,
                           qk_precision prec, const GramConfig &cfg, hipStream_t stream,
-                          qk_gram_stats *stats = nullptr);
+                          qk_gram_stats *stats = nullptr, void *ws = nullptr, size_t ws_cap = 0);
+
+// Scratch of the allocation-free Gram entry point: a static device array of
+// kNoAllocScratchBytes per device.  noalloc_scratch returns its address on
+// the current device (looked up once per device with hipGetSymbolAddress).
+constexpr size_t kNoAllocScratchBytes = size_t(8) << 20;
+constexpr int kMaxScratchDevices = 64;
+qk_status noalloc_scratch(void **ptr);
 GramConfig default_gram_config(qk_precision prec, int max_pad);
 GramConfig current_gram_config(qk_precision prec, int max_pad);
 std::vector<GramConfig> gram_config_candidates(qk_precision prec, int max_pad);
@@ -195,3 +204,4 @@ std::vector<qk_gate> compile_circuit(const qk_circuit_spec &spec);
 qk_status validate_spec(const qk_circuit_spec *spec);
 
 }  // namespace qk
+static_assert(qk::kNoAllocScratchBytes == QK_NOALLOC_SCRATCH_BYTES, "scratch size of the header");

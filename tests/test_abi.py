@@ -54,5 +54,7 @@ def test_invalid_calls_fail_before_device_work():
     # NULL outputs / handles are rejected with QK_EINVAL
     assert lib.mps_simulate(None, ctypes.c_int64(4), None, 16, ctypes.c_double(0.0), None, None) == -1
     assert lib.mps_gram(None, None, 0, None, ctypes.c_int64(0), None) == -1
+    assert lib.mps_gram_block_noalloc(None, ctypes.c_int64(0), ctypes.c_int64(1), None, ctypes.c_int64(0),
+                                      ctypes.c_int64(1), 0, 0, None, ctypes.c_int64(1), None) == -1
     assert lib.mps_batch_info(None, None) == -1
     assert lib.qk_last_error()
