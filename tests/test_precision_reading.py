@@ -1,0 +1,126 @@
+"""Which "split-BF16" the kernels build, checked by emulation on the CPU.
+
+The target is |dK| <= 1e-6 (Fig. 2's contraction in reduced precision).  Two
+kinds of states, against the plain complex128 overlap:
+
+* random: 165-site, bond-64 left-canonical states and a near-duplicate of
+  one of them (K ~ 0.5);
+* simulated: circuits of the 100-qubit, d = 4, chi = 64 precision workload
+  run by the oracle (Sec. II-B truncation), self-overlaps.  Their Schmidt
+  spectra decay fast, so the final contraction weights a few entries of E
+  heavily and per-entry rounding does not average out as on random states.
+
+Findings (each a test below):
+* the built split-BF16 (31-bit codes in four 8-bit digits, ten digit
+  products, exact leading accumulator) and split-int8 (same digits, exact
+  int32 sums) stay near 1e-8 on both kinds;
+* a floating three-piece bf16 split with six products in one FP32
+  accumulator would pass if the bf16 MFMA summed its products exactly, but
+  the gfx950 instruction drops the low bits of products far below the
+  largest one of the same output (measured on the GPU: 2^20 - 2^20 + 2^-10
+  gives 0 and 1 + 3*2^-25 gives 1 where the f32 MFMA gives 2^-10 and
+  1 + 2^-23), and with that cut its self-overlaps drift one way by ~1e-6;
+* three 9-bit digits (27-bit codes, six products) pass on random states but
+  reach ~1e-6 on simulated ones, so they are not used;
+* three 8-bit digits with six products are worse than three 9-bit ones.
+"""
+import multiprocessing as mp
+
+import numpy as np
+import pytest
+
+import synthdata as sd
+from oracle import gram as ogram
+from oracle import mps as omps
+from tests import emulate_forms as ef
+
+FORMS = {
+    "split_bf16": ef.split_bf16_form,
+    "split_i8": ef.split_i8_form,
+    "three_9bit": ef.three_9bit_form,
+    "three_8bit": lambda: ef.FixedPoint(3, 8, ef.SIX, acc="exact", margin=2.0 ** -7),
+    "floating_exact": lambda: ef.FloatingR2(trunc_bits=None),
+    "floating_cut": lambda: ef.FloatingR2(trunc_bits=24),
+}
+REAL_POINTS = 6
+_STATES = {}
+
+
+def _limit_threads():
+    try:
+        import threadpoolctl
+        threadpoolctl.threadpool_limits(1)
+    except ImportError:
+        pass
+
+
+def _simulate(i):
+    _limit_threads()
+    w = sd.WORKLOADS["precision"]
+    x = sd.workload_features(w, REAL_POINTS)[i]
+    return omps.simulate(x, w.distance, w.reps, w.chi, w.cutoff, w.coef_z, w.coef_xx, routing=1).tensors
+
+
+def _one(task):
+    _limit_threads()
+    name, ka, kb = task
+    return task, abs(FORMS[name]().overlap(_STATES[ka], _STATES[kb])) ** 2
+
+
+@pytest.fixture(scope="module")
+def errors():
+    """dK[form][(state a, state b)] in forked workers."""
+    rng = np.random.default_rng(11)
+    a = ef.random_left_canonical(165, 64, rng)
+    b = ef.perturbed(a, 0.004, rng)
+    _STATES.update(ra=a, rb=b)
+    ctx = mp.get_context("fork")
+    with ctx.Pool(REAL_POINTS) as pool:
+        for i, t in enumerate(pool.map(_simulate, range(REAL_POINTS))):
+            _STATES[f"s{i}"] = t
+    ref = {("ra", "ra"): 1.0, ("rb", "rb"): 1.0, ("ra", "rb"): abs(ogram.overlap(a, b)) ** 2}
+    assert 0.1 < ref[("ra", "rb")] < 0.9          # a mid-range entry, not only the diagonal
+    for i in range(REAL_POINTS):
+        ref[(f"s{i}", f"s{i}")] = 1.0
+    tasks = []
+    for name in FORMS:
+        pairs = list(ref) if not name.startswith("floating") else [("ra", "ra"), ("rb", "rb"), ("ra", "rb")]
+        tasks += [(name, ka, kb) for (ka, kb) in pairs]
+    with ctx.Pool(8) as pool:
+        out = pool.map(_one, sorted(tasks, key=lambda t: t[0] != "floating_cut"))
+    res = {}
+    for (name, ka, kb), k in out:
+        res.setdefault(name, {})[(ka, kb)] = k - ref[(ka, kb)]
+    for name, d in res.items():
+        print(name, {f"{ka}{kb}": f"{v:+.2e}" for (ka, kb), v in d.items()})
+    return res
+
+
+def _max(d, kind):
+    return max(abs(v) for (ka, _), v in d.items() if ka.startswith(kind))
+
+
+def test_built_forms_reach_1e8_on_both_kinds(errors):
+    for name in ("split_bf16", "split_i8"):
+        assert _max(errors[name], "r") < 5e-8, name
+        assert _max(errors[name], "s") < 5e-8, name
+
+
+def test_three_9bit_digits_fail_on_simulated_states(errors):
+    d = errors["three_9bit"]
+    assert _max(d, "r") < 4e-7          # random states suggest a 2.5x margin ...
+    assert _max(d, "s") > 8e-7          # ... simulated ones take it away
+    assert _max(d, "s") > 10 * _max(errors["split_bf16"], "s")
+
+
+def test_floating_split_with_mfma_truncation_drifts(errors):
+    cut, exact = errors["floating_cut"], errors["floating_exact"]
+    # with the instruction's truncation the self-overlaps fall short by about
+    # 1e-6, one-signed (every cut is toward zero on positive sums); without
+    # it the same split would pass on these states
+    assert cut[("ra", "ra")] < -5e-7 and cut[("rb", "rb")] < -5e-7
+    assert max(abs(v) for v in exact.values()) < 1e-6
+
+
+def test_three_8bit_digits_worse_than_three_9bit(errors):
+    assert _max(errors["three_8bit"], "r") > 1.5 * _max(errors["three_9bit"], "r")
