@@ -84,7 +84,16 @@ typedef struct {
                                  /*    E_i block cancelled                    */
   double coef_z;
   double coef_xx;
-  int32_t reserved[4];           /* must be zero                              */
+  int32_t gate_split;            /* 1: apply each two-qubit gate through its  */
+                                 /*    operator-Schmidt decomposition (the   */
+                                 /*    gate SVD before application, footnote  */
+                                 /*    of Sec. III-A): the kept count is at   */
+                                 /*    most rank(G) x the bond between the    */
+                                 /*    two sites, rank 2 for Rxx (1 at a zero */
+                                 /*    angle), 4 for SWAP, so the gate's zero */
+                                 /*    singular values never survive as       */
+                                 /*    rounding noise; 0: plain theta SVD     */
+  int32_t reserved[3];           /* must be zero                              */
 } qk_circuit_spec;
 
 /* Gate-list record: op 0 = RZ (site, feature), 1 = RXX (left site, feature i,

@@ -108,16 +108,52 @@ def truncation_rank(s: np.ndarray, chi: int, cutoff: float) -> int:
     return max(1, min(chi, k_cut))
 
 
+def gate_factors(u4: np.ndarray, tol: float = 1e-12):
+    """Operator-Schmidt factors of a two-qubit gate (its SVD before
+    application, footnote of Sec. III-A): u4[(S,T),(s,t)] =
+    sum_k L[k][S,s] R[k][T,t], terms whose singular value is below tol times
+    the largest dropped (Rxx: two terms, 2|cos(t/2)| and 2|sin(t/2)|; one at
+    a zero angle; SWAP: four)."""
+    m = u4.reshape(2, 2, 2, 2).transpose(0, 2, 1, 3).reshape(4, 4)   # (S s), (T t)
+    u, sv, vh = np.linalg.svd(m)
+    r = int(np.sum(sv > tol * sv[0]))
+    L = (u[:, :r] * np.sqrt(sv[:r])).T.reshape(r, 2, 2)
+    R = (np.sqrt(sv[:r])[:, None] * vh[:r]).reshape(r, 2, 2)
+    return L, R
+
+
+def _split_svd(A: List[np.ndarray], p: int, u4: np.ndarray):
+    """SVD of theta applied through the gate's factors: theta = Bp Bq with
+    Bp[(a,S),(c,k)] = sum_s L[k][S,s] A_p[a,s,c] and Bq[(c,k),(T,b)] =
+    sum_t R[k][T,t] A_{p+1}[c,t,b]; with Bp = Q1 R1 and Bq^H = Q2 R2 the SVD
+    of the core R1 R2^H gives those of theta, at most rank(G) D_c values."""
+    L, R = gate_factors(u4)
+    r = L.shape[0]
+    Dl, _, Dc = A[p].shape
+    Dr = A[p + 1].shape[2]
+    Bp = np.einsum("kSs,asc->aSck", L, A[p]).reshape(Dl * 2, Dc * r)
+    Bq = np.einsum("kTt,ctb->ckTb", R, A[p + 1]).reshape(Dc * r, 2 * Dr)
+    q1, r1 = np.linalg.qr(Bp)
+    q2, r2 = np.linalg.qr(Bq.conj().T)
+    u, s, vh = np.linalg.svd(r1 @ r2.conj().T, full_matrices=False)
+    return q1 @ u, s, vh @ q2.conj().T
+
+
 def apply_two_qubit(A: List[np.ndarray], p: int, u4: np.ndarray, chi: int, cutoff: float,
-                    absorb_right: bool, res: MPSResult) -> None:
-    """Fig. 1b on sites (p, p+1); the orthogonality centre must be p or p+1."""
+                    absorb_right: bool, res: MPSResult, gate_split: bool = False) -> None:
+    """Fig. 1b on sites (p, p+1); the orthogonality centre must be p or p+1.
+    With gate_split the gate is applied through its operator-Schmidt factors
+    (_split_svd) instead of as the dense two-site theta."""
     Dl = A[p].shape[0]
     Dr = A[p + 1].shape[2]
-    theta = np.tensordot(A[p], A[p + 1], axes=(2, 0))            # (Dl, s, t, Dr)
-    g = u4.reshape(2, 2, 2, 2)                                      # (s', t', s, t)
-    theta = np.einsum("STst,astb->aSTb", g, theta)
-    mat = theta.reshape(Dl * 2, 2 * Dr)
-    u, s, vh = np.linalg.svd(mat, full_matrices=False)
+    if gate_split:
+        u, s, vh = _split_svd(A, p, u4)
+    else:
+        theta = np.tensordot(A[p], A[p + 1], axes=(2, 0))            # (Dl, s, t, Dr)
+        g = u4.reshape(2, 2, 2, 2)                                      # (s', t', s, t)
+        theta = np.einsum("STst,astb->aSTb", g, theta)
+        mat = theta.reshape(Dl * 2, 2 * Dr)
+        u, s, vh = np.linalg.svd(mat, full_matrices=False)
     k = truncation_rank(s, chi, cutoff)
     w = s ** 2
     total = w.sum()
@@ -141,8 +177,10 @@ def apply_two_qubit(A: List[np.ndarray], p: int, u4: np.ndarray, chi: int, cutof
 
 def simulate(x: np.ndarray, d: int, reps: int, chi: int, cutoff: float,
              coef_z: float = 2.0, coef_xx: float = 2.0, routing: int = 0,
-             glist: np.ndarray | None = None) -> MPSResult:
-    """MPS of |psi(x)> = U(x)|+>^m, truncated at bond cap ``chi``."""
+             glist: np.ndarray | None = None, gate_split: bool = False) -> MPSResult:
+    """MPS of |psi(x)> = U(x)|+>^m, truncated at bond cap ``chi``; with
+    ``gate_split`` every two-qubit gate is applied through its
+    operator-Schmidt factors (footnote of Sec. III-A)."""
     x = np.asarray(x, dtype=np.float64)
     m = len(x)
     if glist is None:
@@ -166,7 +204,7 @@ def simulate(x: np.ndarray, d: int, reps: int, chi: int, cutoff: float,
             center = move_center(A, center, p + 1)
         p_next = nxt[gi]
         absorb_right = p_next is None or p_next > p
-        apply_two_qubit(A, p, u4, chi, cutoff, absorb_right, res)
+        apply_two_qubit(A, p, u4, chi, cutoff, absorb_right, res, gate_split)
         res.trace.append((A[p].shape[2], sum(t.shape[0] * t.shape[2] for t in A)))
         center = p + 1 if absorb_right else p
     move_center(A, center, m - 1)

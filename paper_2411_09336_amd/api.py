@@ -50,7 +50,7 @@ class _Spec(C.Structure):
     _fields_ = [("n_qubits", C.c_int32), ("interaction_distance", C.c_int32),
                 ("repetitions", C.c_int32), ("routing", C.c_int32),
                 ("coef_z", C.c_double), ("coef_xx", C.c_double),
-                ("reserved", C.c_int32 * 4)]
+                ("gate_split", C.c_int32), ("reserved", C.c_int32 * 3)]
 
 
 class _Gate(C.Structure):
@@ -252,12 +252,14 @@ class CircuitSpec:
     coef_z: float = 2.0
     coef_xx: float = 2.0
     routing: int = 0
+    gate_split: int = 0
 
     def _c(self) -> _Spec:
         s = _Spec()
         s.n_qubits, s.interaction_distance, s.repetitions, s.routing = (
             self.n_qubits, self.distance, self.reps, self.routing)
         s.coef_z, s.coef_xx = float(self.coef_z), float(self.coef_xx)
+        s.gate_split = int(self.gate_split)
         return s
 
 

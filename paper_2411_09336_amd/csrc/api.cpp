@@ -79,7 +79,8 @@ qk_status validate_spec(const qk_circuit_spec *spec) {
   if (spec->routing != 0 && spec->routing != 1) return fail(QK_EINVAL, "routing must be 0 or 1");
   if (!std::isfinite(spec->coef_z) || !std::isfinite(spec->coef_xx))
     return fail(QK_EINVAL, "angle coefficients must be finite");
-  for (int k = 0; k < 4; ++k)
+  if (spec->gate_split != 0 && spec->gate_split != 1) return fail(QK_EINVAL, "gate_split must be 0 or 1");
+  for (int k = 0; k < 3; ++k)
     if (spec->reserved[k] != 0) return fail(QK_EINVAL, "reserved fields must be zero");
   return QK_OK;
 }

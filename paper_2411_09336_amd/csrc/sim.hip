@@ -67,6 +67,7 @@ struct SvParams {
   int32_t *dims;
   int32_t m;
   int32_t chi;
+  int32_t gate_split;  // cap the kept count at rank(G) x the middle bond
   double coef_xx;
   double cutoff;
   const double *X;
@@ -694,6 +695,18 @@ __device__ __attribute__((noinline)) void svd_step(const SvParams &P, const int6
           }
         }
         k = max(1, min(min(P.chi, kcut), max(nnz, 1)));
+        if (P.gate_split) {
+          // theta = sum_r (L_r A_p)(R_r A_{p+1}) over the rank(G) terms of
+          // the gate's operator-Schmidt decomposition: rank <= rank(G) Dm.
+          // Rxx(phi) = cos(phi/2) II - i sin(phi/2) XX: a term counts when its
+          // coefficient exceeds 1e-12 of the larger one (cos(pi/2) rounds to
+          // ~6e-17, not zero); SWAP has four terms
+          const double cmax = fmax(fabs(cg), fabs(sg));
+          const int rg = st.op == OP_RXX
+                             ? (fabs(cg) > 1e-12 * cmax ? 1 : 0) + (fabs(sg) > 1e-12 * cmax ? 1 : 0)
+                             : 4;
+          k = max(1, min(k, rg * Dm));
+        }
         double kept = 0.0;
   #pragma unroll 1
       for (int u = k - 1; u >= 0; --u) kept += s_sorted[u];
@@ -947,6 +960,7 @@ qk_status run_simulation(qk_mps_batch *b, const double *features_dev, const std:
   P.dims = b->dims_dev;
   P.m = m;
   P.chi = chi;
+  P.gate_split = spec.gate_split;
   P.coef_xx = spec.coef_xx;
   P.cutoff = cutoff;
   P.X = features_dev;

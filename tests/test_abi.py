@@ -41,7 +41,8 @@ def test_gate_list_matches_oracle_bytes(m, d, reps, routing):
 
 @pytest.mark.parametrize("bad", [dict(n_qubits=0, distance=1, reps=1), dict(n_qubits=4, distance=-1, reps=1),
                                  dict(n_qubits=4, distance=1, reps=-2), dict(n_qubits=4, distance=1, reps=1, routing=5),
-                                 dict(n_qubits=4, distance=1, reps=1, coef_z=float("nan"))])
+                                 dict(n_qubits=4, distance=1, reps=1, coef_z=float("nan")),
+                                 dict(n_qubits=4, distance=1, reps=1, gate_split=2)])
 def test_invalid_spec_is_rejected(bad):
     with pytest.raises(q.QKError) as e:
         q.circuit_compile(q.CircuitSpec(**bad))

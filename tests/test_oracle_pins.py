@@ -316,3 +316,67 @@ def test_degenerate_cut_threshold(gap, flag):
     mps.apply_two_qubit(A, 0, np.eye(4, dtype=complex), 1, 0.0, True, res)
     assert (a - b) / top == pytest.approx(gap, rel=1e-3)
     assert res.degenerate_cuts == int(flag)
+
+
+# ---------------------------------------------------------------- gate pre-decomposition (Sec. III-A footnote)
+@pytest.mark.parametrize("th,rank", [(0.3, 2), (-1.7, 2), (2.9, 2), (0.0, 1), (np.pi, 1), (-np.pi, 1)])
+def test_gate_factors_of_rxx_closed_form(th, rank):
+    """Rxx(t) = cos(t/2) II - i sin(t/2) XX: two operator-Schmidt terms of
+    weight 2|cos(t/2)| and 2|sin(t/2)| (Hilbert-Schmidt norm 2 of II and XX);
+    one at t = 0 and t = pi, where the other coefficient vanishes."""
+    L, R = mps.gate_factors(gates.rxx(th))
+    assert L.shape[0] == rank
+    u4 = np.einsum("kSs,kTt->STst", L, R).reshape(4, 4)
+    assert np.allclose(u4, gates.rxx(th), atol=1e-14)
+    weights = sorted(np.linalg.norm(L[k]) * np.linalg.norm(R[k]) for k in range(rank))
+    expect = sorted(w for w in (2 * abs(np.cos(th / 2)), 2 * abs(np.sin(th / 2))) if w > 1e-12)
+    assert np.allclose(weights, expect, atol=1e-13)
+
+
+def test_gate_factors_of_swap():
+    """SWAP = (II + XX + YY + ZZ) / 2: four terms of weight 1."""
+    L, R = mps.gate_factors(gates.SWAP)
+    assert L.shape[0] == 4
+    assert np.allclose(np.einsum("kSs,kTt->STst", L, R).reshape(4, 4), gates.SWAP, atol=1e-14)
+    assert np.allclose([np.linalg.norm(L[k]) * np.linalg.norm(R[k]) for k in range(4)], 1.0, atol=1e-13)
+
+
+def test_gate_split_application_equals_dense_theta():
+    """Both ways of applying a gate to sites with a small middle bond give the
+    same two-site tensor; the split way keeps at most rank(G) x D_c values,
+    while the dense theta's SVD also returns the gate's zero singular values as
+    rounding noise, which cutoff 0 keeps."""
+    rng = np.random.default_rng(21)
+    Dl, Dc, Dr = 4, 1, 4
+    for u4, rank in ((gates.rxx(0.7), 2), (gates.rxx(0.0), 1), (gates.SWAP, 4)):
+        ap = rng.standard_normal((Dl, 2, Dc)) + 1j * rng.standard_normal((Dl, 2, Dc))
+        aq = rng.standard_normal((Dc, 2, Dr)) + 1j * rng.standard_normal((Dc, 2, Dr))
+        ref = np.einsum("STst,astb->aSTb", u4.reshape(2, 2, 2, 2), np.tensordot(ap, aq, axes=(2, 0)))
+        for split in (False, True):
+            A = [ap.copy(), aq.copy()]
+            res = mps.MPSResult(tensors=A)
+            mps.apply_two_qubit(A, 0, u4, 64, 0.0, True, res, gate_split=split)
+            got = np.tensordot(A[0], A[1], axes=(2, 0))
+            scale = np.linalg.norm(ref)    # the kept values are renormalised to unit weight
+            assert np.allclose(got * scale, ref, atol=1e-13 * scale)
+            k = A[0].shape[2]
+            if split:
+                assert k == min(rank * Dc, 2 * Dl, 2 * Dr)
+            elif rank * Dc < 2 * Dl:
+                assert k > rank * Dc    # the noise values survive
+
+
+@pytest.mark.parametrize("m,d,reps,routing", [(6, 3, 2, 0), (7, 2, 2, 1), (8, 1, 2, 0), (5, 4, 1, 1)])
+def test_gate_split_untruncated_equals_statevector(m, d, reps, routing):
+    """With features at the ends of [0, 1] some Rxx angles are exactly zero
+    (identity gates); the split simulation still reproduces the state vector,
+    with bonds no larger than the dense one's."""
+    rng = np.random.default_rng(m + 10 * d + routing)
+    x = rng.random(m)
+    x[1], x[m - 2] = 1.0, 0.0
+    psi = sv.state_logical(x, d, reps, 2.0, 2.0)
+    r = mps.simulate(x, d, reps, 64, 0.0, routing=routing, gate_split=True)
+    assert abs(np.vdot(psi, mps.to_statevector(r.tensors))) ** 2 > 1 - 1e-13
+    plain = mps.simulate(x, d, reps, 64, 0.0, routing=routing)
+    assert all(a <= b for a, b in zip(r.bond_dims, plain.bond_dims))
+    assert sum(t[0] for t in r.trace) < sum(t[0] for t in plain.trace)
