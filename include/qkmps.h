@@ -312,10 +312,11 @@ qk_status mps_gram_multi(const qk_gram_job *jobs, int32_t n_jobs,
  * side 8 / 16 / 32, one work queue or one per XCD) computes the symmetric
  * Gram of the first min(sample, n) MPS of `b` (one warm-up run, then the
  * best of two timed runs, wall clock including the launch's host work).
- * The fastest configuration is stored for this device, precision and pad
- * bucket and used by every later mps_gram* call on this process; `report`
- * (may be NULL) receives it with its time and the default configuration's
- * time.  Not thread-safe with concurrent Gram calls of the same bucket. */
+ * The fastest configuration, if it beats the default by more than 2 % (the
+ * timing's run-to-run spread is about 1 %), else the default, is stored for
+ * this device, precision and pad bucket and used by every later mps_gram*
+ * call on this process; `report` (may be NULL) receives it with its time and
+ * the default configuration's time.  Not thread-safe with concurrent Gram calls of the same bucket. */
 typedef struct {
   int32_t maxp;           /* block size of the winning configuration        */
   int32_t tile_side;      /* pair-tile side                                  */

@@ -299,6 +299,31 @@ __device__ void overlap_plain(const GramJobDev &J, int64_t ia, int64_t ib, T2 *E
   __syncthreads();
 }
 
+// A pointer that is the same in every lane, moved to scalar registers.
+template <typename T>
+__device__ inline T *uniform_ptr(T *p) {
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  return reinterpret_cast<T *>((uint64_t(__builtin_amdgcn_readfirstlane(uint32_t(v >> 32))) << 32) |
+                               uint32_t(__builtin_amdgcn_readfirstlane(uint32_t(v))));
+}
+
+// Fragments are read with buffer loads through a descriptor of the whole
+// site block (scalar base, 32-bit lane offset, scalar fragment offset): no
+// 64-bit vector address arithmetic per fragment, and a read outside the
+// block's bytes returns zero.  Word 3 is the gfx9-family raw-buffer format.
+typedef __amdgpu_buffer_rsrc_t SiteRsrc;
+template <int64_t BYTES>
+__device__ inline SiteRsrc site_rsrc(const uint8_t *site) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t *>(uniform_ptr(site)), 0, int(BYTES), 0x00020000);
+}
+
+__device__ inline uint4 rsrc_load_u4(SiteRsrc r, int voff, int soff) {
+  typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+  const v4u v = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
+
+
 // ------------------------------------------------------------------------
 // Split-BF16 form with fixed-point slices (layout in qk_internal.h).
 //
@@ -352,6 +377,29 @@ __device__ inline void slice4e(double x, int e, uint32_t (&o)[4]) {
 
 // Same slices for xh = x 2^-e already in (-1, 1).
 __device__ inline void slice4(double xh, uint32_t (&o)[4]) { slice4e(xh, 0, o); }
+
+// Row exponent of the values the kernel slices itself (T and E'): smallest e
+// with mx (1 + 2^-7) < 2^e, so that |X| + 0x808080 < 2^31 in slice4_word.
+__device__ inline int exp_above_w(double mx) { return mx > 0.0 ? ilogb(mx * (1.0 + 0x1p-7)) + 1 : 0; }
+
+// The same four slices as slice4e, as floats n_k 2^-8k, from one FP64 FMA:
+// with scale = 2^(31-e), the low word of x scale + 1.5 2^52 + 0x808080 is
+// Y = X + 0x808080 for X = round(x 2^(31-e)), whose top byte is the signed
+// leading digit n0 and whose lower bytes are n_k + 128 (k = 1..3) -- the
+// same balanced digits, without carries.  Each slice is then one byte
+// conversion and one exact FMA; its bf16 bits are the float's upper half.
+__device__ inline void slice4_word(double x, double scale, float (&f)[4]) {
+  const uint32_t y = uint32_t(__double_as_longlong(fma(x, scale, 0x1.8p52 + 0x808080)));
+  f[0] = float(int(y) >> 24);
+  f[1] = fmaf(float(uint8_t(y >> 16)), 0x1p-8f, -0x1p-1f);
+  f[2] = fmaf(float(uint8_t(y >> 8)), 0x1p-16f, -0x1p-9f);
+  f[3] = fmaf(float(uint8_t(y)), 0x1p-24f, -0x1p-17f);
+}
+
+// bf16 bits of two exact floats packed in one word (a low, b high).
+__device__ inline uint32_t pack_bf16_pair(float a, float b) {
+  return __builtin_amdgcn_perm(__float_as_uint(b), __float_as_uint(a), 0x07060302u);
+}
 
 struct Sl4 {
   uint4 v[4];
@@ -419,8 +467,11 @@ struct SplitCtx {
   int lane, j, g, cb, hf;
 };
 
-__device__ inline uint4 split_frag(const uint8_t *site, int s, int k, int q, int kc, int c, int lane) {
-  return gload_u4(site + kSplitExpBytes + (size_t(((((s * 4 + k) * 2 + q) * 2 + kc) * 4 + c)) * 1024 + lane * 16));
+constexpr int64_t kSplitSiteBytes = kSplitExpBytes + int64_t(2) * 4 * 2 * 2 * 4 * kFragBytes;
+static_assert(kSplitSiteBytes == split_site_bytes(), "split-BF16 site block size");
+
+__device__ inline uint4 split_frag(SiteRsrc site, int s, int k, int q, int kc, int c, int lane) {
+  return rsrc_load_u4(site, lane * 16, kSplitExpBytes + ((((s * 4 + k) * 2 + q) * 2 + kc) * 4 + c) * kFragBytes);
 }
 
 // GEMM1 for physical index s: T[a][b'] (a in rows 32h.., b' in block c) in
@@ -435,13 +486,14 @@ __device__ inline void split_gemm1(const SplitCtx &C, const uint8_t *B, const ui
       h1[u][q] = f32x4{0, 0, 0, 0};
       l1[u][q] = f32x4{0, 0, 0, 0};
     }
+  const SiteRsrc rB = site_rsrc<kSplitSiteBytes>(B);
 #pragma unroll
   for (int kc = 0; kc < 2; ++kc) {
     Sl4 Br, Bi;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      Br.v[k] = split_frag(B, s, k, 0, kc, C.cb, C.lane);
-      Bi.v[k] = split_frag(B, s, k, 1, kc, C.cb, C.lane);
+      Br.v[k] = split_frag(rB, s, k, 0, kc, C.cb, C.lane);
+      Bi.v[k] = split_frag(rB, s, k, 1, kc, C.cb, C.lane);
     }
     const Sl4 Bin = neg4(Bi);
 #pragma unroll
@@ -487,19 +539,20 @@ __device__ inline void split_gemm1(const SplitCtx &C, const uint8_t *B, const ui
 // group row `grow` of buffer `buf`: A-operand group (grow, kc = u2 >> 1) where
 // u2 = 2 h + u is the 16-row tile of the contraction index.
 __device__ inline void split_store(const SplitCtx &C, uint8_t *buf, int grow, const double (&V)[2][2][4], int ex) {
+  const double scale = ldexp(1.0, 31 - ex);
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
     const int t = 2 * C.hf + u;
     uint8_t *dst = buf + size_t(grow * 2 + (t >> 1)) * 8192 + C.lane * 16 + (t & 1) * 8;
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
-      uint32_t sl[4][4];
+      float sl[4][4];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) slice4e(V[u][q][e], ex, sl[e]);
+      for (int e = 0; e < 4; ++e) slice4_word(V[u][q][e], scale, sl[e]);
 #pragma unroll
       for (int k = 0; k < 4; ++k)
         *reinterpret_cast<uint2 *>(dst + (k * 2 + q) * 1024) =
-            make_uint2(sl[0][k] | (sl[1][k] << 16), sl[2][k] | (sl[3][k] << 16));
+            make_uint2(pack_bf16_pair(sl[0][k], sl[1][k]), pack_bf16_pair(sl[2][k], sl[3][k]));
     }
   }
 }
@@ -516,14 +569,16 @@ __device__ inline void split_gemm2(const SplitCtx &C, const uint8_t *A, const ui
       h2[u][q] = f32x4{0, 0, 0, 0};
       l2[u][q] = f32x4{0, 0, 0, 0};
     }
+  const SiteRsrc rA = site_rsrc<kSplitSiteBytes>(A);
 #pragma unroll
   for (int kc = 0; kc < 2; ++kc) {
     Sl4 Ar, Ai;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      Ar.v[k] = split_frag(A, s, k, 0, kc, C.cb, C.lane);
-      Ai.v[k] = split_frag(A, s, k, 1, kc, C.cb, C.lane);
+      Ar.v[k] = split_frag(rA, s, k, 0, kc, C.cb, C.lane);
+      Ai.v[k] = split_frag(rA, s, k, 1, kc, C.cb, C.lane);
     }
+    const Sl4 Ain = neg4(Ai);   // shared by both row tiles (the products are those of -Tr Ai)
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       const int bt = 2 * C.hf + u;
@@ -534,13 +589,12 @@ __device__ inline void split_gemm2(const SplitCtx &C, const uint8_t *A, const ui
         Tr.v[k] = *reinterpret_cast<const uint4 *>(tg + (k * 2 + 0) * 1024);
         Ti.v[k] = *reinterpret_cast<const uint4 *>(tg + (k * 2 + 1) * 1024);
       }
-      const Sl4 Trn = neg4(Tr);
-      // re += Tr Ar + Ti Ai ; im += Ti Ar - Tr Ai
+      // re += Tr Ar + Ti Ai ; im += Ti Ar + Tr (-Ai)
       __builtin_amdgcn_s_setprio(1);
       slice_mac<true>(Tr, Ar, h2[u][0], l2[u][0]);
       slice_mac<true>(Ti, Ai, h2[u][0], l2[u][0]);
       slice_mac<false>(Ti, Ar, h2[u][1], l2[u][1]);
-      slice_mac<false>(Trn, Ai, h2[u][1], l2[u][1]);
+      slice_mac<false>(Tr, Ain, h2[u][1], l2[u][1]);
       __builtin_amdgcn_s_setprio(0);
     }
   }
@@ -567,8 +621,9 @@ __device__ void overlap_split(const GramJobDev &J, int64_t ia, int64_t ib, uint8
   C.lane = tid & 63;
   C.j = C.lane & 15;
   C.g = C.lane >> 4;
-  C.cb = wave & 3;
-  C.hf = wave >> 2;
+  // wave-uniform (scalar) block indices: fragment offsets stay in SGPRs
+  C.cb = __builtin_amdgcn_readfirstlane(wave & 3);
+  C.hf = __builtin_amdgcn_readfirstlane(wave >> 2);
   const uint8_t *abase = reinterpret_cast<const uint8_t *>(J.a_base) + ia * J.a_stride;
   const uint8_t *bbase = reinterpret_cast<const uint8_t *>(J.b_base) + ib * J.b_stride;
   uint8_t *X = buf0, *Y = buf1;
@@ -602,7 +657,7 @@ __device__ void overlap_split(const GramJobDev &J, int64_t ia, int64_t ib, uint8
     __syncthreads();
     // 2. slice T0 -> Y  ||  GEMM1(s = 1)
     {
-      const int eT0 = exp_above(fmax(s_mx[(0 * 2 + 0) * kSP + col], s_mx[(0 * 2 + 1) * kSP + col]));
+      const int eT0 = exp_above_w(fmax(s_mx[(0 * 2 + 0) * kSP + col], s_mx[(0 * 2 + 1) * kSP + col]));
       if (C.hf == 0 && C.g == 0) s_eT[0 * kSP + col] = eT0;
       split_store(C, Y, C.cb, Td0, eT0);
       split_gemm1(C, B, X, s_ea, 1, Td1, tmax);
@@ -611,7 +666,7 @@ __device__ void overlap_split(const GramJobDev &J, int64_t ia, int64_t ib, uint8
     __syncthreads();
     // 3. slice T1 -> X  ||  GEMM2(s = 0)
     {
-      const int eT1 = exp_above(fmax(s_mx[(1 * 2 + 0) * kSP + col], s_mx[(1 * 2 + 1) * kSP + col]));
+      const int eT1 = exp_above_w(fmax(s_mx[(1 * 2 + 0) * kSP + col], s_mx[(1 * 2 + 1) * kSP + col]));
       if (C.hf == 0 && C.g == 0) s_eT[1 * kSP + col] = eT1;
       split_store(C, X, C.cb, Td1, eT1);
       split_gemm2(C, A, Y, s_eT, 0, Ep);
@@ -638,7 +693,7 @@ __device__ void overlap_split(const GramJobDev &J, int64_t ia, int64_t ib, uint8
         s_ov[1] = Ep[0][1][0];
       }
     } else {
-      const int er = exp_above(fmax(s_mx[(0 * 2 + 0) * kSP + col], s_mx[(0 * 2 + 1) * kSP + col]));
+      const int er = exp_above_w(fmax(s_mx[(0 * 2 + 0) * kSP + col], s_mx[(0 * 2 + 1) * kSP + col]));
       split_store(C, Y, C.cb, Ep, er);
       if (C.hf == 0 && C.g == 0) s_ea[col] = er;
     }
@@ -732,30 +787,9 @@ __device__ inline void tile_fence(double (&v)[2][4]) {
     for (int e = 0; e < 4; ++e) asm volatile("" : "+v"(v[q][e])::"memory");
 }
 
-// A pointer that is the same in every lane, moved to scalar registers.
-template <typename T>
-__device__ inline T *uniform_ptr(T *p) {
-  const uint64_t v = reinterpret_cast<uint64_t>(p);
-  return reinterpret_cast<T *>((uint64_t(__builtin_amdgcn_readfirstlane(uint32_t(v >> 32))) << 32) |
-                               uint32_t(__builtin_amdgcn_readfirstlane(uint32_t(v))));
-}
-
-// Fragments are read with buffer loads through a descriptor of the whole
-// site block (scalar base, 32-bit lane offset, scalar fragment offset): no
-// 64-bit vector address arithmetic per fragment, and a read outside the
-// block's bytes returns zero.  Word 3 is the gfx9-family raw-buffer format.
-typedef __amdgpu_buffer_rsrc_t SiteRsrc;
-__device__ inline SiteRsrc site_rsrc(const uint8_t *site) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t *>(uniform_ptr(site)), 0, int(kI8SiteBytes),
-                                           0x00020000);
-}
-
 // Fragment (s, slice k, plane q, column block ct) of a packed int8 site block.
 __device__ inline uint4 i8_frag(SiteRsrc site, int s, int k, int q, int ct, int lane) {
-  const int frag = kI8ExpBytes + kI8SumBytes + (((s * 4 + k) * 2 + q) * 4 + ct) * kI8FragBytes;
-  typedef unsigned int v4u __attribute__((ext_vector_type(4)));
-  const v4u v = __builtin_amdgcn_raw_buffer_load_b128(site, lane * 16, frag, 0);
-  return make_uint4(v.x, v.y, v.z, v.w);
+  return rsrc_load_u4(site, lane * 16, kI8ExpBytes + kI8SumBytes + (((s * 4 + k) * 2 + q) * 4 + ct) * kI8FragBytes);
 }
 
 // Class accumulators of one complex 16 x 16 tile: class c holds the digit
@@ -853,7 +887,7 @@ struct I8Operand {
 };
 
 __device__ inline void i8_load(const I8Ctx &C, const uint8_t *site, int s, I8Operand &o) {
-  const SiteRsrc r = site_rsrc(site);
+  const SiteRsrc r = site_rsrc<kI8SiteBytes>(site);
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     o.f[k] = i8_frag(r, s, k, 0, C.cb, C.lane);

@@ -51,7 +51,7 @@ constexpr int kSplitExpBytes = 256;
 // Every site of the split form is a 64 x 64 block (zero beyond the batch's
 // pads); batches with pads above 64 have no split form.
 constexpr int kSplitMaxPad = 64;
-inline int64_t split_site_bytes() {
+constexpr int64_t split_site_bytes() {
   return kSplitExpBytes + int64_t(2) * kSlices * 2 * (kSplitMaxPad / 32) * (kSplitMaxPad / 16) * kFragBytes;
 }
 

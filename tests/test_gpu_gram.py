@@ -157,7 +157,7 @@ def test_split_values_at_top_of_exponent_range(prec):
 def test_autotune_keeps_results_and_uses_choice(small_sets):
     """The autotuner times every configuration (block size 32 / 64 for the
     plain forms when the pads allow, pair-tile side, queues) and stores the
-    fastest; Gram results afterwards are bit-identical to the defaults (the
+    fastest if it beats the default by more than 2 %; Gram results afterwards are bit-identical to the defaults (the
     configuration changes scheduling, not arithmetic)."""
     import paper_2411_09336_amd as q
     torch = require_gpu()
@@ -171,6 +171,10 @@ def test_autotune_keeps_results_and_uses_choice(small_sets):
             assert rep["n_candidates"] == ncand
             assert rep["maxp"] in (32, 64) and rep["tile_side"] in (8, 16, 32) and rep["queues"] in (1, 8)
             assert rep["best_ms"] <= rep["default_ms"]
+            default = (64, 16, 8 if prec == "split_i8" else 1)
+            if (rep["maxp"], rep["tile_side"], rep["queues"]) != default:
+                # a configuration replaces the default only when clearly faster
+                assert rep["best_ms"] < 0.98 * rep["default_ms"]
             k1 = q.gram(b, precision=prec)
             assert torch.equal(k0, k1)
     finally:
