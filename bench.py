@@ -117,7 +117,7 @@ def counter_traffic(form, config):
     return data.get("traffic_bytes_per_launch"), data
 
 
-def write_counter_record(form, fetch_csv, write_csv, fetch_scale, write_scale, command, config):
+def write_counter_record(form, fetch_csv, write_csv, fetch_scale, write_scale, command, config, steps=20):
     """Record of the FETCH_SIZE / WRITE_SIZE runs of one timed launch (the
     first dispatch of the form's kernel after the warmup-free partial run),
     scaled to bytes by the copy-kernel factors."""
@@ -146,8 +146,8 @@ def write_counter_record(form, fetch_csv, write_csv, fetch_scale, write_scale, c
            "fetch_bytes_per_counted_kib": fetch_scale, "write_bytes_per_counted_kib": write_scale,
            "traffic_bytes_per_launch": fetch_b + write_b,
            "slab_seconds_in_counter_runs": [fetch_s, write_s],
-           "note": "HBM bytes of one timed slab launch (rows 0..r1 of 8 equal-work slabs of the 6400 x 6400 "
-                   "Gram): FETCH_SIZE and WRITE_SIZE in separate runs, scaled by a plain copy kernel",
+           "note": f"HBM bytes of one timed slab launch (the first of {steps} equal-work row slabs of the 6400 x "
+                   "6400 Gram): FETCH_SIZE and WRITE_SIZE in separate runs, scaled by a plain copy kernel",
            "command": command}
     with open(counter_record_path(form), "w") as f:
         json.dump(rec, f, indent=1)
@@ -305,6 +305,13 @@ def main():
                     help="kernel configuration of the counter runs (as reported by their autotune line)")
     ap.add_argument("--counter-scale", nargs=2, type=float, default=(2047.93, 1024.0),
                     metavar=("FETCH", "WRITE"), help="bytes per counted KiB (plain copy kernel)")
+    ap.add_argument("--config", choices=("fp32", "precision"), default=None,
+                    help="only run a precision configuration at its stated size and print one JSON line: 'fp32' "
+                         "(50 qubits, 512 points, d=2, chi=32) or 'precision' (100 qubits, 2048 points, d=4, "
+                         "chi=64): every point simulated on the GPU, the full symmetric Gram in every form, "
+                         "|dK| against FP64 over all entries and against the oracle on the first 256 points")
+    ap.add_argument("--oracle-gram", metavar="MPS_NPY", default=None,
+                    help=argparse.SUPPRESS)   # child process of --config: the oracle's Gram of a file of MPS
     ap.add_argument("--routing", type=int, default=1,
                     help="0: 2(k-1) SWAPs per Rxx (paper); 1: cancelled inverse SWAP pairs (same circuit)")
     args = ap.parse_args()
@@ -320,9 +327,13 @@ def main():
                              f"rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) --output-format csv -- python3 "
                              f"bench.py --form {args.form} --steps {args.steps} --steps-run 1 --no-cpu "
                              f"--warmup 0",
-                             {k: int(v) for k, v in (kv.split("=") for kv in args.counter_config.split(","))})
+                             {k: int(v) for k, v in (kv.split("=") for kv in args.counter_config.split(","))},
+                             args.steps)
         return
-    default_run = not (args.calibrate_copy or args.kernel_probe or args.d_sweep or args.svm)
+    default_run = not (args.calibrate_copy or args.kernel_probe or args.d_sweep or args.svm or args.config)
+    if args.oracle_gram:
+        oracle_gram_file(args.oracle_gram, args.cpu_workers)
+        return
     cpu = None
     if default_run and not args.no_cpu and args.steps_run == 0:
         # forked before any GPU call: the workers hold no GPU state
@@ -345,6 +356,9 @@ def main():
         return
     if args.svm:
         svm_auc(args.routing)
+        return
+    if args.config:
+        config_mode(args.config, args)
         return
     run(args, cpu)
 
@@ -629,6 +643,182 @@ def run_extras(q, sd, w, spec, sim, gb, form, S, N, stream, routing):
         log(f"[bench] memory trace {name}: {memtrace[name]}")
     out["memory_trace"] = memtrace
     return out
+
+
+def _oracle_rows(task):
+    """One row block of the oracle's Gram: overlaps of MPS i (rows) with MPS
+    j >= i, whose site tensors are read from a memory-mapped file (one flat
+    complex128 array, offsets per site), one BLAS thread."""
+    rows, path, meta = task
+    try:
+        import threadpoolctl
+        threadpoolctl.threadpool_limits(1)
+    except Exception:
+        pass
+    import numpy as np
+    from oracle import gram as ogram
+    buf = np.load(path, mmap_mode="r")
+    mps = [[np.asarray(buf[o:o + int(np.prod(sh))]).reshape(sh) for (o, sh) in sites] for sites in meta]
+    return [(i, j, abs(ogram.overlap(mps[i], mps[j])) ** 2) for i in rows for j in range(i, len(mps))]
+
+
+def write_mps_file(mps, path):
+    """All site tensors of `mps` in one flat complex128 .npy file; returns the
+    per-MPS lists of (offset, shape)."""
+    import numpy as np
+    meta, off = [], 0
+    for m_ in mps:
+        sites = []
+        for t in m_:
+            sites.append((off, t.shape))
+            off += t.size
+        meta.append(sites)
+    buf = np.lib.format.open_memmap(path, mode="w+", dtype=np.complex128, shape=(max(off, 1),))
+    for m_, sites in zip(mps, meta):
+        for t, (o, _) in zip(m_, sites):
+            buf[o:o + t.size] = t.ravel()
+    buf.flush()
+    del buf
+    return meta
+
+
+def oracle_gram_file(path, workers=0):
+    """The oracle's symmetric Gram of the MPS in `path` (write_mps_file;
+    offsets in path + '.json'), in a process pool on the host cores, progress
+    on stderr; K goes to path + '.K.npy'.  Run as a child process of a GPU
+    run, so its workers are forked from a process that never touched the GPU."""
+    import multiprocessing as mp
+
+    import numpy as np
+    meta = json.load(open(path + ".json"))
+    S = len(meta)
+    nw = workers or max(1, min(16, host_cpu_description()["available"] or 1))
+    blocks = [b for b in (list(range(k, S, 4 * nw)) for k in range(4 * nw)) if b]
+    K = np.zeros((S, S))
+    t0 = t_log = time.perf_counter()
+    with mp.get_context("fork").Pool(nw) as pool:
+        for n, part in enumerate(pool.imap_unordered(_oracle_rows, [(b, path, meta) for b in blocks]), 1):
+            for i, j, v in part:
+                K[i, j] = K[j, i] = v
+            if time.perf_counter() - t_log > 15 or n == len(blocks):
+                t_log = time.perf_counter()
+                log(f"[bench] oracle: {n}/{len(blocks)} row blocks, {t_log - t0:.0f} s ({nw} workers)")
+    np.save(path + ".K.npy", K)
+
+
+def config_mode(name, args):
+    """A precision configuration at its stated size (Sec. III; the paper's
+    SWAP routing, Sec. II-C): every point simulated on the GPU, the full
+    symmetric Gram in FP64, FP32, split-BF16 and split-int8 (each timed with
+    HIP events), |dK| of every form against FP64 over all N (N + 1) / 2
+    entries, and against the oracle's overlaps of the same exported MPS on
+    the first 256 points (32,896 entries), computed in a process pool on the
+    host cores; 16 near-duplicates of the first points give mid-range K."""
+    import numpy as np
+    import torch
+
+    import paper_2411_09336_amd as q
+    import synthdata as sd
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    w = sd.WORKLOADS[name]
+    N, S, D = w.n_points, min(256, w.n_points), 16
+    X = sd.workload_features(w)
+    routing = 0
+    spec = q.CircuitSpec(w.n_qubits, w.distance, w.reps, w.coef_z, w.coef_xx, routing)
+    xs = torch.tensor(np.vstack([X, sd.perturb_near_duplicates(X[:D])]), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    t_last = [t0]
+
+    def progress(done, total):
+        if time.perf_counter() - t_last[0] > 20 or done == total:
+            t_last[0] = time.perf_counter()
+            log(f"[bench] {name}: simulation {done}/{total} two-qubit gates, {t_last[0] - t0:.0f} s")
+        return False
+
+    sim = q.simulate(xs, spec, w.chi, w.cutoff, progress=progress, every=500)
+    torch.cuda.synchronize()
+    t_sim = time.perf_counter() - t0
+    info = sim.info()
+    log(f"[bench] {name}: {N + D} circuits in {t_sim:.1f} s, max bond {info['max_bond']}")
+    gb = sim.gather(list(range(N)), forms=("fp64",), stream=stream)
+    forms = ("fp64", "fp32", "split_bf16", "split_i8")
+    K, t_form = {}, {}
+    for f in forms:
+        gb.pack(f)
+        q.gram_block(gb, 0, 8, gb, 0, N, precision=f, upper_only=True, stream=stream)   # warm-up
+        stream.synchronize()
+        e0, e1 = _events()
+        e0.record(stream)
+        Kf = q.gram(gb, precision=f, stream=stream)
+        e1.record(stream)
+        e1.synchronize()
+        K[f], t_form[f] = Kf, e0.elapsed_time(e1) / 1e3
+        log(f"[bench] {name}: {f} Gram {N}x{N} in {t_form[f]:.2f} s")
+        if f != "fp64":
+            gb.drop(f)
+    upper = torch.ones((N, N), dtype=torch.bool, device="cuda").triu_()
+    n_comp = N * (N + 1) // 2
+    n_off = N * (N - 1) // 2
+    out = {f: {"seconds": round(t_form[f], 3), "entries_per_s": round(n_off / t_form[f], 1)} for f in forms}
+    for f in forms[1:]:
+        d = (K[f] - K["fp64"]).abs()[upper]
+        out[f].update(dK_vs_fp64_max=float(d.max().item()), dK_vs_fp64_mean=float(d.mean().item()))
+    # near-duplicate block (rows: first D points, columns: their near-duplicates)
+    nd = {}
+    for f in forms:
+        Kn = q.gram_block(sim, 0, D, sim, N, D, precision=f, stream=stream).diagonal()
+        nd[f] = Kn
+    for f in forms[1:]:
+        out[f]["near_dup_dK_vs_fp64_max"] = float((nd[f] - nd["fp64"]).abs().max().item())
+    # the oracle's overlaps of the same MPS on the first S points, in a
+    # child process (its own pool on the host cores)
+    oracle = None
+    if not args.no_cpu:
+        import shutil
+        import subprocess
+        import tempfile
+        tmp = tempfile.mkdtemp(prefix="qk_oracle_")
+        path = os.path.join(tmp, "mps.npy")
+        try:
+            log(f"[bench] {name}: exporting {S} MPS for the oracle")
+            meta = write_mps_file([sim.export(i) for i in range(S)], path)
+            json.dump(meta, open(path + ".json", "w"))
+            t1 = time.perf_counter()
+            cmd = [sys.executable, os.path.abspath(__file__), "--oracle-gram", path,
+                   "--cpu-workers", str(args.cpu_workers)]
+            rc = subprocess.run(cmd, timeout=900).returncode
+            t_or = time.perf_counter() - t1
+            if rc == 0:
+                Ko = np.load(path + ".K.npy")
+                iu = np.triu_indices(S)
+                for f in forms:
+                    d = np.abs(K[f][:S, :S].cpu().numpy() - Ko)[iu]
+                    out[f].update(dK_vs_oracle_max=float(d.max()), dK_vs_oracle_mean=float(d.mean()))
+                host = host_cpu_description()
+                oracle = {"points": S, "entries": S * (S + 1) // 2, "seconds": round(t_or, 2),
+                          "workers": args.cpu_workers or max(1, min(16, host["available"] or 1)),
+                          "nproc": host["nproc"], "cpu_model": host["model"],
+                          "entries_per_s": round(S * (S + 1) / 2 / t_or, 1)}
+                log(f"[bench] {name}: oracle {oracle}")
+            else:
+                log(f"[bench] {name}: oracle child process ended with {rc}")
+        finally:
+            shutil.rmtree(tmp, ignore_errors=True)
+    Kh = K["fp64"].cpu().numpy()
+    offd = Kh[~np.eye(N, dtype=bool)]
+    print(json.dumps({
+        "config": name, "workload": f"{N} points x {w.n_qubits} qubits, d={w.distance}, reps={w.reps}, "
+                                    f"chi={w.chi}, cutoff={w.cutoff}, routing {routing} (2(k-1) SWAPs per Rxx)",
+        "entries_offdiag": n_off, "entries_compared": n_comp, "forms": out, "oracle": oracle,
+        "simulation": {"circuits": N + D, "seconds": round(t_sim, 2), "max_bond": info["max_bond"],
+                       "unconverged_svds": info["unconverged_svds"], "degenerate_cuts": info["degenerate_cuts"],
+                       "two_qubit_gates_per_circuit": info["n_two_qubit_gates"]},
+        "K_distribution": {"offdiag_median": float(np.median(offd)), "offdiag_max": float(offd.max()),
+                           "near_duplicates": [float(nd["fp64"].min().item()), float(nd["fp64"].max().item())],
+                           "hist_edges_log10": list(K_HIST_EDGES), "hist_offdiag": k_histogram(offd)},
+        "data": "synthetic"}), flush=True)
 
 
 def run(args, cpu):

@@ -43,3 +43,45 @@ def test_more_than_one_gpu_is_refused():
                        cwd=bench.ROOT, timeout=120)
     assert r.returncode != 0
     assert "one GPU" in (r.stdout + r.stderr)
+
+
+def test_oracle_rows_from_mapped_file_match_the_oracle_gram(tmp_path):
+    """The configuration modes hand the oracle's workers the MPS through one
+    memory-mapped file (offsets per site); the assembled upper triangle must
+    be the oracle's own Gram of the same MPS."""
+    import multiprocessing as mp
+
+    import numpy as np
+
+    from oracle import gram as ogram
+    from tests import emulate_forms as ef
+    rng = np.random.default_rng(0)
+    mps = [ef.random_left_canonical(12, 8, rng) for _ in range(7)]
+    path = str(tmp_path / "mps.npy")
+    meta = bench.write_mps_file(mps, path)
+    with mp.get_context("fork").Pool(3) as pool:
+        res = pool.map(bench._oracle_rows, [(list(range(k, 7, 3)), path, meta) for k in range(3)])
+    K = np.zeros((7, 7))
+    for part in res:
+        for i, j, v in part:
+            K[i, j] = K[j, i] = v
+    assert np.array_equal(K, ogram.gram(mps))
+
+
+def test_oracle_gram_child_process(tmp_path):
+    """bench.py --oracle-gram (the configuration modes' oracle leg, run as a
+    child process of the GPU run): the K it writes is the oracle's Gram."""
+    import json
+
+    import numpy as np
+
+    from oracle import gram as ogram
+    from tests import emulate_forms as ef
+    rng = np.random.default_rng(1)
+    mps = [ef.random_left_canonical(16, 8, rng) for _ in range(9)]
+    path = str(tmp_path / "mps.npy")
+    json.dump(bench.write_mps_file(mps, path), open(path + ".json", "w"))
+    r = subprocess.run([sys.executable, bench.__file__, "--oracle-gram", path, "--cpu-workers", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    assert np.array_equal(np.load(path + ".K.npy"), ogram.gram(mps))
