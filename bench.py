@@ -305,15 +305,18 @@ def main():
                     help="kernel configuration of the counter runs (as reported by their autotune line)")
     ap.add_argument("--counter-scale", nargs=2, type=float, default=(2047.93, 1024.0),
                     metavar=("FETCH", "WRITE"), help="bytes per counted KiB (plain copy kernel)")
-    ap.add_argument("--config", choices=("fp32", "precision"), default=None,
+    ap.add_argument("--config", choices=("fp32", "precision", "uneven"), default=None,
                     help="only run a precision configuration at its stated size and print one JSON line: 'fp32' "
                          "(50 qubits, 512 points, d=2, chi=32) or 'precision' (100 qubits, 2048 points, d=4, "
                          "chi=64): every point simulated on the GPU, the full symmetric Gram in every form, "
-                         "|dK| against FP64 over all entries and against the oracle on the first 256 points")
+                         "|dK| against FP64 over all entries and against the oracle on the first 256 points; "
+                         "'uneven' (four instances of 20, 60, 110, 165 qubits, 1600 train + 400 test points "
+                         "each, all Gram jobs in one launch)")
     ap.add_argument("--oracle-gram", metavar="MPS_NPY", default=None,
                     help=argparse.SUPPRESS)   # child process of --config: the oracle's Gram of a file of MPS
-    ap.add_argument("--routing", type=int, default=1,
-                    help="0: 2(k-1) SWAPs per Rxx (paper); 1: cancelled inverse SWAP pairs (same circuit)")
+    ap.add_argument("--routing", type=int, default=0,
+                    help="0: 2(k-1) SWAPs per Rxx (the paper's routing, Sec. II-C); 1: back-to-back inverse SWAP "
+                         "pairs cancelled (the same circuit, 2.9x fewer two-qubit gates at d = 8)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -356,6 +359,9 @@ def main():
         return
     if args.svm:
         svm_auc(args.routing)
+        return
+    if args.config == "uneven":
+        config_uneven(args)
         return
     if args.config:
         config_mode(args.config, args)
@@ -821,6 +827,133 @@ def config_mode(name, args):
         "data": "synthetic"}), flush=True)
 
 
+def _oracle_child(mps, workers, name):
+    """The oracle's symmetric Gram of `mps` computed by a child process
+    (bench.py --oracle-gram), or None if it fails."""
+    import shutil
+    import subprocess
+    import tempfile
+
+    import numpy as np
+    tmp = tempfile.mkdtemp(prefix="qk_oracle_")
+    path = os.path.join(tmp, "mps.npy")
+    try:
+        json.dump(write_mps_file(mps, path), open(path + ".json", "w"))
+        cmd = [sys.executable, os.path.abspath(__file__), "--oracle-gram", path, "--cpu-workers", str(workers)]
+        rc = subprocess.run(cmd, timeout=900).returncode
+        if rc != 0:
+            log(f"[bench] {name}: oracle child process ended with {rc}")
+            return None
+        return np.load(path + ".K.npy")
+    finally:
+        shutil.rmtree(tmp, ignore_errors=True)
+
+
+def config_uneven(args):
+    """The uneven batch (Sec. II-D batching): four instances with qubit
+    counts 20, 60, 110 and 165, interaction distances 1, 3, 5, 8 and bond caps
+    16, 32, 64, 128; 2000 points each (the first 1600 train, the last 400
+    test).  Each instance is simulated with its launches recorded as HIP
+    graphs (one graph per 500 two-qubit gates); the Gram kernels are
+    autotuned per bond-pad bucket and form; then, per form, ONE persistent
+    launch computes every instance's 400 x 1600 test x train block and its
+    symmetric 1600 x 1600 train Gram.  |dK| of each form against FP64 over
+    all entries, and of every form against the oracle's overlaps of 48 train
+    and 16 test MPS per instance (a child process on the host cores).  The
+    bond-128 instance is outside the kernels' range (QK_ENOTSUP) and is
+    reported as such."""
+    import numpy as np
+    import torch
+
+    import paper_2411_09336_amd as q
+    import synthdata as sd
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    forms = ("fp64", "split_bf16", "split_i8")
+    inst, report = {}, {}
+    for name in ("uneven_20", "uneven_60", "uneven_110", "uneven_165"):
+        w = sd.WORKLOADS[name]
+        N, ntr = w.n_points, w.n_points - w.n_test
+        X = sd.workload_features(w)
+        spec = q.CircuitSpec(w.n_qubits, w.distance, w.reps, w.coef_z, w.coef_xx, 0)
+        xt = torch.tensor(X, dtype=torch.float64, device="cuda")
+        log(f"[bench] uneven: simulating {name}: {N} circuits, {w.n_qubits} qubits, d={w.distance}, chi={w.chi}")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        try:
+            b = q.simulate(xt, spec, w.chi, w.cutoff, stream=stream, graph_gates=500)
+        except q.QKError as e:
+            report[name] = {"status": "not supported", "error": str(e)}
+            log(f"[bench] uneven: {name}: {e}")
+            continue
+        stream.synchronize()
+        t_sim = time.perf_counter() - t0
+        info = b.info()
+        for f in forms:
+            b.pack(f, stream=stream)
+        train = b.gather(list(range(ntr)), forms=forms, stream=stream)
+        test = b.gather(list(range(ntr, N)), forms=forms, stream=stream)
+        inst[name] = (w, b, train, test, ntr, N - ntr)
+        report[name] = {"status": "ok", "n_qubits": w.n_qubits, "distance": w.distance, "chi": w.chi,
+                        "train": ntr, "test": N - ntr, "simulation_s": round(t_sim, 2),
+                        "two_qubit_gates_per_circuit": info["n_two_qubit_gates"], "max_bond": info["max_bond"],
+                        "degenerate_cuts": info["degenerate_cuts"], "unconverged_svds": info["unconverged_svds"]}
+        log(f"[bench] uneven: {name}: simulated in {t_sim:.1f} s (HIP graphs), max bond {info['max_bond']}")
+    # kernel configurations per form and bond-pad bucket (pads <= 32, <= 64)
+    tuned = {}
+    for f in forms:
+        for name, (w, b, train, test, ntr, nte) in inst.items():
+            tuned[f"{f}/{name}"] = q.autotune(train, precision=f, sample=64, stream=stream)
+    log(f"[bench] uneven: autotuned {len(tuned)} (form, instance) samples")
+    K, launch = {}, {}
+    for f in forms:
+        jobs, outs = [], {}
+        for name, (w, b, train, test, ntr, nte) in inst.items():
+            kr = torch.zeros((nte, ntr), dtype=torch.float64, device="cuda")
+            kt = torch.zeros((ntr, ntr), dtype=torch.float64, device="cuda")
+            outs[name] = (kr, kt)
+            jobs.append(dict(a=test, b=train, na=nte, nb=ntr, out=kr))
+            jobs.append(dict(a=train, b=train, na=ntr, nb=ntr, upper_only=True, out=kt))
+        st = {}
+        q.gram_multi(jobs, precision=f, stream=stream, stats=st)
+        stream.synchronize()
+        K[f] = outs
+        launch[f] = {"jobs": len(jobs), "entries": int(st["entries"]), "kernel_s": round(st["kernel_ms"] / 1e3, 3),
+                     "entries_per_s": round(st["entries"] / (st["kernel_ms"] / 1e3), 1),
+                     "tflops_algorithmic": round(st["flops"] / (st["kernel_ms"] / 1e3) / 1e12, 2)}
+        log(f"[bench] uneven: {f}: one launch, {len(jobs)} jobs, {launch[f]}")
+    for name, (w, b, train, test, ntr, nte) in inst.items():
+        r = report[name]
+        kr0, kt0 = K["fp64"][name]
+        up = torch.ones_like(kt0, dtype=torch.bool).triu_()
+        for f in forms[1:]:
+            kr, kt = K[f][name]
+            d = torch.cat([(kr - kr0).abs().flatten(), (kt - kt0).abs()[up]])
+            r[f"{f}_dK_vs_fp64_max"] = float(d.max().item())
+            r[f"{f}_dK_vs_fp64_mean"] = float(d.mean().item())
+        offd = kt0.cpu().numpy()[~np.eye(ntr, dtype=bool)]
+        r["K_offdiag_median"], r["K_offdiag_max"] = float(np.median(offd)), float(offd.max())
+        r["K_test_train_max"] = float(kr0.max().item())
+        if not args.no_cpu:
+            sel_tr, sel_te = list(range(48)), list(range(ntr, ntr + 16))
+            Ko = _oracle_child([b.export(i) for i in sel_tr + sel_te], args.cpu_workers, name)
+            if Ko is not None:
+                for f in forms:
+                    kr, kt = K[f][name]
+                    ktr = kt[:48, :48].cpu().numpy()
+                    kte = kr[:16, :48].cpu().numpy()
+                    iu = np.triu_indices(48)
+                    d = np.concatenate([np.abs(ktr - Ko[:48, :48])[iu], np.abs(kte - Ko[48:, :48]).ravel()])
+                    r[f"{f}_dK_vs_oracle_max"] = float(d.max())
+                r["oracle_entries"] = int(48 * 49 // 2 + 16 * 48)
+        log(f"[bench] uneven: {name}: {r}")
+    print(json.dumps({"config": "uneven", "instances": report, "launch_per_form": launch,
+                      "autotune": tuned, "forms": list(forms),
+                      "workload": "4 instances (m, d, chi) = (20,1,16), (60,3,32), (110,5,64), (165,8,128); "
+                                  "2000 points each (1600 train + 400 test), reps 2, cutoff 1e-10, routing 0",
+                      "data": "synthetic"}), flush=True)
+
+
 def run(args, cpu):
     import numpy as np
     import torch
@@ -941,7 +1074,7 @@ def run(args, cpu):
         e1.synchronize()
         Kblk[f], t_blk[f] = out, e0.elapsed_time(e1) / 1e3
         log(f"[bench] block K[0:{S}, 0:{C}] in {f}: {t_blk[f]:.3f} s ({S * C / t_blk[f]:.1f} entries/s)")
-    del gc
+    del gc, col_batch          # the comparison batches (the dict holds them too)
     speedup = t_blk["fp64"] / t_blk[form]
     ii = torch.as_tensor(idx, device="cuda")
     upper = torch.ones((N, N), dtype=torch.bool, device="cuda").triu_()
@@ -989,6 +1122,34 @@ def run(args, cpu):
     if args.extras:
         extras = run_extras(q, sd, w, spec, sim, gb, form, S, N, stream, args.routing)
 
+    # FP64 on the first timed slab of the full matrix (the timed form's first
+    # launch, same rows, columns and tiles): the speedup at full size.  The
+    # split batch goes first: both 6400-MPS batches do not fit in HBM at once.
+    fp64_slab = None
+    if process_age() < SOFT_BUDGET_S:
+        del gb
+        torch.cuda.synchronize()
+        gd = sim.gather(idx, forms=("fp64",), stream=stream)
+        r0, r1 = slabs[0], slabs[1]
+        Kd = torch.zeros((r1 - r0, N - r0), dtype=torch.float64, device="cuda")
+        e0, e1 = _events()
+        e0.record(stream)
+        q.gram_block(gd, r0, r1 - r0, gd, r0, N - r0, precision="fp64", upper_only=True, out=Kd, stream=stream)
+        e1.record(stream)
+        e1.synchronize()
+        t_fd = e0.elapsed_time(e1) / 1e3
+        n_slab = sum(N - r for r in range(r0, r1))
+        up = torch.ones_like(Kd, dtype=torch.bool).triu_()
+        d_slab = float((K[r0:r1, r0:] - Kd).abs()[up].max().item())
+        fp64_slab = {"rows": [r0, r1], "entries": n_slab, "seconds": round(t_fd, 3),
+                     "entries_per_s": round(n_slab / t_fd, 2), "speedup_of_form": round(t_fd / launch_s[0], 3),
+                     "form_slab_seconds": round(launch_s[0], 3), "dK_vs_form_max": d_slab}
+        log(f"[bench] FP64 on the first timed slab (rows {r0}:{r1}, {n_slab} entries): {t_fd:.2f} s -> "
+            f"{n_slab / t_fd:.1f} entries/s; {form} {t_fd / launch_s[0]:.2f}x faster; max|dK| {d_slab:.2e}")
+        del gd, Kd, up
+    else:
+        skipped.append("FP64 on the first full-size slab (time budget)")
+
     # ---------------------------------------------------------------- roofline of the timed kernel
     fpe = flops_per_entry(dims[0], dims[0])
     entries_run = sum(N - r for r in range(slabs[0], slabs[nrun]))
@@ -1035,7 +1196,8 @@ def run(args, cpu):
         "gram_seconds": round(t_gram, 3),
         "fp64_gpu": {"entries_per_s": round(S * C / t_blk["fp64"], 2), "speedup_of_form": round(speedup, 3),
                      "measured_on": f"block K[0:{S}, 0:{C}] of the full matrix ({S * C} entries), "
-                                    f"the same work in every form"},
+                                    f"the same work in every form",
+                     "full_size_slab": fp64_slab},
         "forms_on_same_work": {
             f: {"entries_per_s": round(S * C / t_blk[f], 2), "speedup_vs_fp64": round(t_blk["fp64"] / t_blk[f], 3),
                 "dK_vs_fp64_max": float((Kblk[f] - Kblk["fp64"]).abs().max().item()),
