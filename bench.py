@@ -853,8 +853,9 @@ def config_uneven(args):
     """The uneven batch (Sec. II-D batching): four instances with qubit
     counts 20, 60, 110 and 165, interaction distances 1, 3, 5, 8 and bond caps
     16, 32, 64, 128; 2000 points each (the first 1600 train, the last 400
-    test).  Each instance is simulated with its launches recorded as HIP
-    graphs (one graph per 500 two-qubit gates); the Gram kernels are
+    test).  Each instance is simulated by one HIP graph that records a
+    chunk of circuits from start to end, replayed over the batch (two
+    replays of 1000 circuits); the Gram kernels are
     autotuned per bond-pad bucket and form; then, per form, ONE persistent
     launch computes every instance's 400 x 1600 test x train block and its
     symmetric 1600 x 1600 train Gram.  |dK| of each form against FP64 over
@@ -881,7 +882,7 @@ def config_uneven(args):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         try:
-            b = q.simulate(xt, spec, w.chi, w.cutoff, stream=stream, graph_gates=500)
+            b = q.simulate(xt, spec, w.chi, w.cutoff, stream=stream, graph_circuits=0)
         except q.QKError as e:
             report[name] = {"status": "not supported", "error": str(e)}
             log(f"[bench] uneven: {name}: {e}")
@@ -898,7 +899,7 @@ def config_uneven(args):
                         "train": ntr, "test": N - ntr, "simulation_s": round(t_sim, 2),
                         "two_qubit_gates_per_circuit": info["n_two_qubit_gates"], "max_bond": info["max_bond"],
                         "degenerate_cuts": info["degenerate_cuts"], "unconverged_svds": info["unconverged_svds"]}
-        log(f"[bench] uneven: {name}: simulated in {t_sim:.1f} s (HIP graphs), max bond {info['max_bond']}")
+        log(f"[bench] uneven: {name}: simulated in {t_sim:.1f} s (HIP graph replays), max bond {info['max_bond']}")
     # kernel configurations per form and bond-pad bucket (pads <= 32, <= 64)
     tuned = {}
     for f in forms:

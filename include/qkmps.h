@@ -213,18 +213,25 @@ qk_status mps_simulate_trace(const double *features_dev, int64_t n_points,
                              double cutoff, int32_t *trace_dev,
                              void *hip_stream, qk_mps_batch **out);
 
-/* mps_simulate with the kernel launches recorded as HIP graphs: the launches
- * of every `gates_per_graph` two-qubit gates (0: the whole circuit) are
- * captured on a private stream, instantiated and launched as one graph,
- * ordered after earlier work on hip_stream and before later work on it.  Each
- * circuit goes through the same steps with the same kernels as in
- * mps_simulate (only the launch boundaries differ), so the batch is
- * bit-identical.  Removes per-launch host overhead for circuits whose steps
- * are short; returns QK_EDEVICE if capture or instantiation fails.  The call
- * returns after the simulation has finished. */
+/* mps_simulate with the simulation recorded once as a HIP graph and
+ * replayed over the batch in chunks of circuits.  The graph holds every
+ * launch that takes `circuits_per_graph` circuits from |+> through the whole
+ * circuit to the normalised final state (Sec. II-B: gates, truncated SVDs,
+ * centre moves); it is captured on a private stream, instantiated once and
+ * launched ceil(n_points / circuits_per_graph) times, each replay on the
+ * next chunk (the last one may be shorter), ordered after earlier work on
+ * hip_stream and before later work on it.  0 picks equal chunks of at most
+ * QK_GRAPH_CIRCUITS circuits.  Each circuit goes through the same steps with
+ * the same kernels as in mps_simulate, so the batch is bit-identical; the
+ * SVD scratch is sized for one chunk (512 KiB per circuit) instead of the
+ * whole batch, and the host launch work is that of one chunk whatever the
+ * batch size.  QK_EINVAL if circuits_per_graph < 0; QK_EDEVICE if capture,
+ * instantiation or a replay fails.  The call returns after the simulation
+ * has finished. */
+#define QK_GRAPH_CIRCUITS 1024
 qk_status mps_simulate_graph(const double *features_dev, int64_t n_points,
                              const qk_circuit_spec *spec, int32_t chi_max,
-                             double cutoff, int64_t gates_per_graph,
+                             double cutoff, int64_t circuits_per_graph,
                              void *hip_stream, qk_mps_batch **out);
 
 /* ---------------------------------------------------------------- Gram */

@@ -392,13 +392,13 @@ def import_batch(mps_list: Sequence[Sequence[np.ndarray]], stream=None) -> MPSBa
 
 
 def simulate(features, spec: CircuitSpec, chi: int, cutoff: float, stream=None, progress=None,
-             every: int = 0, graph_gates=None) -> MPSBatch:
+             every: int = 0, graph_circuits=None) -> MPSBatch:
     """Truncated MPS simulation of every row of ``features`` (a CUDA float64 tensor, n x m).
 
     ``progress(done, total)`` (optional) is called every ``every`` two-qubit
-    gates; returning True aborts.  ``graph_gates`` (not with ``progress``)
-    records the launches of that many two-qubit gates per HIP graph (0: one
-    graph for the whole circuit)."""
+    gates; returning True aborts.  ``graph_circuits`` (not with ``progress``)
+    records the simulation of that many circuits as one HIP graph and
+    replays it over the batch (0: equal chunks of at most 1024 circuits)."""
     import torch
     if not isinstance(features, torch.Tensor) or features.device.type != "cuda":
         raise TypeError("features must be a CUDA tensor")
@@ -407,11 +407,11 @@ def simulate(features, spec: CircuitSpec, chi: int, cutoff: float, stream=None, 
         raise ValueError("features must be n x n_qubits")
     cs = spec._c()
     h = C.c_void_p(0)
-    if graph_gates is not None:
+    if graph_circuits is not None:
         if progress is not None:
-            raise ValueError("progress callbacks are not available with graph capture")
+            raise ValueError("progress callbacks are not available with graph replay")
         _check(_load().mps_simulate_graph(C.c_void_p(x.data_ptr()), x.shape[0], C.byref(cs), int(chi),
-                                          float(cutoff), int(graph_gates), _stream_ptr(stream), C.byref(h)))
+                                          float(cutoff), int(graph_circuits), _stream_ptr(stream), C.byref(h)))
     elif progress is None:
         _check(_load().mps_simulate(C.c_void_p(x.data_ptr()), x.shape[0], C.byref(cs), int(chi), float(cutoff),
                                     _stream_ptr(stream), C.byref(h)))

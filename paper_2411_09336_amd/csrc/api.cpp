@@ -279,7 +279,7 @@ qk_status mps_simulate(const double *features_dev, int64_t n_points, const qk_ci
 
 static qk_status simulate_impl(const double *features_dev, int64_t n_points, const qk_circuit_spec *spec,
                                int32_t chi_max, double cutoff, void *hip_stream, qk_progress_fn fn, void *user,
-                               int64_t every, int64_t graph_gates, int32_t *trace_dev, qk_mps_batch **out);
+                               int64_t every, int64_t graph_circuits, int32_t *trace_dev, qk_mps_batch **out);
 
 qk_status mps_simulate_progress(const double *features_dev, int64_t n_points, const qk_circuit_spec *spec,
                                 int32_t chi_max, double cutoff, void *hip_stream, qk_progress_fn fn, void *user,
@@ -302,11 +302,17 @@ qk_status mps_simulate_trace(const double *features_dev, int64_t n_points, const
 }
 
 qk_status mps_simulate_graph(const double *features_dev, int64_t n_points, const qk_circuit_spec *spec,
-                             int32_t chi_max, double cutoff, int64_t gates_per_graph, void *hip_stream,
+                             int32_t chi_max, double cutoff, int64_t circuits_per_graph, void *hip_stream,
                              qk_mps_batch **out) {
-  if (gates_per_graph < 0) return fail(QK_EINVAL, "gates_per_graph < 0");
+  if (circuits_per_graph < 0) return fail(QK_EINVAL, "circuits_per_graph < 0");
+  int64_t c = circuits_per_graph;
+  if (c == 0 && n_points > 0) {
+    // the batch in equal replays of at most QK_GRAPH_CIRCUITS circuits
+    const int64_t r = (n_points + QK_GRAPH_CIRCUITS - 1) / QK_GRAPH_CIRCUITS;
+    c = (n_points + r - 1) / r;
+  }
   return simulate_impl(features_dev, n_points, spec, chi_max, cutoff, hip_stream, nullptr, nullptr, 0,
-                       gates_per_graph == 0 ? INT64_MAX : gates_per_graph, nullptr, out);
+                       std::max<int64_t>(c, 1), nullptr, out);
 }
 
 extern "C++" {
@@ -362,7 +368,7 @@ static qk_status shrink_to_bonds(qk_mps_batch **pb, hipStream_t stream) {
 
 static qk_status simulate_impl(const double *features_dev, int64_t n_points, const qk_circuit_spec *spec,
                                int32_t chi_max, double cutoff, void *hip_stream, qk_progress_fn fn, void *user,
-                               int64_t every, int64_t graph_gates, int32_t *trace_dev, qk_mps_batch **out) {
+                               int64_t every, int64_t graph_circuits, int32_t *trace_dev, qk_mps_batch **out) {
   if (!out) return fail(QK_EINVAL, "out is NULL");
   *out = nullptr;
   qk_status st = validate_spec(spec);
@@ -385,7 +391,7 @@ static qk_status simulate_impl(const double *features_dev, int64_t n_points, con
   st = batch_create(n_points, m, pad, stream, &b);
   if (st != QK_OK) return st;
   auto gates = compile_circuit(*spec);
-  st = run_simulation(b, features_dev, gates, *spec, chi_max, cutoff, stream, fn, user, every, graph_gates,
+  st = run_simulation(b, features_dev, gates, *spec, chi_max, cutoff, stream, fn, user, every, graph_circuits,
                       trace_dev);
   if (st == QK_OK) st = shrink_to_bonds(&b, stream);
   if (st != QK_OK) {

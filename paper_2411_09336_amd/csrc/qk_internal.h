@@ -197,7 +197,7 @@ qk_status run_simulation(qk_mps_batch *b, const double *features_dev,
                          const std::vector<qk_gate> &gates,
                          const qk_circuit_spec &spec, int chi, double cutoff,
                          hipStream_t stream, qk_progress_fn fn = nullptr,
-                         void *user = nullptr, int64_t every = 0, int64_t graph_gates = 0,
+                         void *user = nullptr, int64_t every = 0, int64_t graph_circuits = 0,
                          int32_t *trace = nullptr);
 
 std::vector<qk_gate> compile_circuit(const qk_circuit_spec &spec);

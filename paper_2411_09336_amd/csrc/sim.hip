@@ -80,7 +80,15 @@ struct SvParams {
   int64_t n;
   int32_t *trace;     // optional: per circuit and two-qubit gate (cut bond, sum_l D_l D_{l+1})
   int32_t trace_n2q;  // two-qubit gates per circuit (row length of the trace / 2)
+  const int64_t *base;  // graph replays: first circuit of the replay (nullptr: 0)
 };
+
+// Circuit of this workgroup: workgroup i of a launch simulates circuit
+// base + i, where base is read from device memory in a graph replay (each
+// replay advances it by the launch's grid) and is 0 otherwise.  The SVD
+// scratch slot is the workgroup index, so a graph needs scratch only for
+// the circuits of one replay.
+__device__ inline int64_t circuit_of(const int64_t *base) { return (base ? *base : 0) + blockIdx.x; }
 
 // DPP lane moves of a double.  Lanes without a source lane receive zero
 // (bound_ctrl), so no copy of the source is needed as the fallback value.
@@ -414,7 +422,7 @@ __device__ __attribute__((noinline)) void svd_step(const SvParams &P, const int6
   const int Pp = P.pad[p], Pm = P.pad[p + 1], Pn = P.pad[p + 2];
   double2 *Ap = P.f64 + ci * P.mps_stride + P.site_off[p];
   double2 *Aq = P.f64 + ci * P.mps_stride + P.site_off[p + 1];
-  double2 *S = P.scratch + ci * (2 * kSvMaxN * kSvMaxN);
+  double2 *S = P.scratch + int64_t(blockIdx.x) * (2 * kSvMaxN * kSvMaxN);
 
   double cg = 1.0, sg = 0.0;
   if (st.op == OP_RXX) {
@@ -809,7 +817,7 @@ __device__ inline void rz_run(const SvParams &P, int64_t ci, const qk_gate *recs
 // circuit to circuit).
 __global__ __launch_bounds__(kSvThreads) void sim_steps_kernel(SvParams P, const SimStep *steps, int s0, int s1,
                                                               const qk_gate *recs, double coef_z) {
-  const int64_t ci = blockIdx.x;
+  const int64_t ci = circuit_of(P.base);
   if (ci >= P.n) return;
   for (int s = s0; s < s1; ++s) {
     const SimStep st = steps[s];
@@ -835,8 +843,8 @@ __global__ __launch_bounds__(kSvThreads) void sim_steps_kernel(SvParams P, const
 }
 
 __global__ void init_plus_kernel(double2 *f64, int64_t mps_stride, const int64_t *site_off, const int32_t *pad,
-                                 int32_t *dims, int32_t m, int64_t n) {
-  const int64_t ci = blockIdx.x;
+                                 int32_t *dims, int32_t m, int64_t n, const int64_t *base) {
+  const int64_t ci = circuit_of(base);
   if (ci >= n) return;
   const double h = 0.70710678118654752440;
   for (int l = threadIdx.x; l <= m; l += blockDim.x) {
@@ -850,8 +858,8 @@ __global__ void init_plus_kernel(double2 *f64, int64_t mps_stride, const int64_t
 }
 
 __global__ void normalize_last_kernel(double2 *f64, int64_t mps_stride, const int64_t *site_off,
-                                      const int32_t *pad, int32_t m, int64_t n) {
-  const int64_t ci = blockIdx.x;
+                                      const int32_t *pad, int32_t m, int64_t n, const int64_t *base) {
+  const int64_t ci = circuit_of(base);
   if (ci >= n) return;
   __shared__ double s_red[256];
   double2 *A = f64 + ci * mps_stride + site_off[m - 1];
@@ -868,6 +876,11 @@ __global__ void normalize_last_kernel(double2 *f64, int64_t mps_stride, const in
   if (nrm <= 0.0) return;
   const double inv = 1.0 / sqrt(nrm);
   for (int e = threadIdx.x; e < cnt; e += blockDim.x) A[e] = make_double2(A[e].x * inv, A[e].y * inv);
+}
+
+// First circuit of the next graph replay (one thread).
+__global__ void set_base_kernel(int64_t *base, int64_t v, int64_t add) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *base = add ? *base + v : v;
 }
 
 }  // namespace
@@ -910,8 +923,8 @@ qk_status launch_repad_f64(const qk_mps_batch *src, qk_mps_batch *dst, hipStream
 }
 
 qk_status run_simulation(qk_mps_batch *b, const double *features_dev, const std::vector<qk_gate> &gates,
-                         const qk_circuit_spec &spec, int chi, double cutoff, hipStream_t stream_in, qk_progress_fn fn,
-                         void *user, int64_t every, int64_t graph_gates, int32_t *trace) {
+                         const qk_circuit_spec &spec, int chi, double cutoff, hipStream_t stream, qk_progress_fn fn,
+                         void *user, int64_t every, int64_t graph_circuits, int32_t *trace) {
   const int64_t n = b->n;
   const int m = b->m;
   int n2q = 0;
@@ -919,7 +932,7 @@ qk_status run_simulation(qk_mps_batch *b, const double *features_dev, const std:
   b->n_two_qubit_gates = n2q;
   if (n == 0) return QK_OK;
   if (n > 0x7fffffff) return fail(QK_EINVAL, "too many points for one launch");
-  hipStream_t stream = stream_in;
+  if (graph_circuits > 0 && fn) return fail(QK_EINVAL, "progress callbacks are not available with graph replay");
 
   // reject non-finite features before any launch
   {
@@ -930,91 +943,13 @@ qk_status run_simulation(qk_mps_batch *b, const double *features_dev, const std:
       if (!std::isfinite(v)) return fail(QK_EINVAL, "non-finite feature value");
   }
 
-  const DevAlloc al = allocator_for_current_device();
-  const size_t rec_bytes = sizeof(qk_gate) * std::max<size_t>(gates.size(), 1);
-  auto *recs_dev = static_cast<qk_gate *>(dev_alloc(al, rec_bytes, stream, true));
-  if (!recs_dev) return fail(QK_ENOMEM, "device allocation of the gate list failed");
-  auto *scratch = static_cast<double2 *>(
-      dev_alloc(al, sizeof(double2) * 2 * kSvMaxN * kSvMaxN * size_t(n), stream, true));
-  if (!scratch) {
-    dev_free(al, recs_dev, stream, true);
-    return fail(QK_ENOMEM, "device allocation of SVD scratch failed");
-  }
-  if (!gates.empty() &&
-      hipMemcpyAsync(recs_dev, gates.data(), sizeof(qk_gate) * gates.size(), hipMemcpyHostToDevice, stream) !=
-          hipSuccess) {
-    dev_free(al, scratch, stream, true);
-    dev_free(al, recs_dev, stream, true);
-    return fail(QK_EDEVICE, "copy of the gate list failed");
-  }
+  // Graph mode: one graph records the launches that simulate `grid` circuits
+  // from start to end and is replayed until every circuit is done; otherwise
+  // the launches cover the whole batch.
+  const bool graph = graph_circuits > 0;
+  const int64_t grid = graph ? std::min(n, graph_circuits) : n;
+  const int64_t replays = (n + grid - 1) / grid;
 
-  hipLaunchKernelGGL(init_plus_kernel, dim3(unsigned(n)), dim3(64), 0, stream, b->f64, b->mps_stride, b->site_off_dev,
-                     b->pad_dev, b->dims_dev, m, n);
-  QK_HIP_CHECK(hipGetLastError());
-
-  SvParams P{};
-  P.f64 = b->f64;
-  P.mps_stride = b->mps_stride;
-  P.site_off = b->site_off_dev;
-  P.pad = b->pad_dev;
-  P.dims = b->dims_dev;
-  P.m = m;
-  P.chi = chi;
-  P.gate_split = spec.gate_split;
-  P.coef_xx = spec.coef_xx;
-  P.cutoff = cutoff;
-  P.X = features_dev;
-  P.ldx = m;
-  P.scratch = scratch;
-  P.disc = b->disc_dev;
-  P.maxdisc = b->maxdisc_dev;
-  P.degen = b->degen_dev;
-  P.unconv = b->unconv_dev;
-  P.n = n;
-  P.trace = trace;
-  P.trace_n2q = n2q;
-
-
-  // HIP-graph mode: the launches of every `graph_gates` two-qubit gates are
-  // recorded by stream capture on a private stream (the caller's stream may
-  // be the legacy null stream, which cannot be captured), then instantiated
-  // and launched as one graph.  Events order the private stream after the
-  // caller's work and the caller's stream after the graphs.  The captured
-  // launches are exactly the eager ones, so results are bit-identical.
-  hipStream_t cap = nullptr;
-  hipEvent_t ev_in = nullptr, ev_out = nullptr;
-  bool capturing = false;
-  if (graph_gates > 0) {
-    QK_HIP_CHECK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
-    if (hipEventCreateWithFlags(&ev_in, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&ev_out, hipEventDisableTiming) != hipSuccess ||
-        hipEventRecord(ev_in, stream_in) != hipSuccess || hipStreamWaitEvent(cap, ev_in, 0) != hipSuccess) {
-      if (ev_in) (void)hipEventDestroy(ev_in);
-      if (ev_out) (void)hipEventDestroy(ev_out);
-      (void)hipStreamDestroy(cap);
-      return fail(QK_EDEVICE, "graph stream set-up failed");
-    }
-  }
-  auto begin_segment = [&]() -> qk_status {
-    if (graph_gates <= 0 || capturing) return QK_OK;
-    QK_HIP_CHECK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
-    stream = cap;
-    capturing = true;
-    return QK_OK;
-  };
-  auto end_segment = [&]() -> qk_status {
-    if (!capturing) return QK_OK;
-    capturing = false;
-    hipGraph_t graph = nullptr;
-    QK_HIP_CHECK(hipStreamEndCapture(cap, &graph));
-    hipGraphExec_t exec = nullptr;
-    const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    hipError_t le = ie == hipSuccess ? hipGraphLaunch(exec, cap) : ie;
-    if (exec) (void)hipGraphExecDestroy(exec);
-    (void)hipGraphDestroy(graph);
-    if (le != hipSuccess) return fail(QK_EDEVICE, std::string("graph launch failed: ") + hipGetErrorString(le));
-    return QK_OK;
-  };
   // The step list shared by every circuit: runs of Rz records, centre moves
   // and two-qubit gates in circuit order, then the final moves to the last
   // site.  gate_no[i] is the number of two-qubit gates done after step i
@@ -1056,88 +991,154 @@ qk_status run_simulation(qk_mps_batch *b, const double *features_dev, const std:
     }
     for (; center < m - 1; ++center) push({STEP_TWO_SITE, center, MOVE_RIGHT, OP_ID, -1, -1, -1, 0}, 0);
   }
-  SimStep *steps_dev = nullptr;
-  qk_status st = QK_OK;
-  if (!steps.empty()) {
-    steps_dev = static_cast<SimStep *>(dev_alloc(al, sizeof(SimStep) * steps.size(), stream, true));
-    if (!steps_dev ||
-        hipMemcpyAsync(steps_dev, steps.data(), sizeof(SimStep) * steps.size(), hipMemcpyHostToDevice, stream) !=
-            hipSuccess) {
-      (void)hipGetLastError();
-      st = fail(QK_ENOMEM, "device allocation of the step list failed");
-    }
-  }
 
-  // Launches of at most kMaxChunkSteps steps, each ending where a progress
-  // callback or the end of a graph segment is due.
+  // Device buffers: gate records, step list, SVD scratch of one slot per
+  // workgroup of a launch, and (graph mode) the first circuit of a replay.
+  const DevAlloc al = allocator_for_current_device();
+  void *recs_dev = nullptr, *steps_dev = nullptr, *scratch = nullptr, *base_dev = nullptr;
+  auto release = [&]() {
+    for (void *ptr : {recs_dev, steps_dev, scratch, base_dev})
+      if (ptr) dev_free(al, ptr, stream, true);
+  };
+  recs_dev = dev_alloc(al, sizeof(qk_gate) * std::max<size_t>(gates.size(), 1), stream, true);
+  steps_dev = dev_alloc(al, sizeof(SimStep) * std::max<size_t>(steps.size(), 1), stream, true);
+  scratch = dev_alloc(al, sizeof(double2) * 2 * kSvMaxN * kSvMaxN * size_t(grid), stream, true);
+  if (graph) base_dev = dev_alloc(al, 256, stream, true);
+  if (!recs_dev || !steps_dev || !scratch || (graph && !base_dev)) {
+    release();
+    return fail(QK_ENOMEM, "device allocation of the simulation buffers failed");
+  }
+  if ((!gates.empty() && hipMemcpyAsync(recs_dev, gates.data(), sizeof(qk_gate) * gates.size(),
+                                        hipMemcpyHostToDevice, stream) != hipSuccess) ||
+      (!steps.empty() && hipMemcpyAsync(steps_dev, steps.data(), sizeof(SimStep) * steps.size(),
+                                        hipMemcpyHostToDevice, stream) != hipSuccess)) {
+    (void)hipGetLastError();
+    release();
+    return fail(QK_EDEVICE, "copy of the gate and step lists failed");
+  }
+  const auto *recs = static_cast<const qk_gate *>(recs_dev);
+  const auto *steps_d = static_cast<const SimStep *>(steps_dev);
+  auto *base = static_cast<int64_t *>(base_dev);
+
+  SvParams P{};
+  P.f64 = b->f64;
+  P.mps_stride = b->mps_stride;
+  P.site_off = b->site_off_dev;
+  P.pad = b->pad_dev;
+  P.dims = b->dims_dev;
+  P.m = m;
+  P.chi = chi;
+  P.gate_split = spec.gate_split;
+  P.coef_xx = spec.coef_xx;
+  P.cutoff = cutoff;
+  P.X = features_dev;
+  P.ldx = m;
+  P.scratch = static_cast<double2 *>(scratch);
+  P.disc = b->disc_dev;
+  P.maxdisc = b->maxdisc_dev;
+  P.degen = b->degen_dev;
+  P.unconv = b->unconv_dev;
+  P.n = n;
+  P.trace = trace;
+  P.trace_n2q = n2q;
+  P.base = base;
+
+  // The launches of one pass over `grid` circuits on stream s: the |+>
+  // state, the step list in launches of at most kMaxChunkSteps steps (a
+  // launch also ends where a progress callback is due), the normalisation of
+  // the last site, and in graph mode the advance of the first circuit.
   constexpr size_t kMaxChunkSteps = 256;
-  int64_t seg2q = 0;
-  size_t s0 = 0;
-  while (st == QK_OK && s0 < steps.size()) {
-    st = begin_segment();
-    if (st != QK_OK) break;
-    size_t s1 = s0;
-    bool seg_end = false, report = false;
-    while (s1 < steps.size() && s1 - s0 < kMaxChunkSteps) {
-      const int64_t g = gate_no[s1++];
-      if (g > 0) {
-        seg_end = graph_gates > 0 && ++seg2q == graph_gates;
-        report = fn && every > 0 && g % every == 0;
-        if (seg_end || report) break;
+  auto pass = [&](hipStream_t s) -> qk_status {
+    hipLaunchKernelGGL(init_plus_kernel, dim3(unsigned(grid)), dim3(64), 0, s, b->f64, b->mps_stride,
+                       b->site_off_dev, b->pad_dev, b->dims_dev, m, n, P.base);
+    if (hipGetLastError() != hipSuccess) return fail(QK_EDEVICE, "initial-state launch failed");
+    size_t s0 = 0;
+    while (s0 < steps.size()) {
+      size_t s1 = s0;
+      bool report = false;
+      while (s1 < steps.size() && s1 - s0 < kMaxChunkSteps) {
+        const int64_t g = gate_no[s1++];
+        if (g > 0 && fn && every > 0 && g % every == 0) {
+          report = true;
+          break;
+        }
       }
+      hipLaunchKernelGGL(sim_steps_kernel, dim3(unsigned(grid)), dim3(kSvThreads), 0, s, P, steps_d, int(s0),
+                         int(s1), recs, spec.coef_z);
+      if (hipGetLastError() != hipSuccess) return fail(QK_EDEVICE, "simulation launch failed");
+      if (report) {
+        if (hipStreamSynchronize(s) != hipSuccess) return fail(QK_EDEVICE, "simulation step failed");
+        if (fn(gate_no[s1 - 1], n2q, user) != 0)
+          return fail(QK_EABORTED, "simulation aborted by the progress callback");
+      }
+      s0 = s1;
     }
-    hipLaunchKernelGGL(sim_steps_kernel, dim3(unsigned(n)), dim3(kSvThreads), 0, stream, P, steps_dev, int(s0),
-                       int(s1), recs_dev, spec.coef_z);
+    hipLaunchKernelGGL(normalize_last_kernel, dim3(unsigned(grid)), dim3(256), 0, s, b->f64, b->mps_stride,
+                       b->site_off_dev, b->pad_dev, m, n, P.base);
+    if (hipGetLastError() != hipSuccess) return fail(QK_EDEVICE, "normalisation launch failed");
+    if (graph) {
+      hipLaunchKernelGGL(set_base_kernel, dim3(1), dim3(64), 0, s, base, grid, int64_t(1));
+      if (hipGetLastError() != hipSuccess) return fail(QK_EDEVICE, "replay-advance launch failed");
+    }
+    return QK_OK;
+  };
+
+  qk_status st = QK_OK;
+  if (!graph) {
+    st = pass(stream);
+  } else {
+    // The pass is recorded by stream capture on a private stream (the
+    // caller's stream may be the legacy null stream, which cannot be
+    // captured) and replayed `replays` times there; events order the
+    // private stream after the caller's earlier work and the caller's stream
+    // after the replays.  The first circuit starts at 0 (a kernel, not a
+    // memset, so that the sequence could itself be captured).
+    hipLaunchKernelGGL(set_base_kernel, dim3(1), dim3(64), 0, stream, base, int64_t(0), int64_t(0));
     if (hipGetLastError() != hipSuccess) {
-      st = fail(QK_EDEVICE, "simulation launch failed");
-      break;
+      release();
+      return fail(QK_EDEVICE, "replay-start launch failed");
     }
-    const int64_t done2q = gate_no[s1 - 1];
-    s0 = s1;
-    if (seg_end) {
-      st = end_segment();
-      seg2q = 0;
-    }
-    if (st == QK_OK && report) {
-      if (capturing) {
-        st = end_segment();
-        seg2q = 0;
-        if (st != QK_OK) break;
+    hipStream_t cap = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    hipGraph_t g = nullptr;
+    hipGraphExec_t exec = nullptr;
+    if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&ev_out, hipEventDisableTiming) != hipSuccess ||
+        hipEventRecord(ev_in, stream) != hipSuccess || hipStreamWaitEvent(cap, ev_in, 0) != hipSuccess) {
+      st = fail(QK_EDEVICE, "graph stream set-up failed");
+    } else if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      st = fail(QK_EDEVICE, "graph capture failed to start");
+    } else {
+      st = pass(cap);
+      // the capture is ended on every path so that the stream stays usable
+      const hipError_t ce = hipStreamEndCapture(cap, &g);
+      if (st == QK_OK && ce != hipSuccess) st = fail(QK_EDEVICE, std::string("graph capture failed: ") + hipGetErrorString(ce));
+      if (st == QK_OK) {
+        const hipError_t ie = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+        if (ie != hipSuccess) st = fail(QK_EDEVICE, std::string("graph instantiation failed: ") + hipGetErrorString(ie));
       }
-      if (hipStreamSynchronize(stream) != hipSuccess) {
-        st = fail(QK_EDEVICE, "simulation step failed");
-      } else if (fn(done2q, n2q, user) != 0) {
-        st = fail(QK_EABORTED, "simulation aborted by the progress callback");
+      for (int64_t r = 0; st == QK_OK && r < replays; ++r) {
+        const hipError_t le = hipGraphLaunch(exec, cap);
+        if (le != hipSuccess) st = fail(QK_EDEVICE, std::string("graph launch failed: ") + hipGetErrorString(le));
       }
     }
+    if (cap) {
+      // the caller's stream continues after the replays
+      if (ev_out && hipEventRecord(ev_out, cap) == hipSuccess) (void)hipStreamWaitEvent(stream, ev_out, 0);
+      (void)hipStreamSynchronize(cap);
+    }
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (g) (void)hipGraphDestroy(g);
+    if (ev_in) (void)hipEventDestroy(ev_in);
+    if (ev_out) (void)hipEventDestroy(ev_out);
+    if (cap) (void)hipStreamDestroy(cap);
   }
-  if (st == QK_OK) st = begin_segment();
-  if (st == QK_OK) {
-    hipLaunchKernelGGL(normalize_last_kernel, dim3(unsigned(n)), dim3(256), 0, stream, b->f64, b->mps_stride,
-                       b->site_off_dev, b->pad_dev, m, n);
-    if (hipGetLastError() != hipSuccess) st = fail(QK_EDEVICE, "normalisation launch failed");
+  release();
+  if (st != QK_OK) {
+    (void)hipStreamSynchronize(stream);
+    return st;
   }
-  if (capturing) {
-    // on an earlier error, still close the capture so the stream is usable
-    const qk_status se = end_segment();
-    if (st == QK_OK) st = se;
-  }
-  if (graph_gates > 0) {
-    // the caller's stream continues after the graphs
-    (void)hipEventRecord(ev_out, cap);
-    (void)hipStreamWaitEvent(stream_in, ev_out, 0);
-    stream = stream_in;
-  }
-  dev_free(al, scratch, stream, true);
-  dev_free(al, recs_dev, stream, true);
-  dev_free(al, steps_dev, stream, true);
-  if (graph_gates > 0) {
-    (void)hipStreamSynchronize(stream_in);
-    (void)hipEventDestroy(ev_in);
-    (void)hipEventDestroy(ev_out);
-    (void)hipStreamDestroy(cap);
-  }
-  if (st != QK_OK) return st;
   QK_HIP_CHECK(hipStreamSynchronize(stream));
   if (fn && fn(n2q, n2q, user) != 0) return fail(QK_EABORTED, "simulation aborted by the progress callback");
   return QK_OK;

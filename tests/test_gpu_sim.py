@@ -233,16 +233,19 @@ def test_paper_bandwidth_165_qubits_vs_oracle():
         assert np.abs(K - Ko).max() < tol
 
 
-def test_graph_captured_simulation_bit_identical():
-    """mps_simulate_graph records the same launches as HIP graphs (segments of
-    64 two-qubit gates, and the whole circuit as one graph): every run gives
-    the eager batch bit for bit, including runs interleaved with other eager
-    GPU work on the same stream."""
+def test_graph_replayed_simulation_bit_identical():
+    """mps_simulate_graph records the simulation of a chunk of circuits as one
+    HIP graph and replays it over the batch: 7 circuits in chunks of 3 (two
+    full replays and a ragged one of 1), of 1 (seven replays), of 7 and of 10
+    (one replay, grid larger than needed only in the request), and the
+    default.  Every circuit of every replay equals the eager batch bit for
+    bit, and so do K (FP64), also with eager GPU work on the same stream and
+    host synchronisations between the calls."""
     import time
     import paper_2411_09336_amd as q
     torch = require_gpu()
     w = sd.WORKLOADS["fp32"]
-    X = sd.workload_features(w, 6)
+    X = sd.workload_features(w, 7)
     xt = torch.tensor(X, dtype=torch.float64, device="cuda")
     spec = q.CircuitSpec(w.n_qubits, w.distance, w.reps, w.coef_z, w.coef_xx, 0)
     torch.cuda.synchronize()
@@ -252,21 +255,37 @@ def test_graph_captured_simulation_bit_identical():
     t_eager = time.perf_counter() - t0
     ref_mps = [ref.export(i) for i in range(len(X))]
     ref_dims = ref.bond_dims()
-    for run, seg in enumerate((64, 0, 64)):
+    ref_stats = ref.trunc_stats()
+    K0 = q.gram(ref, precision="fp64")
+    for chunk in (3, 1, 7, 10, 0, 3):
         junk = torch.randn(1 << 20, device="cuda").sum()       # eager work between runs
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        g = q.simulate(xt, spec, w.chi, w.cutoff, graph_gates=seg)
+        g = q.simulate(xt, spec, w.chi, w.cutoff, graph_circuits=chunk)
         torch.cuda.synchronize()
         t_graph = time.perf_counter() - t0
-        print("graph segment", seg, "eager", t_eager, "s graph", t_graph, "s", float(junk) * 0)
+        print("graph chunk", chunk, "eager", t_eager, "s graph", t_graph, "s", float(junk) * 0)
         assert np.array_equal(g.bond_dims(), ref_dims)
+        for a, b in zip(g.trunc_stats(), ref_stats):
+            assert np.array_equal(a, b)
         for i in range(len(X)):
             for a, b in zip(g.export(i), ref_mps[i]):
                 assert np.array_equal(a, b)
-        K1 = q.gram(g, precision="fp64")
-        K0 = q.gram(ref, precision="fp64")
-        assert torch.equal(K1, K0)
+        assert torch.equal(q.gram(g, precision="fp64"), K0)
+
+
+def test_graph_replay_arguments():
+    import paper_2411_09336_amd as q
+    torch = require_gpu()
+    xt = torch.zeros((2, 4), dtype=torch.float64, device="cuda")
+    spec = q.CircuitSpec(4, 1, 1)
+    with pytest.raises(q.QKError) as e:
+        q.simulate(xt, spec, 8, 0.0, graph_circuits=-1)
+    assert e.value.status == -1
+    with pytest.raises(ValueError):
+        q.simulate(xt, spec, 8, 0.0, graph_circuits=1, progress=lambda d, t: False)
+    empty = q.simulate(xt[:0], spec, 8, 0.0, graph_circuits=0)
+    assert empty.n == 0
 
 
 @pytest.mark.parametrize("routing", [0, 1])
