@@ -79,8 +79,9 @@ class FixedPoint:
     """``pairs``: digit pairs (a, b) kept in every product; ``re2_extra``:
     pairs kept in addition in the real part of T^T conj(A) only."""
 
-    def __init__(self, n_digits, bits, pairs, acc="exact", margin=2.0 ** -24, re2_extra=()):
+    def __init__(self, n_digits, bits, pairs, acc="exact", margin=2.0 ** -24, re2_extra=(), margin_y=None):
         self.n, self.bits, self.pairs, self.acc, self.margin = n_digits, bits, list(pairs), acc, margin
+        self.margin_y = margin if margin_y is None else margin_y
         self.re2_extra = list(re2_extra)
         self.B = n_digits * bits - 1            # |code| < 2^B
 
@@ -108,7 +109,7 @@ class FixedPoint:
     def cgemm(self, X, Y, conj_y):
         """X Y (or X conj(Y)) with row exponents of X and column exponents of Y."""
         ex = _exponent(np.maximum(np.abs(X.real), np.abs(X.imag)).max(1), self.margin)[:, None]
-        ey = _exponent(np.maximum(np.abs(Y.real), np.abs(Y.imag)).max(0), self.margin)[None, :]
+        ey = _exponent(np.maximum(np.abs(Y.real), np.abs(Y.imag)).max(0), self.margin_y)[None, :]
         Xr, Xi = self._split(X.real, ex), self._split(X.imag, ex)
         Yr, Yi = self._split(Y.real, ey), self._split(Y.imag, ey)
         neg = lambda ds: [-d for d in ds]
@@ -133,24 +134,36 @@ class FixedPoint:
 
 
 TEN = [(a, b) for a in range(4) for b in range(4) if a + b <= 3]
+EIGHT = [(a, b) for a in range(3) for b in range(3) if a + b <= 3]
 SIX = [(0, 0), (0, 1), (1, 0), (0, 2), (1, 1), (2, 0)]
 
 
 def split_bf16_form():
-    """The kernels' split-BF16: 31-bit codes in four balanced 8-bit digits,
-    the ten pairs of weight >= 2^-24 (and (2, 2) in the real part of
-    T^T conj(A)), exact leading + FP32 accumulator, FP64 combine."""
+    """The kernels' split-BF16: 27-bit codes in three balanced 9-bit digits
+    (bf16 carries |n| <= 256 exactly), the eight pairs of weight >= 2^-27,
+    exact leading + FP32 accumulator, FP64 combine; row exponents of the
+    kernel-sliced operands (E, T^T) with margin 2^-7, column exponents of
+    the packed site tensors with margin 2^-30."""
+    return FixedPoint(3, 9, EIGHT, acc="bf16", margin=2.0 ** -7, margin_y=2.0 ** -30)
+
+
+def split_bf16_4x8_form():
+    """A costlier split-BF16: 31-bit codes in four balanced 8-bit digits, the
+    ten pairs of weight >= 2^-24 (and (2, 2) in the real part of
+    T^T conj(A)): 41 instead of 32 digit products per complex product."""
     return FixedPoint(4, 8, TEN, acc="bf16", margin=2.0 ** -30, re2_extra=[(2, 2)])
 
 
 def split_i8_form():
-    """The kernels' split-int8: the same digits and pairs, all sums exact."""
+    """The kernels' split-int8: 31-bit codes in four balanced 8-bit digits,
+    the ten pairs of weight >= 2^-24 and (2, 2) in the real part of
+    T^T conj(A), all sums exact."""
     return FixedPoint(4, 8, TEN, acc="exact", margin=2.0 ** -7, re2_extra=[(2, 2)])
 
 
-def three_9bit_form():
-    """27-bit codes in three balanced 9-bit digits (bf16 carries |n| <= 256
-    exactly), the six pairs of weight >= 2^-18, exact leading accumulator."""
+def three_9bit_six_form():
+    """27-bit codes in three balanced 9-bit digits with only the six pairs of
+    weight >= 2^-18 (the two of weight 2^-27 dropped)."""
     return FixedPoint(3, 9, SIX, acc="bf16")
 
 
