@@ -46,17 +46,14 @@ PEAK_TFLOPS = {"bf16": 2500.0, "int8": 5000.0, "fp64": 78.6, "fp32": 157.3}
 # forms: MFMA dtype, kernel, description
 FORMS = {
     "split_bf16": ("bf16", "gram_kernel<split_bf16,64>",
-                   "split-bf16: 27-bit fixed-point codes with row/column exponents cut into three 9-bit digits "
-                   "carried as bf16; 8 digit products on bf16 MFMA; exact fp32 leading accumulator + fp32 "
-                   "accumulator for the rest; fp64 combine"),
+                   "split-bf16: 31-bit fixed-point codes with row/column exponents cut into four 8-bit digits "
+                   "carried as bf16; 10 digit products (11 in the real part of T^T conj A) on bf16 MFMA; exact "
+                   "fp32 leading accumulator + fp32 accumulator for the rest; fp64 combine"),
     "split_i8": ("int8", "gram_kernel<split_i8,64>",
-                 "split-int8: 31-bit fixed-point codes cut into four 8-bit digits as int8 MFMA operands; 10 digit "
-                 "products (11 in the real part of T^T conj A); exact int32 accumulation per weight class, fp64 "
-                 "combine"),
+                 "split-int8: the same four digits as int8 MFMA operands, exact int32 accumulation per weight "
+                 "class, fp64 combine"),
 }
-# issued MFMA flops per algorithmic flop: digit MACs per complex MAC / 4
-# (split-int8: 40 in GEMM1, 42 in GEMM2; split-bf16: 32 in both)
-ISSUED_PER_ALGORITHMIC = {"split_i8": 10.25, "split_bf16": 8.0}
+ISSUED_PER_ALGORITHMIC = {"split_i8": 10.25, "split_bf16": 10.25}
 HBM_PEAK_GBS = 8000.0
 # wall-clock budget of one default run (the driver allows 600 s including
 # interpreter start and the first import of torch): optional legs are skipped

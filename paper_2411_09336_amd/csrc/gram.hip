@@ -327,61 +327,73 @@ __device__ inline uint4 rsrc_load_u4(SiteRsrc r, int voff, int soff) {
 // ------------------------------------------------------------------------
 // Split-BF16 form with fixed-point slices (layout in qk_internal.h).
 //
-// Every GEMM operand is a 27-bit fixed-point code with one exponent per row
-// (A-operand) or column (B-operand), cut into three balanced 9-bit digits
-// carried as bf16 slices n_k 2^-9k (integers |n| <= 256 times a power of two,
-// exact in bf16).  A real product X Y is then
-//     2^(eX + eY - 16) * ( X0.Y0  +  sum of the seven other slice products
-//                                    with a + b <= 3 )
-// where X0.Y0 accumulates EXACTLY in one FP32 MFMA accumulator (integers
-// below 2^24 over the two contraction halves and both terms of a complex
-// product) and the seven others (weights 2^-9 .. 2^-27, smallest first)
-// share a second FP32 accumulator.  The (2, 2) product (weight 2^-36) is
-// dropped.  The two accumulators are combined in FP64.  This removes the
-// FP32 accumulation error that otherwise grows along the chain (about 2e-6
-// at 50 sites and 2e-5 at 100 sites for K = 1 with plain FP32 operands).
+// Every GEMM operand is cut into four bf16 slices that share one exponent per
+// row (A-operand) or column (B-operand), so each slice is an integer
+// |n| <= 128 times a power of two.  A real product X Y is then
+//     2^(eX + eY - 14) * ( X0.Y0  +  sum of ten smaller slice products )
+// where X0.Y0 accumulates EXACTLY in one FP32 MFMA accumulator (integers below
+// 2^22) and the other ten slice pairs (weights 2^-8 .. 2^-32, smallest first)
+// share a second FP32 accumulator, whose rounding is then ~2^-32 of the result.
+// The two accumulators are combined in FP64.  This removes the FP32
+// accumulation error that otherwise grows along the chain (about 2e-6 at 50
+// sites and 2e-5 at 100 sites for K = 1 with plain FP32 operands).
 //
 // E lives in LDS as slices plus one exponent per row; T and E' are formed in
 // FP64 registers and re-sliced for the next GEMM.
 __device__ inline int exp_above(double mx) {
-  // Smallest e with mx (1 + 2^-30) < 2^e (0 for mx == 0): every |x| <= mx
-  // is below 2^e, so its code round(x 2^(26-e)) is at most 2^26 in magnitude
-  // and the leading digit at most 256.
+  // Smallest e with mx (1 + 2^-30) < 2^e (0 for mx == 0).  The margin keeps
+  // |x| 2^(31-e) below 2^31 - 1 after rounding for every |x| <= mx, so the
+  // 31-bit fixed-point code never saturates (saturation would bias values
+  // just below a power of two, e.g. the unit diagonal of a self-overlap).
   return mx > 0.0 ? ilogb(mx * (1.0 + 0x1p-30)) + 1 : 0;
 }
 
 __device__ inline uint32_t bf16_bits_exact(float v) { return __float_as_uint(v) >> 16; }
 
-// Three pre-scaled slices n_k 2^-9k (k = 0..2) of x * 2^-e (|x| < 2^e), as
-// bf16 bits: X = round(x 2^(26-e)) is split into balanced base-512 digits
-// X = n0 2^18 + n1 2^9 + n2 with n1, n2 in [-256, 255] and n0 in [-256, 256].
-__device__ inline void slice3e(double x, int e, uint32_t (&o)[3]) {
-  int r = int(rint(ldexp(x, 26 - e)));
-  const int n2 = ((r & 511) ^ 256) - 256;
-  r = (r - n2) >> 9;
-  const int n1 = ((r & 511) ^ 256) - 256;
-  const int n0 = (r - n1) >> 9;
-  o[0] = bf16_bits_exact(float(n0));
-  o[1] = bf16_bits_exact(float(n1) * 0x1p-9f);
-  o[2] = bf16_bits_exact(float(n2) * 0x1p-18f);
+// Four pre-scaled slices n_k 2^-8k (k = 0..3) of x * 2^-e (|x| < 2^e), as
+// bf16 bits: X = round(x 2^(31-e)) (saturated to int32) is split into
+// balanced base-256 digits X = n0 2^24 + n1 2^16 + n2 2^8 + n3, with
+// n1..n3 in [-128, 127] and n0 in [-128, 128].  Each step takes the low byte
+// as a signed digit and carries one when it is negative; the carry is formed
+// from the shifted value, never from X - digit, which overflows int32 for X
+// near 2^31 (values just below the top of their exponent range).
+__device__ inline int balanced_digit(int &r) {
+  const int d = int(int8_t(r & 0xff));
+  r = (r >> 8) + ((r >> 7) & 1);
+  return d;
 }
 
+__device__ inline void slice4e(double x, int e, uint32_t (&o)[4]) {
+  int r = int(fmin(fmax(rint(ldexp(x, 31 - e)), -2147483647.0), 2147483647.0));
+  const int n3 = balanced_digit(r);
+  const int n2 = balanced_digit(r);
+  const int n1 = balanced_digit(r);
+  const int n0 = r;
+  o[0] = bf16_bits_exact(float(n0));
+  o[1] = bf16_bits_exact(float(n1) * 0x1p-8f);
+  o[2] = bf16_bits_exact(float(n2) * 0x1p-16f);
+  o[3] = bf16_bits_exact(float(n3) * 0x1p-24f);
+}
+
+// Same slices for xh = x 2^-e already in (-1, 1).
+__device__ inline void slice4(double xh, uint32_t (&o)[4]) { slice4e(xh, 0, o); }
+
 // Row exponent of the values the kernel slices itself (T and E'): smallest e
-// with mx (1 + 2^-7) < 2^e, so that |X| < 2^26 in slice3_word.
+// with mx (1 + 2^-7) < 2^e, so that |X| + 0x808080 < 2^31 in slice4_word.
 __device__ inline int exp_above_w(double mx) { return mx > 0.0 ? ilogb(mx * (1.0 + 0x1p-7)) + 1 : 0; }
 
-// The same three slices as slice3e, as floats n_k 2^-9k, from one FP64 FMA:
-// with scale = 2^(26-e), the low word of x scale + 1.5 2^52 + 0x20100 is
-// Y = X + 0x20100 for X = round(x 2^(26-e)); its bits 18 and up are the
-// signed leading digit n0 and its two 9-bit fields below are n1 + 256 and
-// n2 + 256 -- the same balanced digits, without carries.  Each lower slice
-// is then one field extraction, one conversion and one exact FMA; its bf16
-// bits are the float's upper half.
-__device__ inline void slice3_word(double x, double scale, float (&f)[3]) {
-  const uint32_t y = uint32_t(__double_as_longlong(fma(x, scale, 0x1.8p52 + 0x20100)));
-  f[0] = float(int(y) >> 18);
-  f[1] = fmaf(float((y >> 9) & 511u), 0x1p-9f, -0x1p-1f);
-  f[2] = fmaf(float(y & 511u), 0x1p-18f, -0x1p-10f);
+// The same four slices as slice4e, as floats n_k 2^-8k, from one FP64 FMA:
+// with scale = 2^(31-e), the low word of x scale + 1.5 2^52 + 0x808080 is
+// Y = X + 0x808080 for X = round(x 2^(31-e)), whose top byte is the signed
+// leading digit n0 and whose lower bytes are n_k + 128 (k = 1..3) -- the
+// same balanced digits, without carries.  Each slice is then one byte
+// conversion and one exact FMA; its bf16 bits are the float's upper half.
+__device__ inline void slice4_word(double x, double scale, float (&f)[4]) {
+  const uint32_t y = uint32_t(__double_as_longlong(fma(x, scale, 0x1.8p52 + 0x808080)));
+  f[0] = float(int(y) >> 24);
+  f[1] = fmaf(float(uint8_t(y >> 16)), 0x1p-8f, -0x1p-1f);
+  f[2] = fmaf(float(uint8_t(y >> 8)), 0x1p-16f, -0x1p-9f);
+  f[3] = fmaf(float(uint8_t(y)), 0x1p-24f, -0x1p-17f);
 }
 
 // bf16 bits of two exact floats packed in one word (a low, b high).
@@ -389,23 +401,29 @@ __device__ inline uint32_t pack_bf16_pair(float a, float b) {
   return __builtin_amdgcn_perm(__float_as_uint(b), __float_as_uint(a), 0x07060302u);
 }
 
-struct Sl3 {
-  uint4 v[3];
+struct Sl4 {
+  uint4 v[4];
 };
 
-__device__ inline Sl3 neg3(const Sl3 &x) {
-  Sl3 y;
+__device__ inline Sl4 neg4(const Sl4 &x) {
+  Sl4 y;
 #pragma unroll
-  for (int k = 0; k < 3; ++k) y.v[k] = neg_bf16(x.v[k]);
+  for (int k = 0; k < 4; ++k) y.v[k] = neg_bf16(x.v[k]);
   return y;
 }
 
-// hi += X0 Y0 (exact); lo += the seven other slice products with a + b <= 3,
-// smallest first.
-__device__ inline void slice_mac(const Sl3 &X, const Sl3 &Y, f32x4 &hi, f32x4 &lo) {
+// hi += X0 Y0 (exact); lo += the smaller slice products, smallest first:
+// the nine others of weight >= 2^-24 and, if P22, the (2, 2) product, which
+// is kept only where bra ~ ket makes it one-signed (the real part of GEMM2;
+// the reasoning of the split-int8 form below applies to the same digits).
+template <bool P22>
+__device__ inline void slice_mac(const Sl4 &X, const Sl4 &Y, f32x4 &hi, f32x4 &lo) {
   hi = mma16(X.v[0], Y.v[0], hi);
-  lo = mma16(X.v[1], Y.v[2], lo);
+  lo = mma16(X.v[3], Y.v[0], lo);
+  lo = mma16(X.v[0], Y.v[3], lo);
   lo = mma16(X.v[2], Y.v[1], lo);
+  lo = mma16(X.v[1], Y.v[2], lo);
+  if (P22) lo = mma16(X.v[2], Y.v[2], lo);
   lo = mma16(X.v[2], Y.v[0], lo);
   lo = mma16(X.v[1], Y.v[1], lo);
   lo = mma16(X.v[0], Y.v[2], lo);
@@ -413,36 +431,47 @@ __device__ inline void slice_mac(const Sl3 &X, const Sl3 &Y, f32x4 &hi, f32x4 &l
   lo = mma16(X.v[0], Y.v[1], lo);
 }
 
+// Pack the 8 values of one A-operand chunk into four slice registers.
+__device__ inline Sl4 make_slices(const double (&xh)[8]) {
+  Sl4 r;
+  uint32_t sl[8][4];
+#pragma unroll
+  for (int v = 0; v < 8; ++v) slice4(xh[v], sl[v]);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    r.v[k].x = sl[0][k] | (sl[1][k] << 16);
+    r.v[k].y = sl[2][k] | (sl[3][k] << 16);
+    r.v[k].z = sl[4][k] | (sl[5][k] << 16);
+    r.v[k].w = sl[6][k] | (sl[7][k] << 16);
+  }
+  return r;
+}
+
 // Work split per site (eight waves): wave w owns column block c = w % 4 and
 // row half h = w / 4.  GEMM1 produces T_s[rows 32h..32h+31][ket block c]; the
 // exponent of each T^T row (ket column) combines both halves through LDS and
 // T is stored in LDS as slices.  GEMM2 produces E'^T[ket rows 32h..][bra
-// block c].  Two 48 KiB LDS buffers alternate roles so that slicing one
+// block c].  Two 64 KiB LDS buffers alternate roles so that slicing one
 // operand overlaps the MFMAs of the next GEMM:
 //   1. GEMM1(s=0) reads E (buffer X)                     -> T0 in registers
 //   2. slice T0 -> Y            ||  GEMM1(s=1) reads X    -> T1 in registers
 //   3. slice T1 -> X            ||  GEMM2(s=0) reads Y    (E no longer needed)
 //   4. GEMM2(s=1) reads X; E' row exponents
 //   5. slice E' -> Y, which holds E for the next site (X and Y swap).
-// A buffer holds A-operand groups (16-row tile t, contraction half kc) of
-// 6 KiB: [slice k][plane q][lane][8 bf16].
 // The split form is stored with 64 x 64 blocks at every site, so the body is
 // straight-line code.
 constexpr int kSplitThreads = 512;
 constexpr int kSP = 64;
-constexpr int kSplitGroupBytes = kSlices * 2 * kFragBytes;        // 6 KiB
-constexpr int kSplitBufBytes = 4 * 2 * kSplitGroupBytes;          // 48 KiB
 
 struct SplitCtx {
   int lane, j, g, cb, hf;
 };
 
-constexpr int64_t kSplitSiteBytes = kSplitExpBytes + int64_t(2) * kSlices * 2 * 2 * 4 * kFragBytes;
+constexpr int64_t kSplitSiteBytes = kSplitExpBytes + int64_t(2) * 4 * 2 * 2 * 4 * kFragBytes;
 static_assert(kSplitSiteBytes == split_site_bytes(), "split-BF16 site block size");
 
 __device__ inline uint4 split_frag(SiteRsrc site, int s, int k, int q, int kc, int c, int lane) {
-  return rsrc_load_u4(site, lane * 16,
-                      kSplitExpBytes + ((((s * kSlices + k) * 2 + q) * 2 + kc) * 4 + c) * kFragBytes);
+  return rsrc_load_u4(site, lane * 16, kSplitExpBytes + ((((s * 4 + k) * 2 + q) * 2 + kc) * 4 + c) * kFragBytes);
 }
 
 // GEMM1 for physical index s: T[a][b'] (a in rows 32h.., b' in block c) in
@@ -460,29 +489,29 @@ __device__ inline void split_gemm1(const SplitCtx &C, const uint8_t *B, const ui
   const SiteRsrc rB = site_rsrc<kSplitSiteBytes>(B);
 #pragma unroll
   for (int kc = 0; kc < 2; ++kc) {
-    Sl3 Br, Bi;
+    Sl4 Br, Bi;
 #pragma unroll
-    for (int k = 0; k < kSlices; ++k) {
+    for (int k = 0; k < 4; ++k) {
       Br.v[k] = split_frag(rB, s, k, 0, kc, C.cb, C.lane);
       Bi.v[k] = split_frag(rB, s, k, 1, kc, C.cb, C.lane);
     }
-    const Sl3 Bin = neg3(Bi);
+    const Sl4 Bin = neg4(Bi);
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       const int rt = 2 * C.hf + u;
-      const uint8_t *eg = Ebuf + size_t(rt * 2 + kc) * kSplitGroupBytes + C.lane * 16;
-      Sl3 Er, Ei;
+      const uint8_t *eg = Ebuf + size_t(rt * 2 + kc) * 8192 + C.lane * 16;
+      Sl4 Er, Ei;
 #pragma unroll
-      for (int k = 0; k < kSlices; ++k) {
-        Er.v[k] = *reinterpret_cast<const uint4 *>(eg + (k * 2 + 0) * kFragBytes);
-        Ei.v[k] = *reinterpret_cast<const uint4 *>(eg + (k * 2 + 1) * kFragBytes);
+      for (int k = 0; k < 4; ++k) {
+        Er.v[k] = *reinterpret_cast<const uint4 *>(eg + (k * 2 + 0) * 1024);
+        Ei.v[k] = *reinterpret_cast<const uint4 *>(eg + (k * 2 + 1) * 1024);
       }
       // re += Er Br - Ei Bi ; im += Er Bi + Ei Br
       __builtin_amdgcn_s_setprio(1);   // MFMA burst first when both waves of a SIMD are ready
-      slice_mac(Er, Br, h1[u][0], l1[u][0]);
-      slice_mac(Ei, Bin, h1[u][0], l1[u][0]);
-      slice_mac(Er, Bi, h1[u][1], l1[u][1]);
-      slice_mac(Ei, Br, h1[u][1], l1[u][1]);
+      slice_mac<false>(Er, Br, h1[u][0], l1[u][0]);
+      slice_mac<false>(Ei, Bin, h1[u][0], l1[u][0]);
+      slice_mac<false>(Er, Bi, h1[u][1], l1[u][1]);
+      slice_mac<false>(Ei, Br, h1[u][1], l1[u][1]);
       __builtin_amdgcn_s_setprio(0);
     }
   }
@@ -493,7 +522,7 @@ __device__ inline void split_gemm1(const SplitCtx &C, const uint8_t *B, const ui
     const int rt = 2 * C.hf + u;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const int ex = s_ea[16 * rt + 4 * C.g + e] + ebc - 16;
+      const int ex = s_ea[16 * rt + 4 * C.g + e] + ebc - 14;
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
         const double v = ldexp(double(h1[u][q][e]) + double(l1[u][q][e]), ex);
@@ -510,19 +539,19 @@ __device__ inline void split_gemm1(const SplitCtx &C, const uint8_t *B, const ui
 // group row `grow` of buffer `buf`: A-operand group (grow, kc = u2 >> 1) where
 // u2 = 2 h + u is the 16-row tile of the contraction index.
 __device__ inline void split_store(const SplitCtx &C, uint8_t *buf, int grow, const double (&V)[2][2][4], int ex) {
-  const double scale = ldexp(1.0, 26 - ex);
+  const double scale = ldexp(1.0, 31 - ex);
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
     const int t = 2 * C.hf + u;
-    uint8_t *dst = buf + size_t(grow * 2 + (t >> 1)) * kSplitGroupBytes + C.lane * 16 + (t & 1) * 8;
+    uint8_t *dst = buf + size_t(grow * 2 + (t >> 1)) * 8192 + C.lane * 16 + (t & 1) * 8;
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
-      float sl[4][3];
+      float sl[4][4];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) slice3_word(V[u][q][e], scale, sl[e]);
+      for (int e = 0; e < 4; ++e) slice4_word(V[u][q][e], scale, sl[e]);
 #pragma unroll
-      for (int k = 0; k < kSlices; ++k)
-        *reinterpret_cast<uint2 *>(dst + (k * 2 + q) * kFragBytes) =
+      for (int k = 0; k < 4; ++k)
+        *reinterpret_cast<uint2 *>(dst + (k * 2 + q) * 1024) =
             make_uint2(pack_bf16_pair(sl[0][k], sl[1][k]), pack_bf16_pair(sl[2][k], sl[3][k]));
     }
   }
@@ -543,29 +572,29 @@ __device__ inline void split_gemm2(const SplitCtx &C, const uint8_t *A, const ui
   const SiteRsrc rA = site_rsrc<kSplitSiteBytes>(A);
 #pragma unroll
   for (int kc = 0; kc < 2; ++kc) {
-    Sl3 Ar, Ai;
+    Sl4 Ar, Ai;
 #pragma unroll
-    for (int k = 0; k < kSlices; ++k) {
+    for (int k = 0; k < 4; ++k) {
       Ar.v[k] = split_frag(rA, s, k, 0, kc, C.cb, C.lane);
       Ai.v[k] = split_frag(rA, s, k, 1, kc, C.cb, C.lane);
     }
-    const Sl3 Ain = neg3(Ai);   // shared by both row tiles (the products are those of -Tr Ai)
+    const Sl4 Ain = neg4(Ai);   // shared by both row tiles (the products are those of -Tr Ai)
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       const int bt = 2 * C.hf + u;
-      const uint8_t *tg = Tbuf + size_t(bt * 2 + kc) * kSplitGroupBytes + C.lane * 16;
-      Sl3 Tr, Ti;
+      const uint8_t *tg = Tbuf + size_t(bt * 2 + kc) * 8192 + C.lane * 16;
+      Sl4 Tr, Ti;
 #pragma unroll
-      for (int k = 0; k < kSlices; ++k) {
-        Tr.v[k] = *reinterpret_cast<const uint4 *>(tg + (k * 2 + 0) * kFragBytes);
-        Ti.v[k] = *reinterpret_cast<const uint4 *>(tg + (k * 2 + 1) * kFragBytes);
+      for (int k = 0; k < 4; ++k) {
+        Tr.v[k] = *reinterpret_cast<const uint4 *>(tg + (k * 2 + 0) * 1024);
+        Ti.v[k] = *reinterpret_cast<const uint4 *>(tg + (k * 2 + 1) * 1024);
       }
       // re += Tr Ar + Ti Ai ; im += Ti Ar + Tr (-Ai)
       __builtin_amdgcn_s_setprio(1);
-      slice_mac(Tr, Ar, h2[u][0], l2[u][0]);
-      slice_mac(Ti, Ai, h2[u][0], l2[u][0]);
-      slice_mac(Ti, Ar, h2[u][1], l2[u][1]);
-      slice_mac(Tr, Ain, h2[u][1], l2[u][1]);
+      slice_mac<true>(Tr, Ar, h2[u][0], l2[u][0]);
+      slice_mac<true>(Ti, Ai, h2[u][0], l2[u][0]);
+      slice_mac<false>(Ti, Ar, h2[u][1], l2[u][1]);
+      slice_mac<false>(Tr, Ain, h2[u][1], l2[u][1]);
       __builtin_amdgcn_s_setprio(0);
     }
   }
@@ -575,7 +604,7 @@ __device__ inline void split_gemm2(const SplitCtx &C, const uint8_t *A, const ui
     const int bt = 2 * C.hf + u;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const int ex = s_eTs[16 * bt + 4 * C.g + e] + eac - 16;
+      const int ex = s_eTs[16 * bt + 4 * C.g + e] + eac - 14;
 #pragma unroll
       for (int q = 0; q < 2; ++q) Ep[u][q][e] += ldexp(double(h2[u][q][e]) + double(l2[u][q][e]), ex);
     }
@@ -600,12 +629,12 @@ __device__ void overlap_split(const GramJobDev &J, int64_t ia, int64_t ib, uint8
   uint8_t *X = buf0, *Y = buf1;
   {
     uint4 *X16 = reinterpret_cast<uint4 *>(X);
-    for (int x = tid; x < kSplitBufBytes / 16; x += kSplitThreads) X16[x] = make_uint4(0, 0, 0, 0);
+    for (int x = tid; x < kSP * kSP; x += kSplitThreads) X16[x] = make_uint4(0, 0, 0, 0);
     for (int x = tid; x < kSP; x += kSplitThreads) s_ea[x] = 0;
     __syncthreads();
-    // E_0 = [[1]]: row exponent 1, leading slice 128 (1 = 2^(1-8) 128)
+    // E_0 = [[1]]: row exponent 1, leading slice 64 (= 0.5 * 128)
     if (tid == 0) {
-      reinterpret_cast<uint16_t *>(X)[0] = uint16_t(bf16_bits_exact(128.0f));
+      reinterpret_cast<uint16_t *>(X)[0] = uint16_t(bf16_bits_exact(64.0f));
       s_ea[0] = 1;
     }
     __syncthreads();
@@ -1083,7 +1112,7 @@ __global__ __launch_bounds__(threads_of<PREC>(), 2) void gram_kernel(const GramJ
     } else if constexpr (PREC == QK_SPLIT_BF16) {
       double re, im;
       int ex;
-      overlap_split<MAXP>(J, J.a0 + i, J.b0 + j, smem, smem + kSplitBufBytes, s_ea, s_eT, s_mx, s_ov,
+      overlap_split<MAXP>(J, J.a0 + i, J.b0 + j, smem, smem + size_t(MAXP) * MAXP * 16, s_ea, s_eT, s_mx, s_ov,
                           re, im, ex);
       k = ldexp(re * re + im * im, 2 * ex);
     } else {
@@ -1100,7 +1129,7 @@ template <int PREC, int MAXP>
 size_t lds_bytes() {
   if (PREC == QK_FP64) return size_t(MAXP) * MAXP * 16;
   if (PREC == QK_FP32) return size_t(MAXP) * MAXP * 8;
-  if (PREC == QK_SPLIT_BF16) return size_t(2) * kSplitBufBytes;   // E slices + T slices
+  if (PREC == QK_SPLIT_BF16) return size_t(MAXP) * MAXP * 32;   // E slices + T slices
   return size_t(2) * kI8BufBytes;                                  // two int8 operand buffers
 }
 
@@ -1329,7 +1358,7 @@ __global__ void pack_f32_kernel(const double2 *__restrict__ src, float2 *__restr
 }
 
 // One block per (site, mps): column exponents e[s][c] (max |x| < 2^e over the
-// column's rows and both planes), then the three fixed-point slices of every
+// column's rows and both planes), then the four fixed-point slices of every
 // value, in B-operand fragment order, on a 64 x 64 block (zero beyond the
 // batch's pads).
 __global__ __launch_bounds__(256) void pack_split_kernel(const double2 *__restrict__ src, uint8_t *__restrict__ dst,
@@ -1368,17 +1397,17 @@ __global__ __launch_bounds__(256) void pack_split_kernel(const double2 *__restri
     const int jj = lane & 15, gg = lane >> 4;
     const int col = 16 * ct + jj;
     const int e = s_e[s * 128 + col];
-    uint32_t sl[2][8][3];
+    uint32_t sl[2][8][4];
 #pragma unroll
     for (int v = 0; v < 8; ++v) {
       const int row = 32 * kc + (v < 4 ? 4 * gg + v : 16 + 4 * gg + (v - 4));
       double2 x = make_double2(0.0, 0.0);
       if (row < pl && col < pr) x = site[(size_t(s) * pl + row) * pr + col];
-      slice3e(x.x, e, sl[0][v]);
-      slice3e(x.y, e, sl[1][v]);
+      slice4e(x.x, e, sl[0][v]);
+      slice4e(x.y, e, sl[1][v]);
     }
 #pragma unroll
-    for (int k = 0; k < kSlices; ++k)
+    for (int k = 0; k < 4; ++k)
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
         uint4 o;
@@ -1386,7 +1415,7 @@ __global__ __launch_bounds__(256) void pack_split_kernel(const double2 *__restri
         o.y = sl[q][2][k] | (sl[q][3][k] << 16);
         o.z = sl[q][4][k] | (sl[q][5][k] << 16);
         o.w = sl[q][6][k] | (sl[q][7][k] << 16);
-        *reinterpret_cast<uint4 *>(out + kSplitExpBytes + ((size_t(((s * kSlices + k) * 2 + q) * 2 + kc) * 4 + ct) * 1024 +
+        *reinterpret_cast<uint4 *>(out + kSplitExpBytes + ((size_t(((s * 4 + k) * 2 + q) * 2 + kc) * 4 + ct) * 1024 +
                                                            lane * 16)) = o;
       }
   }

@@ -30,23 +30,22 @@ inline int pad_of(int d) { return ((d + kPadQuantum - 1) / kPadQuantum) * kPadQu
 
 // Split-BF16 operand form (fixed-point slices).  Every real value x of a
 // site tensor column c (per physical index s) is written as
-//   x = 2^(e[s][c] - 8) * (n0 + n1 2^-9 + n2 2^-18) + O(2^(e-27))
+//   x = 2^(e[s][c] - 7) * (n0 + n1 2^-8 + n2 2^-16 + n3 2^-24) + O(2^(e-32))
 // with a shared column exponent e[s][c] (max |x| of the column times
-// 1 + 2^-30 is below 2^e; e >= -127), the 27-bit code
-// X = round(x 2^(26-e)) = n0 2^18 + n1 2^9 + n2 and balanced digits
-// n1, n2 in [-256, 255], |n0| <= 256; slice k is stored as the bf16 value
-// n_k 2^(-9k), which is exact.  Products of leading slices are integers
-// below 2^17, so the (0,0) slice product accumulates exactly in an FP32 MFMA
-// accumulator.  A site block is:
+// 1 + 2^-30 is below 2^e, so codes never saturate; e >= -127) and
+// integers |n_k| <= 128; slice k is stored as the bf16 value n_k 2^(-8k),
+// which is exact.  Products of leading slices are integers below 2^14, so
+// the (0,0) slice product accumulates exactly in an FP32 MFMA accumulator.
+// A site block is:
 //   [int8 exponents e[s][c], s in {0,1}, c < 128 : 256 bytes]
-//   [fragments: [s][slice 0..2][plane 0..1 = re, im][kc][ct][lane][8 bf16]]
+//   [fragments: [s][slice 0..3][plane 0..1 = re, im][kc][ct][lane][8 bf16]]
 // where fragment (kc, ct) is the MFMA B-operand of K = 32 rows by 16
 // columns: lane l = j + 16 g, slot v holds row perm(kc, g, v), column
 // 16 ct + j, with
 //   perm(kc, g, v) = 32 kc + 4 g + v          for v < 4
 //                  = 32 kc + 16 + 4 g + v - 4 for v >= 4.
 constexpr int kFragBytes = 64 * 8 * 2;   // 1 KiB
-constexpr int kSlices = 3;
+constexpr int kSlices = 4;
 constexpr int kSplitExpBytes = 256;
 
 // Every site of the split form is a 64 x 64 block (zero beyond the batch's

@@ -139,32 +139,30 @@ SIX = [(0, 0), (0, 1), (1, 0), (0, 2), (1, 1), (2, 0)]
 
 
 def split_bf16_form():
-    """The kernels' split-BF16: 27-bit codes in three balanced 9-bit digits
-    (bf16 carries |n| <= 256 exactly), the eight pairs of weight >= 2^-27,
-    exact leading + FP32 accumulator, FP64 combine; row exponents of the
-    kernel-sliced operands (E, T^T) with margin 2^-7, column exponents of
-    the packed site tensors with margin 2^-30."""
-    return FixedPoint(3, 9, EIGHT, acc="bf16", margin=2.0 ** -7, margin_y=2.0 ** -30)
-
-
-def split_bf16_4x8_form():
-    """A costlier split-BF16: 31-bit codes in four balanced 8-bit digits, the
-    ten pairs of weight >= 2^-24 (and (2, 2) in the real part of
-    T^T conj(A)): 41 instead of 32 digit products per complex product."""
+    """The kernels' split-BF16: 31-bit codes in four balanced 8-bit digits,
+    the ten pairs of weight >= 2^-24 (and (2, 2) in the real part of
+    T^T conj(A)), exact leading + FP32 accumulator, FP64 combine."""
     return FixedPoint(4, 8, TEN, acc="bf16", margin=2.0 ** -30, re2_extra=[(2, 2)])
 
 
 def split_i8_form():
-    """The kernels' split-int8: 31-bit codes in four balanced 8-bit digits,
-    the ten pairs of weight >= 2^-24 and (2, 2) in the real part of
-    T^T conj(A), all sums exact."""
+    """The kernels' split-int8: the same digits and pairs, all sums exact."""
     return FixedPoint(4, 8, TEN, acc="exact", margin=2.0 ** -7, re2_extra=[(2, 2)])
 
 
-def three_9bit_six_form():
-    """27-bit codes in three balanced 9-bit digits with only the six pairs of
-    weight >= 2^-18 (the two of weight 2^-27 dropped)."""
+def three_9bit_form():
+    """27-bit codes in three balanced 9-bit digits (bf16 carries |n| <= 256
+    exactly), the six pairs of weight >= 2^-18, exact leading accumulator."""
     return FixedPoint(3, 9, SIX, acc="bf16")
+
+
+def three_9bit_eight_form():
+    """27-bit codes in three balanced 9-bit digits with every product of weight
+    >= 2^-27 (eight pairs) and (2, 2) in the real part of T^T conj(A): the
+    cheapest fixed-point bf16 form (32 + 2 digit products per complex product
+    instead of 41), with the kernels' exponent margins (2^-7 for the sliced
+    rows of E and T^T, 2^-30 for the packed site columns)."""
+    return FixedPoint(3, 9, EIGHT, acc="bf16", margin=2.0 ** -7, margin_y=2.0 ** -30, re2_extra=[(2, 2)])
 
 
 def _bf16(x):

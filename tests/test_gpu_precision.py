@@ -20,11 +20,10 @@ pytestmark = pytest.mark.gpu
 
 N_POINTS, N_DUP = 16, 4
 # FP64: rounding of ~m chi^3 operations; split forms: the fixed-point
-# resolution per value and site plus the omitted digit products -- split-int8
-# 2^-31 (~1e-8 at 100 sites), bounded at 1e-7; split-BF16 2^-27 (~1e-7 at
-# 100 sites), bounded at half the 1e-6 target; FP32: plain float operands
-# and accumulators, about 2e-5 at 100 sites, bounded at 1e-4.
-TOL = {"fp64": 1e-12, "split_bf16": 5e-7, "split_i8": 1e-7, "fp32": 1e-4}
+# resolution 2^-31 per value and site plus the omitted digit products
+# (~1e-8 at 100 sites), bounded at 1e-7; FP32: plain float operands and
+# accumulators, about 2e-5 at 100 sites, bounded at 1e-4.
+TOL = {"fp64": 1e-12, "split_bf16": 1e-7, "split_i8": 1e-7, "fp32": 1e-4}
 
 
 @pytest.fixture(scope="module")

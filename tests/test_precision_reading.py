@@ -11,22 +11,27 @@ kinds of states, against the plain complex128 overlap:
   heavily and per-entry rounding does not average out as on random states.
 
 Findings (each a test below):
-* the built split-BF16 (27-bit codes in three 9-bit digits, the eight digit
-  products of weight >= 2^-27, exact leading accumulator) stays below
-  3e-7 on both kinds, inside the target with a margin of more than 3;
-  split-int8 (31-bit codes in four 8-bit digits, ten products, exact int32
-  sums) and a four-digit split-BF16 (41 instead of 32 digit products per
-  complex product) stay near 1e-8 -- the built split-BF16 trades that
-  digit of precision for 22 % fewer matrix-core instructions;
-* the same three digits with only the six products of weight >= 2^-18
-  reach ~1e-6 on simulated states, so the two products of weight 2^-27
-  are kept;
+* the built split-BF16 (31-bit codes in four 8-bit digits, ten digit
+  products, exact leading accumulator) and split-int8 (same digits, exact
+  int32 sums) stay near 1e-8 on both kinds;
 * a floating three-piece bf16 split with six products in one FP32
   accumulator would pass if the bf16 MFMA summed its products exactly, but
   the gfx950 instruction drops the low bits of products far below the
   largest one of the same output (measured on the GPU: 2^20 - 2^20 + 2^-10
   gives 0 and 1 + 3*2^-25 gives 1 where the f32 MFMA gives 2^-10 and
   1 + 2^-23), and with that cut its self-overlaps drift one way by ~1e-6;
+* three 9-bit digits (27-bit codes, six products) pass on random states but
+  reach ~1e-6 on simulated ones, so they are not used;
+* three 9-bit digits with all eight products of weight >= 2^-27 (and (2, 2)
+  in the real part of GEMM2) would need 17 % fewer digit products than the
+  built form, and run 20 % faster on the GPU, but their self-overlaps scatter
+  ~13 times wider: on 400 oracle-simulated circuits of the uneven workload's
+  20-qubit instance their error has a standard deviation of ~6e-8 and
+  reaches ~2.3e-7, against ~5e-9 and ~1.3e-8 for the built form (27-bit
+  codes round every site tensor, T and E at 2^-27 of their row or column
+  maximum, and that rounding, not the dropped products, sets the error);
+  over 2000 points of the 110-qubit instance the GPU measured 5.1e-7, too
+  close to the 1e-6 target;
 * three 8-bit digits with six products are worse than three 9-bit ones.
 """
 import multiprocessing as mp
@@ -41,9 +46,8 @@ from tests import emulate_forms as ef
 
 FORMS = {
     "split_bf16": ef.split_bf16_form,
-    "split_bf16_4x8": ef.split_bf16_4x8_form,
     "split_i8": ef.split_i8_form,
-    "three_9bit_six": ef.three_9bit_six_form,
+    "three_9bit": ef.three_9bit_form,
     "three_8bit": lambda: ef.FixedPoint(3, 8, ef.SIX, acc="exact", margin=2.0 ** -7),
     "floating_exact": lambda: ef.FloatingR2(trunc_bits=None),
     "floating_cut": lambda: ef.FloatingR2(trunc_bits=24),
@@ -106,18 +110,17 @@ def _max(d, kind):
     return max(abs(v) for (ka, _), v in d.items() if ka.startswith(kind))
 
 
-def test_built_forms_within_target_on_both_kinds(errors):
-    for kind in ("r", "s"):
-        assert _max(errors["split_bf16"], kind) < 3e-7, kind
-        for name in ("split_i8", "split_bf16_4x8"):
-            assert _max(errors[name], kind) < 5e-8, (name, kind)
+def test_built_forms_reach_1e8_on_both_kinds(errors):
+    for name in ("split_bf16", "split_i8"):
+        assert _max(errors[name], "r") < 5e-8, name
+        assert _max(errors[name], "s") < 5e-8, name
 
 
-def test_dropping_the_2_27_products_fails_on_simulated_states(errors):
-    d = errors["three_9bit_six"]
+def test_three_9bit_digits_fail_on_simulated_states(errors):
+    d = errors["three_9bit"]
     assert _max(d, "r") < 4e-7          # random states suggest a 2.5x margin ...
-    assert _max(d, "s") > 6e-7          # ... simulated ones take it away
-    assert _max(d, "s") > 3 * _max(errors["split_bf16"], "s")
+    assert _max(d, "s") > 8e-7          # ... simulated ones take it away
+    assert _max(d, "s") > 10 * _max(errors["split_bf16"], "s")
 
 
 def test_floating_split_with_mfma_truncation_drifts(errors):
@@ -130,4 +133,24 @@ def test_floating_split_with_mfma_truncation_drifts(errors):
 
 
 def test_three_8bit_digits_worse_than_three_9bit(errors):
-    assert _max(errors["three_8bit"], "r") > 1.5 * _max(errors["three_9bit_six"], "r")
+    assert _max(errors["three_8bit"], "r") > 1.5 * _max(errors["three_9bit"], "r")
+
+
+def _uneven20(k):
+    _limit_threads()
+    w = sd.WORKLOADS["uneven_20"]
+    x = sd.workload_features(w)[k]
+    t = omps.simulate(x, w.distance, w.reps, w.chi, w.cutoff, w.coef_z, w.coef_xx, routing=0).tensors
+    ref = abs(ogram.overlap(t, t)) ** 2
+    return [abs(f().overlap(t, t)) ** 2 - ref for f in (ef.split_bf16_form, ef.three_9bit_eight_form)]
+
+
+def test_three_9bit_eight_products_scatter_wider():
+    with mp.get_context("fork").Pool(8) as pool:
+        err = np.array(pool.map(_uneven20, range(400)))
+    built, nine = err[:, 0], err[:, 1]
+    print("built: max", np.abs(built).max(), "std", built.std(), "| three 9-bit, eight products: max",
+          np.abs(nine).max(), "std", nine.std())
+    assert np.abs(built).max() < 3e-8
+    assert np.abs(nine).max() > 1.5e-7
+    assert nine.std() > 8 * built.std()
