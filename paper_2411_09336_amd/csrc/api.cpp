@@ -412,8 +412,6 @@ static qk_status check_pair_batches(const qk_mps_batch *a, const qk_mps_batch *b
   return QK_OK;
 }
 
-static int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
-
 static qk_status make_job(const qk_mps_batch *a, int64_t a0, int64_t na, const qk_mps_batch *b,
                           int64_t b0, int64_t nb, int32_t upper, double *K, int64_t ldk,
                           qk_precision prec, hipStream_t stream, GramJobDev *job, bool pack = true) {

@@ -54,13 +54,8 @@ __device__ inline T __attribute__((address_space(1))) *gview_rw(T *p) {
   return (T __attribute__((address_space(1))) *)p;
 }
 
-// 16-byte and complex loads through global views (native vector types: the
-// HIP vector structs cannot be copied from address-space-qualified lvalues).
-__device__ inline uint4 gload_u4(const void *p) {
-  typedef unsigned int v4u __attribute__((ext_vector_type(4)));
-  const v4u v = *gview(reinterpret_cast<const v4u *>(p));
-  return make_uint4(v.x, v.y, v.z, v.w);
-}
+// Complex loads through global views (native vector types: the HIP vector
+// structs cannot be copied from address-space-qualified lvalues).
 template <typename T2>
 __device__ inline T2 gload_c(const T2 *p) {
   typedef decltype(T2().x) T;
@@ -375,8 +370,6 @@ __device__ inline void slice4e(double x, int e, uint32_t (&o)[4]) {
   o[3] = bf16_bits_exact(float(n3) * 0x1p-24f);
 }
 
-// Same slices for xh = x 2^-e already in (-1, 1).
-__device__ inline void slice4(double xh, uint32_t (&o)[4]) { slice4e(xh, 0, o); }
 
 // Row exponent of the values the kernel slices itself (T and E'): smallest e
 // with mx (1 + 2^-7) < 2^e, so that |X| + 0x808080 < 2^31 in slice4_word.
@@ -429,22 +422,6 @@ __device__ inline void slice_mac(const Sl4 &X, const Sl4 &Y, f32x4 &hi, f32x4 &l
   lo = mma16(X.v[0], Y.v[2], lo);
   lo = mma16(X.v[1], Y.v[0], lo);
   lo = mma16(X.v[0], Y.v[1], lo);
-}
-
-// Pack the 8 values of one A-operand chunk into four slice registers.
-__device__ inline Sl4 make_slices(const double (&xh)[8]) {
-  Sl4 r;
-  uint32_t sl[8][4];
-#pragma unroll
-  for (int v = 0; v < 8; ++v) slice4(xh[v], sl[v]);
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    r.v[k].x = sl[0][k] | (sl[1][k] << 16);
-    r.v[k].y = sl[2][k] | (sl[3][k] << 16);
-    r.v[k].z = sl[4][k] | (sl[5][k] << 16);
-    r.v[k].w = sl[6][k] | (sl[7][k] << 16);
-  }
-  return r;
 }
 
 // Work split per site (eight waves): wave w owns column block c = w % 4 and
