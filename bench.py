@@ -305,10 +305,11 @@ def main():
                     help="kernel configuration of the counter runs (as reported by their autotune line)")
     ap.add_argument("--counter-scale", nargs=2, type=float, default=(2047.93, 1024.0),
                     metavar=("FETCH", "WRITE"), help="bytes per counted KiB (plain copy kernel)")
-    ap.add_argument("--config", choices=("fp32", "precision", "uneven"), default=None,
+    ap.add_argument("--config", choices=("fp32", "precision", "full_distinct", "uneven"), default=None,
                     help="only run a precision configuration at its stated size and print one JSON line: 'fp32' "
-                         "(50 qubits, 512 points, d=2, chi=32) or 'precision' (100 qubits, 2048 points, d=4, "
-                         "chi=64): every point simulated on the GPU, the full symmetric Gram in every form, "
+                         "(50 qubits, 512 points, d=2, chi=32), 'precision' (100 qubits, 2048 points, d=4, "
+                         "chi=64) or 'full_distinct' (the full-scale circuit, 165 qubits, d=8, chi=64, on 2048 "
+                         "distinct points): every point simulated on the GPU, the full symmetric Gram in every form, "
                          "|dK| against FP64 over all entries and against the oracle on the first 256 points; "
                          "'uneven' (four instances of 20, 60, 110, 165 qubits, 1600 train + 400 test points "
                          "each, all Gram jobs in one launch)")
@@ -1057,12 +1058,14 @@ def run(args, cpu):
 
     # ---------------------------------------------------------------- 4. every form on K[0:S, 0:C]
     C = min(max(args.block_cols, S), N)
-    sim.pack("split_i8")
-    gc = sim.gather(idx[:C], forms=("fp64", "split_i8"), stream=stream)
-    col_batch = {"fp64": gc, "split_i8": gc, form: gb}
+    others = tuple(f for f in FORMS if f != form)
+    for f in others:
+        sim.pack(f)
+    gc = sim.gather(idx[:C], forms=("fp64",) + others, stream=stream)
+    col_batch = {"fp64": gc, form: gb, **{f: gc for f in others}}
     tuned = {form: tune}
     Kblk, t_blk = {}, {}
-    for f in ("fp64", "split_i8", form):
+    for f in ("fp64",) + others + (form,):
         if f not in tuned and not args.no_tune:
             tuned[f] = q.autotune(sim, precision=f, sample=64, stream=stream)
         out = torch.zeros((S, C), dtype=torch.float64, device="cuda")
@@ -1091,7 +1094,7 @@ def run(args, cpu):
 
     # near-duplicate block: rows = the first D points, columns = their near-duplicates
     Knd = {}
-    for f in ("fp64", "split_i8", form):
+    for f in ("fp64",) + tuple(FORMS):
         out = torch.zeros((D, D), dtype=torch.float64, device="cuda")
         q.gram_block(sim, 0, D, sim, S, D, precision=f, out=out, stream=stream)
         Knd[f] = out

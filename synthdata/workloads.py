@@ -49,6 +49,10 @@ WORKLOADS = {
     "uneven_165": Workload("uneven_165", 2000, 165, 8, 2, 128, 1e-10, seed=3, n_test=400),
     # full scale: 165 qubits, 6400 points, chi = 64.
     "full": Workload("full", 6400, 165, 8, 2, 64, 1e-8, n_dirs=10, mean_scale=0.3),
+    # the full-scale circuit on 2048 distinct points (every point simulated):
+    # the precision of every form at 165 qubits beyond the timed workload's
+    # 240 distinct states.
+    "full_distinct": Workload("full_distinct", 2048, 165, 8, 2, 64, 1e-8, n_dirs=10, mean_scale=0.3),
     # paper-faithful bandwidth at 165 qubits (gamma = 0.1: coef_z = 2 gamma,
     # coef_xx = gamma^2 pi), d = 1, two repetitions.
     "paper_d1": Workload("paper_d1", 6400, 165, 1, 2, 64, 1e-8,
