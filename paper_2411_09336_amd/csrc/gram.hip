@@ -513,24 +513,25 @@ __device__ inline void split_gemm1(const SplitCtx &C, const uint8_t *B, const ui
 }
 
 // Slice four 4-value rows (u = 0, 1; q = re, im) with exponent ex into LDS
-// group row `grow` of buffer `buf`: A-operand group (grow, kc = u2 >> 1) where
-// u2 = 2 h + u is the 16-row tile of the contraction index.
+// group row `grow` of buffer `buf`: the 16-row tiles t = 2 h + u of the
+// contraction index are slots 0..3 (u = 0) and 4..7 (u = 1) of A-operand
+// group (grow, kc = h), so each lane stores one full 16-byte slot per slice
+// and plane (contiguous across the wave: no bank conflicts).
 __device__ inline void split_store(const SplitCtx &C, uint8_t *buf, int grow, const double (&V)[2][2][4], int ex) {
   const double scale = ldexp(1.0, 31 - ex);
+  uint8_t *dst = buf + size_t(grow * 2 + C.hf) * 8192 + C.lane * 16;
 #pragma unroll
-  for (int u = 0; u < 2; ++u) {
-    const int t = 2 * C.hf + u;
-    uint8_t *dst = buf + size_t(grow * 2 + (t >> 1)) * 8192 + C.lane * 16 + (t & 1) * 8;
+  for (int q = 0; q < 2; ++q) {
+    float sl[2][4][4];
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      float sl[4][4];
+    for (int u = 0; u < 2; ++u)
 #pragma unroll
-      for (int e = 0; e < 4; ++e) slice4_word(V[u][q][e], scale, sl[e]);
+      for (int e = 0; e < 4; ++e) slice4_word(V[u][q][e], scale, sl[u][e]);
 #pragma unroll
-      for (int k = 0; k < 4; ++k)
-        *reinterpret_cast<uint2 *>(dst + (k * 2 + q) * 1024) =
-            make_uint2(pack_bf16_pair(sl[0][k], sl[1][k]), pack_bf16_pair(sl[2][k], sl[3][k]));
-    }
+    for (int k = 0; k < 4; ++k)
+      *reinterpret_cast<uint4 *>(dst + (k * 2 + q) * 1024) =
+          make_uint4(pack_bf16_pair(sl[0][0][k], sl[0][1][k]), pack_bf16_pair(sl[0][2][k], sl[0][3][k]),
+                     pack_bf16_pair(sl[1][0][k], sl[1][1][k]), pack_bf16_pair(sl[1][2][k], sl[1][3][k]));
   }
 }
 
