@@ -207,6 +207,49 @@ def _oracle_worker(task):
             return n, dt
 
 
+def _oracle_sim_worker(task):
+    """One worker of the simulation baseline: the oracle simulates circuit k
+    of the full workload (one BLAS thread) and returns its seconds."""
+    k, routing = task
+    import numpy  # noqa: F401  (BLAS loaded first, so that the limit below applies to it)
+    try:
+        import threadpoolctl
+        threadpoolctl.threadpool_limits(1)
+    except Exception:
+        pass
+    import synthdata as sd
+    from oracle import mps as omps
+    w = sd.WORKLOADS["full"]
+    x = sd.workload_features(w, k + 1)[k]
+    t0 = time.perf_counter()
+    r = omps.simulate(x, w.distance, w.reps, w.chi, w.cutoff, w.coef_z, w.coef_xx, routing=routing)
+    return time.perf_counter() - t0, max(r.bond_dims)
+
+
+def cpu_simulation_baseline(n, routing, workers):
+    """The oracle's simulation of n circuits of the full workload (165 qubits,
+    d = 8, chi = 64) in a pool of `workers` processes on the host cores: one
+    JSON line with seconds per circuit and circuits/s.  No GPU use."""
+    import multiprocessing as mp
+    host = host_cpu_description()
+    workers = workers or max(1, min(16, host["available"] or 1))
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(workers) as pool:
+        out = []
+        for dt, bond in pool.imap_unordered(_oracle_sim_worker, [(k, routing) for k in range(n)]):
+            out.append((dt, bond))
+            log(f"[bench] oracle simulation: {len(out)}/{n} circuits, last {dt:.1f} s")
+    wall = time.perf_counter() - t0
+    secs = [dt for dt, _ in out]
+    print(json.dumps({"cpu_simulation": {
+        "circuits": n, "workers": workers, "wall_s": round(wall, 2), "circuits_per_s": round(n / wall, 4),
+        "seconds_per_circuit_mean": round(sum(secs) / n, 2), "seconds_per_circuit_max": round(max(secs), 2),
+        "max_bond": max(b for _, b in out), "routing": routing,
+        "workload": "165 qubits, d=8, reps=2, chi=64, cutoff=1e-8 (the full workload's circuit)",
+        "kind": "oracle (NumPy complex128, LAPACK SVD, one BLAS thread per process)",
+        "cpu_model": host["model"], "nproc": host["nproc"], "cpus_available": host["available"]}}), flush=True)
+
+
 class CpuBaseline:
     """The oracle timed on the host cores: `workers` processes forked before
     any GPU call (so none of them holds GPU state), each computing overlaps
@@ -298,6 +341,10 @@ def main():
                     help="interaction-distance sweep (100 qubits, gamma 1, d = 2..12, 8 points each): "
                          "simulation and overlap times, largest bond and memory per MPS, against the CPU "
                          "oracle where it finishes in seconds; one JSON line, then exit")
+    ap.add_argument("--cpu-sim", type=int, default=0, metavar="N",
+                    help="only time the oracle's simulation of N full-workload circuits on the host cores "
+                         "(process pool of --cpu-workers, default min(16, available cores)); one JSON line, "
+                         "no GPU use")
     ap.add_argument("--counter-record", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="only write profiles/gram_<form>_counters.json from rocprofv3 counter CSVs of "
                          "'--steps-run 1' runs (no GPU use), then exit")
@@ -337,6 +384,9 @@ def main():
     default_run = not (args.calibrate_copy or args.kernel_probe or args.d_sweep or args.svm or args.config)
     if args.oracle_gram:
         oracle_gram_file(args.oracle_gram, args.cpu_workers)
+        return
+    if args.cpu_sim > 0:
+        cpu_simulation_baseline(args.cpu_sim, args.routing, args.cpu_workers)
         return
     cpu = None
     if default_run and not args.no_cpu and args.steps_run == 0:
@@ -657,12 +707,12 @@ def _oracle_rows(task):
     j >= i, whose site tensors are read from a memory-mapped file (one flat
     complex128 array, offsets per site), one BLAS thread."""
     rows, path, meta = task
+    import numpy as np   # BLAS loaded first, so that the limit below applies to it
     try:
         import threadpoolctl
         threadpoolctl.threadpool_limits(1)
     except Exception:
         pass
-    import numpy as np
     from oracle import gram as ogram
     buf = np.load(path, mmap_mode="r")
     mps = [[np.asarray(buf[o:o + int(np.prod(sh))]).reshape(sh) for (o, sh) in sites] for sites in meta]
