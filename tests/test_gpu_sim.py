@@ -274,6 +274,29 @@ def test_graph_replayed_simulation_bit_identical():
         assert torch.equal(q.gram(g, precision="fp64"), K0)
 
 
+def test_graph_replay_large_batch_bit_identical():
+    """The 512 circuits of the 50-qubit workload in replays of 300 (one replay
+    larger than the 256 workgroups the chip holds at once, and a ragged one
+    of 212): bond dimensions, truncation statistics and the FP64 Gram equal
+    the eager batch bit for bit."""
+    import paper_2411_09336_amd as q
+    torch = require_gpu()
+    w = sd.WORKLOADS["fp32"]
+    X = sd.workload_features(w)
+    assert len(X) == 512
+    xt = torch.tensor(X, dtype=torch.float64, device="cuda")
+    spec = q.CircuitSpec(w.n_qubits, w.distance, w.reps, w.coef_z, w.coef_xx, 0)
+    ref = q.simulate(xt, spec, w.chi, w.cutoff)
+    g = q.simulate(xt, spec, w.chi, w.cutoff, graph_circuits=300)
+    assert np.array_equal(g.bond_dims(), ref.bond_dims())
+    for a, b in zip(g.trunc_stats(), ref.trunc_stats()):
+        assert np.array_equal(a, b)
+    for i in (0, 255, 256, 299, 300, 511):
+        for a, b in zip(g.export(i), ref.export(i)):
+            assert np.array_equal(a, b)
+    assert torch.equal(q.gram(g, precision="fp64"), q.gram(ref, precision="fp64"))
+
+
 def test_graph_replay_arguments():
     import paper_2411_09336_amd as q
     torch = require_gpu()
