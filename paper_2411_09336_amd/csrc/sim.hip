@@ -52,6 +52,10 @@ constexpr int kSvThreads = kSvWaves * 64; // 1024
 constexpr int kSvMaxN = 128;
 constexpr int kMaxSweeps = 30;
 constexpr double kJacobiTol = 1e-14;
+// A sweep whose rotations all have |<X,Y>| below kJacobiLarge |X| |Y| ends
+// the iteration: cyclic Jacobi converges quadratically, so the next sweep's
+// would fall below kJacobiTol and rotate nothing.
+constexpr double kJacobiLarge = 1e-8;
 // columns whose weight is below this fraction of ||M||_F^2 are numerical zeros
 constexpr double kZeroWeight = 1e-28;
 constexpr double kDegenerateGap = 1e-10;
@@ -248,7 +252,8 @@ __device__ inline double quad_sum(double x) {
 // <X', Y'>; the outputs are stored exchanged, Y' in the slot of X and X' in
 // the slot of Y.  Every lane then forms A' = pa P + wa Q, B' = pb R + wb S
 // with (P, Q, R, S) = (A, B, A, B) for TYPE 0 and (B_{l-1}, A, B, A_{l+1})
-// for TYPE 1.  Returns whether this wave rotated some pair.
+// for TYPE 1.  Returns whether this wave rotated some pair by more than
+// kJacobiLarge (relative |<X,Y>|).
 //
 // Column norms: a FULL round reduces |X|^2 and |Y|^2 with <X, Y> and stores
 // them; the other rounds reduce <X, Y> only and update the stored norms by
@@ -292,7 +297,7 @@ __device__ __forceinline__ bool jacobi_round(double (&Ar)[kSvRows], double (&Ai)
   // rotation parameters: waves 0..3, lane = 4 j + q sums the partials of
   // pair 16 wave + j over waves 4q..4q+3, then over the quad
   const int npairs = TYPE == 0 ? H : H - 1;
-  bool rotated = false;
+  bool large = false;
   if (wave < 4 && 16 * wave < npairs) {
     const int j = lane >> 2, q = lane & 3, pr = 16 * wave + j;
     // positions of X and Y
@@ -320,7 +325,7 @@ __device__ __forceinline__ bool jacobi_round(double (&Ar)[kSvRows], double (&Ai)
     y = quad_sum(y);
     const double g2 = fma(x, x, y * y);
     const bool rot = pr < npairs && a > zero_w && b > zero_w && g2 > (kJacobiTol * kJacobiTol) * (a * b);
-    rotated = __any(rot);
+    large = __any(rot && g2 > (kJacobiLarge * kJacobiLarge) * (a * b));
     if (pr < npairs && q < 2) {
       double c = 1.0, s = 0.0, ur = 1.0, ui = 0.0, tg = 0.0;
       if (rot) {
@@ -374,7 +379,7 @@ __device__ __forceinline__ bool jacobi_round(double (&Ar)[kSvRows], double (&Ai)
     Br[rr] = fma(pb, rr_, fma(wbr, sr, -wbi * si));
     Bi[rr] = fma(pb, ri, fma(wbr, si, wbi * sr));
   }
-  return rotated;
+  return large;
 }
 
 // One entry of the step list shared by every circuit of a batch: a run of
@@ -640,13 +645,13 @@ __device__ __attribute__((noinline)) void svd_step(const SvParams &P, const int6
   bool converged = false;
   int sweep = 0;
   for (; sweep < kMaxSweeps && !converged; ++sweep) {
-    bool rotated = jacobi_round<0, true>(Ar, Ai, Br, Bi, sh, wave, H, zw);  // wave-uniform
-    if (H > 1) rotated |= jacobi_round<1, false>(Ar, Ai, Br, Bi, sh, wave, H, zw);
+    bool large = jacobi_round<0, true>(Ar, Ai, Br, Bi, sh, wave, H, zw);  // wave-uniform
+    if (H > 1) large |= jacobi_round<1, false>(Ar, Ai, Br, Bi, sh, wave, H, zw);
     for (int half = 1; half < H; ++half) {
-      rotated |= jacobi_round<0, false>(Ar, Ai, Br, Bi, sh, wave, H, zw);
-      rotated |= jacobi_round<1, false>(Ar, Ai, Br, Bi, sh, wave, H, zw);
+      large |= jacobi_round<0, false>(Ar, Ai, Br, Bi, sh, wave, H, zw);
+      large |= jacobi_round<1, false>(Ar, Ai, Br, Bi, sh, wave, H, zw);
     }
-    converged = __syncthreads_or(rotated ? 1 : 0) == 0;
+    converged = __syncthreads_or(large ? 1 : 0) == 0;
   }
 
   // ---------------------------------------------------------- norms, order, k
