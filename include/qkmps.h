@@ -244,7 +244,7 @@ typedef struct {
   int32_t workgroups;   /* persistent workgroups launched                     */
   int32_t tile_side;    /* pair-tile side of the kernel configuration         */
   int32_t queues;       /* work queues (1, or one per XCD)                    */
-  int32_t block;        /* block size of the FP64 / FP32 forms (32 or 64)     */
+  int32_t block;        /* block size of the FP64 / FP32 forms (32, 64, 128)  */
   double flops;         /* algorithmic flops of the contracted overlaps: 8 per */
                         /* complex MAC of Fig. 2's site updates, counted from  */
                         /* the actual bond dimensions of every pair            */
@@ -257,9 +257,11 @@ typedef struct {
  * If b == NULL or b == a the matrix is symmetric: only i <= j is contracted
  * and mirrored (the diagonal is computed, not assumed).
  * `a` and `b` must have the same m.  The precision's packed form is built
- * (and kept) on first use.  The MFMA kernels support bond pads up to 64
- * (bond dimensions up to 64): QK_ENOTSUP for larger batches.  `stats` may
- * be NULL. */
+ * (and kept) on first use.  The FP64 and FP32 forms support bond pads up
+ * to 128 (bond dimensions up to 128; above 64 with E in a global scratch
+ * slot of 2 x 128 x 128 complex values per workgroup, drawn from the
+ * device's allocator for the call), the split forms up to 64: QK_ENOTSUP
+ * for larger batches.  `stats` may be NULL. */
 qk_status mps_gram(const qk_mps_batch *a, const qk_mps_batch *b,
                    qk_precision prec, double *K_dev, int64_t ldk,
                    void *hip_stream, qk_gram_stats *stats);
@@ -283,7 +285,9 @@ qk_status mps_gram_block(const qk_mps_batch *a, int64_t a0, int64_t na,
  * array of QK_NOALLOC_SCRATCH_BYTES per device, held from the library's
  * set-up on that device until the process ends, and both batches must
  * already hold the precision's packed planes (mps_batch_pack; QK_FP64 is
- * always present) -- QK_ENOTSUP otherwise, before any launch.  QK_EINVAL,
+ * always present) and bond pads up to 64 (the kernels for pads up to 128
+ * need per-workgroup scratch beyond the array) -- QK_ENOTSUP otherwise,
+ * before any launch.  QK_EINVAL,
  * before any launch, when the work queue does not fit the array: with the
  * default pair tiles of side 16 that is about 520,000 tiles, e.g. a
  * symmetric Gram of up to ~16,000 MPS.  Every call on a device uses that
@@ -314,8 +318,9 @@ qk_status mps_gram_multi(const qk_gram_job *jobs, int32_t n_jobs,
                          qk_gram_stats *stats);
 
 /* Autotuner of the Gram kernels' tile shapes.  For `prec` and the bond-pad
- * bucket of batch `b` (pads <= 32 or <= 64), every valid configuration (block
- * size 32 or 64 for the FP64 / FP32 forms when the pads allow, pair-tile
+ * bucket of batch `b` (pads <= 32, <= 64 or <= 128), every valid configuration
+ * (block size 32 or 64 for the FP64 / FP32 forms when the pads allow, 128
+ * above 64, pair-tile
  * side 8 / 16 / 32, one work queue or one per XCD) computes the symmetric
  * Gram of the first min(sample, n) MPS of `b` (one warm-up run, then the
  * best of two timed runs, wall clock including the launch's host work).

@@ -66,6 +66,15 @@ __device__ inline T2 gload_c(const T2 *p) {
   r.y = v.y;
   return r;
 }
+template <typename T2>
+__device__ inline void gstore_c(T2 *p, T2 v) {
+  typedef decltype(T2().x) T;
+  typedef T v2 __attribute__((ext_vector_type(2)));
+  v2 w;
+  w.x = v.x;
+  w.y = v.y;
+  *gview_rw(reinterpret_cast<v2 *>(p)) = w;
+}
 constexpr int kThreads = 256;
 
 struct GramTile {
@@ -292,6 +301,135 @@ __device__ void overlap_plain(const GramJobDev &J, int64_t ia, int64_t ib, T2 *E
   ov_im = E[0].y;
   ov_exp = expacc;
   __syncthreads();
+}
+
+// ------------------------------------------------------------------------
+// FP64 / FP32 forms for bond pads up to 128.  E (128 x 128 complex, 256 KiB
+// in FP64) is above one CU's LDS, so it lives in a slot of global scratch
+// per workgroup, where it stays in L2: two buffers, E read and E' written,
+// each in the A-operand fragment order of the LDS variant above.  Eight
+// waves; wave w computes E' for the ket column block w.  T_s passes from
+// GEMM1 to GEMM2 one 16-row block at a time, so only the accumulators of
+// the wave's E' block (8 x 16 x 16 complex) are held across the site.
+constexpr int kWideP = 128;
+constexpr int kWideThreads = 512;
+constexpr int kWideWaves = kWideThreads / 64;
+
+template <typename T, typename V4, typename T2>
+__device__ void overlap_wide(const GramJobDev &J, int64_t ia, int64_t ib, T2 *E0, T2 *E1, T *s_red,
+                             T &ov_re, T &ov_im, int &ov_exp) {
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int j = lane & 15, g = lane >> 4;
+  const T2 *abase = reinterpret_cast<const T2 *>(J.a_base) + ia * J.a_stride;
+  const T2 *bbase = reinterpret_cast<const T2 *>(J.b_base) + ib * J.b_stride;
+  T2 *Ec = E0, *En = E1;
+  {
+    // E_0 = [[1]] on the first site's pads (element [0][0] is lane 0 of
+    // fragment 0)
+    const int n0 = gview(J.a_pad)[0] * gview(J.b_pad)[0];
+    for (int x = tid; x < n0; x += kWideThreads) {
+      T2 z;
+      z.x = x == 0 ? T(1) : T(0);
+      z.y = T(0);
+      gstore_c(Ec + x, z);
+    }
+    __syncthreads();
+  }
+  int expacc = 0;
+  constexpr int NT = kWideP / 16;
+  const int ct = wave;
+  for (int l = 0; l < J.m; ++l) {
+    const int Da = gview(J.a_pad)[l], Dan = gview(J.a_pad)[l + 1], Db = gview(J.b_pad)[l], Dbn = gview(J.b_pad)[l + 1];
+    const T2 *A = abase + gview(J.a_off)[l];
+    const T2 *B = bbase + gview(J.b_off)[l];
+    const int nrt = Da / 16, nkq = Db / 4, nat = Dan / 16, nct = Dbn / 16, nkqn = Dbn / 4;
+    V4 Ep[NT][2];
+#pragma unroll
+    for (int at = 0; at < NT; ++at) {
+      Ep[at][0] = V4{0, 0, 0, 0};
+      Ep[at][1] = V4{0, 0, 0, 0};
+    }
+    if (ct < nct) {
+      for (int s = 0; s < 2; ++s) {
+        const T2 *Bc = B + size_t(s) * Db * Dbn + 16 * ct + j;
+        for (int rt = 0; rt < nrt; ++rt) {
+          // GEMM1 on row block rt: T_s[a][b'] = sum_b E[a][b] B_s[b][b'],
+          // real and imaginary parts of E in separate accumulators (two
+          // independent MFMA chains per output)
+          V4 t0 = V4{0, 0, 0, 0}, t1 = V4{0, 0, 0, 0}, u0 = V4{0, 0, 0, 0}, u1 = V4{0, 0, 0, 0};
+          const T2 *Er = Ec + size_t(rt) * nkq * 64 + lane;
+#pragma unroll 4
+          for (int kq = 0; kq < nkq; ++kq) {
+            const T2 bv = gload_c(Bc + size_t(4 * kq + g) * Dbn);
+            const T2 ev = gload_c(Er + kq * 64);
+            t0 = mma(ev.x, bv.x, t0);
+            t1 = mma(ev.x, bv.y, t1);
+            u0 = mma(ev.y, -bv.y, u0);
+            u1 = mma(ev.y, bv.x, u1);
+          }
+          t0 += u0;
+          t1 += u1;
+          // GEMM2: E'^T[b'][a'] += sum_{a in block rt} T_s[a][b'] conj(A_s[a][a'])
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const T tr = t0[e], ti = t1[e];
+            const int a = 16 * rt + acc_row<T>(g, e);
+            const T2 *arow = A + (size_t(s) * Da + a) * Dan + j;
+#pragma unroll
+            for (int at = 0; at < NT; ++at) {
+              if (at < nat) {
+                const T2 av = gload_c(arow + 16 * at);
+                Ep[at][0] = mma(tr, av.x, Ep[at][0]);
+                Ep[at][0] = mma(ti, av.y, Ep[at][0]);
+                Ep[at][1] = mma(ti, av.x, Ep[at][1]);
+                Ep[at][1] = mma(-tr, av.y, Ep[at][1]);
+              }
+            }
+          }
+        }
+      }
+    }
+    T lmax = T(0);
+#pragma unroll
+    for (int at = 0; at < NT; ++at)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) lmax = fmax(lmax, fmax(fabs(Ep[at][0][e]), fabs(Ep[at][1][e])));
+    lmax = wave_max(lmax);
+    if (lane == 0) s_red[wave] = lmax;
+    __syncthreads();
+    T gmax = s_red[0];
+#pragma unroll
+    for (int w = 1; w < kWideWaves; ++w) gmax = fmax(gmax, s_red[w]);
+    const int e2 = gmax > T(0) ? ilogb(gmax) : 0;
+    const T scale = ldexp(T(1), -e2);
+    expacc += e2;
+    if (ct < nct) {
+#pragma unroll
+      for (int at = 0; at < NT; ++at) {
+        if (at < nat) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            T2 v;
+            v.x = Ep[at][0][e] * scale;
+            v.y = Ep[at][1][e] * scale;
+            // E'[16 at + j][bp] -> fragment (at, bp / 4), lane j + 16 (bp % 4)
+            const int bp = 16 * ct + acc_row<T>(g, e);
+            gstore_c(En + (at * nkqn + (bp >> 2)) * 64 + j + 16 * (bp & 3), v);
+          }
+        }
+      }
+    }
+    // E' complete and visible to the workgroup; s_red free for the next site
+    __syncthreads();
+    T2 *t = Ec;
+    Ec = En;
+    En = t;
+  }
+  const T2 r = gload_c(Ec);
+  ov_re = r.x;
+  ov_im = r.y;
+  ov_exp = expacc;
+  __syncthreads();   // every wave has read the result before the next pair overwrites it
 }
 
 // A pointer that is the same in every lane, moved to scalar registers.
@@ -1138,6 +1276,74 @@ qk_status launch_one(const GramJobDev *jobs_dev, const GramTile *tiles_dev, int6
   return QK_OK;
 }
 
+// Gram kernel of the plain forms for bond pads up to 128: one pair per
+// workgroup at a time, E and E' in the workgroup's slot of escratch.
+constexpr size_t kWideSlot = size_t(2) * kWideP * kWideP;   // complex elements per workgroup
+
+template <int PREC>
+__global__ __launch_bounds__(kWideThreads, 1) void gram_wide_kernel(const GramJobDev *__restrict__ jobs,
+                                                                  const GramTile *__restrict__ tiles,
+                                                                  int64_t n_tiles, int nq, int side,
+                                                                  unsigned long long *counters, uint8_t *escratch) {
+  __shared__ int64_t s_slot;
+  __shared__ double s_red[kWideWaves];
+  int job;
+  int64_t i, j;
+  bool valid;
+  while (next_pair(jobs, tiles, n_tiles, nq, side, counters, &s_slot, &job, &i, &j, &valid)) {
+    if (!valid) continue;
+    const GramJobDev &J = jobs[job];
+    double k;
+    if constexpr (PREC == QK_FP64) {
+      double2 *E = reinterpret_cast<double2 *>(escratch) + blockIdx.x * kWideSlot;
+      double re, im;
+      int ex;
+      overlap_wide<double, f64x4, double2>(J, J.a0 + i, J.b0 + j, E, E + kWideP * kWideP, s_red, re, im, ex);
+      k = ldexp(re * re + im * im, 2 * ex);
+    } else {
+      float2 *E = reinterpret_cast<float2 *>(escratch) + blockIdx.x * kWideSlot;
+      float re, im;
+      int ex;
+      overlap_wide<float, f32x4, float2>(J, J.a0 + i, J.b0 + j, E, E + kWideP * kWideP,
+                                         reinterpret_cast<float *>(s_red), re, im, ex);
+      k = ldexp(double(re) * re + double(im) * im, 2 * ex);
+    }
+    if (threadIdx.x == 0) write_k(J, i, j, k);
+  }
+}
+
+template <int PREC>
+qk_status launch_wide(const GramJobDev *jobs_dev, const GramTile *tiles_dev, int64_t n_tiles,
+                      unsigned long long *counters, const GramConfig &cfg, const DevAlloc &al, hipStream_t stream,
+                      int *grid_out, hipEvent_t ev0, hipEvent_t ev1) {
+  int dev = 0, cus = 256;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  auto kern = gram_wide_kernel<PREC>;
+  int per_cu = 0;
+  QK_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kWideThreads, 0));
+  per_cu = std::max(per_cu, 1);
+  int64_t grid = int64_t(cus) * per_cu;
+  grid = std::min<int64_t>(grid, std::max<int64_t>(n_tiles * cfg.tile_side * cfg.tile_side, 1));
+  const int nq = int(std::min<int64_t>(cfg.queues, grid));
+  // one E / E' slot per workgroup
+  const size_t slot = (PREC == QK_FP64 ? sizeof(double2) : sizeof(float2)) * kWideSlot;
+  uint8_t *es = static_cast<uint8_t *>(dev_alloc(al, slot * size_t(grid), stream, true));
+  if (!es) return fail(QK_ENOMEM, "device allocation of the Gram E scratch failed");
+  qk_status st = QK_OK;
+  if (ev0 && hipEventRecord(ev0, stream) != hipSuccess) st = fail(QK_EDEVICE, "event record failed");
+  if (st == QK_OK) {
+    hipLaunchKernelGGL(kern, dim3(unsigned(grid)), dim3(kWideThreads), 0, stream, jobs_dev, tiles_dev, n_tiles, nq,
+                       cfg.tile_side, counters, es);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) st = fail(QK_EDEVICE, std::string("Gram kernel launch -> ") + hipGetErrorString(e));
+  }
+  if (st == QK_OK && ev1 && hipEventRecord(ev1, stream) != hipSuccess) st = fail(QK_EDEVICE, "event record failed");
+  dev_free(al, es, stream, true);
+  *grid_out = int(grid);
+  return st;
+}
+
 }  // namespace
 
 // Device scratch of the allocation-free Gram entry point: work-queue
@@ -1172,7 +1378,11 @@ qk_status noalloc_scratch(void **ptr) {
 qk_status launch_gram_cfg(const std::vector<GramJobDev> &jobs_in, int max_pad, qk_precision prec,
                           const GramConfig &cfg, hipStream_t stream, qk_gram_stats *stats, void *ws_given,
                           size_t ws_cap) {
-  if (max_pad > 64) return fail(QK_ENOTSUP, "Gram kernels support bond pads up to 64");
+  if (max_pad > kWideP) return fail(QK_ENOTSUP, "Gram kernels support bond pads up to 128");
+  if (max_pad > 64 && prec != QK_FP64 && prec != QK_FP32)
+    return fail(QK_ENOTSUP, "the split forms support bond pads up to 64");
+  if (max_pad > 64 && ws_given)
+    return fail(QK_ENOTSUP, "the allocation-free Gram supports bond pads up to 64");
   if (cfg.maxp < max_pad) return fail(QK_EINVAL, "tile configuration smaller than the batch's bond pads");
   const int side = cfg.tile_side;
   std::vector<GramJobDev> jobs = jobs_in;
@@ -1235,7 +1445,10 @@ qk_status launch_gram_cfg(const std::vector<GramJobDev> &jobs_in, int max_pad, q
     st = fail(QK_EDEVICE, "event creation failed");
   int grid = 0;
   if (st == QK_OK) {
-    if (prec == QK_FP64)
+    if (cfg.maxp == kWideP && (prec == QK_FP64 || prec == QK_FP32))
+      st = prec == QK_FP64 ? launch_wide<QK_FP64>(jobs_dev, tiles_dev, n_tiles, counters, cfg, al, stream, &grid, ev0, ev1)
+                           : launch_wide<QK_FP32>(jobs_dev, tiles_dev, n_tiles, counters, cfg, al, stream, &grid, ev0, ev1);
+    else if (prec == QK_FP64)
       st = cfg.maxp == 32 ? launch_one<QK_FP64, 32>(jobs_dev, tiles_dev, n_tiles, counters, cfg, stream, &grid, ev0, ev1)
                           : launch_one<QK_FP64, 64>(jobs_dev, tiles_dev, n_tiles, counters, cfg, stream, &grid, ev0, ev1);
     else if (prec == QK_FP32)
@@ -1262,7 +1475,7 @@ qk_status launch_gram_cfg(const std::vector<GramJobDev> &jobs_in, int max_pad, q
 
 // ------------------------------------------------------------------------
 // Kernel configurations and the autotuner.  A configuration is the block
-// size of the plain forms (32 or 64), the pair-tile side and the number of
+// size of the plain forms (32, 64, or 128 with E in global scratch), the pair-tile side and the number of
 // work queues.  Defaults were chosen by measurement on 165-site chi = 64
 // batches; mps_gram_autotune times every valid configuration on a sample of
 // the caller's batch and stores the fastest per (device, form, pad bucket).
@@ -1271,13 +1484,12 @@ namespace {
 std::mutex g_tune_mu;
 std::map<std::tuple<int, int, int>, GramConfig> g_tuned;
 
-int pad_bucket(int max_pad) { return max_pad <= 32 ? 32 : 64; }
+int pad_bucket(int max_pad) { return max_pad <= 32 ? 32 : max_pad <= 64 ? 64 : 128; }
 }  // namespace
 
 GramConfig default_gram_config(qk_precision prec, int max_pad) {
-  (void)max_pad;
   GramConfig c;
-  c.maxp = 64;
+  c.maxp = max_pad > 64 ? kWideP : 64;
   c.tile_side = kDefaultTileSide;
   c.queues = prec == QK_SPLIT_I8 ? kQueues : 1;
   return c;
@@ -1285,7 +1497,7 @@ GramConfig default_gram_config(qk_precision prec, int max_pad) {
 
 std::vector<GramConfig> gram_config_candidates(qk_precision prec, int max_pad) {
   std::vector<GramConfig> out;
-  std::vector<int> maxps{64};
+  std::vector<int> maxps{max_pad > 64 ? kWideP : 64};
   if ((prec == QK_FP64 || prec == QK_FP32) && max_pad <= 32) maxps.push_back(32);
   for (int mp : maxps)
     for (int side : {8, 16, 32})

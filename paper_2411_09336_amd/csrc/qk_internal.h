@@ -164,7 +164,7 @@ struct GramJobDev {
   int64_t pair_begin;              // first flat pair index of this job
 };
 
-// Gram kernel configuration: block size of the plain forms (32 or 64), pair
+// Gram kernel configuration: block size of the plain forms (32, 64 or 128), pair
 // tile side, number of work queues (1, or one per XCD).
 struct GramConfig {
   int maxp = 64;
