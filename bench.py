@@ -360,6 +360,8 @@ def main():
                          "|dK| against FP64 over all entries and against the oracle on the first 256 points; "
                          "'uneven' (four instances of 20, 60, 110, 165 qubits, 1600 train + 400 test points "
                          "each, all Gram jobs in one launch)")
+    ap.add_argument("--wide-points", type=int, default=256,
+                    help="--config uneven: points of the bond-128 instance (165 qubits, d=8; 3/4 train, 1/4 test)")
     ap.add_argument("--oracle-gram", metavar="MPS_NPY", default=None,
                     help=argparse.SUPPRESS)   # child process of --config: the oracle's Gram of a file of MPS
     ap.add_argument("--routing", type=int, default=0,
@@ -904,16 +906,18 @@ def config_uneven(args):
     """The uneven batch (Sec. II-D batching): four instances with qubit
     counts 20, 60, 110 and 165, interaction distances 1, 3, 5, 8 and bond caps
     16, 32, 64, 128; 2000 points each (the first 1600 train, the last 400
-    test).  Each instance is simulated by one HIP graph that records a
-    chunk of circuits from start to end, replayed over the batch (two
-    replays of 1000 circuits); the Gram kernels are
-    autotuned per bond-pad bucket and form; then, per form, ONE persistent
-    launch computes every instance's 400 x 1600 test x train block and its
-    symmetric 1600 x 1600 train Gram.  |dK| of each form against FP64 over
-    all entries, and of every form against the oracle's overlaps of 48 train
-    and 16 test MPS per instance (a child process on the host cores).  The
-    bond-128 instance is outside the kernels' range (QK_ENOTSUP) and is
-    reported as such."""
+    test).  Each instance with bond cap <= 64 is simulated by one HIP graph
+    that records a chunk of circuits from start to end, replayed over the
+    batch (two replays of 1000 circuits); the Gram kernels are autotuned per
+    bond-pad bucket and form; then, per form, ONE persistent launch computes
+    every such instance's 400 x 1600 test x train block and its symmetric
+    1600 x 1600 train Gram.  The bond-128 instance runs on its first
+    --wide-points points (3/4 train, 1/4 test; eager simulation with progress
+    lines, since each circuit takes minutes) in the FP64 and FP32 forms (the
+    split forms take pads up to 64), in a launch of its own.  |dK| of each
+    form against FP64 over all entries, and of every form against the
+    oracle's overlaps of 48 train and 16 test MPS per instance (6 and 2 for
+    the bond-128 instance; a child process on the host cores)."""
     import numpy as np
     import torch
 
@@ -922,63 +926,77 @@ def config_uneven(args):
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
     forms = ("fp64", "split_bf16", "split_i8")
-    inst, report = {}, {}
+    wide_forms = ("fp64", "fp32")
+    inst, report, inst_forms = {}, {}, {}
     for name in ("uneven_20", "uneven_60", "uneven_110", "uneven_165"):
         w = sd.WORKLOADS[name]
-        N, ntr = w.n_points, w.n_points - w.n_test
-        X = sd.workload_features(w)
+        wide = w.chi > 64
+        N = min(args.wide_points, w.n_points) if wide else w.n_points
+        ntr = N * 3 // 4 if wide else w.n_points - w.n_test
+        X = sd.workload_features(w, N)
         spec = q.CircuitSpec(w.n_qubits, w.distance, w.reps, w.coef_z, w.coef_xx, 0)
         xt = torch.tensor(X, dtype=torch.float64, device="cuda")
         log(f"[bench] uneven: simulating {name}: {N} circuits, {w.n_qubits} qubits, d={w.distance}, chi={w.chi}")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        try:
+        if wide:
+            def progress(done, total, name=name, t0=t0):
+                log(f"[bench] uneven: {name}: {done} / {total} two-qubit gates, {time.perf_counter() - t0:.0f} s")
+                return False
+            b = q.simulate(xt, spec, w.chi, w.cutoff, stream=stream, progress=progress, every=1000)
+        else:
             b = q.simulate(xt, spec, w.chi, w.cutoff, stream=stream, graph_circuits=0)
-        except q.QKError as e:
-            report[name] = {"status": "not supported", "error": str(e)}
-            log(f"[bench] uneven: {name}: {e}")
-            continue
         stream.synchronize()
         t_sim = time.perf_counter() - t0
         info = b.info()
-        for f in forms:
+        fs = wide_forms if wide else forms
+        for f in fs:
             b.pack(f, stream=stream)
-        train = b.gather(list(range(ntr)), forms=forms, stream=stream)
-        test = b.gather(list(range(ntr, N)), forms=forms, stream=stream)
+        train = b.gather(list(range(ntr)), forms=fs, stream=stream)
+        test = b.gather(list(range(ntr, N)), forms=fs, stream=stream)
         inst[name] = (w, b, train, test, ntr, N - ntr)
+        inst_forms[name] = fs
         report[name] = {"status": "ok", "n_qubits": w.n_qubits, "distance": w.distance, "chi": w.chi,
                         "train": ntr, "test": N - ntr, "simulation_s": round(t_sim, 2),
+                        "circuits_per_s": round(N / t_sim, 2), "forms": list(fs),
                         "two_qubit_gates_per_circuit": info["n_two_qubit_gates"], "max_bond": info["max_bond"],
                         "degenerate_cuts": info["degenerate_cuts"], "unconverged_svds": info["unconverged_svds"]}
-        log(f"[bench] uneven: {name}: simulated in {t_sim:.1f} s (HIP graph replays), max bond {info['max_bond']}")
-    # kernel configurations per form and bond-pad bucket (pads <= 32, <= 64)
+        how = "eager, one launch per 1000 gates" if wide else "HIP graph replays"
+        log(f"[bench] uneven: {name}: simulated in {t_sim:.1f} s ({how}), max bond {info['max_bond']}")
+    # kernel configurations per form and bond-pad bucket (pads <= 32, <= 64, <= 128)
     tuned = {}
-    for f in forms:
-        for name, (w, b, train, test, ntr, nte) in inst.items():
+    for name, (w, b, train, test, ntr, nte) in inst.items():
+        for f in inst_forms[name]:
             tuned[f"{f}/{name}"] = q.autotune(train, precision=f, sample=64, stream=stream)
     log(f"[bench] uneven: autotuned {len(tuned)} (form, instance) samples")
-    K, launch = {}, {}
-    for f in forms:
-        jobs, outs = [], {}
-        for name, (w, b, train, test, ntr, nte) in inst.items():
+    K, launch = {f: {} for f in forms + wide_forms}, {}
+    # one launch per form for the instances with pads <= 64, one per form for the bond-128 instance
+    groups = [(f, [n for n in inst if f in inst_forms[n] and inst[n][0].chi <= 64], "") for f in forms]
+    groups += [(f, [n for n in inst if inst[n][0].chi > 64], " (bond 128)") for f in wide_forms]
+    for f, names, tag in groups:
+        if not names:
+            continue
+        jobs = []
+        for name in names:
+            w, b, train, test, ntr, nte = inst[name]
             kr = torch.zeros((nte, ntr), dtype=torch.float64, device="cuda")
             kt = torch.zeros((ntr, ntr), dtype=torch.float64, device="cuda")
-            outs[name] = (kr, kt)
+            K[f][name] = (kr, kt)
             jobs.append(dict(a=test, b=train, na=nte, nb=ntr, out=kr))
             jobs.append(dict(a=train, b=train, na=ntr, nb=ntr, upper_only=True, out=kt))
         st = {}
         q.gram_multi(jobs, precision=f, stream=stream, stats=st)
         stream.synchronize()
-        K[f] = outs
-        launch[f] = {"jobs": len(jobs), "entries": int(st["entries"]), "kernel_s": round(st["kernel_ms"] / 1e3, 3),
-                     "entries_per_s": round(st["entries"] / (st["kernel_ms"] / 1e3), 1),
-                     "tflops_algorithmic": round(st["flops"] / (st["kernel_ms"] / 1e3) / 1e12, 2)}
-        log(f"[bench] uneven: {f}: one launch, {len(jobs)} jobs, {launch[f]}")
+        launch[f + tag] = {"jobs": len(jobs), "entries": int(st["entries"]), "block": int(st["block"]),
+                           "kernel_s": round(st["kernel_ms"] / 1e3, 3),
+                           "entries_per_s": round(st["entries"] / (st["kernel_ms"] / 1e3), 1),
+                           "tflops_algorithmic": round(st["flops"] / (st["kernel_ms"] / 1e3) / 1e12, 2)}
+        log(f"[bench] uneven: {f}{tag}: one launch, {len(jobs)} jobs, {launch[f + tag]}")
     for name, (w, b, train, test, ntr, nte) in inst.items():
         r = report[name]
         kr0, kt0 = K["fp64"][name]
         up = torch.ones_like(kt0, dtype=torch.bool).triu_()
-        for f in forms[1:]:
+        for f in inst_forms[name][1:]:
             kr, kt = K[f][name]
             d = torch.cat([(kr - kr0).abs().flatten(), (kt - kt0).abs()[up]])
             r[f"{f}_dK_vs_fp64_max"] = float(d.max().item())
@@ -987,22 +1005,25 @@ def config_uneven(args):
         r["K_offdiag_median"], r["K_offdiag_max"] = float(np.median(offd)), float(offd.max())
         r["K_test_train_max"] = float(kr0.max().item())
         if not args.no_cpu:
-            sel_tr, sel_te = list(range(48)), list(range(ntr, ntr + 16))
+            a_tr, a_te = (6, 2) if w.chi > 64 else (48, 16)
+            sel_tr, sel_te = list(range(a_tr)), list(range(ntr, ntr + a_te))
             Ko = _oracle_child([b.export(i) for i in sel_tr + sel_te], args.cpu_workers, name)
             if Ko is not None:
-                for f in forms:
+                for f in inst_forms[name]:
                     kr, kt = K[f][name]
-                    ktr = kt[:48, :48].cpu().numpy()
-                    kte = kr[:16, :48].cpu().numpy()
-                    iu = np.triu_indices(48)
-                    d = np.concatenate([np.abs(ktr - Ko[:48, :48])[iu], np.abs(kte - Ko[48:, :48]).ravel()])
+                    ktr = kt[:a_tr, :a_tr].cpu().numpy()
+                    kte = kr[:a_te, :a_tr].cpu().numpy()
+                    iu = np.triu_indices(a_tr)
+                    d = np.concatenate([np.abs(ktr - Ko[:a_tr, :a_tr])[iu],
+                                        np.abs(kte - Ko[a_tr:, :a_tr]).ravel()])
                     r[f"{f}_dK_vs_oracle_max"] = float(d.max())
-                r["oracle_entries"] = int(48 * 49 // 2 + 16 * 48)
+                r["oracle_entries"] = int(a_tr * (a_tr + 1) // 2 + a_te * a_tr)
         log(f"[bench] uneven: {name}: {r}")
     print(json.dumps({"config": "uneven", "instances": report, "launch_per_form": launch,
                       "autotune": tuned, "forms": list(forms),
                       "workload": "4 instances (m, d, chi) = (20,1,16), (60,3,32), (110,5,64), (165,8,128); "
-                                  "2000 points each (1600 train + 400 test), reps 2, cutoff 1e-10, routing 0",
+                                  "2000 points each (1600 train + 400 test; the chi=128 instance on its first "
+                                  f"{min(args.wide_points, 2000)} points), reps 2, cutoff 1e-10, routing 0",
                       "data": "synthetic"}), flush=True)
 
 

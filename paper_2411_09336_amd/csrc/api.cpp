@@ -376,7 +376,7 @@ static qk_status simulate_impl(const double *features_dev, int64_t n_points, con
   if (n_points < 0) return fail(QK_EINVAL, "n_points < 0");
   if (n_points > 0 && !features_dev) return fail(QK_EINVAL, "features_dev is NULL");
   if (chi_max < 1) return fail(QK_EINVAL, "chi_max must be >= 1");
-  if (chi_max > kMaxSimChi) return fail(QK_ENOTSUP, "chi_max above 64 is not supported in simulation");
+  if (chi_max > kMaxSimChi) return fail(QK_ENOTSUP, "chi_max above 128 is not supported in simulation");
   if (!std::isfinite(cutoff)) return fail(QK_EINVAL, "cutoff must be finite");
   hipStream_t stream = reinterpret_cast<hipStream_t>(hip_stream);
   const int m = spec->n_qubits;

@@ -24,7 +24,7 @@ qk_status fail(qk_status st, const std::string &msg);
 
 constexpr int kPadQuantum = 32;      // bond pads are multiples of 32
 constexpr int kMaxBond = 128;        // largest supported pad in a batch
-constexpr int kMaxSimChi = 64;       // largest bond cap in simulation
+constexpr int kMaxSimChi = 128;      // largest bond cap in simulation
 
 inline int pad_of(int d) { return ((d + kPadQuantum - 1) / kPadQuantum) * kPadQuantum; }
 

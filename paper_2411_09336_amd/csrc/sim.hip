@@ -51,6 +51,12 @@ constexpr int kSvRows = 8;                // rows per wave
 constexpr int kSvThreads = kSvWaves * 64; // 1024
 constexpr int kSvMaxN = 128;
 constexpr int kMaxSweeps = 30;
+// Two-site steps next to a bond above 64 (bond caps up to 128): Jacobi
+// matrices up to 256 x 256, streamed through a per-circuit slot of global
+// scratch (Jacobi columns and projection source, 1 MiB each).
+constexpr int kWideN = 256;
+constexpr int kWideFrom = 64;     // a neighbouring bond above this takes the wide step
+constexpr size_t kWideSlot = size_t(2) * kWideN * kWideN;
 constexpr double kJacobiTol = 1e-14;
 // A sweep whose rotations all have |<X,Y>| below kJacobiLarge |X| |Y| ends
 // the iteration: cyclic Jacobi converges quadratically, so the next sweep's
@@ -77,6 +83,7 @@ struct SvParams {
   const double *X;
   int64_t ldx;
   double2 *scratch;  // per circuit 2 * kSvMaxN * kSvMaxN
+  double2 *wscratch; // per circuit kWideSlot (bond caps above 64), else nullptr
   double *disc;
   double *maxdisc;
   int32_t *degen;
@@ -219,14 +226,14 @@ __device__ inline void staged_tile_gemm(int K, const FL &ldL, const FR &ldR, dou
 }
 
 // Two-site theta element theta[(s, a), (t, b)] of this step's gate from the
-// pair product P (row stride kSvMaxN).
+// pair product P (row stride ld).
 __device__ inline double2 theta_from_pair(const double2 *Pp2, int op, double cg, double sg, int Dp, int Dn, int s,
-                                          int a, int t, int b) {
-  if (op == OP_SWAP) return Pp2[(t * Dp + a) * kSvMaxN + s * Dn + b];
-  const double2 d = Pp2[(s * Dp + a) * kSvMaxN + t * Dn + b];
+                                          int a, int t, int b, int ld = kSvMaxN) {
+  if (op == OP_SWAP) return Pp2[(t * Dp + a) * ld + s * Dn + b];
+  const double2 d = Pp2[(s * Dp + a) * ld + t * Dn + b];
   if (op == OP_RXX) {
     // Rxx = cos(phi/2) I - i sin(phi/2) X(x)X
-    const double2 x = Pp2[((1 - s) * Dp + a) * kSvMaxN + (1 - t) * Dn + b];
+    const double2 x = Pp2[((1 - s) * Dp + a) * ld + (1 - t) * Dn + b];
     return make_double2(cg * d.x + sg * x.y, cg * d.y - sg * x.x);
   }
   return d;
@@ -391,6 +398,37 @@ struct SimStep {
   int32_t r0, nr;               // Rz run: gate records [r0, r0 + nr); two-site step: r0 = index of
                                 // the two-qubit gate among the circuit's (-1 for a centre move)
 };
+
+// Rows j0 .. j0 + 63 of the projection out[j][x] = nrm sum_y conj(U[y][j])
+// S[y][x] (j < k, x < ncs, y < nr) of a two-site step, written to the
+// non-isometric site tensor; U is the isometric factor already written to
+// A_p (absorb right) or, conjugated, to A_{p+1}.  Wave w forms rows
+// j0 + 4w .. j0 + 4w + 3.
+__device__ __attribute__((noinline)) void project_rows(double2 *Ap, double2 *Aq, const double2 *S, int Dp, int Dn,
+                                                       int Pp, int Pm, int Pn, int nr, int ncs, int k, int j0,
+                                                       double nrm, bool right, double2 (*sL)[kSvMaxN],
+                                                       double2 (*sR)[kSvMaxN]) {
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  double2 acc[4][2];
+  staged_tile_gemm<4>(
+      nr,
+      [&](int jj, int y) {
+        const int j = j0 + jj;
+        if (j >= k) return make_double2(0.0, 0.0);
+        return right ? cconj(Ap[(size_t(y / Dp) * Pp + y % Dp) * Pm + j]) : Aq[(size_t(y / Dn) * Pm + j) * Pn + y % Dn];
+      },
+      [&](int y, int x) { return x < ncs ? S[y * kSvMaxN + x] : make_double2(0.0, 0.0); }, sL, sR, acc);
+#pragma unroll
+  for (int rr = 0; rr < 4; ++rr)
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int j = j0 + wave * 4 + rr, x = 2 * lane + q;
+      if (j < k && x < ncs) {
+        if (right) Aq[(size_t(x / Dn) * Pm + j) * Pn + x % Dn] = make_double2(nrm * acc[rr][q].x, nrm * acc[rr][q].y);
+        else Ap[(size_t(x / Dp) * Pp + x % Dp) * Pm + j] = make_double2(nrm * acc[rr][q].x, -nrm * acc[rr][q].y);
+      }
+    }
+}
 
 // Two-site step of circuit ci (one 1024-thread workgroup).
 __device__ __attribute__((noinline)) void svd_step(const SvParams &P, const int64_t ci, const SimStep &st) {
@@ -769,29 +807,380 @@ __device__ __attribute__((noinline)) void svd_step(const SvParams &P, const int6
     }
   }
   __syncthreads();
-  // projection: out[j][x] = sum_y conj(U[y][j]) S[y][x]; wave w forms rows
-  // j = 4w .. 4w+3
+  // projection: out[j][x] = sum_y conj(U[y][j]) S[y][x] in blocks of 64 rows
+  // j (bond caps above 64 keep up to 128)
+  project_rows(Ap, Aq, S, Dp, Dn, Pp, Pm, Pn, nr, ncs, k, 0, nrm, right, s_u.stage.L, s_u.stage.R);
+  if (k > 64) project_rows(Ap, Aq, S, Dp, Dn, Pp, Pm, Pn, nr, ncs, k, 64, nrm, right, s_u.stage.L, s_u.stage.R);
+  if (tid == 0) dims[p + 1] = k;
+}
+
+// A value of lane 0, in every lane (wave-uniform control flow and
+// identical rotation parameters across the rows of a column pair).
+__device__ inline double lane0(double x) {
+  return __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(x)),
+                          __builtin_amdgcn_readfirstlane(__double2loint(x)));
+}
+
+// Two-site step of circuit ci whose Jacobi matrix may exceed 128 x 128 (a
+// neighbouring bond above 64; one 1024-thread workgroup).  The same
+// operation as svd_step -- pair product, theta, one-sided Jacobi on the
+// columns, truncation by Eq. (8) with the bond cap, isometric factor from the
+// normalised columns and the other factor as an exact projection -- with the
+// matrices in the circuit's global scratch slot (L2-resident) instead of
+// registers:
+//   W: the pair product (row-major), then the Jacobi matrix M column-major
+//      (column c at W + c kWideN, rows 0..255, zero beyond nr);
+//   S: the projection source (row-major, row stride kWideN).
+// M is first reduced as in svd_step (M <- M H_0 H_1 ..., Householder
+// reflections from the right with the rows in order of decreasing norm), so
+// that only its first min(nr, nc) columns carry more than rounding-level
+// weight; the Jacobi sweeps then pair those columns in round-robin order
+// (NP - 1 rounds of NP/2 disjoint pairs: every pair once per sweep).  Wave w
+// rotates pairs w, w + 16, ... of a round, each lane holding rows l, l + 64,
+// l + 128, l + 192 of both columns, with one barrier per round.
+__device__ __attribute__((noinline)) void svd_step_wide(const SvParams &P, const int64_t ci, const SimStep &st) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  __shared__ double w_norm[kWideN];   // squared norm of each Jacobi column (row norms during the LQ)
+  __shared__ double w_sorted[kWideN]; // norms in decreasing order
+  __shared__ int w_col[kWideN];       // column of each rank (pivot row of each LQ step)
+  __shared__ double2 w_vec[kWideN];   // Householder vector of an LQ step
+  __shared__ double2 w_dot[4][kWideN];// partial products row . conj(w)
+  __shared__ double w_part[kSvWaves];
+  __shared__ double w_beta;
+  __shared__ int w_k;
+  __shared__ double w_nrm, w_tot;
+
+  int32_t *dims = P.dims + ci * (P.m + 1);
+  const int p = st.p;
+  const int Dp = dims[p], Dm = dims[p + 1], Dn = dims[p + 2];
+  const int Pp = P.pad[p], Pm = P.pad[p + 1], Pn = P.pad[p + 2];
+  double2 *Ap = P.f64 + ci * P.mps_stride + P.site_off[p];
+  double2 *Aq = P.f64 + ci * P.mps_stride + P.site_off[p + 1];
+  double2 *W = P.wscratch + int64_t(blockIdx.x) * kWideSlot;
+  double2 *S = W + kWideN * kWideN;
+
+  double cg = 1.0, sg = 0.0;
+  if (st.op == OP_RXX) {
+    const double xi = P.X[ci * P.ldx + st.fi], xj = P.X[ci * P.ldx + st.fj];
+    const double phi = P.coef_xx * (1.0 - xi) * (1.0 - xj);
+    sincos(0.5 * phi, &sg, &cg);
+  }
+  const bool right = (st.mode == GATE_RIGHT || st.mode == MOVE_RIGHT);
+  const bool gate = (st.mode == GATE_RIGHT || st.mode == GATE_LEFT);
+  int nr, nc, ncs;
+  if (st.mode == GATE_RIGHT) { nr = 2 * Dp; nc = 2 * Dn; ncs = nc; }
+  else if (st.mode == GATE_LEFT) { nr = 2 * Dn; nc = 2 * Dp; ncs = nc; }
+  else if (st.mode == MOVE_RIGHT) { nr = 2 * Dp; nc = Dm; ncs = 2 * Dn; }
+  else { nr = 2 * Dn; nc = Dm; ncs = 2 * Dp; }
+
+  // ---------------------------------------------------------- pair product -> W
+  // P[(s', a)][(t', b)] = sum_c A_p[s'][a][c] A_{p+1}[t'][c][b]; consecutive
+  // threads take consecutive b (coalesced reads of A_{p+1})
+  for (int e = tid; e < 4 * Dp * Dn; e += kSvThreads) {
+    const int y = e / (2 * Dn), x = e % (2 * Dn);
+    const double2 *ar = Ap + (size_t(y / Dp) * Pp + y % Dp) * Pm;
+    const double2 *bc = Aq + size_t(x / Dn) * Pm * Pn + x % Dn;
+    double re = 0.0, im = 0.0;
+    for (int c = 0; c < Dm; ++c) {
+      const double2 u = ar[c], v = bc[size_t(c) * Pn];
+      re = fma(u.x, v.x, fma(-u.y, v.y, re));
+      im = fma(u.x, v.y, fma(u.y, v.x, im));
+    }
+    W[size_t(y) * kWideN + x] = make_double2(re, im);
+  }
+  __syncthreads();
+  // ---------------------------------------------------------- projection source -> S
+  // gates: theta (absorb right) or theta^H (absorb left), which is also the
+  // Jacobi matrix; centre moves: the identity theta P or its adjoint
+  for (int e = tid; e < nr * ncs; e += kSvThreads) {
+    const int r = e / ncs, c = e % ncs;
+    double2 v;
+    if (st.mode == GATE_RIGHT) v = theta_from_pair(W, st.op, cg, sg, Dp, Dn, r / Dp, r % Dp, c / Dn, c % Dn, kWideN);
+    else if (st.mode == GATE_LEFT)
+      v = cconj(theta_from_pair(W, st.op, cg, sg, Dp, Dn, c / Dp, c % Dp, r / Dn, r % Dn, kWideN));
+    else if (st.mode == MOVE_RIGHT) v = W[size_t(r) * kWideN + c];
+    else v = cconj(W[size_t(c) * kWideN + r]);
+    S[size_t(r) * kWideN + c] = v;
+  }
+  __syncthreads();
+  // ---------------------------------------------------------- Jacobi matrix -> W (column-major)
+  const int NC = nc + (nc & 1);
+  for (int e = tid; e < NC * kWideN; e += kSvThreads) {
+    const int c = e / kWideN, r = e % kWideN;
+    double2 v = make_double2(0.0, 0.0);
+    if (r < nr && c < nc) {
+      if (gate) v = S[size_t(r) * kWideN + c];
+      else if (st.mode == MOVE_RIGHT) v = Ap[(size_t(r / Dp) * Pp + r % Dp) * Pm + c];
+      else v = cconj(Aq[(size_t(r / Dn) * Pm + c) * Pn + r % Dn]);
+    }
+    W[size_t(c) * kWideN + r] = v;
+  }
+  // ||M||_F^2 (invariant under the rotations), from the values just written
   {
-    double2 acc[4][2];
-    staged_tile_gemm<4>(
-        nr,
-        [&](int j, int y) {
-          if (j >= k) return make_double2(0.0, 0.0);
-          return right ? cconj(Ap[(size_t(y / Dp) * Pp + y % Dp) * Pm + j])
-                       : Aq[(size_t(y / Dn) * Pm + j) * Pn + y % Dn];
-        },
-        [&](int y, int x) { return x < ncs ? S[y * kSvMaxN + x] : make_double2(0.0, 0.0); },
-        s_u.stage.L, s_u.stage.R, acc);
-#pragma unroll
-    for (int rr = 0; rr < 4; ++rr)
-#pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        const int j = wave * 4 + rr, x = 2 * lane + q;
-        if (j < k && x < ncs) {
-          if (right) Aq[(size_t(x / Dn) * Pm + j) * Pn + x % Dn] = make_double2(nrm * acc[rr][q].x, nrm * acc[rr][q].y);
-          else Ap[(size_t(x / Dp) * Pp + x % Dp) * Pm + j] = make_double2(nrm * acc[rr][q].x, -nrm * acc[rr][q].y);
+    double t = 0.0;
+    for (int e = tid; e < NC * kWideN; e += kSvThreads) {
+      const int c = e / kWideN, r = e % kWideN;
+      if (r < nr && c < nc) {
+        double2 v;
+        if (gate) v = S[size_t(r) * kWideN + c];
+        else if (st.mode == MOVE_RIGHT) v = Ap[(size_t(r / Dp) * Pp + r % Dp) * Pm + c];
+        else v = cconj(Aq[(size_t(r / Dn) * Pm + c) * Pn + r % Dn]);
+        t = fma(v.x, v.x, fma(v.y, v.y, t));
+      }
+    }
+    t = wave_sum(t);
+    if (lane == 0) w_part[wave] = t;
+    __syncthreads();
+    if (tid == 0) {
+      double u = 0.0;
+      for (int w = 0; w < kSvWaves; ++w) u += w_part[w];
+      w_tot = u;
+    }
+    __syncthreads();
+  }
+  const double zero_w = lane0(kZeroWeight * w_tot);
+
+  // ---------------------------------------------------------- LQ preconditioning
+  // Step i reflects the i-th heaviest row x (restricted to columns >= i) onto
+  // column i: w = x + e^{i arg x_i} |x| e_i, beta = 1 / (|x| (|x| + |x_i|)),
+  // every row r <- r - beta (r . conj w) w.  Thread (r, q) = (tid % 256,
+  // tid / 256) takes row r and the columns c = q mod 4.
+  const int nref = min(nr, nc);
+  {
+    if (tid < kWideN) {
+      double t = 0.0;
+      if (tid < nr)
+        for (int c = 0; c < nc; ++c) {
+          const double2 v = W[size_t(c) * kWideN + tid];
+          t = fma(v.x, v.x, fma(v.y, v.y, t));
+        }
+      w_norm[tid] = t;
+    }
+    __syncthreads();
+    if (tid < kWideN) {
+      const double v = w_norm[tid];
+      int rank = 0;
+#pragma unroll 1
+      for (int u = 0; u < kWideN; ++u) {
+        const double o = w_norm[u];
+        rank += (o > v || (o == v && u < tid)) ? 1 : 0;
+      }
+      w_col[rank] = tid;
+    }
+    __syncthreads();
+    const int r = tid & (kWideN - 1), q = tid >> 8;
+    for (int i = 0; i < nref; ++i) {
+      const int pv = w_col[i];
+      if (tid < kWideN) {
+        // the pivot row restricted to columns >= i, and |x|
+        const double2 x = (tid >= i && tid < nc) ? W[size_t(tid) * kWideN + pv] : make_double2(0.0, 0.0);
+        w_vec[tid] = x;
+        const double n2 = wave_sum(fma(x.x, x.x, x.y * x.y));
+        if (lane == 0) w_part[wave] = n2;
+      }
+      __syncthreads();
+      if (tid == 0) {
+        const double nx = sqrt(w_part[0] + w_part[1] + w_part[2] + w_part[3]);
+        const double2 xi = w_vec[i];
+        const double ax = sqrt(fma(xi.x, xi.x, xi.y * xi.y));
+        const double pr = ax > 0.0 ? xi.x / ax : 1.0, pi = ax > 0.0 ? xi.y / ax : 0.0;
+        w_vec[i] = make_double2(pr * (ax + nx), pi * (ax + nx));
+        w_beta = nx > 0.0 ? 1.0 / (nx * (nx + ax)) : 0.0;
+      }
+      __syncthreads();
+      double dr = 0.0, di = 0.0;
+      if (r < nr)
+        for (int c = i + q; c < nc; c += 4) {
+          const double2 v = W[size_t(c) * kWideN + r], w = w_vec[c];
+          dr = fma(v.x, w.x, fma(v.y, w.y, dr));
+          di = fma(v.y, w.x, fma(-v.x, w.y, di));
+        }
+      w_dot[q][r] = make_double2(dr, di);
+      __syncthreads();
+      if (r < nr) {
+        const double beta = w_beta;
+        const double2 d0 = w_dot[0][r], d1 = w_dot[1][r], d2 = w_dot[2][r], d3 = w_dot[3][r];
+        const double br = beta * ((d0.x + d1.x) + (d2.x + d3.x)), bi = beta * ((d0.y + d1.y) + (d2.y + d3.y));
+        for (int c = i + q; c < nc; c += 4) {
+          const double2 w = w_vec[c];
+          double2 *m = W + size_t(c) * kWideN + r;
+          const double2 v = *m;
+          *m = make_double2(v.x - (br * w.x - bi * w.y), v.y - (br * w.y + bi * w.x));
         }
       }
+      __syncthreads();  // the next step reads its pivot row and rewrites the LDS vectors
+    }
+  }
+
+  // ---------------------------------------------------------- Jacobi sweeps
+  const int NP = max(2, nref + (nref & 1));
+  bool converged = false;
+  const int half = NP / 2, rounds = NP - 1;
+  for (int sweep = 0; sweep < kMaxSweeps && !converged; ++sweep) {
+    bool large = false;
+    for (int rd = 0; rd < rounds; ++rd) {
+      for (int k = wave; k < half; k += kSvWaves) {
+        // round-robin pairing: column NP-1 meets column rd, the others pair
+        // symmetrically around rd (indices mod NP-1)
+        const int i = k == 0 ? NP - 1 : (rd + k) % rounds;
+        const int j = k == 0 ? rd : (rd - k + rounds) % rounds;
+        double2 *X = W + size_t(i) * kWideN + lane;
+        double2 *Y = W + size_t(j) * kWideN + lane;
+        double2 x[4], y[4];
+        double a = 0.0, b = 0.0, gr = 0.0, gi = 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          x[q] = X[64 * q];
+          y[q] = Y[64 * q];
+          a = fma(x[q].x, x[q].x, fma(x[q].y, x[q].y, a));
+          b = fma(y[q].x, y[q].x, fma(y[q].y, y[q].y, b));
+          gr = fma(x[q].x, y[q].x, fma(x[q].y, y[q].y, gr));
+          gi = fma(x[q].x, y[q].y, fma(-x[q].y, y[q].x, gi));
+        }
+        a = lane0(wave_sum(a));
+        b = lane0(wave_sum(b));
+        gr = lane0(wave_sum(gr));
+        gi = lane0(wave_sum(gi));
+        const double g2 = fma(gr, gr, gi * gi);
+        if (a > zero_w && b > zero_w && g2 > (kJacobiTol * kJacobiTol) * (a * b)) {
+          if (g2 > (kJacobiLarge * kJacobiLarge) * (a * b)) large = true;
+          // the Hermitian 2 x 2 rotation of the pair's Gram block (as in
+          // jacobi_round): X' = c X - s u Y, Y' = s X + c u Y,
+          // u = conj<X,Y> / |<X,Y>|
+          const double rg = rsqrt(g2);
+          const double zeta = 0.5 * (b - a) * rg;
+          const double den = fabs(zeta) + sqrt(fma(zeta, zeta, 1.0));
+          double rdn = __builtin_amdgcn_rcp(den);
+          rdn = fma(rdn, fma(-den, rdn, 1.0), rdn);
+          rdn = fma(rdn, fma(-den, rdn, 1.0), rdn);
+          const double t = zeta >= 0.0 ? rdn : -rdn;
+          const double c = rsqrt(fma(t, t, 1.0));
+          const double sn = c * t;
+          const double ur = gr * rg, ui = -gi * rg;
+          const double xr_ = -sn * ur, xi_ = -sn * ui;   // -s u
+          const double yr_ = c * ur, yi_ = c * ui;       //  c u
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const double2 xo = x[q], yo = y[q];
+            X[64 * q] = make_double2(fma(c, xo.x, fma(xr_, yo.x, -xi_ * yo.y)), fma(c, xo.y, fma(xr_, yo.y, xi_ * yo.x)));
+            Y[64 * q] = make_double2(fma(sn, xo.x, fma(yr_, yo.x, -yi_ * yo.y)),
+                                     fma(sn, xo.y, fma(yr_, yo.y, yi_ * yo.x)));
+          }
+        }
+      }
+      __syncthreads();  // the next round reads the columns this one wrote
+    }
+    converged = __syncthreads_or(large ? 1 : 0) == 0;
+  }
+
+  // ---------------------------------------------------------- norms, order, k
+  for (int c = wave; c < kWideN; c += kSvWaves) {
+    double t = 0.0;
+    if (c < NP) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double2 v = W[size_t(c) * kWideN + lane + 64 * q];
+        t = fma(v.x, v.x, fma(v.y, v.y, t));
+      }
+      t = wave_sum(t);
+    }
+    if (lane == 0) w_norm[c] = t;
+  }
+  __syncthreads();
+  if (tid < kWideN) {
+    const double v = w_norm[tid];
+    int rank = 0;
+#pragma unroll 1
+    for (int u = 0; u < kWideN; ++u) {
+      const double o = w_norm[u];
+      rank += (o > v || (o == v && u < tid)) ? 1 : 0;
+    }
+    w_sorted[rank] = v;
+    w_col[rank] = tid;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    const int nsv = min(nr, nc);
+    int nnz = 0;
+#pragma unroll 1
+    for (int u = 0; u < kWideN; ++u) nnz += w_sorted[u] > zero_w ? 1 : 0;
+    double total = 0.0;
+#pragma unroll 1
+    for (int u = kWideN - 1; u >= 0; --u) total += w_sorted[u];
+    int k;
+    if (gate) {
+      int kcut = nsv;
+      if (P.cutoff > 0.0) {
+        // smallest k with sum_{r >= k} w_r <= cutoff * total
+        double tail = 0.0;
+#pragma unroll 1
+        for (int kk = nsv; kk >= 0; --kk) {
+          if (kk < nsv) tail += w_sorted[kk];
+          if (tail <= P.cutoff * total) kcut = kk;
+          else break;
+        }
+      }
+      k = max(1, min(min(P.chi, kcut), max(nnz, 1)));
+      if (P.gate_split) {
+        const double cmax = fmax(fabs(cg), fabs(sg));
+        const int rg = st.op == OP_RXX ? (fabs(cg) > 1e-12 * cmax ? 1 : 0) + (fabs(sg) > 1e-12 * cmax ? 1 : 0) : 4;
+        k = max(1, min(k, rg * Dm));
+      }
+      double kept = 0.0;
+#pragma unroll 1
+      for (int u = k - 1; u >= 0; --u) kept += w_sorted[u];
+      double tail = 0.0;
+#pragma unroll 1
+      for (int u = kWideN - 1; u >= k; --u) tail += w_sorted[u];
+      const double disc = total > 0.0 ? tail / total : 0.0;
+      w_nrm = kept > 0.0 ? 1.0 / sqrt(kept) : 1.0;
+      P.disc[ci] += disc;
+      P.maxdisc[ci] = fmax(P.maxdisc[ci], disc);
+      if (k < nsv && w_sorted[0] > 0.0 &&
+          (sqrt(w_sorted[k - 1]) - sqrt(w_sorted[k])) / sqrt(w_sorted[0]) < kDegenerateGap)
+        P.degen[ci] += 1;
+    } else {
+      k = max(1, min(nsv, max(nnz, 1)));
+      w_nrm = 1.0;
+    }
+    if (!converged) P.unconv[ci] += 1;
+    w_k = k;
+  }
+  __syncthreads();
+  const int k = w_k;
+  const double nrm = w_nrm;
+
+  // ---------------------------------------------------------- write factors
+  for (int e = tid; e < 2 * Pp * Pm; e += kSvThreads) Ap[e] = make_double2(0.0, 0.0);
+  for (int e = tid; e < 2 * Pm * Pn; e += kSvThreads) Aq[e] = make_double2(0.0, 0.0);
+  __syncthreads();
+  // isometric factor: U[:, j] = column w_col[j] / its norm
+  for (int e = tid; e < k * nr; e += kSvThreads) {
+    const int j = e / nr, r = e % nr;
+    const int c = w_col[j];
+    const double inv = 1.0 / sqrt(w_norm[c]);
+    const double2 v = W[size_t(c) * kWideN + r];
+    const double vr = v.x * inv, vi = v.y * inv;
+    if (right) Ap[(size_t(r / Dp) * Pp + r % Dp) * Pm + j] = make_double2(vr, vi);
+    else Aq[(size_t(r / Dn) * Pm + j) * Pn + r % Dn] = make_double2(vr, -vi);
+  }
+  // projection: out[j][x] = nrm sum_y conj(U[y][j]) S[y][x]; consecutive
+  // threads take consecutive x (one column of W per wave, coalesced rows of S)
+  for (int e = tid; e < k * ncs; e += kSvThreads) {
+    const int j = e / ncs, x = e % ncs;
+    const int c = w_col[j];
+    const double inv = 1.0 / sqrt(w_norm[c]);
+    const double2 *u = W + size_t(c) * kWideN;
+    double re = 0.0, im = 0.0;
+    for (int y = 0; y < nr; ++y) {
+      const double2 uv = u[y], sv = S[size_t(y) * kWideN + x];
+      const double ur = uv.x * inv, ui = uv.y * inv;
+      re = fma(ur, sv.x, fma(ui, sv.y, re));
+      im = fma(ur, sv.y, fma(-ui, sv.x, im));
+    }
+    if (right) Aq[(size_t(x / Dn) * Pm + j) * Pn + x % Dn] = make_double2(nrm * re, nrm * im);
+    else Ap[(size_t(x / Dp) * Pp + x % Dp) * Pm + j] = make_double2(nrm * re, -nrm * im);
   }
   if (tid == 0) dims[p + 1] = k;
 }
@@ -826,8 +1215,13 @@ __global__ __launch_bounds__(kSvThreads) void sim_steps_kernel(SvParams P, const
   if (ci >= P.n) return;
   for (int s = s0; s < s1; ++s) {
     const SimStep st = steps[s];
-    if (st.kind == STEP_RZ) rz_run(P, ci, recs + st.r0, st.nr, coef_z);
-    else svd_step(P, ci, st);
+    if (st.kind == STEP_RZ) {
+      rz_run(P, ci, recs + st.r0, st.nr, coef_z);
+    } else {
+      const int32_t *dims = P.dims + ci * (P.m + 1);
+      if (P.wscratch && (dims[st.p] > kWideFrom || dims[st.p + 2] > kWideFrom)) svd_step_wide(P, ci, st);
+      else svd_step(P, ci, st);
+    }
     __syncthreads();  // the next step reads the tensors and bond dims this one wrote
     if (P.trace && st.kind == STEP_TWO_SITE && st.r0 >= 0 && threadIdx.x < 64) {
       // memory trace after a two-qubit gate: the bond at its cut and
@@ -1000,16 +1394,17 @@ qk_status run_simulation(qk_mps_batch *b, const double *features_dev, const std:
   // Device buffers: gate records, step list, SVD scratch of one slot per
   // workgroup of a launch, and (graph mode) the first circuit of a replay.
   const DevAlloc al = allocator_for_current_device();
-  void *recs_dev = nullptr, *steps_dev = nullptr, *scratch = nullptr, *base_dev = nullptr;
+  void *recs_dev = nullptr, *steps_dev = nullptr, *scratch = nullptr, *wscratch = nullptr, *base_dev = nullptr;
   auto release = [&]() {
-    for (void *ptr : {recs_dev, steps_dev, scratch, base_dev})
+    for (void *ptr : {recs_dev, steps_dev, scratch, wscratch, base_dev})
       if (ptr) dev_free(al, ptr, stream, true);
   };
   recs_dev = dev_alloc(al, sizeof(qk_gate) * std::max<size_t>(gates.size(), 1), stream, true);
   steps_dev = dev_alloc(al, sizeof(SimStep) * std::max<size_t>(steps.size(), 1), stream, true);
   scratch = dev_alloc(al, sizeof(double2) * 2 * kSvMaxN * kSvMaxN * size_t(grid), stream, true);
+  if (chi > kWideFrom) wscratch = dev_alloc(al, sizeof(double2) * kWideSlot * size_t(grid), stream, true);
   if (graph) base_dev = dev_alloc(al, 256, stream, true);
-  if (!recs_dev || !steps_dev || !scratch || (graph && !base_dev)) {
+  if (!recs_dev || !steps_dev || !scratch || (chi > kWideFrom && !wscratch) || (graph && !base_dev)) {
     release();
     return fail(QK_ENOMEM, "device allocation of the simulation buffers failed");
   }
@@ -1039,6 +1434,7 @@ qk_status run_simulation(qk_mps_batch *b, const double *features_dev, const std:
   P.X = features_dev;
   P.ldx = m;
   P.scratch = static_cast<double2 *>(scratch);
+  P.wscratch = static_cast<double2 *>(wscratch);
   P.disc = b->disc_dev;
   P.maxdisc = b->maxdisc_dev;
   P.degen = b->degen_dev;

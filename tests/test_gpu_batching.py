@@ -88,8 +88,8 @@ def test_invalid_simulation_arguments():
     spec = q.CircuitSpec(6, 1, 1)
     x = torch.rand((3, 6), dtype=torch.float64, device="cuda")
     with pytest.raises(q.QKError) as e:
-        q.simulate(x, spec, 128, 0.0)
-    assert e.value.status == -4                            # chi above 64
+        q.simulate(x, spec, 129, 0.0)
+    assert e.value.status == -4                            # chi above 128
     x[1, 2] = float("nan")
     with pytest.raises(q.QKError) as e:
         q.simulate(x, spec, 16, 0.0)

@@ -1,7 +1,9 @@
 """Uneven batch (the workload with four instances of different qubit counts,
 interaction distances and bond caps): the instances with chi <= 64 run as
 rectangular test x train and symmetric train Grams, all jobs in one
-persistent launch; the chi = 128 instance is rejected."""
+persistent launch.  The chi = 128 instance's simulation and Gram kernels
+are tested on an 18-qubit slice of its circuit (test_gpu_sim_wide.py,
+test_gpu_gram_wide.py)."""
 import numpy as np
 import pytest
 
@@ -57,15 +59,3 @@ def test_uneven_instances_one_launch():
             print(name, prec, "test x train max|dK| vs oracle", d, "K max", ko.max())
             assert d < tol
             assert np.abs(np.diag(kt.cpu().numpy()) - 1.0).max() < tol
-
-
-def test_chi_128_instance_not_supported():
-    import paper_2411_09336_amd as q
-    torch = require_gpu()
-    w = sd.WORKLOADS["uneven_165"]
-    X = sd.workload_features(w, 2)
-    xt = torch.tensor(X, dtype=torch.float64, device="cuda")
-    spec = q.CircuitSpec(w.n_qubits, w.distance, w.reps, w.coef_z, w.coef_xx, 1)
-    with pytest.raises(q.QKError) as e:
-        q.simulate(xt, spec, w.chi, w.cutoff)
-    assert e.value.status == -4          # QK_ENOTSUP: chi above 64
