@@ -360,8 +360,9 @@ def main():
                          "|dK| against FP64 over all entries and against the oracle on the first 256 points; "
                          "'uneven' (four instances of 20, 60, 110, 165 qubits, 1600 train + 400 test points "
                          "each, all Gram jobs in one launch)")
-    ap.add_argument("--wide-points", type=int, default=256,
-                    help="--config uneven: points of the bond-128 instance (165 qubits, d=8; 3/4 train, 1/4 test)")
+    ap.add_argument("--wide-points", type=int, default=0,
+                    help="--config uneven: points of the bond-128 instance (165 qubits, d=8; 3/4 train, 1/4 test; "
+                         "0 skips it: one circuit takes about ten minutes)")
     ap.add_argument("--oracle-gram", metavar="MPS_NPY", default=None,
                     help=argparse.SUPPRESS)   # child process of --config: the oracle's Gram of a file of MPS
     ap.add_argument("--routing", type=int, default=0,
@@ -911,9 +912,10 @@ def config_uneven(args):
     batch (two replays of 1000 circuits); the Gram kernels are autotuned per
     bond-pad bucket and form; then, per form, ONE persistent launch computes
     every such instance's 400 x 1600 test x train block and its symmetric
-    1600 x 1600 train Gram.  The bond-128 instance runs on its first
-    --wide-points points (3/4 train, 1/4 test; eager simulation with progress
-    lines, since each circuit takes minutes) in the FP64 and FP32 forms (the
+    1600 x 1600 train Gram.  The bond-128 instance runs only on request, on
+    its first --wide-points points (3/4 train, 1/4 test; eager simulation with
+    progress lines: one of its circuits takes about ten minutes on one CU, and
+    up to one circuit per CU runs at a time) in the FP64 and FP32 forms (the
     split forms take pads up to 64), in a launch of its own.  |dK| of each
     form against FP64 over all entries, and of every form against the
     oracle's overlaps of 48 train and 16 test MPS per instance (6 and 2 for
@@ -931,6 +933,9 @@ def config_uneven(args):
     for name in ("uneven_20", "uneven_60", "uneven_110", "uneven_165"):
         w = sd.WORKLOADS[name]
         wide = w.chi > 64
+        if wide and args.wide_points <= 0:
+            report[name] = {"status": "skipped (run it with --wide-points N)"}
+            continue
         N = min(args.wide_points, w.n_points) if wide else w.n_points
         ntr = N * 3 // 4 if wide else w.n_points - w.n_test
         X = sd.workload_features(w, N)
@@ -1023,7 +1028,8 @@ def config_uneven(args):
                       "autotune": tuned, "forms": list(forms),
                       "workload": "4 instances (m, d, chi) = (20,1,16), (60,3,32), (110,5,64), (165,8,128); "
                                   "2000 points each (1600 train + 400 test; the chi=128 instance on its first "
-                                  f"{min(args.wide_points, 2000)} points), reps 2, cutoff 1e-10, routing 0",
+                                  f"{min(args.wide_points, 2000)} points, 0: skipped), reps 2, cutoff 1e-10, "
+                                  "routing 0",
                       "data": "synthetic"}), flush=True)
 
 
