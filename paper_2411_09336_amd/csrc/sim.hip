@@ -814,6 +814,15 @@ __device__ __attribute__((noinline)) void svd_step(const SvParams &P, const int6
   if (tid == 0) dims[p + 1] = k;
 }
 
+// Sum over the 32 lanes of lane half hf (rows 2 hf, 2 hf + 1), as the value
+// of the half's first lane in every lane of the half: identical rotation
+// parameters for all rows of a column pair.
+__device__ inline double half_sum(double x, int hf) {
+  x = row_sum16(x);
+  x += __shfl_xor(x, 16, 64);
+  return __shfl(x, hf << 5, 64);
+}
+
 // A value of lane 0, in every lane (wave-uniform control flow and
 // identical rotation parameters across the rows of a column pair).
 __device__ inline double lane0(double x) {
@@ -836,8 +845,8 @@ __device__ inline double lane0(double x) {
 // that only its first min(nr, nc) columns carry more than rounding-level
 // weight; the Jacobi sweeps then pair those columns in round-robin order
 // (NP - 1 rounds of NP/2 disjoint pairs: every pair once per sweep).  Wave w
-// rotates pairs w, w + 16, ... of a round, each lane holding rows l, l + 64,
-// l + 128, l + 192 of both columns, with one barrier per round.
+// rotates pairs w, w + 16, ... of a round, two at a time (one per lane half,
+// each lane holding 8 rows of both columns), with one barrier per round.
 __device__ __attribute__((noinline)) void svd_step_wide(const SvParams &P, const int64_t ci, const SimStep &st) {
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -1017,33 +1026,39 @@ __device__ __attribute__((noinline)) void svd_step_wide(const SvParams &P, const
   const int NP = max(2, nref + (nref & 1));
   bool converged = false;
   const int half = NP / 2, rounds = NP - 1;
+  // two pairs in flight per wave: lane half hf takes pair k0 + 16 hf, its
+  // lane hl rows hl + 32 q (q < 8); sums over a half, then the value of the
+  // half's first lane in all its lanes (the same rotation for every row)
+  const int hf = lane >> 5, hl = lane & 31;
   for (int sweep = 0; sweep < kMaxSweeps && !converged; ++sweep) {
     bool large = false;
     for (int rd = 0; rd < rounds; ++rd) {
-      for (int k = wave; k < half; k += kSvWaves) {
+      for (int k0 = wave; k0 < half; k0 += 2 * kSvWaves) {
         // round-robin pairing: column NP-1 meets column rd, the others pair
         // symmetrically around rd (indices mod NP-1)
-        const int i = k == 0 ? NP - 1 : (rd + k) % rounds;
-        const int j = k == 0 ? rd : (rd - k + rounds) % rounds;
-        double2 *X = W + size_t(i) * kWideN + lane;
-        double2 *Y = W + size_t(j) * kWideN + lane;
-        double2 x[4], y[4];
+        const int k = k0 + hf * kSvWaves;
+        const bool act = k < half;
+        const int i = !act ? 0 : k == 0 ? NP - 1 : (rd + k) % rounds;
+        const int j = !act ? 0 : k == 0 ? rd : (rd - k + rounds) % rounds;
+        double2 *X = W + size_t(i) * kWideN + hl;
+        double2 *Y = W + size_t(j) * kWideN + hl;
+        double2 x[8], y[8];
         double a = 0.0, b = 0.0, gr = 0.0, gi = 0.0;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          x[q] = X[64 * q];
-          y[q] = Y[64 * q];
+        for (int q = 0; q < 8; ++q) {
+          x[q] = act ? X[32 * q] : make_double2(0.0, 0.0);
+          y[q] = act ? Y[32 * q] : make_double2(0.0, 0.0);
           a = fma(x[q].x, x[q].x, fma(x[q].y, x[q].y, a));
           b = fma(y[q].x, y[q].x, fma(y[q].y, y[q].y, b));
           gr = fma(x[q].x, y[q].x, fma(x[q].y, y[q].y, gr));
           gi = fma(x[q].x, y[q].y, fma(-x[q].y, y[q].x, gi));
         }
-        a = lane0(wave_sum(a));
-        b = lane0(wave_sum(b));
-        gr = lane0(wave_sum(gr));
-        gi = lane0(wave_sum(gi));
+        a = half_sum(a, hf);
+        b = half_sum(b, hf);
+        gr = half_sum(gr, hf);
+        gi = half_sum(gi, hf);
         const double g2 = fma(gr, gr, gi * gi);
-        if (a > zero_w && b > zero_w && g2 > (kJacobiTol * kJacobiTol) * (a * b)) {
+        if (act && a > zero_w && b > zero_w && g2 > (kJacobiTol * kJacobiTol) * (a * b)) {
           if (g2 > (kJacobiLarge * kJacobiLarge) * (a * b)) large = true;
           // the Hermitian 2 x 2 rotation of the pair's Gram block (as in
           // jacobi_round): X' = c X - s u Y, Y' = s X + c u Y,
@@ -1061,10 +1076,10 @@ __device__ __attribute__((noinline)) void svd_step_wide(const SvParams &P, const
           const double xr_ = -sn * ur, xi_ = -sn * ui;   // -s u
           const double yr_ = c * ur, yi_ = c * ui;       //  c u
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
+          for (int q = 0; q < 8; ++q) {
             const double2 xo = x[q], yo = y[q];
-            X[64 * q] = make_double2(fma(c, xo.x, fma(xr_, yo.x, -xi_ * yo.y)), fma(c, xo.y, fma(xr_, yo.y, xi_ * yo.x)));
-            Y[64 * q] = make_double2(fma(sn, xo.x, fma(yr_, yo.x, -yi_ * yo.y)),
+            X[32 * q] = make_double2(fma(c, xo.x, fma(xr_, yo.x, -xi_ * yo.y)), fma(c, xo.y, fma(xr_, yo.y, xi_ * yo.x)));
+            Y[32 * q] = make_double2(fma(sn, xo.x, fma(yr_, yo.x, -yi_ * yo.y)),
                                      fma(sn, xo.y, fma(yr_, yo.y, yi_ * yo.x)));
           }
         }
