@@ -45,7 +45,7 @@ typedef enum {
   QK_EINVAL = -1,     /* invalid argument (NULL, size, NaN feature, mismatch) */
   QK_ENOMEM = -2,     /* device or host allocation failed                     */
   QK_EDEVICE = -3,    /* HIP runtime error or device fault                    */
-  QK_ENOTSUP = -4,    /* valid but unsupported combination (e.g. chi > 64 in  */
+  QK_ENOTSUP = -4,    /* valid but unsupported combination (e.g. chi > 128 in */
                       /* simulation, precision not packed)                     */
   QK_ENUMERIC = -5,   /* an SVD did not converge within its sweep limit       */
   QK_EABORTED = -6
@@ -176,7 +176,11 @@ qk_status qk_circuit_compile(const qk_circuit_spec *spec, qk_gate *out_host,
  * moved next to each gate before its SVD, and singular values are absorbed
  * toward the next two-qubit gate.  The result is left-canonical with the last
  * site normalised, stored in FP64; other precisions are packed on demand.
- * chi_max must be in [1, 64].  On success *out receives a new batch. */
+ * chi_max must be in [1, 128].  Above 64, two-site steps next to a bond
+ * above 64 (Jacobi matrices up to 256 x 256) run with their matrices in a
+ * scratch slot of 2 MiB per circuit of a launch (drawn from the device's
+ * allocator for the call) and take tens of milliseconds each.  On success
+ * *out receives a new batch. */
 qk_status mps_simulate(const double *features_dev, int64_t n_points,
                        const qk_circuit_spec *spec, int32_t chi_max,
                        double cutoff, void *hip_stream, qk_mps_batch **out);
@@ -223,8 +227,8 @@ qk_status mps_simulate_trace(const double *features_dev, int64_t n_points,
  * hip_stream and before later work on it.  0 picks equal chunks of at most
  * QK_GRAPH_CIRCUITS circuits.  Each circuit goes through the same steps with
  * the same kernels as in mps_simulate, so the batch is bit-identical; the
- * SVD scratch is sized for one chunk (512 KiB per circuit) instead of the
- * whole batch, and the host launch work is that of one chunk whatever the
+ * SVD scratch is sized for one chunk (512 KiB per circuit, plus 2 MiB for
+ * chi_max above 64) instead of the whole batch, and the host launch work is that of one chunk whatever the
  * batch size.  QK_EINVAL if circuits_per_graph < 0; QK_EDEVICE if capture,
  * instantiation or a replay fails.  The call returns after the simulation
  * has finished. */
